@@ -1,0 +1,414 @@
+"""Benchmark: QPS at recall@10 >= 0.98 of the AQR-HNSW query path on one MI355X.
+
+Workload (default): 1,000,000 x 128 FP32 base vectors drawn from a seeded
+256-cluster Gaussian mixture with Zipf(1.1) cluster sizes and values clipped
+at 0 (a SIFT-1M-shaped synthetic set), 10,000 queries from the same mixture,
+HNSW M_0 = 16, ef_0^construction = 200, k = 10.
+
+One step = the whole query path for the batch of queries: encode + Stage 1
+(aqr_search) + Stages 2-3 (aqr_rerank), inputs resident in device memory.
+ef is swept and the cheapest ef whose mean recall@10 reaches 0.98 is timed;
+the baseline FP32 HNSW search on the same graph is swept and timed the same
+way.  The CPU oracle (test infrastructure) is timed on a sample of the same
+queries on the host cores.
+
+Prints one JSON line.
+"""
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+TARGET_RECALL = 0.98
+
+
+def log(msg):
+    print(f"[bench {time.strftime('%H:%M:%S')}] {msg}", file=sys.stderr, flush=True)
+
+
+def ground_truth(X, Q, k, device, chunk=131072, extra=32):
+    """Exact k nearest neighbours: FP32 screening, FP64 re-score of k+extra."""
+    import torch
+    torch.backends.cuda.matmul.allow_tf32 = False
+    Xd = torch.from_numpy(X).to(device)
+    Qd = torch.from_numpy(Q).to(device)
+    xn = (Xd * Xd).sum(1)
+    nq = Q.shape[0]
+    cand = k + extra
+    best_d = torch.full((nq, cand), float("inf"), device=device)
+    best_i = torch.zeros((nq, cand), dtype=torch.int64, device=device)
+    for s in range(0, X.shape[0], chunk):
+        e = min(X.shape[0], s + chunk)
+        sc = xn[s:e][None, :] - 2.0 * (Qd @ Xd[s:e].T)
+        d, i = sc.topk(min(cand, e - s), dim=1, largest=False)
+        best_d, idx = torch.cat([best_d, d], 1).topk(cand, dim=1, largest=False)
+        best_i = torch.gather(torch.cat([best_i, i + s], 1), 1, idx)
+    ids, _ = best_i.sort(dim=1)
+    diff = Xd[ids].double() - Qd[:, None, :].double()
+    dist = (diff * diff).sum(-1)
+    dist, order = dist.sort(dim=1, stable=True)
+    ids = torch.gather(ids, 1, order)
+    out = ids[:, :k].cpu().numpy(), dist[:, :k].cpu().numpy()
+    del Xd, Qd, xn, diff
+    torch.cuda.empty_cache()
+    return out
+
+
+def recall_at(ids, X, Q, gt_ids, gt_d, k=10):
+    """Mean recall@k; a returned id also counts when its exact distance ties
+    the k-th true distance within a factor 1 + 1e-6."""
+    ids = np.asarray(ids)[:, :k]
+    hits = 0
+    for q in range(ids.shape[0]):
+        g = set(gt_ids[q].tolist())
+        r = [int(i) for i in ids[q] if i >= 0]
+        h = sum(1 for i in r if i in g)
+        if h < k:
+            thr = gt_d[q, k - 1] * (1 + 1e-6)
+            for i in r:
+                if i not in g:
+                    dd = np.sum((X[i].astype(np.float64) - Q[q].astype(np.float64)) ** 2)
+                    h += dd <= thr
+        hits += min(h, k)
+    return hits / (ids.shape[0] * k)
+
+
+class AqrRunner:
+    def __init__(self, aqr, ix, nq, k, ef, device, visited_log2=0, waves_per_block=0):
+        import torch
+        self.torch = torch
+        self.aqr = aqr
+        self.plan = aqr.QueryPlan(ix, nq, k, max(ef, k), visited_log2=visited_log2,
+                                  waves_per_block=waves_per_block)
+        self.k = torch.full((nq,), k, dtype=torch.int32, device=device)
+        self.ef = torch.full((nq,), ef, dtype=torch.int32, device=device)
+
+    def step(self, Qd):
+        return self.plan.run(Qd, self.k, self.ef)
+
+    def search_only(self, Qd, taps=None):
+        p = self.plan
+        n = Qd.shape[0]
+        self.aqr.aqr_search(p.ix, Qd, self.k, self.ef, p.cand_id[:n], p.cand_D[:n],
+                            p.cand_cnt[:n], p.ws, p.ef_max, p.nc_max, m_ef=p.m_ef, taps=taps,
+                            **p.sp)
+
+    def rerank_only(self, Qd):
+        p = self.plan
+        n = Qd.shape[0]
+        self.aqr.aqr_rerank(p.ix, Qd, p.cand_id[:n], p.cand_cnt[:n], self.k, p.out_id[:n],
+                            p.out_dist[:n], p.out_kind[:n], **p.rr)
+
+
+class Fp32Runner:
+    def __init__(self, aqr, ix, nq, k, ef, device):
+        import torch
+        self.aqr = aqr
+        self.ix = ix
+        self.k_ = k
+        self.ef_ = max(ef, k)
+        self.k = torch.full((nq,), k, dtype=torch.int32, device=device)
+        self.ef = torch.full((nq,), ef, dtype=torch.int32, device=device)
+        self.out_id = torch.empty((nq, k), dtype=torch.int32, device=device)
+        self.out_d = torch.empty((nq, k), dtype=torch.float32, device=device)
+        self.ws = torch.zeros(aqr.aqr_search_workspace_size(), dtype=torch.uint8, device=device)
+
+    def step(self, Qd, taps=None):
+        self.aqr.aqr_search_fp32(self.ix, Qd, self.k, self.ef, self.out_id, self.out_d, self.ws,
+                                 self.ef_, self.k_, taps=taps)
+        return self.out_id, self.out_d
+
+
+def timed(torch, fn, steps, warmup, kernel_events=None):
+    """Run warmup then `steps` timed calls; returns (ms_per_step, per-kernel ms)."""
+    for _ in range(warmup):
+        fn(None)
+    torch.cuda.synchronize()
+    evs = []
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        marks = [torch.cuda.Event(enable_timing=True) for _ in range(kernel_events or 0)]
+        fn(marks)
+        evs.append(marks)
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) * 1e3 / steps
+    per = None
+    if kernel_events:
+        per = [np.mean([m[i].elapsed_time(m[i + 1]) for m in evs])
+               for i in range(kernel_events - 1)]
+    return ms, per
+
+
+def source_sha():
+    h = hashlib.sha256()
+    with open(os.path.join(ROOT, "paper_2602_21600_amd", "csrc", "device.hip"), "rb") as f:
+        h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def traffic_from_profile(name, sha):
+    """HBM bytes per launch from a committed rocprofv3 counter summary of the
+    same kernel source, or None."""
+    p = os.path.join(ROOT, "profiles", f"traffic_{name}.json")
+    if not os.path.exists(p):
+        return None
+    try:
+        rec = json.load(open(p))
+    except ValueError:
+        return None
+    if rec.get("device_hip_sha") != sha:
+        return None
+    return rec.get("hbm_bytes_per_launch")
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--workload", default="sift1m")
+    ap.add_argument("--n", type=int, default=None, help="base subset (testing only)")
+    ap.add_argument("--nq", type=int, default=None)
+    ap.add_argument("--efs", default=None, help="comma-separated ef sweep")
+    ap.add_argument("--cpu-sample", type=int, default=2000)
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--profile", action="store_true",
+                    help="skip sweeps and the CPU leg; time the AQR path at --ef")
+    ap.add_argument("--ef", type=int, default=None)
+    args = ap.parse_args()
+
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1",
+                          "n_gpus": args.gpus}), flush=True)
+        sys.exit(2)
+
+    import torch
+    from paper_2602_21600_amd import aqr
+    from paper_2602_21600_amd import workloads as W
+
+    if not torch.cuda.is_available():
+        print(json.dumps({"error": "no GPU visible"}), flush=True)
+        sys.exit(3)
+    dev = "cuda:0"
+    torch.cuda.set_device(0)
+    wl = W.WORKLOADS[args.workload]
+    k = wl.k[0]
+    t_all = time.perf_counter()
+
+    log(f"generating {args.workload}")
+    X = W.base(args.workload, args.n)
+    Q = W.queries(args.workload, args.nq)
+    n, d = X.shape
+    nq = Q.shape[0]
+    threads = int(os.environ.get("OMP_NUM_THREADS", "0") or 0)
+    threads = threads if threads > 0 else min(16, os.cpu_count() or 1)
+
+    log(f"quantize n={n} d={d} threads={threads}")
+    t = time.perf_counter()
+    qz, codes = aqr.aqr_quantize(X, aqr.default_qparams(M0=wl.M0, efc0=wl.efc0,
+                                                        threads=threads))
+    t_quant = time.perf_counter() - t
+    info = aqr.aqr_quantizer_info(qz)
+    log(f"quantize {t_quant:.1f}s delta={info['delta']:.4f} M_i={info['M']} efc={info['efc']}")
+    t = time.perf_counter()
+    g = aqr.aqr_build(codes, d, qz, threads=threads, level_u=W.level_draws(args.workload, n))
+    t_build = time.perf_counter() - t
+    ginfo = aqr.aqr_graph_info(g)
+    log(f"build {t_build:.1f}s L={ginfo['L']}")
+    ix = aqr.aqr_index_bind(qz, g, codes, X, device=dev)
+    log("index bound; ground truth")
+    gt_ids, gt_d = ground_truth(X, Q, k, dev)
+    Qd = torch.from_numpy(Q).to(dev)
+
+    efs = [int(e) for e in args.efs.split(",")] if args.efs else list(wl.ef) + [384, 512]
+    if args.profile:
+        efs = [args.ef or 128]
+
+    def sweep(make, name):
+        chosen, table = None, []
+        for ef in efs:
+            r = make(ef)
+            ids, _ = r.step(Qd)
+            torch.cuda.synchronize()
+            rec = recall_at(ids.cpu().numpy(), X, Q, gt_ids, gt_d, k)
+            table.append((ef, round(rec, 5)))
+            log(f"{name} ef={ef} recall@10={rec:.4f}")
+            if rec >= TARGET_RECALL:
+                chosen = (ef, rec)
+                break
+        return chosen, table
+
+    aqr_pick, aqr_table = sweep(lambda ef: AqrRunner(aqr, ix, nq, k, ef, dev), "aqr")
+    if aqr_pick is None:
+        aqr_pick = (efs[-1], aqr_table[-1][1])
+    fp_pick, fp_table = (None, [])
+    if not args.profile:
+        fp_pick, fp_table = sweep(lambda ef: Fp32Runner(aqr, ix, nq, k, ef, dev), "fp32")
+        if fp_pick is None:
+            fp_pick = (efs[-1], fp_table[-1][1])
+
+    # ---- timed AQR path ----
+    ef_a = aqr_pick[0]
+    runner = AqrRunner(aqr, ix, nq, k, ef_a, dev)
+
+    def aqr_step(marks):
+        if marks:
+            marks[0].record()
+            runner.search_only(Qd)
+            marks[1].record()
+            runner.rerank_only(Qd)
+            marks[2].record()
+        else:
+            runner.step(Qd)
+
+    log(f"timing AQR at ef={ef_a}: warmup {args.warmup}, steps {args.steps}")
+    ms_aqr, per = timed(torch, aqr_step, args.steps, args.warmup, kernel_events=3)
+    qps_aqr = nq / (ms_aqr / 1e3)
+    search_ms, rerank_ms = per
+    log(f"AQR {qps_aqr:,.0f} QPS ({ms_aqr:.3f} ms/step; search {search_ms:.3f} ms, "
+        f"rerank {rerank_ms:.3f} ms)")
+
+    # per-query counters (separate, untimed run with a large visited cache so
+    # that evaluations count distinct nodes)
+    counts = torch.zeros((nq, 8), dtype=torch.int32, device=dev)
+    big = AqrRunner(aqr, ix, nq, k, ef_a, dev, visited_log2=14, waves_per_block=1)
+    big.search_only(Qd, taps=dict(cap=0, counts=counts))
+    torch.cuda.synchronize()
+    cnt_big = counts.cpu().numpy().astype(np.int64)
+    counts.zero_()
+    runner.search_only(Qd, taps=dict(cap=0, counts=counts))
+    torch.cuda.synchronize()
+    cnt = counts.cpu().numpy().astype(np.int64)
+    d_pad = info["d_pad"]
+    s0 = (2 * ginfo["M"] + 15) // 16 * 16
+    s1 = (ginfo["M"] + 15) // 16 * 16
+    nc = min(max(max(ef_a, k) // 3, k), max(ef_a, k))
+    # algorithmic bytes of one search launch (distinct evaluations)
+    code_bytes = int((cnt_big[:, 1].sum() + cnt_big[:, 2].sum() + nq) * d_pad)
+    adj_bytes = int(cnt_big[:, 0].sum() * s0 * 4 + cnt_big[:, 4].sum() * s1 * 4)
+    io_bytes = int(nq * (4 * d + 8 * nc + 4))
+    alg_bytes = code_bytes + adj_bytes + io_bytes
+    achieved = alg_bytes / (search_ms / 1e3) / 1e9
+    reeval = float(cnt[:, 1].sum() / max(1, cnt_big[:, 1].sum()) - 1.0)
+    lat_us = cnt[:, 5] / 100.0  # 100 MHz real-time clock
+    sha = source_sha()
+    traffic = traffic_from_profile(f"search_u8_{args.workload}_ef{ef_a}", sha)
+
+    # ---- timed FP32 baseline ----
+    fp = None
+    if fp_pick is not None:
+        ef_f = fp_pick[0]
+        frun = Fp32Runner(aqr, ix, nq, k, ef_f, dev)
+
+        def fp_step(marks):
+            if marks:
+                marks[0].record()
+                frun.step(Qd)
+                marks[1].record()
+            else:
+                frun.step(Qd)
+
+        log(f"timing FP32 HNSW at ef={ef_f}")
+        ms_fp, per_fp = timed(torch, fp_step, args.steps, args.warmup, kernel_events=2)
+        counts.zero_()
+        frun.step(Qd, taps=dict(cap=0, counts=counts))
+        torch.cuda.synchronize()
+        cf = counts.cpu().numpy().astype(np.int64)
+        xs = (d + 3) // 4 * 4
+        fp_bytes = int((cf[:, 1].sum() + cf[:, 2].sum() + nq) * xs * 4 +
+                       cf[:, 0].sum() * s0 * 4 + cf[:, 4].sum() * s1 * 4 + nq * (4 * d + 8 * k))
+        fp = {"value": round(nq / (ms_fp / 1e3), 1), "unit": "queries/s", "ef": ef_f,
+              "recall@10": round(fp_pick[1], 5), "ms_per_step": round(ms_fp, 4),
+              "kernel_ms": round(per_fp[0], 4),
+              "achieved_GBps": round(fp_bytes / (per_fp[0] / 1e3) / 1e9, 1),
+              "p50_query_us": round(float(np.percentile(cf[:, 5] / 100.0, 50)), 2),
+              "p99_query_us": round(float(np.percentile(cf[:, 5] / 100.0, 99)), 2),
+              "sweep": fp_table}
+        log(f"FP32 {fp['value']:,.0f} QPS at ef={ef_f}")
+
+    # ---- CPU oracle baseline on a sample of the same queries ----
+    cpu = None
+    parity = None
+    if not args.no_cpu and not args.profile:
+        import oracle as orc
+        orc.set_threads(threads)
+        S = min(args.cpu_sample, nq)
+        gx = aqr.aqr_graph_export(g)
+        index = dict(X=X, codes=codes, d=d, min=info["min"], scale=info["scale"], graph=gx)
+        log(f"CPU oracle on {S} queries with {orc.get_threads()} threads")
+        t = time.perf_counter()
+        ref = orc.query(index, Q[:S], k, ef_a)
+        dt = time.perf_counter() - t
+        cpu = {"value": round(S / dt, 1), "unit": "queries/s", "cores": orc.get_threads(),
+               "kind": "oracle",
+               "sample": f"first {S} of the {nq} queries, same index, ef={ef_a}, k={k}; "
+                         f"encode + Stage 1 + Stages 2-3 in FP64"}
+        s1 = ref["stage1"]
+        gid = runner.plan.cand_id[:S].cpu().numpy().view(np.uint32)
+        gcnt = runner.plan.cand_cnt[:S].cpu().numpy()
+        exact = sum(int(gcnt[q] == s1["cand_cnt"][q] and
+                        np.array_equal(gid[q, :gcnt[q]], s1["cand_id"][q, :gcnt[q]]))
+                    for q in range(S))
+        oid = runner.plan.out_id[:S].cpu().numpy()
+        same_topk = int((oid == ref["id"]).all(axis=1).sum())
+        parity = {"queries": S, "stage1_bit_exact": exact, "topk_identical": same_topk}
+        log(f"oracle {cpu['value']:,.1f} QPS; parity {parity}")
+
+    out = {
+        "metric": "QPS at recall@10>=0.98 on 1 MI355X, AQR-int8 vs FP32 HNSW; p50/p99 latency",
+        "value": round(qps_aqr, 1),
+        "unit": "queries/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_aqr, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "u8",
+        "data": "synthetic",
+        "config": {
+            "workload": f"{args.workload}: {n:,} x {d} FP32 L2, {wl.n_clusters}-cluster "
+                        f"Gaussian mixture; {nq:,} queries; k={k}",
+            "n": n, "d": d, "nq": nq, "k": k, "ef": ef_a, "M0": wl.M0, "efc0": wl.efc0,
+            "M_i": ginfo["M"], "delta": round(info["delta"], 6), "m_ef": 3, "n_rerank": 28,
+            "tau_gap": 0.010, "tau_ratio": 1.008, "recall@10": round(aqr_pick[1], 5),
+            "global_batch": nq, "parallelism": "single GPU, one wavefront per query",
+        },
+        "roofline": {
+            "bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+            "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+            "traffic": traffic,
+            "kernel": "k_search (Stage 1, 8-bit codes)",
+            "kernel_ms": round(search_ms, 4),
+            "alg_bytes_per_launch": alg_bytes,
+            "code_bytes": code_bytes, "adjacency_bytes": adj_bytes, "io_bytes": io_bytes,
+            "reevaluation_overhead": round(reeval, 4),
+        },
+        "rerank_ms": round(rerank_ms, 4),
+        "latency_us": {"p50": round(float(np.percentile(lat_us, 50)), 2),
+                       "p99": round(float(np.percentile(lat_us, 99)), 2),
+                       "what": "per-query Stage-1 device time inside the batch"},
+        "fp32_hnsw": fp,
+        "speedup_vs_fp32": (round(qps_aqr / fp["value"], 3) if fp else None),
+        "aqr_sweep": aqr_table,
+        "cpu_baseline": cpu,
+        "parity_sample": parity,
+        "build_s": {"quantize": round(t_quant, 1), "graph": round(t_build, 1)},
+        "device_hip_sha": sha,
+        "wall_s": round(time.perf_counter() - t_all, 1),
+    }
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,300 @@
+/*
+ * aqr.h -- C-ABI of libaqr, the MI355X (gfx950) AQR-HNSW query path.
+ *
+ * AQR-HNSW (arXiv 2602.21600) searches an HNSW graph with density-aware
+ * 8-bit codes and re-ranks the result in stages.  This library provides:
+ *   aqr_quantize   Alg. 1 stages 1-2 (density, percentile ranges, scales,
+ *                  codes, Eq. 1), host
+ *   aqr_build      Alg. 1 stage 3 (HNSW over the codes), host
+ *   aqr_search     Alg. 2 stage 1 (query encoding + coarse quantised graph
+ *                  search), device
+ *   aqr_rerank     Alg. 2 stages 2-3 (asymmetric distances, early
+ *                  termination, exact FP32 re-rank, assembly), device
+ * plus the baseline FP32 HNSW search on the same graph and support calls.
+ *
+ * Conventions
+ *   - Every call returns an aqr_status; aqr_last_error() gives a message for
+ *     the calling thread.  No C++ exception crosses this interface and the
+ *     library never aborts.
+ *   - Host pointers are read during the call only.  Device pointers are
+ *     allocated and owned by the caller; the library allocates no device
+ *     memory.  Handles (aqr_quantizer, aqr_graph, aqr_index) are created and
+ *     freed by the library.
+ *   - Device calls are asynchronous on the given stream (a hipStream_t passed
+ *     as void*, NULL = default stream).  Arguments are validated on the host
+ *     before any launch; a device fault surfaces at the caller's next
+ *     synchronisation.
+ *   - Keys: every ordering is by (distance, id), id ascending on ties.
+ *   - A bound index is read-only; concurrent calls on different streams are
+ *     allowed when each call has its own workspace and outputs.
+ */
+#ifndef AQR_H
+#define AQR_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define AQR_VERSION 1
+#define AQR_NONE 0xFFFFFFFFu
+
+typedef enum aqr_status {
+    AQR_OK = 0,
+    AQR_ERR_INVALID_ARG = 1, /* a null pointer, a size out of range, a non-finite value */
+    AQR_ERR_OOM = 2,         /* host allocation failed, or a caller buffer is too small */
+    AQR_ERR_DEVICE = 3,      /* a HIP call failed */
+    AQR_ERR_BUSY = 4,        /* serving: no slot or budget for the request */
+    AQR_ERR_CORRUPT = 5,     /* an index blob failed its checks */
+    AQR_ERR_STATE = 6        /* a handle is used in the wrong state */
+} aqr_status;
+
+/* Message of the last failing call on this thread (never NULL). */
+const char* aqr_last_error(void);
+int32_t aqr_version(void);
+
+/* ------------------------------------------------------------------------ */
+/* Alg. 1 stages 1-2: quantiser (host)                                       */
+/* ------------------------------------------------------------------------ */
+
+typedef struct aqr_qparams {
+    int32_t k_rho;            /* neighbours of the local density (Section 3.1: 10) */
+    int32_t threads;          /* host threads, 0 = all hardware threads */
+    int64_t n_sample;         /* density sample size n_s (5000) */
+    int64_t sample_threshold; /* densities are sampled when n > this (10000) */
+    double eps;               /* epsilon of density, delta and scales (1e-6) */
+    double p_max;             /* maximum percentile width P_max, fraction (0.01) */
+    int32_t M0;               /* base connectivity M_0 */
+    int32_t efc0;             /* base construction depth ef_0 */
+} aqr_qparams;
+
+typedef struct aqr_qinfo {
+    int32_t d;      /* dimension */
+    int32_t d_pad;  /* bytes per code row: d rounded up to 16 */
+    int32_t M;      /* M_i = floor(M_0 (1 + delta (1 + eta)))  (Alg. 1) */
+    int32_t efc;    /* ef^construction = floor(ef_0 / (1 + delta eta))  (Alg. 1) */
+    double delta;   /* global heterogeneity (Alg. 1) */
+    double p_lo;    /* lower percentile, fraction: delta * P_max */
+    double p_hi;    /* upper percentile, fraction: 1 - delta * P_max */
+    double s_dist;  /* distance scale of Eq. 1 */
+    double eta;     /* dimension heterogeneity sigma_w / mean_w */
+    double w_mean;  /* mean density weight */
+} aqr_qinfo;
+
+typedef struct aqr_quantizer aqr_quantizer;
+
+/*
+ * Train the quantiser on X (host, n x d FP32, row-major) and encode it.
+ * Section 3.1 Stage 1 (densities from the k_rho nearest neighbours, sampled
+ * for large n; delta) and Stage 2 (percentile bounds, min_j/max_j/scale_j,
+ * density weights, Eq. 1, eta; Alg. 1), and the vector encoding
+ * code = clamp(rint(fl32(fl32(x - min_j) * scale_j)), 0, 255).
+ * If *qz is NULL a quantiser is trained and returned in *qz (free with
+ * aqr_quantizer_free); if *qz is an existing quantiser, X is only encoded.
+ * codes_out (host, n x d_pad bytes, may be NULL) receives the codes, padding
+ * bytes 0.  Non-finite input values give AQR_ERR_INVALID_ARG.
+ */
+aqr_status aqr_quantize(const float* X, int64_t n, int32_t d, const aqr_qparams* p,
+                        aqr_quantizer** qz, uint8_t* codes_out);
+
+/* Copy out the scalars and the per-dimension min_j, max_j, scale_j (each d
+ * floats; any array pointer may be NULL). */
+aqr_status aqr_quantizer_info(const aqr_quantizer* qz, aqr_qinfo* info, float* min_out,
+                              float* max_out, float* scale_out);
+
+/* Create a quantiser from stored parameters (info->d, M, efc and the
+ * scalars are taken as given). */
+aqr_status aqr_quantizer_create(const aqr_qinfo* info, const float* mn, const float* mx,
+                                const float* scale, aqr_quantizer** out);
+void aqr_quantizer_free(aqr_quantizer* qz);
+
+/* ------------------------------------------------------------------------ */
+/* Alg. 1 stage 3: HNSW graph over the codes (host)                          */
+/* ------------------------------------------------------------------------ */
+
+typedef struct aqr_bparams {
+    int32_t M;             /* connectivity; <= 0 takes M_i of the quantiser */
+    int32_t efc;           /* construction depth; <= 0 takes ef^c of the quantiser */
+    int32_t threads;       /* 1 = sequential and deterministic, 0 = all hardware threads */
+    int32_t reserved;
+    uint64_t seed;         /* level draws when level_u is NULL (SplitMix64) */
+} aqr_bparams;
+
+typedef struct aqr_ginfo {
+    int64_t n;
+    int32_t M;          /* layer cap M on layers >= 1, 2M on layer 0 */
+    int32_t efc;
+    int32_t L;          /* top level */
+    uint32_t ep;        /* entry point */
+    int64_t upper_rows; /* sum of levels: rows of the upper-layer table */
+} aqr_ginfo;
+
+typedef struct aqr_graph aqr_graph;
+
+/*
+ * Build the HNSW graph over codes (host, n x d_pad bytes) by inserting the
+ * points in index order (Alg. 1: G.Insert(q_i, i, M_i, ef^c)).  Levels are
+ * floor(-ln(u_i) / ln(M)) with u_i = level_u[i] in (0, 1] (host, n doubles),
+ * or drawn from SplitMix64(seed) when level_u is NULL.  With threads == 1
+ * the build is sequential and deterministic; otherwise points are inserted
+ * concurrently (the graph then depends on thread timing).
+ */
+aqr_status aqr_build(const uint8_t* codes, int64_t n, int32_t d, const aqr_quantizer* qz,
+                     const aqr_bparams* p, const double* level_u, aqr_graph** g);
+
+aqr_status aqr_graph_info(const aqr_graph* g, aqr_ginfo* info);
+
+/*
+ * Export / import the graph as plain arrays (host):
+ *   level[n]                int32
+ *   adj0[n][2M]             uint32, layer-0 neighbours, unused = AQR_NONE
+ *   upper_off[n+1]          int64, node i owns rows upper_off[i]..upper_off[i+1]-1,
+ *                           row upper_off[i]+l-1 is layer l
+ *   upper_adj[rows][M]      uint32, unused = AQR_NONE
+ */
+aqr_status aqr_graph_export(const aqr_graph* g, int32_t* level, uint32_t* adj0,
+                            int64_t* upper_off, uint32_t* upper_adj);
+aqr_status aqr_graph_import(int64_t n, int32_t M, const int32_t* level, const uint32_t* adj0,
+                            const int64_t* upper_off, const uint32_t* upper_adj, uint32_t ep,
+                            aqr_graph** g);
+void aqr_graph_free(aqr_graph* g);
+
+/* ------------------------------------------------------------------------ */
+/* device index                                                              */
+/* ------------------------------------------------------------------------ */
+
+typedef struct aqr_index aqr_index;
+
+/* Bytes of the device arena aqr_index_bind needs for this quantiser/graph. */
+aqr_status aqr_index_bytes(const aqr_quantizer* qz, const aqr_graph* g, size_t* bytes);
+
+/*
+ * Copy the index into a caller-owned device arena (dev_arena, arena_bytes
+ * >= aqr_index_bytes) on stream s and wait for the copy: codes (host,
+ * n x d_pad), FP32 originals X (host, n x d, kept for the exact re-rank,
+ * Alg. 1), the graph and the quantiser.  The returned handle refers to the
+ * arena; it does not own it.  The arena must outlive the handle.
+ */
+aqr_status aqr_index_bind(const aqr_quantizer* qz, const aqr_graph* g, const uint8_t* codes,
+                          const float* X, void* dev_arena, size_t arena_bytes, void* stream,
+                          aqr_index** ix);
+void aqr_index_free(aqr_index* ix);
+
+/* ------------------------------------------------------------------------ */
+/* Alg. 2 stage 1: coarse quantised search (device)                          */
+/* ------------------------------------------------------------------------ */
+
+typedef struct aqr_sparams {
+    int32_t ef_max;       /* >= every ef_eff = max(ef, k) of the batch (<= 1024) */
+    int32_t out_stride;   /* row stride of the per-query outputs (N_c or k) */
+    int32_t m_ef;         /* ef multiplier when nc is not given (Table 3: 2 or 3) */
+    int32_t waves_per_block; /* 0 = library default */
+    int32_t blocks;       /* persistent grid size, 0 = fill the device */
+    int32_t visited_log2; /* log2 of visited-cache buckets (4 ids each), 0 = default */
+    const int32_t* order; /* device, nullable: work order of the queries (a permutation) */
+} aqr_sparams;
+
+typedef struct aqr_taps {
+    int32_t cap;          /* ids recorded per query in the lists below */
+    uint32_t* expanded;   /* device [nq][cap], nullable: layer-0 expansion order */
+    uint32_t* evaluated;  /* device [nq][cap], nullable: layer-0 evaluated ids, in
+                             order, re-evaluations after cache evictions included */
+    uint32_t* counts;     /* device [nq][8], nullable: layer-0 expansions,
+                             layer-0 evaluations, upper-layer evaluations,
+                             admissions to W, upper-layer expansions, query
+                             duration and start time (low, high word) in ticks
+                             of the 100 MHz device real-time clock */
+} aqr_taps;
+
+/* Workspace bytes for aqr_search / aqr_search_fp32. */
+size_t aqr_search_workspace_size(void);
+
+/*
+ * Stage 1 for nq queries Q (device, nq x d FP32).  Per query (device arrays
+ * of nq int32): k, ef, and optionally nc (NULL derives
+ * N_c = clamp(floor(ef_eff / m_ef), k, ef_eff), ef_eff = max(ef, k)).
+ * Each query is encoded (Section 3.2, same rounding as aqr_quantize),
+ * descends the upper layers greedily and searches layer 0 with ef_eff
+ * (Alg. 2 l.4-7).  Outputs (device): cand_id and cand_D [nq][out_stride]
+ * hold the first N_c entries of the result list, ascending by (D, id), where
+ * D = sum_j (q^_j - x^_j)^2 is the exact integer code distance (the paper's
+ * d^q is s_dist * D); cand_cnt[nq] = number written, or -1 for a query with
+ * invalid parameters (k < 1, ef_eff > ef_max, N_c > out_stride) or a
+ * non-finite value.  ws: device workspace of aqr_search_workspace_size()
+ * bytes.  taps may be NULL.
+ */
+aqr_status aqr_search(const aqr_index* ix, const float* Q, int64_t nq, const int32_t* k,
+                      const int32_t* ef, const int32_t* nc, const aqr_sparams* sp,
+                      uint32_t* cand_id, uint32_t* cand_D, int32_t* cand_cnt, void* ws,
+                      size_t ws_bytes, const aqr_taps* taps, void* stream);
+
+/* Query encoding alone (device): qcodes [nq][d_pad] bytes, padding 0. */
+aqr_status aqr_encode_queries(const aqr_index* ix, const float* Q, int64_t nq, uint8_t* qcodes,
+                              void* stream);
+
+/* ------------------------------------------------------------------------ */
+/* Alg. 2 stages 2-3: re-rank (device)                                       */
+/* ------------------------------------------------------------------------ */
+
+typedef struct aqr_rparams {
+    int32_t n_rerank;     /* N_rerank (Table 3: 12..28) */
+    int32_t out_stride;   /* row stride of out_id/out_dist/out_kind (>= every k) */
+    float tau_gap;        /* gap threshold (Table 3) */
+    float tau_ratio;      /* ratio threshold (Table 3) */
+    float eps;            /* epsilon of gap and ratio (1e-6) */
+    int32_t force_et;     /* -1 automatic, 0 never, 1 always */
+    int32_t waves_per_block; /* 0 = library default */
+    int32_t reserved;
+} aqr_rparams;
+
+typedef struct aqr_rtaps {
+    uint32_t* a_id;   /* device [nq][nc_stride], nullable: the A list (Stage 2 order) */
+    float* a_dist;    /* device [nq][nc_stride], nullable: its d^a */
+    uint8_t* et;      /* device [nq], nullable: early-termination decision */
+    int32_t* nrr;     /* device [nq], nullable: candidates re-ranked exactly */
+} aqr_rtaps;
+
+/*
+ * Stages 2-3 for nq queries (Alg. 2 l.9-24), on the Stage-1 lists
+ * cand_id/cand_cnt (device, stride nc_stride) and the FP32 queries Q:
+ *   d^a = sum_j (q_j - x~_j)^2 with x~_j = fl32(fl32(x^_j / scale_j) + min_j),
+ *   A = candidates sorted by (d^a, id);
+ *   early termination when |A| > k: gap = (d_{k+1}-d_k)/(d_k+eps) > tau_gap or
+ *   ratio = d_{k+1}/(d_k+eps) > tau_ratio;
+ *   n_rr = min(|A|, k) under early termination, else min(|A|, max(n_rerank, k));
+ *   exact d^e = sum_j (q_j - x_j)^2 (FP32, fused multiply-add) on A[0..n_rr);
+ *   R = the exact entries, then A[n_rr..] with their d^a while |R| < k;
+ *   top k of R by (distance, id), padded with (-1, +inf).
+ * Outputs (device, [nq][out_stride]): out_id int32, out_dist float,
+ * out_kind uint8 (nullable; 1 exact, 2 asymmetric, 0 padding).  A query
+ * with cand_cnt < 0 or k outside [1, out_stride] is all padding.
+ */
+aqr_status aqr_rerank(const aqr_index* ix, const float* Q, int64_t nq, const uint32_t* cand_id,
+                      const int32_t* cand_cnt, int32_t nc_stride, const int32_t* k,
+                      const aqr_rparams* rp, int32_t* out_id, float* out_dist, uint8_t* out_kind,
+                      const aqr_rtaps* taps, void* stream);
+
+/* ------------------------------------------------------------------------ */
+/* baseline: HNSW on FP32 vectors over the same graph (device)               */
+/* ------------------------------------------------------------------------ */
+
+/*
+ * Baseline HNSW search (Section 4.1 "Baseline HNSW") on the FP32 originals
+ * of the index, same graph and same search as aqr_search with FP32 squared
+ * L2 distances (fused multiply-add).  Per query k and ef (device); outputs
+ * (device) out_id/out_dist [nq][sp->out_stride]: the first k of the result
+ * list, padded with (-1, +inf); a query with invalid parameters is all
+ * padding.
+ */
+aqr_status aqr_search_fp32(const aqr_index* ix, const float* Q, int64_t nq, const int32_t* k,
+                           const int32_t* ef, const aqr_sparams* sp, int32_t* out_id,
+                           float* out_dist, void* ws, size_t ws_bytes, const aqr_taps* taps,
+                           void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* AQR_H */

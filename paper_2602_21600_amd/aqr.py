@@ -1,0 +1,402 @@
+"""Python binding of libaqr (argument marshalling only).
+
+Every function here forwards to the C-ABI entry point of the same name in
+libaqr.so (declared in include/aqr.h); all computation happens in the
+library's host code and gfx950 kernels.  PyTorch provides device memory
+and streams.  If libaqr.so is missing the import of this module's
+functions fails with an error: there is no fallback path.
+"""
+import ctypes as C
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libaqr.so")
+
+OK, INVALID_ARG, OOM, DEVICE, BUSY, CORRUPT, STATE = range(7)
+NONE = 0xFFFFFFFF
+
+
+class AqrError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"libaqr status {status}: {msg}")
+        self.status = status
+
+
+class QParams(C.Structure):
+    _fields_ = [("k_rho", C.c_int32), ("threads", C.c_int32), ("n_sample", C.c_int64),
+                ("sample_threshold", C.c_int64), ("eps", C.c_double), ("p_max", C.c_double),
+                ("M0", C.c_int32), ("efc0", C.c_int32)]
+
+
+class QInfo(C.Structure):
+    _fields_ = [("d", C.c_int32), ("d_pad", C.c_int32), ("M", C.c_int32), ("efc", C.c_int32),
+                ("delta", C.c_double), ("p_lo", C.c_double), ("p_hi", C.c_double),
+                ("s_dist", C.c_double), ("eta", C.c_double), ("w_mean", C.c_double)]
+
+
+class BParams(C.Structure):
+    _fields_ = [("M", C.c_int32), ("efc", C.c_int32), ("threads", C.c_int32),
+                ("reserved", C.c_int32), ("seed", C.c_uint64)]
+
+
+class GInfo(C.Structure):
+    _fields_ = [("n", C.c_int64), ("M", C.c_int32), ("efc", C.c_int32), ("L", C.c_int32),
+                ("ep", C.c_uint32), ("upper_rows", C.c_int64)]
+
+
+class SParams(C.Structure):
+    _fields_ = [("ef_max", C.c_int32), ("out_stride", C.c_int32), ("m_ef", C.c_int32),
+                ("waves_per_block", C.c_int32), ("blocks", C.c_int32),
+                ("visited_log2", C.c_int32), ("order", C.c_void_p)]
+
+
+class Taps(C.Structure):
+    _fields_ = [("cap", C.c_int32), ("expanded", C.c_void_p), ("evaluated", C.c_void_p),
+                ("counts", C.c_void_p)]
+
+
+class RParams(C.Structure):
+    _fields_ = [("n_rerank", C.c_int32), ("out_stride", C.c_int32), ("tau_gap", C.c_float),
+                ("tau_ratio", C.c_float), ("eps", C.c_float), ("force_et", C.c_int32),
+                ("waves_per_block", C.c_int32), ("reserved", C.c_int32)]
+
+
+class RTaps(C.Structure):
+    _fields_ = [("a_id", C.c_void_p), ("a_dist", C.c_void_p), ("et", C.c_void_p),
+                ("nrr", C.c_void_p)]
+
+
+_lib = None
+
+_vp = C.c_void_p
+_i32 = C.c_int32
+_i64 = C.c_int64
+_u32 = C.c_uint32
+_sz = C.c_size_t
+
+# (name, restype, argtypes)
+_SIGS = [
+    ("aqr_last_error", C.c_char_p, []),
+    ("aqr_version", _i32, []),
+    ("aqr_quantize", _i32, [_vp, _i64, _i32, C.POINTER(QParams), C.POINTER(_vp), _vp]),
+    ("aqr_quantizer_info", _i32, [_vp, C.POINTER(QInfo), _vp, _vp, _vp]),
+    ("aqr_quantizer_create", _i32, [C.POINTER(QInfo), _vp, _vp, _vp, C.POINTER(_vp)]),
+    ("aqr_quantizer_free", None, [_vp]),
+    ("aqr_build", _i32, [_vp, _i64, _i32, _vp, C.POINTER(BParams), _vp, C.POINTER(_vp)]),
+    ("aqr_graph_info", _i32, [_vp, C.POINTER(GInfo)]),
+    ("aqr_graph_export", _i32, [_vp, _vp, _vp, _vp, _vp]),
+    ("aqr_graph_import", _i32, [_i64, _i32, _vp, _vp, _vp, _vp, _u32, C.POINTER(_vp)]),
+    ("aqr_graph_free", None, [_vp]),
+    ("aqr_index_bytes", _i32, [_vp, _vp, C.POINTER(_sz)]),
+    ("aqr_index_bind", _i32, [_vp, _vp, _vp, _vp, _vp, _sz, _vp, C.POINTER(_vp)]),
+    ("aqr_index_free", None, [_vp]),
+    ("aqr_search_workspace_size", _sz, []),
+    ("aqr_search", _i32, [_vp, _vp, _i64, _vp, _vp, _vp, C.POINTER(SParams), _vp, _vp, _vp,
+                          _vp, _sz, C.POINTER(Taps), _vp]),
+    ("aqr_encode_queries", _i32, [_vp, _vp, _i64, _vp, _vp]),
+    ("aqr_rerank", _i32, [_vp, _vp, _i64, _vp, _vp, _i32, _vp, C.POINTER(RParams), _vp, _vp,
+                          _vp, C.POINTER(RTaps), _vp]),
+    ("aqr_search_fp32", _i32, [_vp, _vp, _i64, _vp, _vp, C.POINTER(SParams), _vp, _vp, _vp,
+                               _sz, C.POINTER(Taps), _vp]),
+]
+
+SYMBOLS = [s[0] for s in _SIGS]
+
+
+def lib():
+    """Load libaqr.so; raises if it has not been built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"libaqr.so not found at {LIB_PATH}; build it with "
+                           "`python -c 'import __graft_entry__ as g; g.build()'`")
+    # PyTorch loads its HIP runtime by path; importing it first makes libaqr's
+    # dependency on libamdhip64.so.7 resolve to that same copy, so the process
+    # holds a single HIP runtime shared by torch's allocations and libaqr.
+    import torch  # noqa: F401
+    L = C.CDLL(LIB_PATH)
+    for name, res, args in _SIGS:
+        f = getattr(L, name)
+        f.restype = res
+        f.argtypes = args
+    _lib = L
+    return L
+
+
+def _check(st):
+    if st != OK:
+        raise AqrError(st, lib().aqr_last_error().decode(errors="replace"))
+
+
+def _np_ptr(a):
+    return None if a is None else a.ctypes.data_as(C.c_void_p)
+
+
+def _dev_ptr(t):
+    """Device pointer of a torch CUDA tensor (None passes as NULL)."""
+    if t is None:
+        return None
+    if not t.is_cuda:
+        raise ValueError("expected a device tensor")
+    if not t.is_contiguous():
+        raise ValueError("expected a contiguous tensor")
+    return C.c_void_p(t.data_ptr())
+
+
+def _stream_ptr(stream):
+    if stream is None:
+        import torch
+        stream = torch.cuda.current_stream()
+    return C.c_void_p(stream.cuda_stream)
+
+
+# --------------------------------------------------------------------------
+# handles
+# --------------------------------------------------------------------------
+
+class _Handle:
+    _free = None
+
+    def __init__(self, ptr):
+        self.ptr = ptr
+
+    def __del__(self):
+        p, self.ptr = getattr(self, "ptr", None), None
+        if p and _lib is not None:
+            getattr(_lib, self._free)(p)
+
+    @property
+    def as_parameter(self):
+        return self.ptr
+
+
+class Quantizer(_Handle):
+    _free = "aqr_quantizer_free"
+
+
+class Graph(_Handle):
+    _free = "aqr_graph_free"
+
+
+class Index(_Handle):
+    _free = "aqr_index_free"
+
+    def __init__(self, ptr, arena, d, d_pad):
+        super().__init__(ptr)
+        self.arena = arena  # keep the device memory alive
+        self.d = d
+        self.d_pad = d_pad
+
+
+# --------------------------------------------------------------------------
+# C-ABI wrappers
+# --------------------------------------------------------------------------
+
+def aqr_version():
+    return int(lib().aqr_version())
+
+
+def default_qparams(M0=16, efc0=200, p_max=0.01, threads=0):
+    return dict(k_rho=10, threads=threads, n_sample=5000, sample_threshold=10000, eps=1e-6,
+                p_max=p_max, M0=M0, efc0=efc0)
+
+
+def aqr_quantize(X, params=None, qz=None, codes=True):
+    """Train (qz None) or reuse a quantiser; returns (Quantizer, codes or None)."""
+    X = np.ascontiguousarray(X, np.float32)
+    n, d = X.shape
+    p = QParams(**(params or default_qparams()))
+    h = C.c_void_p(qz.ptr if qz is not None else None)
+    d_pad = (d + 15) // 16 * 16
+    out = np.zeros((n, d_pad), np.uint8) if codes else None
+    _check(lib().aqr_quantize(_np_ptr(X), n, d, C.byref(p), C.byref(h), _np_ptr(out)))
+    return (qz if qz is not None else Quantizer(h.value)), out
+
+
+def aqr_quantizer_info(qz):
+    info = QInfo()
+    _check(lib().aqr_quantizer_info(qz.ptr, C.byref(info), None, None, None))
+    d = info.d
+    mn = np.zeros(d, np.float32)
+    mx = np.zeros(d, np.float32)
+    sc = np.zeros(d, np.float32)
+    _check(lib().aqr_quantizer_info(qz.ptr, None, _np_ptr(mn), _np_ptr(mx), _np_ptr(sc)))
+    res = {f: getattr(info, f) for f, _ in QInfo._fields_}
+    res.update(min=mn, max=mx, scale=sc)
+    return res
+
+
+def aqr_quantizer_create(info, mn, mx, scale):
+    qi = QInfo(**{f: info[f] for f, _ in QInfo._fields_})
+    mn = np.ascontiguousarray(mn, np.float32)
+    mx = np.ascontiguousarray(mx, np.float32)
+    sc = np.ascontiguousarray(scale, np.float32)
+    h = C.c_void_p()
+    _check(lib().aqr_quantizer_create(C.byref(qi), _np_ptr(mn), _np_ptr(mx), _np_ptr(sc),
+                                      C.byref(h)))
+    return Quantizer(h.value)
+
+
+def aqr_build(codes, d, qz, M=0, efc=0, threads=0, seed=0, level_u=None):
+    codes = np.ascontiguousarray(codes, np.uint8)
+    n = codes.shape[0]
+    bp = BParams(M=M, efc=efc, threads=threads, reserved=0, seed=seed)
+    lu = None if level_u is None else np.ascontiguousarray(level_u, np.float64)
+    h = C.c_void_p()
+    _check(lib().aqr_build(_np_ptr(codes), n, d, qz.ptr, C.byref(bp), _np_ptr(lu), C.byref(h)))
+    return Graph(h.value)
+
+
+def aqr_graph_info(g):
+    gi = GInfo()
+    _check(lib().aqr_graph_info(g.ptr, C.byref(gi)))
+    return {f: getattr(gi, f) for f, _ in GInfo._fields_}
+
+
+def aqr_graph_export(g):
+    gi = aqr_graph_info(g)
+    n, M, rows = gi["n"], gi["M"], gi["upper_rows"]
+    level = np.zeros(n, np.int32)
+    adj0 = np.zeros((n, 2 * M), np.uint32)
+    off = np.zeros(n + 1, np.int64)
+    upper = np.zeros((max(rows, 1), M), np.uint32)
+    _check(lib().aqr_graph_export(g.ptr, _np_ptr(level), _np_ptr(adj0), _np_ptr(off),
+                                  _np_ptr(upper)))
+    return dict(n=n, M=M, level=level, adj0=adj0, upper_off=off, upper_adj=upper, ep=gi["ep"],
+                L=gi["L"], efc=gi["efc"])
+
+
+def aqr_graph_import(gd):
+    level = np.ascontiguousarray(gd["level"], np.int32)
+    adj0 = np.ascontiguousarray(gd["adj0"], np.uint32)
+    off = np.ascontiguousarray(gd["upper_off"], np.int64)
+    upper = np.ascontiguousarray(gd["upper_adj"], np.uint32)
+    h = C.c_void_p()
+    _check(lib().aqr_graph_import(int(gd["n"]), int(gd["M"]), _np_ptr(level), _np_ptr(adj0),
+                                  _np_ptr(off), _np_ptr(upper), int(gd["ep"]), C.byref(h)))
+    return Graph(h.value)
+
+
+def aqr_index_bytes(qz, g):
+    b = C.c_size_t()
+    _check(lib().aqr_index_bytes(qz.ptr, g.ptr, C.byref(b)))
+    return int(b.value)
+
+
+def aqr_index_bind(qz, g, codes, X, device=None, stream=None):
+    """Allocate the device arena with torch and bind the index into it."""
+    import torch
+    codes = np.ascontiguousarray(codes, np.uint8)
+    X = np.ascontiguousarray(X, np.float32)
+    nbytes = aqr_index_bytes(qz, g)
+    arena = torch.empty(nbytes + 256, dtype=torch.uint8, device=device or "cuda")
+    base = arena.data_ptr()
+    pad = (-base) % 256
+    h = C.c_void_p()
+    _check(lib().aqr_index_bind(qz.ptr, g.ptr, _np_ptr(codes), _np_ptr(X),
+                                C.c_void_p(base + pad), nbytes, _stream_ptr(stream), C.byref(h)))
+    info = aqr_quantizer_info(qz)
+    return Index(h.value, arena, info["d"], info["d_pad"])
+
+
+def aqr_search_workspace_size():
+    return int(lib().aqr_search_workspace_size())
+
+
+def _taps(taps):
+    if taps is None:
+        return None
+    t = Taps(cap=int(taps.get("cap", 0)), expanded=_dev_ptr(taps.get("expanded")),
+             evaluated=_dev_ptr(taps.get("evaluated")), counts=_dev_ptr(taps.get("counts")))
+    return C.byref(t), t
+
+
+def aqr_search(ix, Q, k, ef, cand_id, cand_D, cand_cnt, ws, ef_max, out_stride, nc=None, m_ef=3,
+               waves_per_block=0, blocks=0, visited_log2=0, order=None, taps=None, stream=None):
+    sp = SParams(ef_max=ef_max, out_stride=out_stride, m_ef=m_ef,
+                 waves_per_block=waves_per_block, blocks=blocks, visited_log2=visited_log2,
+                 order=_dev_ptr(order))
+    tp = _taps(taps)
+    _check(lib().aqr_search(ix.ptr, _dev_ptr(Q), Q.shape[0], _dev_ptr(k), _dev_ptr(ef),
+                            _dev_ptr(nc), C.byref(sp), _dev_ptr(cand_id), _dev_ptr(cand_D),
+                            _dev_ptr(cand_cnt), _dev_ptr(ws), ws.numel() * ws.element_size(),
+                            tp[0] if tp else None, _stream_ptr(stream)))
+
+
+def aqr_search_fp32(ix, Q, k, ef, out_id, out_dist, ws, ef_max, out_stride, waves_per_block=0,
+                    blocks=0, visited_log2=0, order=None, taps=None, stream=None):
+    sp = SParams(ef_max=ef_max, out_stride=out_stride, m_ef=1,
+                 waves_per_block=waves_per_block, blocks=blocks, visited_log2=visited_log2,
+                 order=_dev_ptr(order))
+    tp = _taps(taps)
+    _check(lib().aqr_search_fp32(ix.ptr, _dev_ptr(Q), Q.shape[0], _dev_ptr(k), _dev_ptr(ef),
+                                 C.byref(sp), _dev_ptr(out_id), _dev_ptr(out_dist), _dev_ptr(ws),
+                                 ws.numel() * ws.element_size(), tp[0] if tp else None,
+                                 _stream_ptr(stream)))
+
+
+def aqr_encode_queries(ix, Q, qcodes, stream=None):
+    _check(lib().aqr_encode_queries(ix.ptr, _dev_ptr(Q), Q.shape[0], _dev_ptr(qcodes),
+                                    _stream_ptr(stream)))
+
+
+def aqr_rerank(ix, Q, cand_id, cand_cnt, k, out_id, out_dist, out_kind=None, n_rerank=28,
+               tau_gap=0.010, tau_ratio=1.008, eps=1e-6, force_et=-1, out_stride=None,
+               waves_per_block=0, taps=None, stream=None):
+    out_stride = out_id.shape[1] if out_stride is None else out_stride
+    rp = RParams(n_rerank=n_rerank, out_stride=out_stride, tau_gap=tau_gap, tau_ratio=tau_ratio,
+                 eps=eps, force_et=force_et, waves_per_block=waves_per_block, reserved=0)
+    rt = None
+    if taps is not None:
+        rt = RTaps(a_id=_dev_ptr(taps.get("a_id")), a_dist=_dev_ptr(taps.get("a_dist")),
+                   et=_dev_ptr(taps.get("et")), nrr=_dev_ptr(taps.get("nrr")))
+    _check(lib().aqr_rerank(ix.ptr, _dev_ptr(Q), Q.shape[0], _dev_ptr(cand_id),
+                            _dev_ptr(cand_cnt), cand_id.shape[1], _dev_ptr(k), C.byref(rp),
+                            _dev_ptr(out_id), _dev_ptr(out_dist), _dev_ptr(out_kind),
+                            C.byref(rt) if rt is not None else None, _stream_ptr(stream)))
+
+
+# --------------------------------------------------------------------------
+# convenience: a bound index with preallocated query buffers
+# --------------------------------------------------------------------------
+
+class QueryPlan:
+    """Device buffers for batches of up to nq queries (allocated with torch).
+
+    run() issues Stage 1 and Stages 2-3 on the current stream: the whole
+    query path of Alg. 2 for one batch.
+    """
+
+    def __init__(self, ix, nq, k_max, ef_max, m_ef=3, n_rerank=28, tau_gap=0.010,
+                 tau_ratio=1.008, eps=1e-6, nc_max=None, visited_log2=0, waves_per_block=0,
+                 blocks=0):
+        import torch
+        self.ix = ix
+        self.nq = nq
+        self.k_max = k_max
+        self.ef_max = max(ef_max, k_max)
+        self.m_ef = m_ef
+        self.nc_max = nc_max or min(self.ef_max, max(k_max, self.ef_max // m_ef))
+        self.rr = dict(n_rerank=n_rerank, tau_gap=tau_gap, tau_ratio=tau_ratio, eps=eps)
+        self.sp = dict(visited_log2=visited_log2, waves_per_block=waves_per_block, blocks=blocks)
+        dev = ix.arena.device
+        self.cand_id = torch.empty((nq, self.nc_max), dtype=torch.int32, device=dev)
+        self.cand_D = torch.empty((nq, self.nc_max), dtype=torch.int32, device=dev)
+        self.cand_cnt = torch.empty(nq, dtype=torch.int32, device=dev)
+        self.out_id = torch.empty((nq, k_max), dtype=torch.int32, device=dev)
+        self.out_dist = torch.empty((nq, k_max), dtype=torch.float32, device=dev)
+        self.out_kind = torch.empty((nq, k_max), dtype=torch.uint8, device=dev)
+        self.ws = torch.zeros(aqr_search_workspace_size(), dtype=torch.uint8, device=dev)
+
+    def run(self, Q, k, ef, nc=None, order=None):
+        n = Q.shape[0]
+        assert n <= self.nq
+        cid, cD, cc = self.cand_id[:n], self.cand_D[:n], self.cand_cnt[:n]
+        aqr_search(self.ix, Q, k, ef, cid, cD, cc, self.ws, self.ef_max, self.nc_max, nc=nc,
+                   m_ef=self.m_ef, order=order, **self.sp)
+        aqr_rerank(self.ix, Q, cid, cc, k, self.out_id[:n], self.out_dist[:n],
+                   self.out_kind[:n], **self.rr)
+        return self.out_id[:n], self.out_dist[:n]

@@ -1,0 +1,1327 @@
+// device.hip -- gfx950 kernels and device-side entry points of libaqr.
+//
+// Query path of AQR-HNSW (Section 3.2, Alg. 2) on an MI355X:
+//   * k_search: one wavefront per query in a persistent loop (queries are
+//     pulled from an atomic counter).  Per query: encode the FP32 query to
+//     8-bit codes (Alg. 2 l.4), greedy descent through the upper layers,
+//     then the layer-0 search with width ef (Alg. 2 l.6-7).  The same kernel
+//     instantiated on FP32 rows is the baseline HNSW search.
+//   * k_rerank: one wavefront per query: asymmetric distances on decoded
+//     codes, sort, early termination, exact FP32 distances on the survivors
+//     and assembly of the top k (Alg. 2 l.9-24).
+//
+// Layer-0 search form.  The result list W is one sorted array of (D, id)
+// keys in LDS with an "expanded" flag per entry; the next node to expand is
+// the nearest unexpanded entry and the search ends when none is left.  All
+// unvisited neighbours of one expansion are scored together and merged into
+// W as one batch (keys below the current bound, W kept at ef entries).
+// The visited set is an LDS cache that may forget ids but never reports an
+// id it has not seen.  Under the strict (D, id) order these choices give
+// the same expansions, the same distinct visited set and the same result
+// as the two-heap search of HNSW: a node scored again after being
+// forgotten has the same key, so it is either in W already (dropped on key
+// equality) or not below the bound.
+//
+// Distances.  Code rows are read 16 bytes per lane; a row is spread over G
+// lanes (G = 16-byte chunks of the row, rounded up to a power of two, at
+// most 64) so one wave reads 64/G rows per pass, each row one contiguous
+// segment.  The 8-bit squared distance is exact in uint32 as
+// |q|^2 + sum(x*x - 2 q*x) with the 4 x u8 dot product instruction, reduced
+// across the G lanes by butterfly shuffles.  FP32 rows use fused
+// multiply-add on direct differences.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <climits>
+#include <cmath>
+#include <cstring>
+#include <new>
+#include <vector>
+
+#include "internal.hpp"
+
+namespace aqr {
+namespace dev {
+
+constexpr uint32_t kNone = 0xFFFFFFFFu;
+constexpr int kWave = 64;
+constexpr int kMaxD = 4096;
+
+struct Idx {
+    const uint8_t* codes;    // n x dp bytes
+    const float* X;          // n x xs floats
+    const uint32_t* adj0;    // n x s0
+    const int32_t* ubase;    // n: first upper row of the node (level >= 1) or -1
+    const uint32_t* uadj;    // rows x s1
+    const float* qmin;       // dp (padding 0)
+    const float* qscale;     // dp (padding 1)
+    int64_t n;
+    int32_t d, dp, xs, s0, s1;
+    uint32_t ep;
+    int32_t L;
+    int32_t idbits;          // ceil(log2(n)), at least 1
+};
+
+struct Taps {
+    int32_t cap;
+    uint32_t* expanded;
+    uint32_t* evaluated;
+    uint32_t* counts;
+};
+
+struct RTaps {
+    uint32_t* a_id;
+    float* a_dist;
+    uint8_t* et;
+    int32_t* nrr;
+};
+
+// ---------------------------------------------------------------------------
+// wave primitives
+// ---------------------------------------------------------------------------
+
+__device__ __forceinline__ int lane_id() {
+    return (int)__builtin_amdgcn_mbcnt_hi(~0u, __builtin_amdgcn_mbcnt_lo(~0u, 0u));
+}
+__device__ __forceinline__ uint64_t ballot(bool p) { return __builtin_amdgcn_ballot_w64(p); }
+// number of set bits of m below this lane
+__device__ __forceinline__ int below(uint64_t m) {
+    return (int)__builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32),
+                                          __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
+}
+__device__ __forceinline__ void wsync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+__device__ __forceinline__ int uni(int x) { return __builtin_amdgcn_readfirstlane(x); }
+__device__ __forceinline__ uint64_t uni64(uint64_t x) {
+    uint32_t lo = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)x);
+    uint32_t hi = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)(x >> 32));
+    return ((uint64_t)hi << 32) | lo;
+}
+__device__ __forceinline__ uint32_t shfl_xor_u32(uint32_t v, int m) {
+    return (uint32_t)__shfl_xor((int)v, m, kWave);
+}
+__device__ __forceinline__ float shfl_xor_f32(float v, int m) { return __shfl_xor(v, m, kWave); }
+__device__ __forceinline__ uint64_t wave_min_u64(uint64_t v) {
+    for (int m = 32; m >= 1; m >>= 1) {
+        uint32_t lo = shfl_xor_u32((uint32_t)v, m);
+        uint32_t hi = shfl_xor_u32((uint32_t)(v >> 32), m);
+        uint64_t o = ((uint64_t)hi << 32) | lo;
+        v = o < v ? o : v;
+    }
+    return v;
+}
+__device__ __forceinline__ int wave_min_i32(int v) {
+    for (int m = 32; m >= 1; m >>= 1) v = min(v, __shfl_xor(v, m, kWave));
+    return v;
+}
+__device__ __forceinline__ uint32_t wave_sum_u32(uint32_t v) {
+    for (int m = 32; m >= 1; m >>= 1) v += shfl_xor_u32(v, m);
+    return v;
+}
+
+__device__ __forceinline__ uint32_t dot4(uint32_t a, uint32_t b, uint32_t c) {
+    return __builtin_amdgcn_udot4(a, b, c, false);
+}
+
+// ---------------------------------------------------------------------------
+// row distances
+// ---------------------------------------------------------------------------
+
+// Query encoding, Section 3.2: clamp(rint(fl32(fl32(q - min) * scale)), 0, 255).
+// The build compiles with -ffp-contract=off, so the two FP32 operations stay
+// separate and correctly rounded.
+__device__ __forceinline__ uint32_t encode1(float v, float mn, float sc) {
+    float t = v - mn;
+    float u = t * sc;
+    float r = __builtin_rintf(u);
+    r = r < 0.0f ? 0.0f : (r > 255.0f ? 255.0f : r);
+    return (uint32_t)r;
+}
+
+template <bool F32>
+struct Rows;
+
+// 8-bit code rows: chunk = 16 codes; partial = sum(x*x - 2 q*x) (mod 2^32)
+template <>
+struct Rows<false> {
+    using Acc = uint32_t;
+    __device__ static __forceinline__ uint4 load(const Idx& ix, uint32_t id, int ch) {
+        return reinterpret_cast<const uint4*>(ix.codes + (int64_t)id * ix.dp)[ch];
+    }
+    __device__ static __forceinline__ uint32_t part(uint4 x, uint4 q) {
+        uint32_t xx = dot4(x.x, x.x, 0u);
+        xx = dot4(x.y, x.y, xx);
+        xx = dot4(x.z, x.z, xx);
+        xx = dot4(x.w, x.w, xx);
+        uint32_t xq = dot4(x.x, q.x, 0u);
+        xq = dot4(x.y, q.y, xq);
+        xq = dot4(x.z, q.z, xq);
+        xq = dot4(x.w, q.w, xq);
+        return xx - 2u * xq;
+    }
+    __device__ static __forceinline__ uint32_t zero() { return 0u; }
+    __device__ static __forceinline__ uint32_t add(uint32_t a, uint32_t b) { return a + b; }
+    __device__ static __forceinline__ uint32_t xor_shfl(uint32_t v, int m) {
+        return shfl_xor_u32(v, m);
+    }
+    // key distance bits from the reduced partial and |q|^2
+    __device__ static __forceinline__ uint32_t dbits(uint32_t s, uint32_t qq) { return qq + s; }
+};
+
+// FP32 rows: chunk = 4 floats; partial = sum (q - x)^2 by fused multiply-add
+template <>
+struct Rows<true> {
+    using Acc = float;
+    __device__ static __forceinline__ uint4 load(const Idx& ix, uint32_t id, int ch) {
+        return reinterpret_cast<const uint4*>(ix.X + (int64_t)id * ix.xs)[ch];
+    }
+    __device__ static __forceinline__ float part(uint4 x, uint4 q) {
+        float acc = 0.0f;
+        float d0 = __uint_as_float(q.x) - __uint_as_float(x.x);
+        acc = __builtin_fmaf(d0, d0, acc);
+        float d1 = __uint_as_float(q.y) - __uint_as_float(x.y);
+        acc = __builtin_fmaf(d1, d1, acc);
+        float d2 = __uint_as_float(q.z) - __uint_as_float(x.z);
+        acc = __builtin_fmaf(d2, d2, acc);
+        float d3 = __uint_as_float(q.w) - __uint_as_float(x.w);
+        acc = __builtin_fmaf(d3, d3, acc);
+        return acc;
+    }
+    __device__ static __forceinline__ float zero() { return 0.0f; }
+    __device__ static __forceinline__ float add(float a, float b) { return a + b; }
+    __device__ static __forceinline__ float xor_shfl(float v, int m) { return shfl_xor_f32(v, m); }
+    __device__ static __forceinline__ uint32_t dbits(float s, uint32_t) { return __float_as_uint(s); }
+};
+
+struct Geo {
+    int G, lg, rpp, nch, sub, grp;
+};
+
+__device__ __forceinline__ Geo make_geo(int lg, int nch, int lane) {
+    Geo g;
+    g.lg = lg;
+    g.G = 1 << lg;
+    g.rpp = kWave >> lg;
+    g.nch = nch;
+    g.sub = lane & (g.G - 1);
+    g.grp = lane >> lg;
+    return g;
+}
+
+// Score nn rows whose ids are ids[0..nn) (LDS); keys[r] = (dist bits << 32) | id.
+template <bool F32, int CPL, int U>
+__device__ __forceinline__ void eval_rows(const Idx& ix, const uint32_t* ids, int nn,
+                                          uint64_t* keys, const uint4 (&qv)[CPL], uint32_t qq,
+                                          const Geo& g) {
+    using R = Rows<F32>;
+    for (int r0 = 0; r0 < nn; r0 += g.rpp * U) {
+        uint4 x[U][CPL];
+        uint32_t id[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int r = r0 + u * g.rpp + g.grp;
+            id[u] = r < nn ? ids[r] : kNone;
+#pragma unroll
+            for (int c = 0; c < CPL; ++c) {
+                const int ch = g.sub + c * g.G;
+                if (id[u] != kNone && ch < g.nch)
+                    x[u][c] = R::load(ix, id[u], ch);
+                else
+                    x[u][c] = make_uint4(0u, 0u, 0u, 0u);
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            typename R::Acc s = R::zero();
+#pragma unroll
+            for (int c = 0; c < CPL; ++c) s = R::add(s, R::part(x[u][c], qv[c]));
+            for (int m = g.G >> 1; m >= 1; m >>= 1) s = R::add(s, R::xor_shfl(s, m));
+            const int r = r0 + u * g.rpp + g.grp;
+            if (g.sub == 0 && r < nn)
+                keys[r] = ((uint64_t)R::dbits(s, qq) << 32) | (uint64_t)id[u];
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// forgetful visited cache: buckets of four 16-bit entries
+// ---------------------------------------------------------------------------
+// h = id * C mod 2^B is a bijection of [0, 2^B) (C odd); the top vb bits of
+// h choose the bucket and the low B - vb bits (<= 15) are stored with a
+// valid bit, so (bucket, entry) identifies the id exactly.  A bucket keeps
+// its four most recent entries.
+struct VisCache {
+    uint64_t* b;
+    int vb;      // log2 buckets
+    int B;       // hash width
+    __device__ __forceinline__ bool test_insert(uint32_t id) const {
+        const uint32_t mask = B >= 32 ? 0xFFFFFFFFu : ((1u << B) - 1u);
+        const uint32_t h = (id * 0x9E3779B1u) & mask;
+        const uint32_t bucket = h >> (B - vb);
+        const uint32_t e = (h & ((1u << (B - vb)) - 1u)) | 0x8000u;
+        const uint64_t w = b[bucket];
+        const bool hit = ((uint32_t)(w & 0xFFFFu) == e) | ((uint32_t)((w >> 16) & 0xFFFFu) == e) |
+                         ((uint32_t)((w >> 32) & 0xFFFFu) == e) | ((uint32_t)(w >> 48) == e);
+        if (!hit) b[bucket] = (w << 16) | e;
+        return hit;
+    }
+};
+
+// ---------------------------------------------------------------------------
+// LDS layout of one wave in the search kernel
+// ---------------------------------------------------------------------------
+struct SearchLds {
+    int ef_cap, st_cap, vb, xs, dp;
+    __host__ __device__ size_t bytes() const {
+        size_t o = 0;
+        o += 2 * (size_t)ef_cap * 8;       // W keys, two buffers
+        o += 2 * (size_t)ef_cap;           // W flags
+        o = (o + 7) & ~(size_t)7;
+        o += (size_t)st_cap * (4 + 8 + 8 + 4);  // ids, keys, admitted keys, their W ranks
+        o += ((size_t)8 << vb);            // visited buckets
+        o += (size_t)xs * 4;               // FP32 query
+        o += (size_t)dp;                   // query codes
+        o = (o + 15) & ~(size_t)15;
+        return o;
+    }
+};
+
+struct SearchArgs {
+    Idx ix;
+    const float* Q;
+    int64_t nq;
+    const int32_t* kq;
+    const int32_t* efq;
+    const int32_t* ncq;
+    const int32_t* order;
+    int32_t m_ef;
+    int32_t ef_cap;
+    int32_t out_stride;
+    int32_t vb;
+    int32_t mode;       // 0: Stage-1 candidates; 1: FP32 baseline top-k
+    int32_t lg, nch;    // row geometry
+    size_t wave_lds;
+    uint32_t* out_id;
+    uint32_t* out_D;    // mode 0: integer D; mode 1: FP32 distance bits
+    int32_t* out_cnt;
+    int32_t* counter;
+    Taps taps;
+};
+
+// Stage 1 of one valid query, run by the whole wave.  Every branch that
+// steers a loop here is on a wave-uniform value (a ballot, a popcount or a
+// readfirstlane), and every single-lane block is closed by a wave barrier
+// before the next loop control, so all lanes stay converged at each
+// cross-lane operation.
+template <bool F32, int CPL, int U>
+__device__ __forceinline__ void search_query(const SearchArgs& a, const int64_t q, const int efe,
+                                             const int nc, const int lane, const Geo& g,
+                                             const VisCache& vis, uint64_t* Wk0, uint64_t* Wk1,
+                                             uint8_t* Wf0, uint8_t* Wf1, uint32_t* st_id,
+                                             uint64_t* st_key, uint64_t* adm, int32_t* adm_lb,
+                                             uint64_t* visb, float* qf, uint8_t* qc) {
+    const Idx& ix = a.ix;
+    uint32_t qq = 0;
+    if (!F32) {
+        uint32_t part = 0;
+        for (int j = lane; j < ix.dp; j += kWave) {
+            uint32_t c = j < ix.d ? encode1(qf[j], ix.qmin[j], ix.qscale[j]) : 0u;
+            qc[j] = (uint8_t)c;
+            part += c * c;
+        }
+        qq = wave_sum_u32(part);
+    }
+    wsync();
+    uint4 qv[CPL];
+#pragma unroll
+    for (int c = 0; c < CPL; ++c) {
+        const int ch = g.sub + c * g.G;
+        if (ch < g.nch)
+            qv[c] = F32 ? reinterpret_cast<const uint4*>(qf)[ch]
+                        : reinterpret_cast<const uint4*>(qc)[ch];
+        else
+            qv[c] = make_uint4(0u, 0u, 0u, 0u);
+    }
+
+    uint32_t n_exp = 0, n_eval = 0, n_up = 0, n_adm = 0, n_upx = 0;
+    const uint64_t t_start = __builtin_amdgcn_s_memrealtime();
+
+    // ---- greedy descent through the upper layers (search width 1) ----
+    uint32_t cur = ix.ep;
+    if (lane == 0) st_id[0] = cur;
+    wsync();
+    eval_rows<F32, CPL, U>(ix, st_id, 1, st_key, qv, qq, g);
+    wsync();
+    uint64_t curkey = uni64(st_key[0]);
+    for (int l = ix.L; l >= 1; --l) {
+        for (;;) {
+            const uint32_t* row = ix.uadj + ((int64_t)ix.ubase[cur] + (l - 1)) * ix.s1;
+            int cnt = 0;
+            for (int b0 = 0; b0 < ix.s1; b0 += kWave) {
+                uint32_t e = (b0 + lane < ix.s1) ? row[b0 + lane] : kNone;
+                uint64_t m = ballot(e != kNone);
+                if (e != kNone) st_id[cnt + below(m)] = e;
+                cnt += __popcll(m);
+            }
+            wsync();
+            eval_rows<F32, CPL, U>(ix, st_id, cnt, st_key, qv, qq, g);
+            wsync();
+            n_up += cnt;
+            ++n_upx;
+            uint64_t best = ~0ull;
+            for (int j = lane; j < cnt; j += kWave) best = min(best, st_key[j]);
+            best = uni64(wave_min_u64(best));
+            if (best < curkey) {
+                curkey = best;
+                cur = (uint32_t)best;
+            } else {
+                break;
+            }
+        }
+    }
+
+    // ---- layer-0 search with width efe ----
+    for (int i = lane; i < (1 << a.vb); i += kWave) visb[i] = 0ull;
+    wsync();
+    if (lane == 0) {
+        Wk0[0] = curkey;
+        Wf0[0] = 0;
+        vis.test_insert((uint32_t)curkey);
+    }
+    wsync();
+    uint64_t* Wk = Wk0;
+    uint64_t* Wn = Wk1;
+    uint8_t* Wf = Wf0;
+    uint8_t* Wg = Wf1;
+    int wsize = 1;
+    int first = 0;
+    for (;;) {
+        // nearest unexpanded entry of W
+        int idx = -1;
+        for (int b0 = first & ~(kWave - 1); b0 < wsize; b0 += kWave) {
+            const int i = b0 + lane;
+            const bool p = i >= first && i < wsize && Wf[i] == 0;
+            const uint64_t m = ballot(p);
+            if (m) {
+                idx = b0 + (int)__builtin_ctzll(m);
+                break;
+            }
+        }
+        idx = uni(idx);
+        if (idx < 0) break;
+        const uint32_t c = (uint32_t)uni64(Wk[idx]);
+        first = idx + 1;
+        wsync();
+        if (lane == 0) {
+            Wf[idx] = 1;
+            if (a.taps.expanded && (int)n_exp < a.taps.cap)
+                a.taps.expanded[q * a.taps.cap + n_exp] = c;
+        }
+        wsync();
+        ++n_exp;
+        // unvisited neighbours of c
+        const uint32_t* row = ix.adj0 + (int64_t)c * ix.s0;
+        int nn = 0;
+        for (int b0 = 0; b0 < ix.s0; b0 += kWave) {
+            const uint32_t e = (b0 + lane < ix.s0) ? row[b0 + lane] : kNone;
+            const bool isnew = e != kNone && !vis.test_insert(e);
+            const uint64_t m = ballot(isnew);
+            if (isnew) st_id[nn + below(m)] = e;
+            nn += __popcll(m);
+        }
+        wsync();
+        if (uni(nn) == 0) continue;
+        if (a.taps.evaluated) {
+            for (int j = lane; j < nn; j += kWave) {
+                const int p = (int)n_eval + j;
+                if (p < a.taps.cap) a.taps.evaluated[q * a.taps.cap + p] = st_id[j];
+            }
+        }
+        n_eval += nn;
+        eval_rows<F32, CPL, U>(ix, st_id, nn, st_key, qv, qq, g);
+        wsync();
+        // keys below the bound that are not in W already
+        const uint64_t bound = wsize == efe ? Wk[wsize - 1] : ~0ull;
+        int m_adm = 0;
+        for (int b0 = 0; b0 < nn; b0 += kWave) {
+            const int j = b0 + lane;
+            bool take = false;
+            uint64_t key = 0;
+            int lb = 0;
+            if (j < nn) {
+                key = st_key[j];
+                take = key < bound;
+            }
+            if (take) {
+                int lo = 0, hi = wsize;
+                while (lo < hi) {
+                    const int mid = (lo + hi) >> 1;
+                    if (Wk[mid] < key)
+                        lo = mid + 1;
+                    else
+                        hi = mid;
+                }
+                lb = lo;
+                take = !(lb < wsize && Wk[lb] == key);
+            }
+            const uint64_t m = ballot(take);
+            if (take) {
+                const int p = m_adm + below(m);
+                adm[p] = key;
+                adm_lb[p] = lb;
+            }
+            m_adm += __popcll(m);
+        }
+        m_adm = uni(m_adm);
+        if (m_adm == 0) continue;
+        wsync();
+        n_adm += m_adm;
+        // merge: admitted key j lands at rank(j among admitted) + lb(j);
+        // W entry i moves to i + (admitted keys below it)
+        int pmin = INT_MAX;
+        for (int j = lane; j < m_adm; j += kWave) {
+            const uint64_t key = adm[j];
+            int r = 0;
+            for (int t = 0; t < m_adm; ++t) r += adm[t] < key ? 1 : 0;
+            const int pos = r + adm_lb[j];
+            if (pos < efe) {
+                Wn[pos] = key;
+                Wg[pos] = 0;
+            }
+            pmin = min(pmin, pos);
+        }
+        for (int i = lane; i < wsize; i += kWave) {
+            const uint64_t wk = Wk[i];
+            int r = 0;
+            for (int t = 0; t < m_adm; ++t) r += adm[t] < wk ? 1 : 0;
+            const int pos = i + r;
+            if (pos < efe) {
+                Wn[pos] = wk;
+                Wg[pos] = Wf[i];
+            }
+        }
+        pmin = uni(wave_min_i32(pmin));
+        first = min(first, pmin);
+        wsize = min(efe, wsize + m_adm);
+        uint64_t* tk = Wk;
+        Wk = Wn;
+        Wn = tk;
+        uint8_t* tf = Wf;
+        Wf = Wg;
+        Wg = tf;
+        wsync();
+    }
+
+    // ---- outputs ----
+    const int cnt = min(nc, wsize);
+    if (a.mode == 0) {
+        for (int t = lane; t < cnt; t += kWave) {
+            const uint64_t key = Wk[t];
+            a.out_id[q * a.out_stride + t] = (uint32_t)key;
+            a.out_D[q * a.out_stride + t] = (uint32_t)(key >> 32);
+        }
+        if (lane == 0) a.out_cnt[q] = cnt;
+    } else {
+        for (int t = lane; t < a.out_stride; t += kWave) {
+            uint32_t id = kNone, db = 0x7F800000u;
+            if (t < cnt) {
+                const uint64_t key = Wk[t];
+                id = (uint32_t)key;
+                db = (uint32_t)(key >> 32);
+            }
+            a.out_id[q * a.out_stride + t] = id;
+            a.out_D[q * a.out_stride + t] = db;
+        }
+    }
+    if (a.taps.counts && lane == 0) {
+        const uint64_t t_end = __builtin_amdgcn_s_memrealtime();
+        uint32_t* cq = a.taps.counts + q * 8;
+        cq[0] = n_exp;
+        cq[1] = n_eval;
+        cq[2] = n_up;
+        cq[3] = n_adm;
+        cq[4] = n_upx;
+        cq[5] = (uint32_t)(t_end - t_start);
+        cq[6] = (uint32_t)t_start;
+        cq[7] = (uint32_t)(t_start >> 32);
+    }
+}
+
+template <bool F32, int CPL, int U>
+__global__ __launch_bounds__(256) void k_search(SearchArgs a) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    const int lane = lane_id();
+    const int wave = threadIdx.x / kWave;
+    const Idx& ix = a.ix;
+    const int ef_cap = a.ef_cap;
+    const int st_cap = max(ix.s0, ix.s1) <= 64 ? 64 : ((max(ix.s0, ix.s1) + 63) / 64) * 64;
+
+    unsigned char* base = smem + (size_t)wave * a.wave_lds;
+    uint64_t* Wk0 = reinterpret_cast<uint64_t*>(base);
+    uint64_t* Wk1 = Wk0 + ef_cap;
+    uint8_t* Wf0 = reinterpret_cast<uint8_t*>(Wk1 + ef_cap);
+    uint8_t* Wf1 = Wf0 + ef_cap;
+    size_t off = ((size_t)2 * ef_cap * 8 + 2 * (size_t)ef_cap + 7) & ~(size_t)7;
+    uint32_t* st_id = reinterpret_cast<uint32_t*>(base + off);
+    uint64_t* st_key = reinterpret_cast<uint64_t*>(base + off + (size_t)st_cap * 4);
+    uint64_t* adm = st_key + st_cap;
+    int32_t* adm_lb = reinterpret_cast<int32_t*>(adm + st_cap);
+    uint64_t* visb = reinterpret_cast<uint64_t*>(adm_lb + st_cap);
+    float* qf = reinterpret_cast<float*>(visb + ((size_t)1 << a.vb));
+    uint8_t* qc = reinterpret_cast<uint8_t*>(qf + ix.xs);
+
+    const Geo g = make_geo(a.lg, a.nch, lane);
+    VisCache vis{visb, a.vb, max(ix.idbits, a.vb + 1)};
+
+    for (;;) {
+        // Every lane takes part in the work-counter atomic (only lane 0 adds
+        // one) and lane 0's old value is read with readfirstlane: no divergent
+        // branch precedes this cross-lane read, and the branches below that
+        // steer the loop are on wave-uniform values.
+        const int got = atomicAdd(a.counter, lane == 0 ? 1 : 0);
+        const int w = uni(got);
+        if ((int64_t)w >= a.nq) break;
+        const int64_t q = a.order ? (int64_t)a.order[w] : (int64_t)w;
+        if (uni((q >= 0 && q < a.nq) ? 1 : 0)) {  // skip entries outside [0, nq)
+            const int k = a.kq[q];
+            const int ef = a.efq[q];
+            const int efe = max(ef, k);
+            int nc;
+            if (a.mode == 0) {
+                if (a.ncq)
+                    nc = a.ncq[q];
+                else
+                    nc = min(max(efe / a.m_ef, k), efe);
+            } else {
+                nc = k;
+            }
+            int bad =
+                uni((k < 1 || efe > ef_cap || nc < 1 || nc > a.out_stride || nc > efe) ? 1 : 0);
+            if (!bad) {
+                // load the FP32 query into LDS (zero padded); reject non-finite values
+                bool nonfinite = false;
+                for (int j = lane; j < ix.xs; j += kWave) {
+                    const float v = j < ix.d ? a.Q[q * ix.d + j] : 0.0f;
+                    nonfinite |= !__builtin_isfinite(v);
+                    qf[j] = v;
+                }
+                bad = uni(ballot(nonfinite) != 0 ? 1 : 0);
+            }
+            if (bad) {
+                if (a.mode == 0) {
+                    if (lane == 0) a.out_cnt[q] = -1;
+                } else {
+                    for (int t = lane; t < a.out_stride; t += kWave) {
+                        a.out_id[q * a.out_stride + t] = kNone;
+                        a.out_D[q * a.out_stride + t] = 0x7F800000u;
+                    }
+                }
+            } else {
+                search_query<F32, CPL, U>(a, q, efe, nc, lane, g, vis, Wk0, Wk1, Wf0, Wf1, st_id,
+                                          st_key, adm, adm_lb, visb, qf, qc);
+            }
+        }
+        wsync();
+    }
+}
+
+__global__ void k_reset(int32_t* counter) {
+    if (threadIdx.x == 0 && blockIdx.x == 0) *counter = 0;
+}
+
+__global__ void k_encode(Idx ix, const float* Q, int64_t nq, uint8_t* out) {
+    const int64_t q = blockIdx.x;
+    if (q >= nq) return;
+    for (int j = threadIdx.x; j < ix.dp; j += blockDim.x) {
+        uint32_t c = 0;
+        if (j < ix.d) c = encode1(Q[q * ix.d + j], ix.qmin[j], ix.qscale[j]);
+        out[q * ix.dp + j] = (uint8_t)c;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// re-rank: Stage 2 (asymmetric), early termination, Stage 3 (exact), assembly
+// ---------------------------------------------------------------------------
+
+struct RerankArgs {
+    Idx ix;
+    const float* Q;
+    int64_t nq;
+    const uint32_t* cid;
+    const int32_t* ccnt;
+    int32_t nc_stride;
+    int32_t nc_cap;
+    int32_t r_cap;
+    const int32_t* kq;
+    int32_t n_rerank;
+    int32_t out_stride;
+    float tau_gap, tau_ratio, eps;
+    int32_t force_et;
+    int32_t lg8, nch8;   // geometry of code rows
+    int32_t lgf, nchf;   // geometry of FP32 rows
+    size_t wave_lds;
+    int32_t* out_id;
+    float* out_dist;
+    uint8_t* out_kind;
+    RTaps taps;
+};
+
+struct RerankLds {
+    int nc_cap, r_cap, xs;
+    __host__ __device__ size_t bytes() const {
+        size_t o = 0;
+        o += (size_t)nc_cap * 8 * 2;   // A keys, sorted A
+        o += (size_t)r_cap * 8 * 2;    // R keys, sorted R
+        o += (size_t)r_cap * 2;        // kinds
+        o += (size_t)nc_cap * 4;       // ids staging
+        o = (o + 15) & ~(size_t)15;
+        o += (size_t)xs * 4;           // FP32 query
+        return (o + 15) & ~(size_t)15;
+    }
+};
+
+// Asymmetric partial over one 16-code chunk: decode x~ = fl32(code / scale) + min
+// (IEEE division), then sum (q - x~)^2 by fused multiply-add.
+__device__ __forceinline__ float asym_chunk(uint4 x, const float (&qr)[16], const float (&mr)[16],
+                                            const float (&sr)[16]) {
+    float acc = 0.0f;
+    const uint32_t w[4] = {x.x, x.y, x.z, x.w};
+#pragma unroll
+    for (int t = 0; t < 16; ++t) {
+        const float code = (float)((w[t >> 2] >> (8 * (t & 3))) & 0xFFu);
+        const float xt = code / sr[t] + mr[t];
+        const float df = qr[t] - xt;
+        acc = __builtin_fmaf(df, df, acc);
+    }
+    return acc;
+}
+
+template <int CPL8, int CPLF>
+__global__ __launch_bounds__(256) void k_rerank(RerankArgs a) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    const int lane = lane_id();
+    const int wave = threadIdx.x / kWave;
+    const int64_t q = (int64_t)blockIdx.x * (blockDim.x / kWave) + wave;
+    if (q >= a.nq) return;
+    const Idx& ix = a.ix;
+    const int nc_cap = a.nc_cap;
+    const int r_cap = a.r_cap;
+    unsigned char* base = smem + (size_t)wave * a.wave_lds;
+    uint64_t* A = reinterpret_cast<uint64_t*>(base);
+    uint64_t* As = A + nc_cap;
+    uint64_t* Rk = As + nc_cap;
+    uint64_t* Rs = Rk + r_cap;
+    uint8_t* kind = reinterpret_cast<uint8_t*>(Rs + r_cap);
+    uint8_t* kinds = kind + r_cap;
+    uint32_t* ids = reinterpret_cast<uint32_t*>(kinds + r_cap);
+    size_t off = (size_t)nc_cap * 16 + (size_t)r_cap * 18 + (size_t)nc_cap * 4;
+    off = (off + 15) & ~(size_t)15;
+    float* qf = reinterpret_cast<float*>(base + off);
+
+    const int k = a.kq[q];
+    int nc = a.ccnt[q];
+    const bool bad = nc < 0 || nc > a.nc_stride || k < 1 || k > a.out_stride;
+    if (bad) {
+        for (int t = lane; t < a.out_stride; t += kWave) {
+            a.out_id[q * a.out_stride + t] = -1;
+            a.out_dist[q * a.out_stride + t] = __builtin_huge_valf();
+            if (a.out_kind) a.out_kind[q * a.out_stride + t] = 0;
+        }
+        if (lane == 0) {
+            if (a.taps.et) a.taps.et[q] = 0;
+            if (a.taps.nrr) a.taps.nrr[q] = 0;
+        }
+        return;
+    }
+    for (int j = lane; j < ix.xs; j += kWave) qf[j] = j < ix.d ? a.Q[q * ix.d + j] : 0.0f;
+    // candidate ids outside [0, n) are dropped (they cannot come from aqr_search)
+    int ncv = 0;
+    for (int b0 = 0; b0 < nc; b0 += kWave) {
+        const int j = b0 + lane;
+        const uint32_t id = j < nc ? a.cid[q * a.nc_stride + j] : kNone;
+        const bool ok = j < nc && (int64_t)id < ix.n;
+        const uint64_t m = ballot(ok);
+        if (ok) ids[ncv + below(m)] = id;
+        ncv += __popcll(m);
+    }
+    nc = ncv;
+    wsync();
+
+    // Stage 2: d^a on decoded codes, G8 lanes per code row
+    {
+        const Geo g = make_geo(a.lg8, a.nch8, lane);
+        float qr[CPL8][16], mr[CPL8][16], sr[CPL8][16];
+#pragma unroll
+        for (int c = 0; c < CPL8; ++c) {
+            const int ch = g.sub + c * g.G;
+#pragma unroll
+            for (int t = 0; t < 16; ++t) {
+                const int j = ch * 16 + t;
+                const bool in = ch < g.nch;
+                qr[c][t] = in ? qf[j] : 0.0f;
+                mr[c][t] = in ? ix.qmin[j] : 0.0f;
+                sr[c][t] = in ? ix.qscale[j] : 1.0f;
+            }
+        }
+        for (int r0 = 0; r0 < nc; r0 += g.rpp) {
+            const int r = r0 + g.grp;
+            const uint32_t id = r < nc ? ids[r] : kNone;
+            float s = 0.0f;
+#pragma unroll
+            for (int c = 0; c < CPL8; ++c) {
+                const int ch = g.sub + c * g.G;
+                if (id != kNone && ch < g.nch) {
+                    const uint4 x =
+                        reinterpret_cast<const uint4*>(ix.codes + (int64_t)id * ix.dp)[ch];
+                    s += asym_chunk(x, qr[c], mr[c], sr[c]);
+                }
+            }
+            for (int m = g.G >> 1; m >= 1; m >>= 1) s += shfl_xor_f32(s, m);
+            if (g.sub == 0 && r < nc) A[r] = ((uint64_t)__float_as_uint(s) << 32) | id;
+        }
+    }
+    wsync();
+    // sort A by (d^a, id): rank by counting
+    for (int i = lane; i < nc; i += kWave) {
+        const uint64_t v = A[i];
+        int r = 0;
+        for (int t = 0; t < nc; ++t) r += A[t] < v ? 1 : 0;
+        As[r] = v;
+    }
+    wsync();
+    // early termination (Alg. 2 l.15-17)
+    int et = 0;
+    if (nc > k) {
+        const float dk = __uint_as_float((uint32_t)(As[k - 1] >> 32));
+        const float dk1 = __uint_as_float((uint32_t)(As[k] >> 32));
+        const float gap = (dk1 - dk) / (dk + a.eps);
+        const float ratio = dk1 / (dk + a.eps);
+        et = (gap > a.tau_gap) || (ratio > a.tau_ratio);
+    }
+    if (a.force_et >= 0) et = a.force_et != 0;
+    et = uni(et);
+    const int want = et ? k : max(a.n_rerank, k);
+    const int nrr = uni(min(nc, want));
+    // Stage 3: exact FP32 distances on A[0..nrr), GF lanes per row
+    {
+        const Geo g = make_geo(a.lgf, a.nchf, lane);
+        uint4 qv[CPLF];
+#pragma unroll
+        for (int c = 0; c < CPLF; ++c) {
+            const int ch = g.sub + c * g.G;
+            qv[c] = ch < g.nch ? reinterpret_cast<const uint4*>(qf)[ch] : make_uint4(0, 0, 0, 0);
+        }
+        for (int r0 = 0; r0 < nrr; r0 += g.rpp) {
+            const int r = r0 + g.grp;
+            const uint32_t id = r < nrr ? (uint32_t)As[r] : kNone;
+            float s = 0.0f;
+#pragma unroll
+            for (int c = 0; c < CPLF; ++c) {
+                const int ch = g.sub + c * g.G;
+                if (id != kNone && ch < g.nch)
+                    s += Rows<true>::part(Rows<true>::load(ix, id, ch), qv[c]);
+            }
+            for (int m = g.G >> 1; m >= 1; m >>= 1) s += shfl_xor_f32(s, m);
+            if (g.sub == 0 && r < nrr) {
+                Rk[r] = ((uint64_t)__float_as_uint(s) << 32) | id;
+                kind[r] = 1;
+            }
+        }
+    }
+    // assembly: fill from A while fewer than k
+    const int fill = max(0, min(nc - nrr, k - nrr));
+    for (int t = lane; t < fill; t += kWave) {
+        Rk[nrr + t] = As[nrr + t];
+        kind[nrr + t] = 2;
+    }
+    const int nr = nrr + fill;
+    wsync();
+    for (int i = lane; i < nr; i += kWave) {
+        const uint64_t v = Rk[i];
+        int r = 0;
+        for (int t = 0; t < nr; ++t) r += Rk[t] < v ? 1 : 0;
+        Rs[r] = v;
+        kinds[r] = kind[i];
+    }
+    wsync();
+    for (int t = lane; t < a.out_stride; t += kWave) {
+        const int64_t o = q * a.out_stride + t;
+        if (t < k && t < nr) {
+            a.out_id[o] = (int32_t)(uint32_t)Rs[t];
+            a.out_dist[o] = __uint_as_float((uint32_t)(Rs[t] >> 32));
+            if (a.out_kind) a.out_kind[o] = kinds[t];
+        } else {
+            a.out_id[o] = -1;
+            a.out_dist[o] = __builtin_huge_valf();
+            if (a.out_kind) a.out_kind[o] = 0;
+        }
+    }
+    if (a.taps.a_id) {
+        for (int t = lane; t < nc; t += kWave) {
+            a.taps.a_id[q * a.nc_stride + t] = (uint32_t)As[t];
+            a.taps.a_dist[q * a.nc_stride + t] = __uint_as_float((uint32_t)(As[t] >> 32));
+        }
+    }
+    if (lane == 0) {
+        if (a.taps.et) a.taps.et[q] = (uint8_t)et;
+        if (a.taps.nrr) a.taps.nrr[q] = nrr;
+    }
+}
+
+}  // namespace dev
+}  // namespace aqr
+
+// ===========================================================================
+// host side
+// ===========================================================================
+
+using namespace aqr;
+using aqr::dev::Idx;
+
+struct aqr_index {
+    Idx v;
+    int device;
+    int32_t M;
+    int num_cu;
+    size_t max_lds;
+};
+
+namespace {
+
+struct Layout {
+    size_t codes, X, adj0, ubase, uadj, qmin, qscale, total;
+    int32_t dp, xs, s0, s1;
+    int64_t rows;
+};
+
+size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+Layout layout_of(const aqr_quantizer* qz, const aqr_graph* g) {
+    Layout L{};
+    const int64_t n = g->n;
+    L.dp = qz->info.d_pad;
+    L.xs = round_up(qz->info.d, 4);
+    L.s0 = round_up(2 * g->M, 16);
+    L.s1 = round_up(g->M, 16);
+    L.rows = std::max<int64_t>(g->upper_off[n], 1);
+    size_t o = 0;
+    L.codes = o;
+    o = align256(o + (size_t)n * L.dp);
+    L.X = o;
+    o = align256(o + (size_t)n * L.xs * 4);
+    L.adj0 = o;
+    o = align256(o + (size_t)n * L.s0 * 4);
+    L.ubase = o;
+    o = align256(o + (size_t)n * 4);
+    L.uadj = o;
+    o = align256(o + (size_t)L.rows * L.s1 * 4);
+    L.qmin = o;
+    o = align256(o + (size_t)L.dp * 4);
+    L.qscale = o;
+    o = align256(o + (size_t)L.dp * 4);
+    L.total = o;
+    return L;
+}
+
+aqr_status hip_fail(hipError_t e, const char* what) {
+    return fail(AQR_ERR_DEVICE, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+int ilog2_ceil(int64_t x) {
+    int b = 0;
+    while (((int64_t)1 << b) < x) ++b;
+    return b;
+}
+
+int pow2_lg_for(int nch) {
+    // smallest lg with 2^lg >= min(nch, 64)
+    int lg = 0;
+    while ((1 << lg) < std::min(nch, 64)) ++lg;
+    return lg;
+}
+
+}  // namespace
+
+extern "C" aqr_status aqr_index_bytes(const aqr_quantizer* qz, const aqr_graph* g, size_t* bytes) {
+    clear_error();
+    if (!qz || !g || !bytes) return fail(AQR_ERR_INVALID_ARG, "aqr_index_bytes: null pointer");
+    *bytes = layout_of(qz, g).total;
+    return AQR_OK;
+}
+
+extern "C" aqr_status aqr_index_bind(const aqr_quantizer* qz, const aqr_graph* g,
+                                     const uint8_t* codes, const float* X, void* dev_arena,
+                                     size_t arena_bytes, void* stream, aqr_index** out) {
+    try {
+        clear_error();
+        if (!qz || !g || !codes || !X || !dev_arena || !out)
+            return fail(AQR_ERR_INVALID_ARG, "aqr_index_bind: null pointer");
+        if (qz->info.d > dev::kMaxD)
+            return fail(AQR_ERR_INVALID_ARG, "aqr_index_bind: d above 4096 is not supported");
+        if (g->n > (int64_t)0x7FFFFFFF)
+            return fail(AQR_ERR_INVALID_ARG, "aqr_index_bind: n above 2^31-1 is not supported");
+        const Layout L = layout_of(qz, g);
+        if (arena_bytes < L.total)
+            return fail(AQR_ERR_OOM, "aqr_index_bind: arena smaller than aqr_index_bytes()");
+        if (((uintptr_t)dev_arena & 255) != 0)
+            return fail(AQR_ERR_INVALID_ARG, "aqr_index_bind: arena must be 256-byte aligned");
+        hipStream_t s = (hipStream_t)stream;
+        const int64_t n = g->n;
+        const int32_t d = qz->info.d, M = g->M;
+        unsigned char* A = (unsigned char*)dev_arena;
+        hipError_t e;
+        // host staging in the device layout
+        std::vector<float> xs;
+        const float* Xsrc = X;
+        if (L.xs != d) {
+            xs.assign((size_t)n * L.xs, 0.0f);
+            for (int64_t i = 0; i < n; ++i)
+                std::memcpy(&xs[(size_t)i * L.xs], X + i * d, sizeof(float) * d);
+            Xsrc = xs.data();
+        }
+        std::vector<uint32_t> a0((size_t)n * L.s0, AQR_NONE);
+        for (int64_t i = 0; i < n; ++i)
+            std::memcpy(&a0[(size_t)i * L.s0], &g->adj0[(size_t)i * 2 * M], sizeof(uint32_t) * 2 * M);
+        std::vector<int32_t> ub(n, -1);
+        for (int64_t i = 0; i < n; ++i)
+            if (g->level[i] > 0) ub[i] = (int32_t)g->upper_off[i];
+        std::vector<uint32_t> ua((size_t)L.rows * L.s1, AQR_NONE);
+        for (int64_t r = 0; r < g->upper_off[n]; ++r)
+            std::memcpy(&ua[(size_t)r * L.s1], &g->upper_adj[(size_t)r * M], sizeof(uint32_t) * M);
+        std::vector<float> qmin(L.dp, 0.0f), qsc(L.dp, 1.0f);
+        for (int32_t j = 0; j < d; ++j) {
+            qmin[j] = qz->mn[j];
+            qsc[j] = qz->scale[j];
+        }
+        struct Cp {
+            size_t off;
+            const void* src;
+            size_t bytes;
+        } cps[] = {
+            {L.codes, codes, (size_t)n * L.dp},
+            {L.X, Xsrc, (size_t)n * L.xs * 4},
+            {L.adj0, a0.data(), a0.size() * 4},
+            {L.ubase, ub.data(), ub.size() * 4},
+            {L.uadj, ua.data(), ua.size() * 4},
+            {L.qmin, qmin.data(), qmin.size() * 4},
+            {L.qscale, qsc.data(), qsc.size() * 4},
+        };
+        for (const Cp& c : cps) {
+            e = hipMemcpyAsync(A + c.off, c.src, c.bytes, hipMemcpyHostToDevice, s);
+            if (e != hipSuccess) return hip_fail(e, "aqr_index_bind: copy");
+        }
+        e = hipStreamSynchronize(s);
+        if (e != hipSuccess) return hip_fail(e, "aqr_index_bind: synchronize");
+        aqr_index* ix = new aqr_index();
+        Idx& v = ix->v;
+        v.codes = A + L.codes;
+        v.X = reinterpret_cast<const float*>(A + L.X);
+        v.adj0 = reinterpret_cast<const uint32_t*>(A + L.adj0);
+        v.ubase = reinterpret_cast<const int32_t*>(A + L.ubase);
+        v.uadj = reinterpret_cast<const uint32_t*>(A + L.uadj);
+        v.qmin = reinterpret_cast<const float*>(A + L.qmin);
+        v.qscale = reinterpret_cast<const float*>(A + L.qscale);
+        v.n = n;
+        v.d = d;
+        v.dp = L.dp;
+        v.xs = L.xs;
+        v.s0 = L.s0;
+        v.s1 = L.s1;
+        v.ep = g->ep;
+        v.L = g->L;
+        v.idbits = std::max(1, ilog2_ceil(n));
+        ix->M = M;
+        e = hipGetDevice(&ix->device);
+        if (e != hipSuccess) {
+            delete ix;
+            return hip_fail(e, "aqr_index_bind: hipGetDevice");
+        }
+        hipDeviceProp_t prop;
+        e = hipGetDeviceProperties(&prop, ix->device);
+        if (e != hipSuccess) {
+            delete ix;
+            return hip_fail(e, "aqr_index_bind: hipGetDeviceProperties");
+        }
+        ix->num_cu = prop.multiProcessorCount;
+        ix->max_lds = prop.sharedMemPerBlock;
+        *out = ix;
+        return AQR_OK;
+    } catch (const std::bad_alloc&) {
+        return fail(AQR_ERR_OOM, "aqr_index_bind: out of host memory");
+    } catch (...) {
+        return fail(AQR_ERR_STATE, "aqr_index_bind: unexpected failure");
+    }
+}
+
+extern "C" void aqr_index_free(aqr_index* ix) { delete ix; }
+
+extern "C" size_t aqr_search_workspace_size(void) { return 256; }
+
+namespace {
+
+template <bool F32, int CPL>
+hipError_t launch_search_cpl(dev::SearchArgs& a, int blocks, int wpb, size_t lds, int ncu,
+                             hipStream_t s) {
+    constexpr int U = CPL >= 8 ? 1 : 8 / CPL / (F32 ? 2 : 1) > 0 ? 8 / CPL / (F32 ? 2 : 1) : 1;
+    auto kern = dev::k_search<F32, CPL, U>;
+    hipError_t e = hipFuncSetAttribute((const void*)kern,
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (e != hipSuccess) return e;
+    if (blocks <= 0) {
+        int per_cu = 0;
+        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, wpb * dev::kWave, lds);
+        if (e != hipSuccess) return e;
+        blocks = std::max(1, per_cu) * std::max(1, ncu);
+        const int64_t need = (a.nq + wpb - 1) / wpb;
+        if ((int64_t)blocks > need) blocks = (int)std::max<int64_t>(1, need);
+    }
+    hipLaunchKernelGGL(kern, dim3(blocks), dim3(wpb * dev::kWave), lds, s, a);
+    return hipGetLastError();
+}
+
+template <bool F32>
+hipError_t launch_search(dev::SearchArgs& a, int cpl, int blocks, int wpb, size_t lds, int ncu,
+                         hipStream_t s) {
+    if (F32) {
+        switch (cpl) {
+            case 1: return launch_search_cpl<F32, 1>(a, blocks, wpb, lds, ncu, s);
+            case 2: return launch_search_cpl<F32, 2>(a, blocks, wpb, lds, ncu, s);
+            case 4: return launch_search_cpl<F32, 4>(a, blocks, wpb, lds, ncu, s);
+            case 8: return launch_search_cpl<F32, 8>(a, blocks, wpb, lds, ncu, s);
+            default: return launch_search_cpl<F32, 16>(a, blocks, wpb, lds, ncu, s);
+        }
+    }
+    switch (cpl) {
+        case 1: return launch_search_cpl<F32, 1>(a, blocks, wpb, lds, ncu, s);
+        case 2: return launch_search_cpl<F32, 2>(a, blocks, wpb, lds, ncu, s);
+        default: return launch_search_cpl<F32, 4>(a, blocks, wpb, lds, ncu, s);
+    }
+}
+
+int cpl_for(int nch) {
+    int cpl = 1;
+    while (cpl * 64 < nch) cpl <<= 1;
+    return cpl;
+}
+
+aqr_status run_search(const aqr_index* ix, const float* Q, int64_t nq, const int32_t* k,
+                      const int32_t* ef, const int32_t* nc, const aqr_sparams* sp,
+                      uint32_t* out_id, uint32_t* out_D, int32_t* out_cnt, void* ws,
+                      size_t ws_bytes, const aqr_taps* taps, void* stream, bool f32,
+                      const char* who) {
+    clear_error();
+    if (!ix || !sp || !k || !ef || !out_id || !out_D || !ws || (!f32 && !out_cnt))
+        return fail(AQR_ERR_INVALID_ARG, std::string(who) + ": null pointer");
+    if (nq < 0) return fail(AQR_ERR_INVALID_ARG, std::string(who) + ": nq < 0");
+    if (nq == 0) return AQR_OK;
+    if (!Q) return fail(AQR_ERR_INVALID_ARG, std::string(who) + ": null queries");
+    if (nq > (int64_t)INT32_MAX) return fail(AQR_ERR_INVALID_ARG, std::string(who) + ": nq too large");
+    if (sp->ef_max < 1 || sp->ef_max > 1024)
+        return fail(AQR_ERR_INVALID_ARG, std::string(who) + ": ef_max must be in [1, 1024]");
+    if (sp->out_stride < 1)
+        return fail(AQR_ERR_INVALID_ARG, std::string(who) + ": out_stride must be >= 1");
+    if (!f32 && !nc && sp->m_ef < 1)
+        return fail(AQR_ERR_INVALID_ARG, std::string(who) + ": m_ef must be >= 1");
+    if (ws_bytes < aqr_search_workspace_size())
+        return fail(AQR_ERR_OOM, std::string(who) + ": workspace too small");
+    if (taps && (taps->expanded || taps->evaluated) && taps->cap < 1)
+        return fail(AQR_ERR_INVALID_ARG, std::string(who) + ": taps->cap must be >= 1");
+    const Idx& v = ix->v;
+    int vb = sp->visited_log2 > 0 ? sp->visited_log2 : 10;
+    if (vb < 4 || vb > 14) return fail(AQR_ERR_INVALID_ARG, std::string(who) + ": visited_log2 out of [4, 14]");
+    const int idb = std::max(v.idbits, vb + 1);
+    if (idb - vb > 15) vb = idb - 15;  // keep the stored remainder within 15 bits
+    const int wpb = sp->waves_per_block > 0 ? sp->waves_per_block : 4;
+    if (wpb != 1 && wpb != 2 && wpb != 4)
+        return fail(AQR_ERR_INVALID_ARG, std::string(who) + ": waves_per_block must be 1, 2 or 4");
+    dev::SearchLds sl{(sp->ef_max + 63) / 64 * 64,
+                      std::max(v.s0, v.s1) <= 64 ? 64 : (std::max(v.s0, v.s1) + 63) / 64 * 64, vb,
+                      v.xs, v.dp};
+    const size_t wl = sl.bytes();
+    const size_t lds = wl * wpb;
+    if (lds > ix->max_lds)
+        return fail(AQR_ERR_INVALID_ARG, std::string(who) + ": LDS per block exceeds the device limit (lower ef_max, visited_log2 or waves_per_block)");
+    dev::SearchArgs a{};
+    a.ix = v;
+    a.Q = Q;
+    a.nq = nq;
+    a.kq = k;
+    a.efq = ef;
+    a.ncq = f32 ? nullptr : nc;
+    a.order = sp->order;
+    a.m_ef = std::max(1, sp->m_ef);
+    a.ef_cap = sl.ef_cap;
+    a.out_stride = sp->out_stride;
+    a.vb = vb;
+    a.mode = f32 ? 1 : 0;
+    const int nch = f32 ? v.xs / 4 : v.dp / 16;
+    a.nch = nch;
+    a.lg = pow2_lg_for(nch);
+    a.wave_lds = wl;
+    a.out_id = out_id;
+    a.out_D = out_D;
+    a.out_cnt = out_cnt;
+    a.counter = reinterpret_cast<int32_t*>(ws);
+    if (taps) {
+        a.taps.cap = taps->cap;
+        a.taps.expanded = taps->expanded;
+        a.taps.evaluated = taps->evaluated;
+        a.taps.counts = taps->counts;
+    }
+    hipStream_t s = (hipStream_t)stream;
+    hipLaunchKernelGGL(dev::k_reset, dim3(1), dim3(64), 0, s, a.counter);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return hip_fail(e, who);
+    const int cpl = cpl_for(nch);
+    if (cpl > 16) return fail(AQR_ERR_INVALID_ARG, std::string(who) + ": row too wide");
+    if (!f32 && cpl > 4) return fail(AQR_ERR_INVALID_ARG, std::string(who) + ": code row too wide");
+    e = f32 ? launch_search<true>(a, cpl, sp->blocks, wpb, lds, ix->num_cu, s)
+            : launch_search<false>(a, cpl, sp->blocks, wpb, lds, ix->num_cu, s);
+    if (e != hipSuccess) return hip_fail(e, who);
+    return AQR_OK;
+}
+
+}  // namespace
+
+extern "C" aqr_status aqr_search(const aqr_index* ix, const float* Q, int64_t nq,
+                                 const int32_t* k, const int32_t* ef, const int32_t* nc,
+                                 const aqr_sparams* sp, uint32_t* cand_id, uint32_t* cand_D,
+                                 int32_t* cand_cnt, void* ws, size_t ws_bytes,
+                                 const aqr_taps* taps, void* stream) {
+    try {
+        return run_search(ix, Q, nq, k, ef, nc, sp, cand_id, cand_D, cand_cnt, ws, ws_bytes, taps,
+                          stream, false, "aqr_search");
+    } catch (...) {
+        return fail(AQR_ERR_STATE, "aqr_search: unexpected failure");
+    }
+}
+
+extern "C" aqr_status aqr_search_fp32(const aqr_index* ix, const float* Q, int64_t nq,
+                                      const int32_t* k, const int32_t* ef, const aqr_sparams* sp,
+                                      int32_t* out_id, float* out_dist, void* ws, size_t ws_bytes,
+                                      const aqr_taps* taps, void* stream) {
+    try {
+        return run_search(ix, Q, nq, k, ef, nullptr, sp, reinterpret_cast<uint32_t*>(out_id),
+                          reinterpret_cast<uint32_t*>(out_dist), nullptr, ws, ws_bytes, taps,
+                          stream, true, "aqr_search_fp32");
+    } catch (...) {
+        return fail(AQR_ERR_STATE, "aqr_search_fp32: unexpected failure");
+    }
+}
+
+extern "C" aqr_status aqr_encode_queries(const aqr_index* ix, const float* Q, int64_t nq,
+                                         uint8_t* qcodes, void* stream) {
+    clear_error();
+    if (!ix || !qcodes) return fail(AQR_ERR_INVALID_ARG, "aqr_encode_queries: null pointer");
+    if (nq < 0) return fail(AQR_ERR_INVALID_ARG, "aqr_encode_queries: nq < 0");
+    if (nq == 0) return AQR_OK;
+    if (!Q) return fail(AQR_ERR_INVALID_ARG, "aqr_encode_queries: null queries");
+    hipLaunchKernelGGL(dev::k_encode, dim3((unsigned)nq), dim3(128), 0, (hipStream_t)stream,
+                       ix->v, Q, nq, qcodes);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return hip_fail(e, "aqr_encode_queries");
+    return AQR_OK;
+}
+
+namespace {
+
+template <int C8, int CF>
+hipError_t launch_rerank_cf(dev::RerankArgs& a, int wpb, size_t lds, hipStream_t s) {
+    auto kern = dev::k_rerank<C8, CF>;
+    hipError_t e = hipFuncSetAttribute((const void*)kern,
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (e != hipSuccess) return e;
+    const int64_t blocks = (a.nq + wpb - 1) / wpb;
+    hipLaunchKernelGGL(kern, dim3((unsigned)blocks), dim3(wpb * dev::kWave), lds, s, a);
+    return hipGetLastError();
+}
+
+template <int C8>
+hipError_t launch_rerank_c8(dev::RerankArgs& a, int cf, int wpb, size_t lds, hipStream_t s) {
+    switch (cf) {
+        case 1: return launch_rerank_cf<C8, 1>(a, wpb, lds, s);
+        case 2: return launch_rerank_cf<C8, 2>(a, wpb, lds, s);
+        case 4: return launch_rerank_cf<C8, 4>(a, wpb, lds, s);
+        case 8: return launch_rerank_cf<C8, 8>(a, wpb, lds, s);
+        default: return launch_rerank_cf<C8, 16>(a, wpb, lds, s);
+    }
+}
+
+}  // namespace
+
+extern "C" aqr_status aqr_rerank(const aqr_index* ix, const float* Q, int64_t nq,
+                                 const uint32_t* cand_id, const int32_t* cand_cnt,
+                                 int32_t nc_stride, const int32_t* k, const aqr_rparams* rp,
+                                 int32_t* out_id, float* out_dist, uint8_t* out_kind,
+                                 const aqr_rtaps* taps, void* stream) {
+    try {
+        clear_error();
+        if (!ix || !rp || !cand_id || !cand_cnt || !k || !out_id || !out_dist)
+            return fail(AQR_ERR_INVALID_ARG, "aqr_rerank: null pointer");
+        if (nq < 0) return fail(AQR_ERR_INVALID_ARG, "aqr_rerank: nq < 0");
+        if (nq == 0) return AQR_OK;
+        if (!Q) return fail(AQR_ERR_INVALID_ARG, "aqr_rerank: null queries");
+        if (nc_stride < 1 || nc_stride > 1024)
+            return fail(AQR_ERR_INVALID_ARG, "aqr_rerank: nc_stride must be in [1, 1024]");
+        if (rp->out_stride < 1 || rp->out_stride > 1024)
+            return fail(AQR_ERR_INVALID_ARG, "aqr_rerank: out_stride must be in [1, 1024]");
+        if (rp->n_rerank < 0) return fail(AQR_ERR_INVALID_ARG, "aqr_rerank: n_rerank < 0");
+        if (!(rp->eps >= 0.0f) || std::isnan(rp->tau_gap) || std::isnan(rp->tau_ratio))
+            return fail(AQR_ERR_INVALID_ARG, "aqr_rerank: bad thresholds");
+        if (taps && ((taps->a_id == nullptr) != (taps->a_dist == nullptr)))
+            return fail(AQR_ERR_INVALID_ARG, "aqr_rerank: a_id and a_dist go together");
+        const Idx& v = ix->v;
+        const int wpb = rp->waves_per_block > 0 ? rp->waves_per_block : 4;
+        if (wpb != 1 && wpb != 2 && wpb != 4)
+            return fail(AQR_ERR_INVALID_ARG, "aqr_rerank: waves_per_block must be 1, 2 or 4");
+        dev::RerankArgs a{};
+        a.ix = v;
+        a.Q = Q;
+        a.nq = nq;
+        a.cid = cand_id;
+        a.ccnt = cand_cnt;
+        a.nc_stride = nc_stride;
+        a.nc_cap = (nc_stride + 15) / 16 * 16;
+        a.r_cap = a.nc_cap + (rp->out_stride + 15) / 16 * 16;
+        a.kq = k;
+        a.n_rerank = rp->n_rerank;
+        a.out_stride = rp->out_stride;
+        a.tau_gap = rp->tau_gap;
+        a.tau_ratio = rp->tau_ratio;
+        a.eps = rp->eps;
+        a.force_et = rp->force_et < 0 ? -1 : (rp->force_et ? 1 : 0);
+        a.nch8 = v.dp / 16;
+        a.lg8 = pow2_lg_for(a.nch8);
+        a.nchf = v.xs / 4;
+        a.lgf = pow2_lg_for(a.nchf);
+        dev::RerankLds rl{a.nc_cap, a.r_cap, v.xs};
+        a.wave_lds = rl.bytes();
+        const size_t lds = a.wave_lds * wpb;
+        if (lds > ix->max_lds)
+            return fail(AQR_ERR_INVALID_ARG, "aqr_rerank: LDS per block exceeds the device limit");
+        a.out_id = out_id;
+        a.out_dist = out_dist;
+        a.out_kind = out_kind;
+        if (taps) {
+            a.taps.a_id = taps->a_id;
+            a.taps.a_dist = taps->a_dist;
+            a.taps.et = taps->et;
+            a.taps.nrr = taps->nrr;
+        }
+        const int c8 = cpl_for(a.nch8), cf = cpl_for(a.nchf);
+        hipStream_t s = (hipStream_t)stream;
+        hipError_t e;
+        switch (c8) {
+            case 1: e = launch_rerank_c8<1>(a, cf, wpb, lds, s); break;
+            case 2: e = launch_rerank_c8<2>(a, cf, wpb, lds, s); break;
+            default: e = launch_rerank_c8<4>(a, cf, wpb, lds, s); break;
+        }
+        if (e != hipSuccess) return hip_fail(e, "aqr_rerank");
+        return AQR_OK;
+    } catch (...) {
+        return fail(AQR_ERR_STATE, "aqr_rerank: unexpected failure");
+    }
+}

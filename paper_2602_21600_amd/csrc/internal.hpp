@@ -1,0 +1,62 @@
+// internal.hpp -- host-side structures shared by the translation units of
+// libaqr (quantiser, graph builder, device index).
+#pragma once
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "../../include/aqr.h"
+
+namespace aqr {
+
+// Thread-local error message; returns the status for one-line use.
+aqr_status fail(aqr_status st, const std::string& msg);
+void clear_error();
+
+inline int32_t round_up(int32_t x, int32_t m) { return (x + m - 1) / m * m; }
+
+// Number of host worker threads for a request (0 = all hardware threads).
+int host_threads(int32_t requested);
+
+// Run fn(t) for t in [0, T) on T threads (T >= 1) and join.
+template <class F>
+void parallel_for_threads(int T, F fn);
+
+struct Quantizer {
+    aqr_qinfo info{};
+    std::vector<float> mn, mx, scale;  // d each
+};
+
+// Graph in the exchange layout (see aqr_graph_export).
+struct Graph {
+    int64_t n = 0;
+    int32_t M = 0, efc = 0;
+    int32_t L = 0;
+    uint32_t ep = 0;
+    std::vector<int32_t> level;
+    std::vector<uint32_t> adj0;      // n * 2M
+    std::vector<int64_t> upper_off;  // n + 1
+    std::vector<uint32_t> upper_adj; // rows * M
+};
+
+}  // namespace aqr
+
+struct aqr_quantizer : aqr::Quantizer {};
+struct aqr_graph : aqr::Graph {};
+
+#include <thread>
+
+namespace aqr {
+template <class F>
+void parallel_for_threads(int T, F fn) {
+    if (T <= 1) {
+        fn(0);
+        return;
+    }
+    std::vector<std::thread> th;
+    th.reserve(T);
+    for (int t = 0; t < T; ++t) th.emplace_back(fn, t);
+    for (auto& x : th) x.join();
+}
+}  // namespace aqr

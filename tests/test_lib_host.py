@@ -1,0 +1,176 @@
+"""Host-side checks of libaqr (no GPU): exported symbols, quantiser and graph
+builder parity with the oracle, and argument validation."""
+import os
+import re
+
+import numpy as np
+import pytest
+
+from paper_2602_21600_amd import aqr
+from paper_2602_21600_amd import workloads as W
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+@pytest.fixture(scope="module")
+def L():
+    return aqr.lib()
+
+
+def _declared_symbols():
+    src = open(os.path.join(ROOT, "include", "aqr.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(aqr_[a-z0-9_]+)\s*\(", src)))
+
+
+def test_exports_every_declared_symbol(L):
+    declared = _declared_symbols()
+    assert len(declared) >= 19
+    for name in declared:
+        assert hasattr(L, name), name
+    assert set(aqr.SYMBOLS) == set(declared)
+    assert aqr.aqr_version() == 1
+
+
+def _train_both(orc, X, M0=16, efc0=100, p_max=0.01, threads=0, **kw):
+    params = aqr.default_qparams(M0=M0, efc0=efc0, p_max=p_max, threads=threads)
+    params.update(kw)
+    qz, codes = aqr.aqr_quantize(X, params)
+    ref = orc.train(X, p_max=p_max, M0=M0, efc0=efc0,
+                    n_s=params["n_sample"], threshold=params["sample_threshold"])
+    return qz, codes, ref
+
+
+@pytest.mark.parametrize("n,d,threshold", [(2000, 24, 10000), (3000, 20, 1000), (1500, 100, 10000)])
+def test_quantize_matches_oracle(orc, n, d, threshold):
+    X, _ = W.tiny(n, d, seed=n + d, clusters=7)
+    qz, codes, ref = _train_both(orc, X, sample_threshold=threshold, n_sample=500)
+    info = aqr.aqr_quantizer_info(qz)
+    # same definitions, same FP64 summation order: identical values
+    assert info["delta"] == ref["delta"]
+    assert info["p_lo"] == ref["p_lo"] and info["p_hi"] == ref["p_hi"]
+    assert info["eta"] == ref["eta"] == 0.0
+    assert info["s_dist"] == ref["s_dist"]
+    assert (info["M"], info["efc"]) == (ref["M"], ref["efc"])
+    np.testing.assert_array_equal(info["min"], ref["min"])
+    np.testing.assert_array_equal(info["max"], ref["max"])
+    np.testing.assert_array_equal(info["scale"], ref["scale"])
+    d_pad = (d + 15) // 16 * 16
+    assert codes.shape == (n, d_pad) and info["d_pad"] == d_pad
+    oc = orc.encode(X, ref["min"], ref["scale"], stride=d_pad)
+    np.testing.assert_array_equal(codes, oc)
+
+
+def test_quantize_small_workload_matches_oracle(orc):
+    X = W.base("small")
+    qz, codes, ref = _train_both(orc, X)
+    info = aqr.aqr_quantizer_info(qz)
+    assert info["delta"] == ref["delta"]
+    np.testing.assert_array_equal(info["min"], ref["min"])
+    np.testing.assert_array_equal(info["max"], ref["max"])
+    np.testing.assert_array_equal(codes, orc.encode(X, ref["min"], ref["scale"], stride=128))
+
+
+def test_quantize_encode_only(orc):
+    X, Y = W.tiny(800, 16, seed=2, nq=50)
+    qz, codes = aqr.aqr_quantize(X, aqr.default_qparams())
+    _, ycodes = aqr.aqr_quantize(Y, qz=qz)
+    info = aqr.aqr_quantizer_info(qz)
+    np.testing.assert_array_equal(ycodes, orc.encode(Y, info["min"], info["scale"], stride=16))
+
+
+def test_quantize_rejects_bad_input(L):
+    X = np.ones((10, 4), np.float32)
+    X[3, 2] = np.nan
+    with pytest.raises(aqr.AqrError) as e:
+        aqr.aqr_quantize(X, aqr.default_qparams())
+    assert e.value.status == aqr.INVALID_ARG
+    X[3, 2] = np.inf
+    with pytest.raises(aqr.AqrError):
+        aqr.aqr_quantize(X, aqr.default_qparams())
+    bad = aqr.default_qparams()
+    bad["k_rho"] = 0
+    with pytest.raises(aqr.AqrError) as e:
+        aqr.aqr_quantize(np.ones((10, 4), np.float32), bad)
+    assert "out of range" in str(e.value)
+    qz, _ = aqr.aqr_quantize(np.random.default_rng(0).random((20, 4)).astype(np.float32),
+                             aqr.default_qparams())
+    with pytest.raises(aqr.AqrError):
+        aqr.aqr_quantize(np.ones((10, 5), np.float32), qz=qz)
+
+
+def _both_graphs(orc, X, M0, efc0, seed):
+    qz, codes, ref = _train_both(orc, X, M0=M0, efc0=efc0)
+    info = aqr.aqr_quantizer_info(qz)
+    u = 1.0 - np.random.default_rng(seed).random(X.shape[0])
+    g = aqr.aqr_build(codes, X.shape[1], qz, threads=1, level_u=u)
+    lv = orc.levels(u, info["M"])
+    og = orc.build(codes, X.shape[1], info["M"], info["efc"], lv)
+    return aqr.aqr_graph_export(g), og, info
+
+
+@pytest.mark.parametrize("n,d,M0,efc0", [(1500, 16, 6, 40), (2500, 32, 16, 100)])
+def test_sequential_build_matches_oracle(orc, n, d, M0, efc0):
+    X, _ = W.tiny(n, d, seed=n, clusters=5)
+    eg, og, info = _both_graphs(orc, X, M0, efc0, seed=n)
+    np.testing.assert_array_equal(eg["level"], og["level"])
+    assert (eg["ep"], eg["L"]) == (og["ep"], og["L"])
+    np.testing.assert_array_equal(eg["upper_off"], og["upper_off"])
+    np.testing.assert_array_equal(eg["adj0"], og["adj0"])
+    np.testing.assert_array_equal(eg["upper_adj"][: og["upper_off"][-1]],
+                                  og["upper_adj"][: og["upper_off"][-1]])
+
+
+def test_sequential_build_small_workload_matches_oracle(orc):
+    X = W.base("small", 4000)
+    eg, og, _ = _both_graphs(orc, X, 16, 100, seed=7)
+    np.testing.assert_array_equal(eg["adj0"], og["adj0"])
+    assert (eg["ep"], eg["L"]) == (og["ep"], og["L"])
+
+
+def test_parallel_build_invariants(orc):
+    from test_oracle_graph import check_invariants
+    X, _ = W.tiny(3000, 24, seed=5, clusters=6)
+    qz, codes = aqr.aqr_quantize(X, aqr.default_qparams(M0=8, efc0=40))
+    g = aqr.aqr_build(codes, 24, qz, threads=4, seed=99)
+    eg = aqr.aqr_graph_export(g)
+    check_invariants(eg, eg["M"])
+    # most points are found by an exhaustive search from the entry point
+    from test_oracle_search import _reachable
+    assert _reachable(eg["adj0"], eg["ep"]).size > 0.99 * 3000
+
+
+def test_graph_import_round_trip_and_corruption(orc):
+    X, _ = W.tiny(600, 8, seed=1)
+    qz, codes = aqr.aqr_quantize(X, aqr.default_qparams(M0=4, efc0=20))
+    eg = aqr.aqr_graph_export(aqr.aqr_build(codes, 8, qz, threads=1, seed=3))
+    g2 = aqr.aqr_graph_import(eg)
+    e2 = aqr.aqr_graph_export(g2)
+    for key in ("level", "adj0", "upper_off"):
+        np.testing.assert_array_equal(eg[key], e2[key])
+    bad = dict(eg)
+    bad["adj0"] = eg["adj0"].copy()
+    bad["adj0"][5, 0] = 10 ** 6
+    with pytest.raises(aqr.AqrError) as e:
+        aqr.aqr_graph_import(bad)
+    assert e.value.status == aqr.CORRUPT
+    bad = dict(eg)
+    bad["level"] = eg["level"].copy()
+    bad["level"][0] += 1
+    with pytest.raises(aqr.AqrError) as e:
+        aqr.aqr_graph_import(bad)
+    assert e.value.status == aqr.CORRUPT
+
+
+def test_null_handles_are_rejected(L):
+    import ctypes as C
+    assert L.aqr_search(None, None, 1, None, None, None, None, None, None, None, None, 0, None,
+                        None) == aqr.INVALID_ARG
+    assert b"null" in L.aqr_last_error()
+    assert L.aqr_rerank(None, None, 1, None, None, 1, None, None, None, None, None, None,
+                        None) == aqr.INVALID_ARG
+    assert L.aqr_search_fp32(None, None, 1, None, None, None, None, None, None, 0, None,
+                             None) == aqr.INVALID_ARG
+    assert L.aqr_index_bind(None, None, None, None, None, 0, None, C.byref(C.c_void_p())) == \
+        aqr.INVALID_ARG
+    assert L.aqr_build(None, 1, 1, None, None, None, C.byref(C.c_void_p())) == aqr.INVALID_ARG
