@@ -82,13 +82,29 @@ def recall_at(ids, X, Q, gt_ids, gt_d, k=10):
     return hits / (ids.shape[0] * k)
 
 
+# Re-rank settings swept after ef, cheapest first: Table 3's "0.97+" row, the
+# upper ends of the ranges of the sensitivity analysis (Section 4.4), and early
+# termination switched off with growing exact re-rank depth.
+RERANK_CONFIGS = [
+    ("table3", 28, 0.010, 1.008),
+    ("sec4.4", 28, 0.03, 1.02),
+    ("no-et", 28, float("inf"), float("inf")),
+    ("no-et-50", 50, float("inf"), float("inf")),
+    ("no-et-100", 100, float("inf"), float("inf")),
+]
+
+
 class AqrRunner:
-    def __init__(self, aqr, ix, nq, k, ef, device, visited_log2=0, waves_per_block=0):
+    def __init__(self, aqr, ix, nq, k, ef, device, visited_log2=0, waves_per_block=0,
+                 rerank=RERANK_CONFIGS[0]):
         import torch
         self.torch = torch
         self.aqr = aqr
+        self.rerank = rerank
+        _, nrr, tg, tr = rerank
         self.plan = aqr.QueryPlan(ix, nq, k, max(ef, k), visited_log2=visited_log2,
-                                  waves_per_block=waves_per_block)
+                                  waves_per_block=waves_per_block, n_rerank=nrr, tau_gap=tg,
+                                  tau_ratio=tr)
         self.k = torch.full((nq,), k, dtype=torch.int32, device=device)
         self.ef = torch.full((nq,), ef, dtype=torch.int32, device=device)
 
@@ -184,6 +200,10 @@ def main():
     ap.add_argument("--profile", action="store_true",
                     help="skip sweeps and the CPU leg; time the AQR path at --ef")
     ap.add_argument("--ef", type=int, default=None)
+    ap.add_argument("--rerank", default="no-et", help="re-rank setting in --profile mode")
+    ap.add_argument("--cache", default=None, help="directory to save/load the built index")
+    ap.add_argument("--copy-mib", type=int, default=256,
+                    help="size of the plain copy kernel timed in --profile mode")
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -212,53 +232,95 @@ def main():
     threads = int(os.environ.get("OMP_NUM_THREADS", "0") or 0)
     threads = threads if threads > 0 else min(16, os.cpu_count() or 1)
 
-    log(f"quantize n={n} d={d} threads={threads}")
-    t = time.perf_counter()
-    qz, codes = aqr.aqr_quantize(X, aqr.default_qparams(M0=wl.M0, efc0=wl.efc0,
-                                                        threads=threads))
-    t_quant = time.perf_counter() - t
+    t_quant = t_build = None
+    cache = args.cache
+    if cache and os.path.exists(os.path.join(cache, "meta.json")):
+        log(f"loading index from {cache}")
+        meta = json.load(open(os.path.join(cache, "meta.json")))
+        arr = {k_: np.load(os.path.join(cache, k_ + ".npy"))
+               for k_ in ("codes", "min", "max", "scale", "level", "adj0", "upper_off",
+                          "upper_adj")}
+        codes = arr["codes"]
+        qz = aqr.aqr_quantizer_create(meta["info"], arr["min"], arr["max"], arr["scale"])
+        gx = dict(n=n, M=meta["M"], level=arr["level"], adj0=arr["adj0"],
+                  upper_off=arr["upper_off"], upper_adj=arr["upper_adj"], ep=meta["ep"])
+        g = aqr.aqr_graph_import(gx)
+    else:
+        log(f"quantize n={n} d={d} threads={threads}")
+        t = time.perf_counter()
+        qz, codes = aqr.aqr_quantize(X, aqr.default_qparams(M0=wl.M0, efc0=wl.efc0,
+                                                            threads=threads))
+        t_quant = time.perf_counter() - t
+        t = time.perf_counter()
+        g = aqr.aqr_build(codes, d, qz, threads=threads,
+                          level_u=W.level_draws(args.workload, n))
+        t_build = time.perf_counter() - t
+        if cache:
+            os.makedirs(cache, exist_ok=True)
+            qi = aqr.aqr_quantizer_info(qz)
+            gx = aqr.aqr_graph_export(g)
+            for k_, v in (("codes", codes), ("min", qi["min"]), ("max", qi["max"]),
+                          ("scale", qi["scale"]), ("level", gx["level"]), ("adj0", gx["adj0"]),
+                          ("upper_off", gx["upper_off"]), ("upper_adj", gx["upper_adj"])):
+                np.save(os.path.join(cache, k_ + ".npy"), v)
+            info_s = {f: qi[f] for f in ("d", "d_pad", "M", "efc", "delta", "p_lo", "p_hi",
+                                         "s_dist", "eta", "w_mean")}
+            json.dump({"info": info_s, "M": gx["M"], "ep": gx["ep"]},
+                      open(os.path.join(cache, "meta.json"), "w"))
     info = aqr.aqr_quantizer_info(qz)
-    log(f"quantize {t_quant:.1f}s delta={info['delta']:.4f} M_i={info['M']} efc={info['efc']}")
-    t = time.perf_counter()
-    g = aqr.aqr_build(codes, d, qz, threads=threads, level_u=W.level_draws(args.workload, n))
-    t_build = time.perf_counter() - t
     ginfo = aqr.aqr_graph_info(g)
-    log(f"build {t_build:.1f}s L={ginfo['L']}")
+    log(f"index ready: quantize {t_quant}s, build {t_build}s, delta={info['delta']:.4f} "
+        f"M_i={info['M']} L={ginfo['L']}")
     ix = aqr.aqr_index_bind(qz, g, codes, X, device=dev)
-    log("index bound; ground truth")
-    gt_ids, gt_d = ground_truth(X, Q, k, dev)
+    gt_ids = gt_d = None
+    if not args.profile:
+        log("ground truth")
+        gt_ids, gt_d = ground_truth(X, Q, k, dev)
     Qd = torch.from_numpy(Q).to(dev)
 
     efs = [int(e) for e in args.efs.split(",")] if args.efs else list(wl.ef) + [384, 512]
-    if args.profile:
-        efs = [args.ef or 128]
 
-    def sweep(make, name):
-        chosen, table = None, []
+    def recall_of(ids):
+        return recall_at(ids.cpu().numpy(), X, Q, gt_ids, gt_d, k)
+
+    aqr_table, fp_table = [], []
+    aqr_pick = fp_pick = None
+    if args.profile:
+        cfg = next(c for c in RERANK_CONFIGS if c[0] == args.rerank)
+        aqr_pick = (args.ef or 256, float("nan"), cfg)
+    else:
         for ef in efs:
-            r = make(ef)
+            for cfg in RERANK_CONFIGS:
+                r = AqrRunner(aqr, ix, nq, k, ef, dev, rerank=cfg)
+                ids, _ = r.step(Qd)
+                torch.cuda.synchronize()
+                rec = recall_of(ids)
+                aqr_table.append((ef, cfg[0], round(rec, 5)))
+                log(f"aqr ef={ef} rerank={cfg[0]} recall@10={rec:.4f}")
+                if rec >= TARGET_RECALL:
+                    aqr_pick = (ef, rec, cfg)
+                    break
+            if aqr_pick:
+                break
+        if aqr_pick is None:
+            best = max(aqr_table, key=lambda t: t[2])
+            aqr_pick = (best[0], best[2], next(c for c in RERANK_CONFIGS if c[0] == best[1]))
+        for ef in efs:
+            r = Fp32Runner(aqr, ix, nq, k, ef, dev)
             ids, _ = r.step(Qd)
             torch.cuda.synchronize()
-            rec = recall_at(ids.cpu().numpy(), X, Q, gt_ids, gt_d, k)
-            table.append((ef, round(rec, 5)))
-            log(f"{name} ef={ef} recall@10={rec:.4f}")
+            rec = recall_of(ids)
+            fp_table.append((ef, round(rec, 5)))
+            log(f"fp32 ef={ef} recall@10={rec:.4f}")
             if rec >= TARGET_RECALL:
-                chosen = (ef, rec)
+                fp_pick = (ef, rec)
                 break
-        return chosen, table
-
-    aqr_pick, aqr_table = sweep(lambda ef: AqrRunner(aqr, ix, nq, k, ef, dev), "aqr")
-    if aqr_pick is None:
-        aqr_pick = (efs[-1], aqr_table[-1][1])
-    fp_pick, fp_table = (None, [])
-    if not args.profile:
-        fp_pick, fp_table = sweep(lambda ef: Fp32Runner(aqr, ix, nq, k, ef, dev), "fp32")
         if fp_pick is None:
             fp_pick = (efs[-1], fp_table[-1][1])
 
     # ---- timed AQR path ----
     ef_a = aqr_pick[0]
-    runner = AqrRunner(aqr, ix, nq, k, ef_a, dev)
+    runner = AqrRunner(aqr, ix, nq, k, ef_a, dev, rerank=aqr_pick[2])
 
     def aqr_step(marks):
         if marks:
@@ -280,7 +342,8 @@ def main():
     # per-query counters (separate, untimed run with a large visited cache so
     # that evaluations count distinct nodes)
     counts = torch.zeros((nq, 8), dtype=torch.int32, device=dev)
-    big = AqrRunner(aqr, ix, nq, k, ef_a, dev, visited_log2=14, waves_per_block=1)
+    big = AqrRunner(aqr, ix, nq, k, ef_a, dev, visited_log2=14, waves_per_block=1,
+                    rerank=aqr_pick[2])
     big.search_only(Qd, taps=dict(cap=0, counts=counts))
     torch.cuda.synchronize()
     cnt_big = counts.cpu().numpy().astype(np.int64)
@@ -302,6 +365,17 @@ def main():
     lat_us = cnt[:, 5] / 100.0  # 100 MHz real-time clock
     sha = source_sha()
     traffic = traffic_from_profile(f"search_u8_{args.workload}_ef{ef_a}", sha)
+
+    copy_info = None
+    if args.profile:
+        # a plain copy of known size: its FETCH_SIZE/WRITE_SIZE readings scale
+        # the counters of the search kernel to bytes
+        src = torch.empty(args.copy_mib << 20, dtype=torch.uint8, device=dev).fill_(1)
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        copy_info = {"bytes": args.copy_mib << 20}
 
     # ---- timed FP32 baseline ----
     fp = None
@@ -346,7 +420,8 @@ def main():
         index = dict(X=X, codes=codes, d=d, min=info["min"], scale=info["scale"], graph=gx)
         log(f"CPU oracle on {S} queries with {orc.get_threads()} threads")
         t = time.perf_counter()
-        ref = orc.query(index, Q[:S], k, ef_a)
+        _, nrr_, tg_, tr_ = aqr_pick[2]
+        ref = orc.query(index, Q[:S], k, ef_a, n_rerank=nrr_, tau_gap=tg_, tau_ratio=tr_)
         dt = time.perf_counter() - t
         cpu = {"value": round(S / dt, 1), "unit": "queries/s", "cores": orc.get_threads(),
                "kind": "oracle",
@@ -380,8 +455,10 @@ def main():
             "workload": f"{args.workload}: {n:,} x {d} FP32 L2, {wl.n_clusters}-cluster "
                         f"Gaussian mixture; {nq:,} queries; k={k}",
             "n": n, "d": d, "nq": nq, "k": k, "ef": ef_a, "M0": wl.M0, "efc0": wl.efc0,
-            "M_i": ginfo["M"], "delta": round(info["delta"], 6), "m_ef": 3, "n_rerank": 28,
-            "tau_gap": 0.010, "tau_ratio": 1.008, "recall@10": round(aqr_pick[1], 5),
+            "M_i": ginfo["M"], "delta": round(info["delta"], 6), "m_ef": 3,
+            "rerank": aqr_pick[2][0], "n_rerank": aqr_pick[2][1],
+            "tau_gap": aqr_pick[2][2], "tau_ratio": aqr_pick[2][3],
+            "recall@10": round(aqr_pick[1], 5),
             "global_batch": nq, "parallelism": "single GPU, one wavefront per query",
         },
         "roofline": {
@@ -403,8 +480,10 @@ def main():
         "aqr_sweep": aqr_table,
         "cpu_baseline": cpu,
         "parity_sample": parity,
-        "build_s": {"quantize": round(t_quant, 1), "graph": round(t_build, 1)},
+        "build_s": {"quantize": t_quant and round(t_quant, 1),
+                    "graph": t_build and round(t_build, 1)},
         "device_hip_sha": sha,
+        "copy_kernel": copy_info,
         "wall_s": round(time.perf_counter() - t_all, 1),
     }
     print(json.dumps(out), flush=True)

@@ -277,10 +277,10 @@ struct SearchLds {
     int ef_cap, st_cap, vb, xs, dp;
     __host__ __device__ size_t bytes() const {
         size_t o = 0;
-        o += 2 * (size_t)ef_cap * 8;       // W keys, two buffers
-        o += 2 * (size_t)ef_cap;           // W flags
+        o += (size_t)ef_cap * 8;           // merge buffer: keys
+        o += (size_t)ef_cap;               // merge buffer: expanded flags
         o = (o + 7) & ~(size_t)7;
-        o += (size_t)st_cap * (4 + 8 + 8 + 4);  // ids, keys, admitted keys, their W ranks
+        o += (size_t)st_cap * (4 + 8);     // new neighbour ids and their keys
         o += ((size_t)8 << vb);            // visited buckets
         o += (size_t)xs * 4;               // FP32 query
         o += (size_t)dp;                   // query codes
@@ -311,18 +311,32 @@ struct SearchArgs {
     Taps taps;
 };
 
-// Stage 1 of one valid query, run by the whole wave.  Every branch that
-// steers a loop here is on a wave-uniform value (a ballot, a popcount or a
-// readfirstlane), and every single-lane block is closed by a wave barrier
-// before the next loop control, so all lanes stay converged at each
-// cross-lane operation.
-template <bool F32, int CPL, int U>
+__device__ __forceinline__ uint64_t readlane64(uint64_t v, int l) {
+    const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)v, l);
+    const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(v >> 32), l);
+    return ((uint64_t)hi << 32) | lo;
+}
+
+// Stage 1 of one valid query, run by the whole wave.
+//
+// The result list W (at most ef_cap = 64*S keys, sorted) and its expanded
+// flags live in LDS.  A merge loads W into registers striped (entry i is
+// slot i/64 of lane i%64, invalid entries ~0), ranks each admitted key
+// against it and checks it for an equal key with 64-bit compares and
+// ballots, then scatters W and the admitted keys to their merged positions
+// in place.  Keeping W out of registers between merges keeps the register
+// peak at the distance phase, which sets the number of waves per CU.
+//
+// Every branch that steers a loop is on a wave-uniform value (a ballot, a
+// popcount or a readfirstlane), and every single-lane block is closed by a
+// wave barrier before the next loop control, so all lanes stay converged at
+// each cross-lane operation.
+template <bool F32, int CPL, int U, int S>
 __device__ __forceinline__ void search_query(const SearchArgs& a, const int64_t q, const int efe,
                                              const int nc, const int lane, const Geo& g,
-                                             const VisCache& vis, uint64_t* Wk0, uint64_t* Wk1,
-                                             uint8_t* Wf0, uint8_t* Wf1, uint32_t* st_id,
-                                             uint64_t* st_key, uint64_t* adm, int32_t* adm_lb,
-                                             uint64_t* visb, float* qf, uint8_t* qc) {
+                                             const VisCache& vis, uint64_t* mk, uint8_t* mf,
+                                             uint32_t* st_id, uint64_t* st_key, uint64_t* visb,
+                                             float* qf, uint8_t* qc) {
     const Idx& ix = a.ix;
     uint32_t qq = 0;
     if (!F32) {
@@ -383,28 +397,25 @@ __device__ __forceinline__ void search_query(const SearchArgs& a, const int64_t 
         }
     }
 
+
     // ---- layer-0 search with width efe ----
     for (int i = lane; i < (1 << a.vb); i += kWave) visb[i] = 0ull;
     wsync();
     if (lane == 0) {
-        Wk0[0] = curkey;
-        Wf0[0] = 0;
         vis.test_insert((uint32_t)curkey);
+        mk[0] = curkey;
+        mf[0] = 0;
     }
     wsync();
-    uint64_t* Wk = Wk0;
-    uint64_t* Wn = Wk1;
-    uint8_t* Wf = Wf0;
-    uint8_t* Wg = Wf1;
     int wsize = 1;
     int first = 0;
+    const int nad = (ix.s0 + kWave - 1) / kWave;  // 64-entry chunks of an adjacency row (<= 4)
     for (;;) {
         // nearest unexpanded entry of W
         int idx = -1;
         for (int b0 = first & ~(kWave - 1); b0 < wsize; b0 += kWave) {
             const int i = b0 + lane;
-            const bool p = i >= first && i < wsize && Wf[i] == 0;
-            const uint64_t m = ballot(p);
+            const uint64_t m = ballot(i >= first && i < wsize && mf[i] == 0);
             if (m) {
                 idx = b0 + (int)__builtin_ctzll(m);
                 break;
@@ -412,11 +423,11 @@ __device__ __forceinline__ void search_query(const SearchArgs& a, const int64_t 
         }
         idx = uni(idx);
         if (idx < 0) break;
-        const uint32_t c = (uint32_t)uni64(Wk[idx]);
+        const uint32_t c = (uint32_t)uni64(mk[idx]);
         first = idx + 1;
         wsync();
         if (lane == 0) {
-            Wf[idx] = 1;
+            mf[idx] = 1;
             if (a.taps.expanded && (int)n_exp < a.taps.cap)
                 a.taps.expanded[q * a.taps.cap + n_exp] = c;
         }
@@ -424,16 +435,23 @@ __device__ __forceinline__ void search_query(const SearchArgs& a, const int64_t 
         ++n_exp;
         // unvisited neighbours of c
         const uint32_t* row = ix.adj0 + (int64_t)c * ix.s0;
+        uint32_t e[4];
+#pragma unroll
+        for (int b = 0; b < 4; ++b)
+            e[b] = (b < nad && b * kWave + lane < ix.s0) ? row[b * kWave + lane] : kNone;
         int nn = 0;
-        for (int b0 = 0; b0 < ix.s0; b0 += kWave) {
-            const uint32_t e = (b0 + lane < ix.s0) ? row[b0 + lane] : kNone;
-            const bool isnew = e != kNone && !vis.test_insert(e);
-            const uint64_t m = ballot(isnew);
-            if (isnew) st_id[nn + below(m)] = e;
-            nn += __popcll(m);
+#pragma unroll
+        for (int b = 0; b < 4; ++b) {
+            if (b < nad) {
+                const bool isnew = e[b] != kNone && !vis.test_insert(e[b]);
+                const uint64_t m = ballot(isnew);
+                if (isnew) st_id[nn + below(m)] = e[b];
+                nn += __popcll(m);
+            }
         }
         wsync();
-        if (uni(nn) == 0) continue;
+        nn = uni(nn);
+        if (nn == 0) continue;
         if (a.taps.evaluated) {
             for (int j = lane; j < nn; j += kWave) {
                 const int p = (int)n_eval + j;
@@ -443,97 +461,90 @@ __device__ __forceinline__ void search_query(const SearchArgs& a, const int64_t 
         n_eval += nn;
         eval_rows<F32, CPL, U>(ix, st_id, nn, st_key, qv, qq, g);
         wsync();
-        // keys below the bound that are not in W already
-        const uint64_t bound = wsize == efe ? Wk[wsize - 1] : ~0ull;
-        int m_adm = 0;
+        // merge the scored neighbours, 64 at a time
         for (int b0 = 0; b0 < nn; b0 += kWave) {
+            const uint64_t bound = wsize == efe ? uni64(mk[efe - 1]) : ~0ull;
             const int j = b0 + lane;
-            bool take = false;
-            uint64_t key = 0;
-            int lb = 0;
-            if (j < nn) {
-                key = st_key[j];
-                take = key < bound;
+            const uint64_t key = j < nn ? st_key[j] : ~0ull;
+            uint64_t A = ballot(key < bound);
+            if (A == 0) continue;
+            uint64_t w[S];
+            uint32_t wfl = 0;
+#pragma unroll
+            for (int s = 0; s < S; ++s) {
+                const int i = s * kWave + lane;
+                w[s] = i < wsize ? mk[i] : ~0ull;
+                wfl |= (i < wsize && mf[i]) ? (1u << s) : 0u;
             }
-            if (take) {
-                int lo = 0, hi = wsize;
-                while (lo < hi) {
-                    const int mid = (lo + hi) >> 1;
-                    if (Wk[mid] < key)
-                        lo = mid + 1;
-                    else
-                        hi = mid;
+            int posW = 0, rankA = 0;
+            uint32_t sh[S];
+#pragma unroll
+            for (int s = 0; s < S; ++s) sh[s] = 0;
+            uint64_t dupm = 0;
+            for (uint64_t it = A; it != 0; it &= it - 1) {
+                const int t = (int)__builtin_ctzll(it);
+                const uint64_t kt = readlane64(key, t);
+                int r = 0;
+                uint64_t eq = 0;
+#pragma unroll
+                for (int s = 0; s < S; ++s) {
+                    r += __popcll(ballot(w[s] < kt));
+                    eq |= ballot(w[s] == kt);
                 }
-                lb = lo;
-                take = !(lb < wsize && Wk[lb] == key);
+                if (eq != 0) {
+                    dupm |= 1ull << t;  // already in W: a forgotten node scored again
+                } else {
+                    if (lane == t) posW = r;
+#pragma unroll
+                    for (int s = 0; s < S; ++s) sh[s] += kt < w[s] ? 1u : 0u;
+                    rankA += kt < key ? 1 : 0;
+                }
             }
-            const uint64_t m = ballot(take);
-            if (take) {
-                const int p = m_adm + below(m);
-                adm[p] = key;
-                adm_lb[p] = lb;
+            A &= ~dupm;
+            const int m_adm = __popcll(A);
+            if (m_adm == 0) continue;
+            n_adm += m_adm;
+            const bool mine = ((A >> lane) & 1ull) != 0;
+            const int pos = posW + rankA;
+            // W entry i moves to i + (admitted keys below it); an admitted key
+            // to (W entries below it) + (admitted keys below it).  All of W is
+            // in registers, so the scatter can overwrite the LDS copy.
+            wsync();
+#pragma unroll
+            for (int s = 0; s < S; ++s) {
+                const int i = s * kWave + lane;
+                const int p = i + (int)sh[s];
+                if (i < wsize && p < efe) {
+                    mk[p] = w[s];
+                    mf[p] = (uint8_t)((wfl >> s) & 1u);
+                }
             }
-            m_adm += __popcll(m);
+            if (mine && pos < efe) {
+                mk[pos] = key;
+                mf[pos] = 0;
+            }
+            const int pm = uni(wave_min_i32(mine ? pos : INT_MAX));
+            first = min(first, pm);
+            wsize = min(efe, wsize + m_adm);
+            wsync();
         }
-        m_adm = uni(m_adm);
-        if (m_adm == 0) continue;
-        wsync();
-        n_adm += m_adm;
-        // merge: admitted key j lands at rank(j among admitted) + lb(j);
-        // W entry i moves to i + (admitted keys below it)
-        int pmin = INT_MAX;
-        for (int j = lane; j < m_adm; j += kWave) {
-            const uint64_t key = adm[j];
-            int r = 0;
-            for (int t = 0; t < m_adm; ++t) r += adm[t] < key ? 1 : 0;
-            const int pos = r + adm_lb[j];
-            if (pos < efe) {
-                Wn[pos] = key;
-                Wg[pos] = 0;
-            }
-            pmin = min(pmin, pos);
-        }
-        for (int i = lane; i < wsize; i += kWave) {
-            const uint64_t wk = Wk[i];
-            int r = 0;
-            for (int t = 0; t < m_adm; ++t) r += adm[t] < wk ? 1 : 0;
-            const int pos = i + r;
-            if (pos < efe) {
-                Wn[pos] = wk;
-                Wg[pos] = Wf[i];
-            }
-        }
-        pmin = uni(wave_min_i32(pmin));
-        first = min(first, pmin);
-        wsize = min(efe, wsize + m_adm);
-        uint64_t* tk = Wk;
-        Wk = Wn;
-        Wn = tk;
-        uint8_t* tf = Wf;
-        Wf = Wg;
-        Wg = tf;
-        wsync();
     }
 
     // ---- outputs ----
     const int cnt = min(nc, wsize);
     if (a.mode == 0) {
-        for (int t = lane; t < cnt; t += kWave) {
-            const uint64_t key = Wk[t];
-            a.out_id[q * a.out_stride + t] = (uint32_t)key;
-            a.out_D[q * a.out_stride + t] = (uint32_t)(key >> 32);
+        for (int i = lane; i < cnt; i += kWave) {
+            const uint64_t key = mk[i];
+            a.out_id[q * a.out_stride + i] = (uint32_t)key;
+            a.out_D[q * a.out_stride + i] = (uint32_t)(key >> 32);
         }
         if (lane == 0) a.out_cnt[q] = cnt;
     } else {
-        for (int t = lane; t < a.out_stride; t += kWave) {
-            uint32_t id = kNone, db = 0x7F800000u;
-            if (t < cnt) {
-                const uint64_t key = Wk[t];
-                id = (uint32_t)key;
-                db = (uint32_t)(key >> 32);
-            }
-            a.out_id[q * a.out_stride + t] = id;
-            a.out_D[q * a.out_stride + t] = db;
+        for (int i = lane; i < a.out_stride; i += kWave) {
+            const bool v = i < cnt;
+            const uint64_t key = v ? mk[i] : ~0ull;
+            a.out_id[q * a.out_stride + i] = v ? (uint32_t)key : kNone;
+            a.out_D[q * a.out_stride + i] = v ? (uint32_t)(key >> 32) : 0x7F800000u;
         }
     }
     if (a.taps.counts && lane == 0) {
@@ -550,7 +561,7 @@ __device__ __forceinline__ void search_query(const SearchArgs& a, const int64_t 
     }
 }
 
-template <bool F32, int CPL, int U>
+template <bool F32, int CPL, int U, int S>
 __global__ __launch_bounds__(256) void k_search(SearchArgs a) {
     extern __shared__ __align__(16) unsigned char smem[];
     const int lane = lane_id();
@@ -560,16 +571,12 @@ __global__ __launch_bounds__(256) void k_search(SearchArgs a) {
     const int st_cap = max(ix.s0, ix.s1) <= 64 ? 64 : ((max(ix.s0, ix.s1) + 63) / 64) * 64;
 
     unsigned char* base = smem + (size_t)wave * a.wave_lds;
-    uint64_t* Wk0 = reinterpret_cast<uint64_t*>(base);
-    uint64_t* Wk1 = Wk0 + ef_cap;
-    uint8_t* Wf0 = reinterpret_cast<uint8_t*>(Wk1 + ef_cap);
-    uint8_t* Wf1 = Wf0 + ef_cap;
-    size_t off = ((size_t)2 * ef_cap * 8 + 2 * (size_t)ef_cap + 7) & ~(size_t)7;
+    uint64_t* mk = reinterpret_cast<uint64_t*>(base);
+    uint8_t* mf = reinterpret_cast<uint8_t*>(mk + ef_cap);
+    const size_t off = ((size_t)ef_cap * 9 + 7) & ~(size_t)7;
     uint32_t* st_id = reinterpret_cast<uint32_t*>(base + off);
     uint64_t* st_key = reinterpret_cast<uint64_t*>(base + off + (size_t)st_cap * 4);
-    uint64_t* adm = st_key + st_cap;
-    int32_t* adm_lb = reinterpret_cast<int32_t*>(adm + st_cap);
-    uint64_t* visb = reinterpret_cast<uint64_t*>(adm_lb + st_cap);
+    uint64_t* visb = st_key + st_cap;
     float* qf = reinterpret_cast<float*>(visb + ((size_t)1 << a.vb));
     uint8_t* qc = reinterpret_cast<uint8_t*>(qf + ix.xs);
 
@@ -620,8 +627,8 @@ __global__ __launch_bounds__(256) void k_search(SearchArgs a) {
                     }
                 }
             } else {
-                search_query<F32, CPL, U>(a, q, efe, nc, lane, g, vis, Wk0, Wk1, Wf0, Wf1, st_id,
-                                          st_key, adm, adm_lb, visb, qf, qc);
+                search_query<F32, CPL, U, S>(a, q, efe, nc, lane, g, vis, mk, mf, st_id, st_key,
+                                             visb, qf, qc);
             }
         }
         wsync();
@@ -1062,11 +1069,12 @@ extern "C" size_t aqr_search_workspace_size(void) { return 256; }
 
 namespace {
 
-template <bool F32, int CPL>
-hipError_t launch_search_cpl(dev::SearchArgs& a, int blocks, int wpb, size_t lds, int ncu,
-                             hipStream_t s) {
-    constexpr int U = CPL >= 8 ? 1 : 8 / CPL / (F32 ? 2 : 1) > 0 ? 8 / CPL / (F32 ? 2 : 1) : 1;
-    auto kern = dev::k_search<F32, CPL, U>;
+template <bool F32, int CPL, int S>
+hipError_t launch_search_s(dev::SearchArgs& a, int blocks, int wpb, size_t lds, int ncu,
+                           hipStream_t s) {
+    // 16-byte loads in flight per lane in the distance phase: 4 for code rows, 2 for FP32 rows
+    constexpr int U = CPL >= 4 ? 1 : 4 / CPL / (F32 ? 2 : 1) > 0 ? 4 / CPL / (F32 ? 2 : 1) : 1;
+    auto kern = dev::k_search<F32, CPL, U, S>;
     hipError_t e = hipFuncSetAttribute((const void*)kern,
                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e != hipSuccess) return e;
@@ -1082,10 +1090,26 @@ hipError_t launch_search_cpl(dev::SearchArgs& a, int blocks, int wpb, size_t lds
     return hipGetLastError();
 }
 
+template <bool F32, int CPL>
+hipError_t launch_search_cpl(dev::SearchArgs& a, int blocks, int wpb, size_t lds, int ncu,
+                             hipStream_t s) {
+    switch (a.ef_cap / 64) {
+        case 1: return launch_search_s<F32, CPL, 1>(a, blocks, wpb, lds, ncu, s);
+        case 2: return launch_search_s<F32, CPL, 2>(a, blocks, wpb, lds, ncu, s);
+        case 3:
+        case 4: return launch_search_s<F32, CPL, 4>(a, blocks, wpb, lds, ncu, s);
+        case 5:
+        case 6:
+        case 7:
+        case 8: return launch_search_s<F32, CPL, 8>(a, blocks, wpb, lds, ncu, s);
+        default: return launch_search_s<F32, CPL, 16>(a, blocks, wpb, lds, ncu, s);
+    }
+}
+
 template <bool F32>
 hipError_t launch_search(dev::SearchArgs& a, int cpl, int blocks, int wpb, size_t lds, int ncu,
                          hipStream_t s) {
-    if (F32) {
+    if constexpr (F32) {
         switch (cpl) {
             case 1: return launch_search_cpl<F32, 1>(a, blocks, wpb, lds, ncu, s);
             case 2: return launch_search_cpl<F32, 2>(a, blocks, wpb, lds, ncu, s);
@@ -1093,11 +1117,12 @@ hipError_t launch_search(dev::SearchArgs& a, int cpl, int blocks, int wpb, size_
             case 8: return launch_search_cpl<F32, 8>(a, blocks, wpb, lds, ncu, s);
             default: return launch_search_cpl<F32, 16>(a, blocks, wpb, lds, ncu, s);
         }
-    }
-    switch (cpl) {
-        case 1: return launch_search_cpl<F32, 1>(a, blocks, wpb, lds, ncu, s);
-        case 2: return launch_search_cpl<F32, 2>(a, blocks, wpb, lds, ncu, s);
-        default: return launch_search_cpl<F32, 4>(a, blocks, wpb, lds, ncu, s);
+    } else {
+        switch (cpl) {
+            case 1: return launch_search_cpl<F32, 1>(a, blocks, wpb, lds, ncu, s);
+            case 2: return launch_search_cpl<F32, 2>(a, blocks, wpb, lds, ncu, s);
+            default: return launch_search_cpl<F32, 4>(a, blocks, wpb, lds, ncu, s);
+        }
     }
 }
 
@@ -1130,14 +1155,18 @@ aqr_status run_search(const aqr_index* ix, const float* Q, int64_t nq, const int
     if (taps && (taps->expanded || taps->evaluated) && taps->cap < 1)
         return fail(AQR_ERR_INVALID_ARG, std::string(who) + ": taps->cap must be >= 1");
     const Idx& v = ix->v;
-    int vb = sp->visited_log2 > 0 ? sp->visited_log2 : 10;
+    int vb = sp->visited_log2 > 0 ? sp->visited_log2 : 9;
     if (vb < 4 || vb > 14) return fail(AQR_ERR_INVALID_ARG, std::string(who) + ": visited_log2 out of [4, 14]");
     const int idb = std::max(v.idbits, vb + 1);
     if (idb - vb > 15) vb = idb - 15;  // keep the stored remainder within 15 bits
     const int wpb = sp->waves_per_block > 0 ? sp->waves_per_block : 4;
     if (wpb != 1 && wpb != 2 && wpb != 4)
         return fail(AQR_ERR_INVALID_ARG, std::string(who) + ": waves_per_block must be 1, 2 or 4");
-    dev::SearchLds sl{(sp->ef_max + 63) / 64 * 64,
+    if (v.s0 > 256)
+        return fail(AQR_ERR_INVALID_ARG, std::string(who) + ": layer-0 rows above 256 entries are not supported");
+    int slots = 1;  // result-list slots per lane: a power of two >= ef_max / 64
+    while (slots * 64 < sp->ef_max) slots <<= 1;
+    dev::SearchLds sl{slots * 64,
                       std::max(v.s0, v.s1) <= 64 ? 64 : (std::max(v.s0, v.s1) + 63) / 64 * 64, vb,
                       v.xs, v.dp};
     const size_t wl = sl.bytes();
