@@ -293,6 +293,48 @@ aqr_status aqr_search_fp32(const aqr_index* ix, const float* Q, int64_t nq, cons
                            float* out_dist, void* ws, size_t ws_bytes, const aqr_taps* taps,
                            void* stream);
 
+/* ------------------------------------------------------------------------ */
+/* batch plans: one captured launch sequence for uneven batches (device)     */
+/* ------------------------------------------------------------------------ */
+
+typedef struct aqr_batch_buffers {
+    const float* Q;       /* device [nq_max][d] queries */
+    int64_t nq_max;
+    const int32_t* k;     /* device [nq_max] per-query k */
+    const int32_t* ef;    /* device [nq_max] per-query ef */
+    uint32_t* cand_id;    /* device [nq_max][sp->out_stride] Stage-1 ids */
+    uint32_t* cand_D;     /* device [nq_max][sp->out_stride] Stage-1 distances */
+    int32_t* cand_cnt;    /* device [nq_max] */
+    int32_t* out_id;      /* device [nq_max][rp->out_stride] */
+    float* out_dist;      /* device [nq_max][rp->out_stride] */
+    uint8_t* out_kind;    /* device [nq_max][rp->out_stride], nullable */
+    int32_t* order;       /* device [nq_max], nullable: work order scratch; when given,
+                             queries run longest first (ef_eff descending) */
+    void* ws;             /* device workspace of aqr_search_workspace_size() bytes */
+    size_t ws_bytes;
+    uint32_t* counts;     /* device [nq_max][8], nullable: per-query counters (aqr_taps) */
+} aqr_batch_buffers;
+
+typedef struct aqr_plan aqr_plan;
+
+/*
+ * A plan binds an index, search and re-rank parameters and caller-owned
+ * device buffers (none of which may move while the plan lives).  Launching
+ * it runs, on the given stream: the longest-first work order (when
+ * buffers->order is given), aqr_search over the batch with per-query k and
+ * ef (N_c derived with sp->m_ef), and aqr_rerank.  With use_graph != 0 the
+ * first launch for a given nq runs the sequence once on the given stream and
+ * records it into a hipGraph on a private stream of the plan; later launches
+ * with the same nq replay the graph on the given stream (one graph launch).
+ * Results are identical either way.  sp->order must be NULL (the plan owns
+ * the order).  A plan is not thread-safe; use one plan per stream.
+ */
+aqr_status aqr_plan_create(const aqr_index* ix, const aqr_sparams* sp, const aqr_rparams* rp,
+                           const aqr_batch_buffers* buffers, int32_t use_graph, aqr_plan** plan);
+/* Run the plan on the first nq queries of the buffers (0 <= nq <= nq_max). */
+aqr_status aqr_plan_launch(aqr_plan* plan, int64_t nq, void* stream);
+void aqr_plan_free(aqr_plan* plan);
+
 #ifdef __cplusplus
 }
 #endif

@@ -68,6 +68,14 @@ class RTaps(C.Structure):
                 ("nrr", C.c_void_p)]
 
 
+class BatchBuffers(C.Structure):
+    _fields_ = [("Q", C.c_void_p), ("nq_max", C.c_int64), ("k", C.c_void_p), ("ef", C.c_void_p),
+                ("cand_id", C.c_void_p), ("cand_D", C.c_void_p), ("cand_cnt", C.c_void_p),
+                ("out_id", C.c_void_p), ("out_dist", C.c_void_p), ("out_kind", C.c_void_p),
+                ("order", C.c_void_p), ("ws", C.c_void_p), ("ws_bytes", C.c_size_t),
+                ("counts", C.c_void_p)]
+
+
 _lib = None
 
 _vp = C.c_void_p
@@ -100,6 +108,10 @@ _SIGS = [
                           _vp, C.POINTER(RTaps), _vp]),
     ("aqr_search_fp32", _i32, [_vp, _vp, _i64, _vp, _vp, C.POINTER(SParams), _vp, _vp, _vp,
                                _sz, C.POINTER(Taps), _vp]),
+    ("aqr_plan_create", _i32, [_vp, C.POINTER(SParams), C.POINTER(RParams),
+                               C.POINTER(BatchBuffers), _i32, C.POINTER(_vp)]),
+    ("aqr_plan_launch", _i32, [_vp, _i64, _vp]),
+    ("aqr_plan_free", None, [_vp]),
 ]
 
 SYMBOLS = [s[0] for s in _SIGS]
@@ -179,6 +191,14 @@ class Quantizer(_Handle):
 
 class Graph(_Handle):
     _free = "aqr_graph_free"
+
+
+class Plan(_Handle):
+    _free = "aqr_plan_free"
+
+    def __init__(self, ptr, keep):
+        super().__init__(ptr)
+        self.keep = keep  # device buffers and parameter structs the plan points to
 
 
 class Index(_Handle):
@@ -400,3 +420,79 @@ class QueryPlan:
         aqr_rerank(self.ix, Q, cid, cc, k, self.out_id[:n], self.out_dist[:n],
                    self.out_kind[:n], **self.rr)
         return self.out_id[:n], self.out_dist[:n]
+
+
+def aqr_plan_create(ix, sparams, rparams, buffers, use_graph=True):
+    """sparams/rparams: dicts of SParams/RParams fields; buffers: dict of torch
+    tensors (Q, k, ef, cand_id, cand_D, cand_cnt, out_id, out_dist, out_kind,
+    order, ws, counts; optional entries may be None)."""
+    sp = SParams(**sparams)
+    rp = RParams(**rparams)
+    t = buffers
+    bb = BatchBuffers(Q=_dev_ptr(t["Q"]), nq_max=t["Q"].shape[0], k=_dev_ptr(t["k"]),
+                      ef=_dev_ptr(t["ef"]), cand_id=_dev_ptr(t["cand_id"]),
+                      cand_D=_dev_ptr(t["cand_D"]), cand_cnt=_dev_ptr(t["cand_cnt"]),
+                      out_id=_dev_ptr(t["out_id"]), out_dist=_dev_ptr(t["out_dist"]),
+                      out_kind=_dev_ptr(t.get("out_kind")), order=_dev_ptr(t.get("order")),
+                      ws=_dev_ptr(t["ws"]), ws_bytes=t["ws"].numel(),
+                      counts=_dev_ptr(t.get("counts")))
+    h = C.c_void_p()
+    _check(lib().aqr_plan_create(ix.ptr, C.byref(sp), C.byref(rp), C.byref(bb),
+                                 1 if use_graph else 0, C.byref(h)))
+    return Plan(h.value, (t, sp, rp, bb, ix))
+
+
+def aqr_plan_launch(plan, nq, stream=None):
+    _check(lib().aqr_plan_launch(plan.ptr, int(nq), _stream_ptr(stream)))
+
+
+class BatchPlan:
+    """Device buffers for uneven batches (per-query k and ef) and a plan over
+    them: longest-first order, Stage 1 and Stages 2-3, optionally replayed
+    as one captured graph.  Copy queries and parameters in with load(), then
+    launch()."""
+
+    def __init__(self, ix, nq_max, k_max, ef_max, m_ef=3, n_rerank=28, tau_gap=0.010,
+                 tau_ratio=1.008, eps=1e-6, longest_first=True, use_graph=True, counts=False,
+                 tuning=None):
+        import torch
+        tuning = dict(tuning or {})
+        dev = ix.arena.device
+        self.ix = ix
+        self.nq_max = nq_max
+        self.k_max = k_max
+        self.ef_max = max(ef_max, k_max)
+        self.nc_max = min(self.ef_max, max(k_max, self.ef_max // m_ef))
+        i32 = torch.int32
+        self.bufs = dict(
+            Q=torch.zeros((nq_max, ix.d), dtype=torch.float32, device=dev),
+            k=torch.ones(nq_max, dtype=i32, device=dev),
+            ef=torch.ones(nq_max, dtype=i32, device=dev),
+            cand_id=torch.zeros((nq_max, self.nc_max), dtype=i32, device=dev),
+            cand_D=torch.zeros((nq_max, self.nc_max), dtype=i32, device=dev),
+            cand_cnt=torch.zeros(nq_max, dtype=i32, device=dev),
+            out_id=torch.zeros((nq_max, k_max), dtype=i32, device=dev),
+            out_dist=torch.zeros((nq_max, k_max), dtype=torch.float32, device=dev),
+            out_kind=torch.zeros((nq_max, k_max), dtype=torch.uint8, device=dev),
+            order=torch.zeros(nq_max, dtype=i32, device=dev) if longest_first else None,
+            ws=torch.zeros(aqr_search_workspace_size(), dtype=torch.uint8, device=dev),
+            counts=torch.zeros((nq_max, 8), dtype=i32, device=dev) if counts else None)
+        sp = dict(ef_max=self.ef_max, out_stride=self.nc_max, m_ef=m_ef,
+                  waves_per_block=tuning.get("waves_per_block", 0),
+                  blocks=tuning.get("blocks", 0), visited_log2=tuning.get("visited_log2", 0),
+                  order=None)
+        rp = dict(n_rerank=n_rerank, out_stride=k_max, tau_gap=tau_gap, tau_ratio=tau_ratio,
+                  eps=eps, force_et=-1, waves_per_block=tuning.get("rerank_waves_per_block", 0),
+                  reserved=0)
+        self.plan = aqr_plan_create(ix, sp, rp, self.bufs, use_graph)
+
+    def load(self, Q, k, ef):
+        n = Q.shape[0]
+        self.bufs["Q"][:n].copy_(Q)
+        self.bufs["k"][:n].copy_(k)
+        self.bufs["ef"][:n].copy_(ef)
+        return n
+
+    def launch(self, nq, stream=None):
+        aqr_plan_launch(self.plan, nq, stream)
+        return self.bufs["out_id"][:nq], self.bufs["out_dist"][:nq]

@@ -32,6 +32,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <atomic>
 #include <climits>
 #include <cmath>
 #include <cstring>
@@ -639,6 +640,38 @@ __global__ void k_reset(int32_t* counter) {
     if (threadIdx.x == 0 && blockIdx.x == 0) *counter = 0;
 }
 
+constexpr int kOrderMaxEf = 1024;
+
+// Work order of a batch, longest first: queries sorted by ef_eff = max(ef, k)
+// descending (a counting sort over ef_eff clamped to [0, 1024], one block).
+// The order inside one ef_eff value follows the slot claims; no result
+// depends on it.
+__global__ __launch_bounds__(1024) void k_order(const int32_t* kq, const int32_t* efq,
+                                                 int64_t nq, int32_t* order) {
+    __shared__ int32_t bin[kOrderMaxEf + 1];
+    for (int i = threadIdx.x; i <= kOrderMaxEf; i += blockDim.x) bin[i] = 0;
+    __syncthreads();
+    for (int64_t q = threadIdx.x; q < nq; q += blockDim.x) {
+        const int e = min(max(max(efq[q], kq[q]), 0), kOrderMaxEf);
+        atomicAdd(&bin[kOrderMaxEf - e], 1);
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        int run = 0;
+        for (int i = 0; i <= kOrderMaxEf; ++i) {
+            const int c = bin[i];
+            bin[i] = run;
+            run += c;
+        }
+    }
+    __syncthreads();
+    for (int64_t q = threadIdx.x; q < nq; q += blockDim.x) {
+        const int e = min(max(max(efq[q], kq[q]), 0), kOrderMaxEf);
+        const int slot = atomicAdd(&bin[kOrderMaxEf - e], 1);
+        order[slot] = (int32_t)q;
+    }
+}
+
 __global__ void k_encode(Idx ix, const float* Q, int64_t nq, uint8_t* out) {
     const int64_t q = blockIdx.x;
     if (q >= nq) return;
@@ -1075,9 +1108,15 @@ hipError_t launch_search_s(dev::SearchArgs& a, int blocks, int wpb, size_t lds, 
     // 16-byte loads in flight per lane in the distance phase: 4 for code rows, 2 for FP32 rows
     constexpr int U = CPL >= 4 ? 1 : 4 / CPL / (F32 ? 2 : 1) > 0 ? 4 / CPL / (F32 ? 2 : 1) : 1;
     auto kern = dev::k_search<F32, CPL, U, S>;
-    hipError_t e = hipFuncSetAttribute((const void*)kern,
-                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-    if (e != hipSuccess) return e;
+    // the dynamic-LDS limit is raised once per size, outside any stream capture
+    static std::atomic<int> lds_set{0};
+    hipError_t e = hipSuccess;
+    if ((int)lds > lds_set.load()) {
+        e = hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                (int)lds);
+        if (e != hipSuccess) return e;
+        lds_set.store((int)lds);
+    }
     if (blocks <= 0) {
         int per_cu = 0;
         e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, wpb * dev::kWave, lds);
@@ -1260,9 +1299,13 @@ namespace {
 template <int C8, int CF>
 hipError_t launch_rerank_cf(dev::RerankArgs& a, int wpb, size_t lds, hipStream_t s) {
     auto kern = dev::k_rerank<C8, CF>;
-    hipError_t e = hipFuncSetAttribute((const void*)kern,
-                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-    if (e != hipSuccess) return e;
+    static std::atomic<int> lds_set{0};
+    if ((int)lds > lds_set.load()) {
+        hipError_t e = hipFuncSetAttribute((const void*)kern,
+                                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+        if (e != hipSuccess) return e;
+        lds_set.store((int)lds);
+    }
     const int64_t blocks = (a.nq + wpb - 1) / wpb;
     hipLaunchKernelGGL(kern, dim3((unsigned)blocks), dim3(wpb * dev::kWave), lds, s, a);
     return hipGetLastError();
@@ -1353,4 +1396,135 @@ extern "C" aqr_status aqr_rerank(const aqr_index* ix, const float* Q, int64_t nq
     } catch (...) {
         return fail(AQR_ERR_STATE, "aqr_rerank: unexpected failure");
     }
+}
+
+// ===========================================================================
+// batch plans: order + Stage 1 + Stages 2-3 as one captured graph
+// ===========================================================================
+
+struct aqr_plan {
+    const aqr_index* ix = nullptr;
+    aqr_sparams sp{};
+    aqr_rparams rp{};
+    aqr_batch_buffers b{};
+    int32_t use_graph = 0;
+    hipGraphExec_t exec = nullptr;
+    int64_t graph_nq = -1;
+    hipStream_t capture_stream = nullptr;  // private, default priority; only records
+};
+
+namespace {
+
+aqr_status plan_enqueue(aqr_plan* p, int64_t nq, hipStream_t s) {
+    const aqr_batch_buffers& b = p->b;
+    aqr_sparams sp = p->sp;
+    if (b.order) {
+        hipLaunchKernelGGL(dev::k_order, dim3(1), dim3(1024), 0, s, b.k, b.ef, nq, b.order);
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return hip_fail(e, "aqr_plan_launch: order");
+        sp.order = b.order;
+    }
+    aqr_taps taps{};
+    taps.counts = b.counts;
+    aqr_status st = aqr_search(p->ix, b.Q, nq, b.k, b.ef, nullptr, &sp, b.cand_id, b.cand_D,
+                               b.cand_cnt, b.ws, b.ws_bytes, b.counts ? &taps : nullptr, s);
+    if (st != AQR_OK) return st;
+    return aqr_rerank(p->ix, b.Q, nq, b.cand_id, b.cand_cnt, sp.out_stride, b.k, &p->rp,
+                      b.out_id, b.out_dist, b.out_kind, nullptr, s);
+}
+
+}  // namespace
+
+extern "C" aqr_status aqr_plan_create(const aqr_index* ix, const aqr_sparams* sp,
+                                      const aqr_rparams* rp, const aqr_batch_buffers* b,
+                                      int32_t use_graph, aqr_plan** out) {
+    try {
+        clear_error();
+        if (!ix || !sp || !rp || !b || !out)
+            return fail(AQR_ERR_INVALID_ARG, "aqr_plan_create: null pointer");
+        if (!b->Q || !b->k || !b->ef || !b->cand_id || !b->cand_D || !b->cand_cnt ||
+            !b->out_id || !b->out_dist || !b->ws)
+            return fail(AQR_ERR_INVALID_ARG, "aqr_plan_create: null buffer");
+        if (b->nq_max < 1 || b->nq_max > (int64_t)INT32_MAX)
+            return fail(AQR_ERR_INVALID_ARG, "aqr_plan_create: nq_max out of range");
+        if (sp->order)
+            return fail(AQR_ERR_INVALID_ARG,
+                        "aqr_plan_create: the work order comes from buffers->order");
+        if (sp->ef_max > dev::kOrderMaxEf)
+            return fail(AQR_ERR_INVALID_ARG, "aqr_plan_create: ef_max above 1024");
+        aqr_plan* p = new aqr_plan();
+        p->ix = ix;
+        p->sp = *sp;
+        p->rp = *rp;
+        p->b = *b;
+        p->use_graph = use_graph;
+        *out = p;
+        return AQR_OK;
+    } catch (...) {
+        return fail(AQR_ERR_OOM, "aqr_plan_create: out of host memory");
+    }
+}
+
+extern "C" aqr_status aqr_plan_launch(aqr_plan* p, int64_t nq, void* stream) {
+    try {
+        clear_error();
+        if (!p) return fail(AQR_ERR_INVALID_ARG, "aqr_plan_launch: null plan");
+        if (nq < 0 || nq > p->b.nq_max)
+            return fail(AQR_ERR_INVALID_ARG, "aqr_plan_launch: nq outside [0, nq_max]");
+        if (nq == 0) return AQR_OK;
+        hipStream_t s = (hipStream_t)stream;
+        if (!p->use_graph) return plan_enqueue(p, nq, s);
+        if (!p->exec || p->graph_nq != nq) {
+            if (p->exec) {
+                (void)hipGraphExecDestroy(p->exec);
+                p->exec = nullptr;
+            }
+            // one eager pass on the caller's stream sets every launch
+            // attribute outside the capture and produces this batch's results
+            aqr_status st = plan_enqueue(p, nq, s);
+            if (st != AQR_OK) return st;
+            // the sequence is recorded on a private stream (the caller's stream
+            // may be the legacy default stream, which cannot be captured) and
+            // the graph is launched on the caller's stream from then on
+            hipError_t e = hipSuccess;
+            if (!p->capture_stream) {
+                e = hipStreamCreateWithFlags(&p->capture_stream, hipStreamNonBlocking);
+                if (e != hipSuccess) {
+                    p->capture_stream = nullptr;
+                    return hip_fail(e, "aqr_plan_launch: capture stream");
+                }
+            }
+            hipStream_t cs = p->capture_stream;
+            e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
+            if (e != hipSuccess) return hip_fail(e, "aqr_plan_launch: begin capture");
+            st = plan_enqueue(p, nq, cs);
+            hipGraph_t graph = nullptr;
+            e = hipStreamEndCapture(cs, &graph);
+            if (st != AQR_OK) {
+                if (graph) (void)hipGraphDestroy(graph);
+                return st;
+            }
+            if (e != hipSuccess) return hip_fail(e, "aqr_plan_launch: end capture");
+            e = hipGraphInstantiate(&p->exec, graph, nullptr, nullptr, 0);
+            (void)hipGraphDestroy(graph);
+            if (e != hipSuccess) {
+                p->exec = nullptr;
+                return hip_fail(e, "aqr_plan_launch: instantiate");
+            }
+            p->graph_nq = nq;
+            return AQR_OK;
+        }
+        hipError_t e = hipGraphLaunch(p->exec, s);
+        if (e != hipSuccess) return hip_fail(e, "aqr_plan_launch: graph launch");
+        return AQR_OK;
+    } catch (...) {
+        return fail(AQR_ERR_STATE, "aqr_plan_launch: unexpected failure");
+    }
+}
+
+extern "C" void aqr_plan_free(aqr_plan* p) {
+    if (!p) return;
+    if (p->exec) (void)hipGraphExecDestroy(p->exec);
+    if (p->capture_stream) (void)hipStreamDestroy(p->capture_stream);
+    delete p;
 }

@@ -1,0 +1,74 @@
+"""Autotuner of the batch launch: waves per block, visited-cache size and
+re-rank waves per block, chosen by timing a sample batch through libaqr.
+
+The search result does not depend on these choices (only the speed does);
+the tests check that.  Results are cached in a JSON file keyed by the index
+shape, ef_max, k_max and the device name.
+"""
+import itertools
+import json
+import os
+import time
+
+from . import aqr
+
+SEARCH_WPB = (1, 2, 4)
+VISITED_LOG2 = (8, 9, 10)
+RERANK_WPB = (2, 4)
+
+
+def _key(ix, ef_max, k_max, device_name):
+    return f"n{ix.arena.numel()}-d{ix.d}-ef{ef_max}-k{k_max}-{device_name}"
+
+
+def time_config(ix, Q, k, ef, k_max, ef_max, tuning, reps=3):
+    import torch
+    plan = aqr.BatchPlan(ix, Q.shape[0], k_max, ef_max, use_graph=False, tuning=tuning)
+    n = plan.load(Q, k, ef)
+    plan.launch(n)
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    for _ in range(reps):
+        plan.launch(n)
+    torch.cuda.synchronize()
+    return (time.perf_counter() - t) * 1e3 / reps
+
+
+def autotune(ix, Q, k, ef, k_max, ef_max, cache_path=None, reps=3, log=None):
+    """Returns (best tuning dict, table of (tuning, ms))."""
+    import torch
+    name = torch.cuda.get_device_name()
+    key = _key(ix, ef_max, k_max, name)
+    if cache_path and os.path.exists(cache_path):
+        try:
+            cached = json.load(open(cache_path)).get(key)
+            if cached:
+                return cached["best"], cached["table"]
+        except ValueError:
+            pass
+    table = []
+    for wpb, vb, rwpb in itertools.product(SEARCH_WPB, VISITED_LOG2, RERANK_WPB):
+        tuning = dict(waves_per_block=wpb, visited_log2=vb, rerank_waves_per_block=rwpb)
+        try:
+            ms = time_config(ix, Q, k, ef, k_max, ef_max, tuning, reps)
+        except aqr.AqrError as e:
+            if log:
+                log(f"tune {tuning}: skipped ({e})")
+            continue
+        table.append((tuning, round(ms, 4)))
+        if log:
+            log(f"tune {tuning}: {ms:.3f} ms")
+    if not table:
+        raise RuntimeError("autotune: no configuration could run")
+    best = min(table, key=lambda t: t[1])[0]
+    if cache_path:
+        data = {}
+        if os.path.exists(cache_path):
+            try:
+                data = json.load(open(cache_path))
+            except ValueError:
+                data = {}
+        data[key] = {"best": best, "table": table}
+        os.makedirs(os.path.dirname(os.path.abspath(cache_path)), exist_ok=True)
+        json.dump(data, open(cache_path, "w"), indent=1)
+    return best, table

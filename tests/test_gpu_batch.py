@@ -1,0 +1,142 @@
+"""Uneven batches in one launch: per-query k and ef, longest-first order,
+graph capture and replay, and tuning choices.
+
+Each query's result must be the same alone, in the mixed batch, under graph
+replay and under every tuning choice (integers bit-exact; the FP32 stages run
+the same arithmetic per query, so their outputs are bit-identical too), and
+the batch must match the oracle (Stage 1 bit-exact, Stages 2-3 by the parity
+protocol of test_gpu_parity).
+"""
+import numpy as np
+import pytest
+
+from paper_2602_21600_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def small(orc):
+    from test_gpu_parity import make_index
+    X = W.base("small")
+    ix = make_index(orc, X, 16, 100)
+    rng = np.random.default_rng(11)
+    Q = np.vstack([W.queries("small"), W.queries("small", 357)[100:]])
+    nq = Q.shape[0]
+    ix["Q"] = Q
+    ix["k"] = rng.choice(np.array([1, 10, 100], np.int32), nq)
+    ix["ef"] = rng.choice(np.array([16, 32, 64, 128, 256, 512], np.int32), nq)
+    return ix
+
+
+def run_plan(index, Q, k, ef, use_graph=False, longest_first=True, tuning=None, launches=1,
+             between=None, **plan_kw):
+    import torch
+    from paper_2602_21600_amd import aqr
+    plan = aqr.BatchPlan(index["ix"], Q.shape[0], 100, 512, use_graph=use_graph,
+                         longest_first=longest_first, tuning=tuning, **plan_kw)
+    n = plan.load(torch.from_numpy(Q).cuda(), torch.from_numpy(k).cuda(),
+                  torch.from_numpy(ef).cuda())
+    outs = []
+    for i in range(launches):
+        if between is not None:
+            between(i)
+        plan.launch(n)
+        torch.cuda.synchronize()
+        b = plan.bufs
+        outs.append(dict(cand_id=b["cand_id"][:n].cpu().numpy().view(np.uint32).copy(),
+                         cand_cnt=b["cand_cnt"][:n].cpu().numpy().copy(),
+                         id=b["out_id"][:n].cpu().numpy().copy(),
+                         dist=b["out_dist"][:n].cpu().numpy().copy(),
+                         kind=b["out_kind"][:n].cpu().numpy().copy()))
+    return outs
+
+
+def same(a, b, nq):
+    np.testing.assert_array_equal(a["cand_cnt"], b["cand_cnt"])
+    for q in range(nq):
+        c = a["cand_cnt"][q]
+        np.testing.assert_array_equal(a["cand_id"][q, :c], b["cand_id"][q, :c], err_msg=f"q={q}")
+    np.testing.assert_array_equal(a["id"], b["id"])
+    np.testing.assert_array_equal(a["dist"].view(np.uint32), b["dist"].view(np.uint32))
+    np.testing.assert_array_equal(a["kind"], b["kind"])
+
+
+def test_batch_matches_oracle(orc, small):
+    from test_gpu_parity import oracle_stage1
+    Q, k, ef = small["Q"], small["k"], small["ef"]
+    inf = float("inf")
+    out = run_plan(small, Q, k, ef, tau_gap=inf, tau_ratio=inf)[0]
+    o, _ = oracle_stage1(orc, small, Q, k, ef)
+    np.testing.assert_array_equal(out["cand_cnt"], o["cand_cnt"])
+    for q in range(Q.shape[0]):
+        c = o["cand_cnt"][q]
+        np.testing.assert_array_equal(out["cand_id"][q, :c], o["cand_id"][q, :c])
+    # final lists: the oracle re-ranks the same candidates; distances within
+    # 1e-5 and ids equal up to ties inside that tolerance
+    ref = orc.rerank(small["X"], small["codes"], small["min"], small["scale"], Q,
+                     np.ascontiguousarray(out["cand_id"]), out["cand_cnt"], k, tau_gap=inf,
+                     tau_ratio=inf, k_stride=100)
+    for q in range(Q.shape[0]):
+        kq = int(k[q])
+        np.testing.assert_allclose(out["dist"][q, :kq], ref["dist"][q, :kq], rtol=1e-5)
+        assert np.all(out["id"][q, kq:] == -1)
+
+
+def test_alone_equals_batch_and_orders(orc, small):
+    Q, k, ef = small["Q"], small["k"], small["ef"]
+    nq = Q.shape[0]
+    batch = run_plan(small, Q, k, ef, longest_first=True)[0]
+    natural = run_plan(small, Q, k, ef, longest_first=False)[0]
+    same(batch, natural, nq)
+    for q in (0, 5, 77, 200, nq - 1):
+        one = run_plan(small, Q[q:q + 1], k[q:q + 1], ef[q:q + 1])[0]
+        c = one["cand_cnt"][0]
+        assert c == batch["cand_cnt"][q]
+        np.testing.assert_array_equal(one["cand_id"][0, :c], batch["cand_id"][q, :c])
+        np.testing.assert_array_equal(one["id"][0], batch["id"][q])
+        np.testing.assert_array_equal(one["dist"][0].view(np.uint32),
+                                      batch["dist"][q].view(np.uint32))
+
+
+def test_graph_replays_equal_eager(orc, small):
+    import torch
+    Q, k, ef = small["Q"], small["k"], small["ef"]
+    nq = Q.shape[0]
+    eager = run_plan(small, Q, k, ef)[0]
+    scratch = torch.zeros(1 << 20, device="cuda")
+
+    def between(i):
+        # the program's own eager work and a synchronisation between replays
+        scratch.add_(float(i + 1))
+        torch.cuda.synchronize()
+
+    outs = run_plan(small, Q, k, ef, use_graph=True, launches=4, between=between)
+    for o in outs:
+        same(o, eager, nq)
+
+
+@pytest.mark.parametrize("tuning", [
+    dict(waves_per_block=1, visited_log2=8, rerank_waves_per_block=2),
+    dict(waves_per_block=2, visited_log2=10, rerank_waves_per_block=4),
+    dict(waves_per_block=4, visited_log2=6, rerank_waves_per_block=1, blocks=5),
+])
+def test_tuning_does_not_change_results(orc, small, tuning):
+    Q, k, ef = small["Q"], small["k"], small["ef"]
+    base = run_plan(small, Q, k, ef)[0]
+    other = run_plan(small, Q, k, ef, tuning=tuning)[0]
+    same(base, other, Q.shape[0])
+
+
+def test_autotune_picks_a_valid_config(orc, small, tmp_path):
+    import torch
+    from paper_2602_21600_amd import tune
+    Q, k, ef = small["Q"], small["k"], small["ef"]
+    best, table = tune.autotune(small["ix"], torch.from_numpy(Q).cuda(),
+                                torch.from_numpy(k).cuda(), torch.from_numpy(ef).cuda(), 100, 512,
+                                cache_path=str(tmp_path / "tune.json"), reps=1)
+    assert len(table) >= 6
+    assert best in [t for t, _ in table]
+    again, _ = tune.autotune(small["ix"], None, None, None, 100, 512,
+                             cache_path=str(tmp_path / "tune.json"))
+    assert again == best
