@@ -335,6 +335,64 @@ aqr_status aqr_plan_create(const aqr_index* ix, const aqr_sparams* sp, const aqr
 aqr_status aqr_plan_launch(aqr_plan* plan, int64_t nq, void* stream);
 void aqr_plan_free(aqr_plan* plan);
 
+/* ------------------------------------------------------------------------ */
+/* serving: continuous admission into a resident persistent kernel           */
+/* ------------------------------------------------------------------------ */
+
+typedef struct aqr_server_params {
+    int32_t ring;         /* request slots (the admission limit) */
+    int32_t k_max;        /* largest k accepted (row length of a result) */
+    int32_t ef_max;       /* largest ef accepted (<= 512; sizes the LDS of every wave) */
+    int32_t m_ef;         /* ef multiplier of N_c */
+    int32_t n_rerank;     /* N_rerank */
+    float tau_gap, tau_ratio, eps;  /* early termination (Table 3 row "0.97+": 0.010, 1.008) */
+    int32_t waves_per_block;        /* 0 = 4 */
+    int32_t visited_log2;           /* 0 = default */
+    int32_t idle_ms;      /* the kernel exits after this long without unclaimed requests */
+    int32_t reserved;
+} aqr_server_params;
+
+typedef struct aqr_server aqr_server;
+
+size_t aqr_server_workspace_size(void);
+
+/*
+ * A server keeps the index resident and runs one persistent kernel on a
+ * private stream, sized to the device (every block resident).  Requests go
+ * into a ring in pinned host memory; each wave takes the next published
+ * request as soon as it is free, so requests that arrive while others run
+ * start on the next free wave.  One wave mirrors the host's publication
+ * counter into device memory; the kernel leaves after idle_ms without
+ * unclaimed requests or on aqr_server_stop, and submit/poll relaunch it when
+ * needed.  ws: caller-owned device workspace (aqr_server_workspace_size()
+ * bytes) for the claim counters.  Each request runs Stage 1 and Stages 2-3
+ * with the same code as aqr_search/aqr_rerank, so its result equals the
+ * batch result for the same query, k and ef.
+ */
+aqr_status aqr_server_create(const aqr_index* ix, const aqr_server_params* p, void* ws,
+                             size_t ws_bytes, aqr_server** server);
+/* Admit one request (host query of d floats); *ticket is an opaque handle
+ * for aqr_server_poll.  A slot stays taken until its result is collected:
+ * AQR_ERR_BUSY when all `ring` slots are taken; AQR_ERR_INVALID_ARG when k or
+ * ef exceed the server limits. */
+aqr_status aqr_server_submit(aqr_server* s, const float* q, int32_t k, int32_t ef,
+                             uint64_t* ticket);
+/* *done = 1 and the result row (k_max entries, padded with (-1, +inf)) is
+ * copied when the request is complete; the slot is then free again. */
+aqr_status aqr_server_poll(aqr_server* s, uint64_t ticket, int32_t* out_id, float* out_dist,
+                           int32_t* done);
+aqr_status aqr_server_stop(aqr_server* s);
+void aqr_server_destroy(aqr_server* s);
+/*
+ * Replay an arrival trace from the host: request i (query Q[i], k[i], ef[i])
+ * arrives at arrival_s[i] seconds after the start and is submitted then, or
+ * as soon as a slot frees up; latency_s[i] runs from its arrival to the poll
+ * that finds it complete.  out_id/out_dist (nullable): [n][k_max].
+ */
+aqr_status aqr_server_replay(aqr_server* s, int64_t n, const double* arrival_s, const float* Q,
+                             const int32_t* k, const int32_t* ef, int32_t* out_id,
+                             float* out_dist, double* latency_s, double* wall_s);
+
 #ifdef __cplusplus
 }
 #endif

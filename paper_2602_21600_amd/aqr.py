@@ -85,6 +85,13 @@ _u32 = C.c_uint32
 _sz = C.c_size_t
 
 # (name, restype, argtypes)
+class ServerParams(C.Structure):
+    _fields_ = [("ring", _i32), ("k_max", _i32), ("ef_max", _i32), ("m_ef", _i32),
+                ("n_rerank", _i32), ("tau_gap", C.c_float), ("tau_ratio", C.c_float),
+                ("eps", C.c_float), ("waves_per_block", _i32), ("visited_log2", _i32),
+                ("idle_ms", _i32), ("reserved", _i32)]
+
+
 _SIGS = [
     ("aqr_last_error", C.c_char_p, []),
     ("aqr_version", _i32, []),
@@ -112,6 +119,14 @@ _SIGS = [
                                C.POINTER(BatchBuffers), _i32, C.POINTER(_vp)]),
     ("aqr_plan_launch", _i32, [_vp, _i64, _vp]),
     ("aqr_plan_free", None, [_vp]),
+    ("aqr_server_workspace_size", _sz, []),
+    ("aqr_server_create", _i32, [_vp, C.POINTER(ServerParams), _vp, _sz, C.POINTER(_vp)]),
+    ("aqr_server_submit", _i32, [_vp, _vp, _i32, _i32, C.POINTER(C.c_uint64)]),
+    ("aqr_server_poll", _i32, [_vp, C.c_uint64, _vp, _vp, C.POINTER(_i32)]),
+    ("aqr_server_stop", _i32, [_vp]),
+    ("aqr_server_destroy", None, [_vp]),
+    ("aqr_server_replay", _i32, [_vp, _i64, _vp, _vp, _vp, _vp, _vp, _vp, _vp,
+                                 C.POINTER(C.c_double)]),
 ]
 
 SYMBOLS = [s[0] for s in _SIGS]
@@ -496,3 +511,71 @@ class BatchPlan:
     def launch(self, nq, stream=None):
         aqr_plan_launch(self.plan, nq, stream)
         return self.bufs["out_id"][:nq], self.bufs["out_dist"][:nq]
+
+
+# --------------------------------------------------------------------------
+# serving
+# --------------------------------------------------------------------------
+
+AQR_ERR_BUSY = 4
+
+
+class Server(_Handle):
+    """A resident persistent kernel fed from a ring of requests in pinned host
+    memory (continuous admission).  submit() admits one query (host array of
+    d floats) and returns a ticket; poll() returns None until the request is
+    complete, then (ids, dists) rows of length k_max padded with (-1, inf)."""
+
+    _free = "aqr_server_destroy"
+
+    def __init__(self, ix, k_max, ef_max, ring=1024, m_ef=3, n_rerank=28, tau_gap=0.010,
+                 tau_ratio=1.008, eps=1e-6, waves_per_block=0, visited_log2=0, idle_ms=50):
+        import torch
+        self.ix = ix
+        self.k_max = k_max
+        self.ws = torch.zeros(int(lib().aqr_server_workspace_size()), dtype=torch.uint8,
+                              device=ix.arena.device)
+        p = ServerParams(ring=ring, k_max=k_max, ef_max=ef_max, m_ef=m_ef, n_rerank=n_rerank,
+                         tau_gap=tau_gap, tau_ratio=tau_ratio, eps=eps,
+                         waves_per_block=waves_per_block, visited_log2=visited_log2,
+                         idle_ms=idle_ms, reserved=0)
+        h = _vp()
+        _check(lib().aqr_server_create(ix.ptr, C.byref(p), _dev_ptr(self.ws), self.ws.numel(),
+                                       C.byref(h)))
+        super().__init__(h.value)
+
+    def submit(self, q, k, ef):
+        q = np.ascontiguousarray(q, np.float32)
+        t = C.c_uint64()
+        st = lib().aqr_server_submit(self.ptr, _np_ptr(q), int(k), int(ef), C.byref(t))
+        if st == AQR_ERR_BUSY:
+            return None
+        _check(st)
+        return t.value
+
+    def poll(self, ticket):
+        ids = np.empty(self.k_max, np.int32)
+        dist = np.empty(self.k_max, np.float32)
+        done = _i32()
+        _check(lib().aqr_server_poll(self.ptr, C.c_uint64(ticket), _np_ptr(ids), _np_ptr(dist),
+                                     C.byref(done)))
+        return (ids, dist) if done.value else None
+
+    def stop(self):
+        _check(lib().aqr_server_stop(self.ptr))
+
+    def replay(self, arrival_s, Q, k, ef):
+        """Replay an arrival trace natively; returns (ids, dists, latency_s, wall_s)."""
+        n = len(arrival_s)
+        arr = np.ascontiguousarray(arrival_s, np.float64)
+        Q = np.ascontiguousarray(Q, np.float32)
+        k = np.ascontiguousarray(k, np.int32)
+        ef = np.ascontiguousarray(ef, np.int32)
+        ids = np.empty((n, self.k_max), np.int32)
+        dist = np.empty((n, self.k_max), np.float32)
+        lat = np.empty(n, np.float64)
+        wall = C.c_double()
+        _check(lib().aqr_server_replay(self.ptr, n, _np_ptr(arr), _np_ptr(Q), _np_ptr(k),
+                                       _np_ptr(ef), _np_ptr(ids), _np_ptr(dist), _np_ptr(lat),
+                                       C.byref(wall)))
+        return ids, dist, lat, wall.value

@@ -33,9 +33,11 @@
 
 #include <algorithm>
 #include <atomic>
+#include <chrono>
 #include <climits>
 #include <cmath>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <vector>
 
@@ -533,7 +535,12 @@ __device__ __forceinline__ void search_query(const SearchArgs& a, const int64_t 
 
     // ---- outputs ----
     const int cnt = min(nc, wsize);
-    if (a.mode == 0) {
+    if (a.mode == 2) {
+        // serving: the caller reads the first cnt keys of W from LDS
+        wsync();
+        if (lane == 0) *reinterpret_cast<int*>(st_id) = cnt;
+        wsync();
+    } else if (a.mode == 0) {
         for (int i = lane; i < cnt; i += kWave) {
             const uint64_t key = mk[i];
             a.out_id[q * a.out_stride + i] = (uint32_t)key;
@@ -739,57 +746,20 @@ __device__ __forceinline__ float asym_chunk(uint4 x, const float (&qr)[16], cons
     return acc;
 }
 
+// Stages 2-3, early termination and assembly for one query, run by the
+// whole wave.  qf: the FP32 query (xs floats, LDS); ids: the nc Stage-1
+// candidates (LDS); A, As, Rk, Rs, kind, kinds: LDS scratch; outputs are
+// the query's rows (out_stride entries) and optional taps.
 template <int CPL8, int CPLF>
-__global__ __launch_bounds__(256) void k_rerank(RerankArgs a) {
-    extern __shared__ __align__(16) unsigned char smem[];
-    const int lane = lane_id();
-    const int wave = threadIdx.x / kWave;
-    const int64_t q = (int64_t)blockIdx.x * (blockDim.x / kWave) + wave;
-    if (q >= a.nq) return;
+__device__ __forceinline__ void rerank_query(const RerankArgs& a, const int lane, const int k,
+                                             int nc, const float* qf, const uint32_t* ids,
+                                             uint64_t* A, uint64_t* As, uint64_t* Rk,
+                                             uint64_t* Rs, uint8_t* kind, uint8_t* kinds,
+                                             int32_t* out_id, float* out_dist, uint8_t* out_kind,
+                                             const int out_stride, uint32_t* a_id_out,
+                                             float* a_dist_out, uint8_t* et_out,
+                                             int32_t* nrr_out) {
     const Idx& ix = a.ix;
-    const int nc_cap = a.nc_cap;
-    const int r_cap = a.r_cap;
-    unsigned char* base = smem + (size_t)wave * a.wave_lds;
-    uint64_t* A = reinterpret_cast<uint64_t*>(base);
-    uint64_t* As = A + nc_cap;
-    uint64_t* Rk = As + nc_cap;
-    uint64_t* Rs = Rk + r_cap;
-    uint8_t* kind = reinterpret_cast<uint8_t*>(Rs + r_cap);
-    uint8_t* kinds = kind + r_cap;
-    uint32_t* ids = reinterpret_cast<uint32_t*>(kinds + r_cap);
-    size_t off = (size_t)nc_cap * 16 + (size_t)r_cap * 18 + (size_t)nc_cap * 4;
-    off = (off + 15) & ~(size_t)15;
-    float* qf = reinterpret_cast<float*>(base + off);
-
-    const int k = a.kq[q];
-    int nc = a.ccnt[q];
-    const bool bad = nc < 0 || nc > a.nc_stride || k < 1 || k > a.out_stride;
-    if (bad) {
-        for (int t = lane; t < a.out_stride; t += kWave) {
-            a.out_id[q * a.out_stride + t] = -1;
-            a.out_dist[q * a.out_stride + t] = __builtin_huge_valf();
-            if (a.out_kind) a.out_kind[q * a.out_stride + t] = 0;
-        }
-        if (lane == 0) {
-            if (a.taps.et) a.taps.et[q] = 0;
-            if (a.taps.nrr) a.taps.nrr[q] = 0;
-        }
-        return;
-    }
-    for (int j = lane; j < ix.xs; j += kWave) qf[j] = j < ix.d ? a.Q[q * ix.d + j] : 0.0f;
-    // candidate ids outside [0, n) are dropped (they cannot come from aqr_search)
-    int ncv = 0;
-    for (int b0 = 0; b0 < nc; b0 += kWave) {
-        const int j = b0 + lane;
-        const uint32_t id = j < nc ? a.cid[q * a.nc_stride + j] : kNone;
-        const bool ok = j < nc && (int64_t)id < ix.n;
-        const uint64_t m = ballot(ok);
-        if (ok) ids[ncv + below(m)] = id;
-        ncv += __popcll(m);
-    }
-    nc = ncv;
-    wsync();
-
     // Stage 2: d^a on decoded codes, G8 lanes per code row
     {
         const Geo g = make_geo(a.lg8, a.nch8, lane);
@@ -800,7 +770,9 @@ __global__ __launch_bounds__(256) void k_rerank(RerankArgs a) {
 #pragma unroll
             for (int t = 0; t < 16; ++t) {
                 const int j = ch * 16 + t;
-                const bool in = ch < g.nch;
+                // padded dimensions (d <= j < d_pad) contribute exactly zero:
+                // code 0 decodes to 0 with min 0, against a query value of 0
+                const bool in = ch < g.nch && j < ix.d;
                 qr[c][t] = in ? qf[j] : 0.0f;
                 mr[c][t] = in ? ix.qmin[j] : 0.0f;
                 sr[c][t] = in ? ix.qscale[j] : 1.0f;
@@ -887,28 +859,283 @@ __global__ __launch_bounds__(256) void k_rerank(RerankArgs a) {
         kinds[r] = kind[i];
     }
     wsync();
-    for (int t = lane; t < a.out_stride; t += kWave) {
-        const int64_t o = q * a.out_stride + t;
+    for (int t = lane; t < out_stride; t += kWave) {
         if (t < k && t < nr) {
-            a.out_id[o] = (int32_t)(uint32_t)Rs[t];
-            a.out_dist[o] = __uint_as_float((uint32_t)(Rs[t] >> 32));
-            if (a.out_kind) a.out_kind[o] = kinds[t];
+            out_id[t] = (int32_t)(uint32_t)Rs[t];
+            out_dist[t] = __uint_as_float((uint32_t)(Rs[t] >> 32));
+            if (out_kind) out_kind[t] = kinds[t];
         } else {
-            a.out_id[o] = -1;
-            a.out_dist[o] = __builtin_huge_valf();
-            if (a.out_kind) a.out_kind[o] = 0;
+            out_id[t] = -1;
+            out_dist[t] = __builtin_huge_valf();
+            if (out_kind) out_kind[t] = 0;
         }
     }
-    if (a.taps.a_id) {
+    if (a_id_out) {
         for (int t = lane; t < nc; t += kWave) {
-            a.taps.a_id[q * a.nc_stride + t] = (uint32_t)As[t];
-            a.taps.a_dist[q * a.nc_stride + t] = __uint_as_float((uint32_t)(As[t] >> 32));
+            a_id_out[t] = (uint32_t)As[t];
+            a_dist_out[t] = __uint_as_float((uint32_t)(As[t] >> 32));
         }
     }
     if (lane == 0) {
-        if (a.taps.et) a.taps.et[q] = (uint8_t)et;
-        if (a.taps.nrr) a.taps.nrr[q] = nrr;
+        if (et_out) *et_out = (uint8_t)et;
+        if (nrr_out) *nrr_out = nrr;
     }
+}
+
+template <int CPL8, int CPLF>
+__global__ __launch_bounds__(256) void k_rerank(RerankArgs a) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    const int lane = lane_id();
+    const int wave = threadIdx.x / kWave;
+    const int64_t q = (int64_t)blockIdx.x * (blockDim.x / kWave) + wave;
+    if (q >= a.nq) return;
+    const Idx& ix = a.ix;
+    const int nc_cap = a.nc_cap;
+    const int r_cap = a.r_cap;
+    unsigned char* base = smem + (size_t)wave * a.wave_lds;
+    uint64_t* A = reinterpret_cast<uint64_t*>(base);
+    uint64_t* As = A + nc_cap;
+    uint64_t* Rk = As + nc_cap;
+    uint64_t* Rs = Rk + r_cap;
+    uint8_t* kind = reinterpret_cast<uint8_t*>(Rs + r_cap);
+    uint8_t* kinds = kind + r_cap;
+    uint32_t* ids = reinterpret_cast<uint32_t*>(kinds + r_cap);
+    size_t off = (size_t)nc_cap * 16 + (size_t)r_cap * 18 + (size_t)nc_cap * 4;
+    off = (off + 15) & ~(size_t)15;
+    float* qf = reinterpret_cast<float*>(base + off);
+
+    const int k = a.kq[q];
+    int nc = a.ccnt[q];
+    const bool bad = nc < 0 || nc > a.nc_stride || k < 1 || k > a.out_stride;
+    if (bad) {
+        for (int t = lane; t < a.out_stride; t += kWave) {
+            a.out_id[q * a.out_stride + t] = -1;
+            a.out_dist[q * a.out_stride + t] = __builtin_huge_valf();
+            if (a.out_kind) a.out_kind[q * a.out_stride + t] = 0;
+        }
+        if (lane == 0) {
+            if (a.taps.et) a.taps.et[q] = 0;
+            if (a.taps.nrr) a.taps.nrr[q] = 0;
+        }
+        return;
+    }
+    for (int j = lane; j < ix.xs; j += kWave) qf[j] = j < ix.d ? a.Q[q * ix.d + j] : 0.0f;
+    // candidate ids outside [0, n) are dropped (they cannot come from aqr_search)
+    int ncv = 0;
+    for (int b0 = 0; b0 < nc; b0 += kWave) {
+        const int j = b0 + lane;
+        const uint32_t id = j < nc ? a.cid[q * a.nc_stride + j] : kNone;
+        const bool ok = j < nc && (int64_t)id < ix.n;
+        const uint64_t m = ballot(ok);
+        if (ok) ids[ncv + below(m)] = id;
+        ncv += __popcll(m);
+    }
+    nc = ncv;
+    wsync();
+
+    rerank_query<CPL8, CPLF>(a, lane, k, nc, qf, ids, A, As, Rk, Rs, kind, kinds,
+                             a.out_id + q * a.out_stride, a.out_dist + q * a.out_stride,
+                             a.out_kind ? a.out_kind + q * a.out_stride : nullptr, a.out_stride,
+                             a.taps.a_id ? a.taps.a_id + q * a.nc_stride : nullptr,
+                             a.taps.a_dist ? a.taps.a_dist + q * a.nc_stride : nullptr,
+                             a.taps.et ? a.taps.et + q : nullptr,
+                             a.taps.nrr ? a.taps.nrr + q : nullptr);
+}
+
+
+// ---------------------------------------------------------------------------
+// serving: a persistent kernel fed through a ring in pinned host memory
+// ---------------------------------------------------------------------------
+// Host side publishes request t (slot t % ring: k, ef, query) and then
+// releases ctl->tail = t + 1 (system scope).  Wave 0 of block 0 is the
+// dispatcher: it mirrors ctl->tail into device memory and raises the device
+// stop flag when the host asks to stop or after idle_ticks of the 100 MHz
+// clock with no unclaimed request.  Every other wave is a worker: it claims
+// the next published request with a compare-and-swap on the device head,
+// runs Stage 1 and Stages 2-3 with the same code as the batch kernels,
+// writes the result rows into the ring and releases done[slot] = t + 1.
+// Workers leave once the stop flag is up and no request is left unclaimed,
+// so every wave of the grid exits.
+struct ServeDev {
+    uint64_t head;      // next request to claim
+    uint64_t tail;      // mirror of the host's tail
+    uint32_t stop;      // raised by the dispatcher
+    uint32_t pad;
+};
+
+struct ServeCtl {       // pinned host memory
+    uint64_t tail;
+    uint32_t stop;
+    uint32_t pad;
+};
+
+struct ServeArgs {
+    SearchArgs s;       // Idx, m_ef, ef_cap, vb, geometry, wave_lds (search part)
+    RerankArgs r;       // geometry and thresholds of the re-rank part
+    size_t search_lds;  // bytes of the search part of one wave's LDS
+    int32_t ring;
+    int32_t k_max;
+    int32_t nc_max;
+    uint64_t idle_ticks;
+    const int32_t* req_slot;  // [ring]: slot of ticket t at t mod ring
+    const float* req_q;     // [ring][d]
+    const int32_t* req_k;   // [ring]
+    const int32_t* req_ef;  // [ring]
+    int32_t* res_id;        // [ring][k_max]
+    float* res_dist;        // [ring][k_max]
+    uint64_t* done;         // [ring]
+    ServeCtl* ctl;
+    ServeDev* dev;
+};
+
+__device__ __forceinline__ uint64_t ld_sys_acq(const uint64_t* p) {
+    return __hip_atomic_load(p, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_SYSTEM);
+}
+__device__ __forceinline__ uint64_t ld_agent_acq(const uint64_t* p) {
+    return __hip_atomic_load(p, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+template <int CPL, int U, int S, int CPL8, int CPLF>
+__global__ __launch_bounds__(256) void k_serve(ServeArgs a) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    const int lane = lane_id();
+    const int wave = threadIdx.x / kWave;
+    const SearchArgs& sa = a.s;
+    const Idx& ix = sa.ix;
+    ServeDev* dv = a.dev;
+
+    if (blockIdx.x == 0 && wave == 0) {
+        // dispatcher
+        if (lane == 0) {
+            uint64_t last = ld_agent_acq(&dv->tail);
+            uint64_t since = __builtin_amdgcn_s_memrealtime();
+            for (;;) {
+                const uint64_t t = ld_sys_acq(&a.ctl->tail);
+                if (t > last) {
+                    __hip_atomic_store(&dv->tail, t, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+                    last = t;
+                }
+                const uint32_t stop =
+                    __hip_atomic_load(&a.ctl->stop, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_SYSTEM);
+                const uint64_t h = ld_agent_acq(&dv->head);
+                const uint64_t now = __builtin_amdgcn_s_memrealtime();
+                if (h < last) since = now;  // unclaimed work: not idle
+                if (stop != 0u || now - since > a.idle_ticks) {
+                    __hip_atomic_store(&dv->stop, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+                    break;
+                }
+                __builtin_amdgcn_s_sleep(8);
+            }
+        }
+        return;
+    }
+
+    // worker LDS: [search part | re-rank part]; the query stays in the
+    // search part's FP32 query buffer throughout
+    unsigned char* base = smem + (size_t)wave * sa.wave_lds;
+    const int ef_cap = sa.ef_cap;
+    const int st_cap = max(ix.s0, ix.s1) <= 64 ? 64 : ((max(ix.s0, ix.s1) + 63) / 64) * 64;
+    uint64_t* mk = reinterpret_cast<uint64_t*>(base);
+    uint8_t* mf = reinterpret_cast<uint8_t*>(mk + ef_cap);
+    const size_t off = ((size_t)ef_cap * 9 + 7) & ~(size_t)7;
+    uint32_t* st_id = reinterpret_cast<uint32_t*>(base + off);
+    uint64_t* st_key = reinterpret_cast<uint64_t*>(base + off + (size_t)st_cap * 4);
+    uint64_t* visb = st_key + st_cap;
+    float* qf = reinterpret_cast<float*>(visb + ((size_t)1 << sa.vb));
+    uint8_t* qc = reinterpret_cast<uint8_t*>(qf + ix.xs);
+    unsigned char* rb = base + a.search_lds;
+    const int nc_cap = a.r.nc_cap, r_cap = a.r.r_cap;
+    uint64_t* A = reinterpret_cast<uint64_t*>(rb);
+    uint64_t* As = A + nc_cap;
+    uint64_t* Rk = As + nc_cap;
+    uint64_t* Rs = Rk + r_cap;
+    uint8_t* kind = reinterpret_cast<uint8_t*>(Rs + r_cap);
+    uint8_t* kinds = kind + r_cap;
+    uint32_t* rids = reinterpret_cast<uint32_t*>(kinds + r_cap);
+
+    const Geo g = make_geo(sa.lg, sa.nch, lane);
+    VisCache vis{visb, sa.vb, max(ix.idbits, sa.vb + 1)};
+    int backoff = 1;
+
+    for (;;) {
+        // claim the next published request (every lane runs the claim; lane
+        // 0's outcome is taken)
+        int64_t t = -1;
+        int quit = 0;
+        if (lane == 0) {
+            const uint64_t h = ld_agent_acq(&dv->head);
+            const uint64_t tl = ld_agent_acq(&dv->tail);
+            if (h < tl) {
+                uint64_t expect = h;
+                if (__hip_atomic_compare_exchange_strong(&dv->head, &expect, h + 1,
+                                                         __ATOMIC_ACQ_REL, __ATOMIC_RELAXED,
+                                                         __HIP_MEMORY_SCOPE_AGENT))
+                    t = (int64_t)h;
+            } else if (__hip_atomic_load(&dv->stop, __ATOMIC_ACQUIRE,
+                                         __HIP_MEMORY_SCOPE_AGENT) != 0u) {
+                // stop is raised only after the last tail was mirrored
+                if (ld_agent_acq(&dv->head) >= ld_agent_acq(&dv->tail)) quit = 1;
+            }
+        }
+        wsync();
+        // all lanes are active again: readfirstlane takes lane 0's values
+        quit = uni(quit);
+        if (quit) break;
+        const int64_t tk = (int64_t)uni64((uint64_t)t);
+        if (tk < 0) {
+            // nothing published: back off (about 0.4 to 3.4 us)
+            for (int i = 0; i < backoff; ++i) __builtin_amdgcn_s_sleep(16);
+            backoff = min(backoff * 2, 8);
+            continue;
+        }
+        backoff = 1;
+        // the request's data was written before the host's release of tail
+        (void)ld_sys_acq(&a.ctl->tail);
+        const int slot = uni(a.req_slot[tk % a.ring]);
+        if (slot < 0 || slot >= a.ring) continue;  // not written by aqr_server_submit
+        const int k = a.req_k[slot];
+        const int ef = a.req_ef[slot];
+        const int efe = max(ef, k);
+        const int nc = min(max(efe / sa.m_ef, k), efe);
+        int bad = uni((k < 1 || k > a.k_max || efe > ef_cap || nc > a.nc_max) ? 1 : 0);
+        if (!bad) {
+            bool nonfinite = false;
+            for (int j = lane; j < ix.xs; j += kWave) {
+                const float v = j < ix.d ? a.req_q[(int64_t)slot * ix.d + j] : 0.0f;
+                nonfinite |= !__builtin_isfinite(v);
+                qf[j] = v;
+            }
+            bad = uni(ballot(nonfinite) != 0 ? 1 : 0);
+        }
+        int32_t* oid = a.res_id + (int64_t)slot * a.k_max;
+        float* od = a.res_dist + (int64_t)slot * a.k_max;
+        if (bad) {
+            for (int j = lane; j < a.k_max; j += kWave) {
+                oid[j] = -1;
+                od[j] = __builtin_huge_valf();
+            }
+        } else {
+            // Stage 1 writes its N_c candidates into the search part; the
+            // re-rank reads them from there
+            search_query<false, CPL, U, S>(sa, 0, efe, nc, lane, g, vis, mk, mf, st_id, st_key,
+                                           visb, qf, qc);
+            const int cnt = uni(*reinterpret_cast<const int*>(st_id));
+            for (int j = lane; j < cnt; j += kWave) rids[j] = (uint32_t)mk[j];
+            wsync();
+            rerank_query<CPL8, CPLF>(a.r, lane, k, cnt, qf, rids, A, As, Rk, Rs, kind, kinds,
+                                     oid, od, nullptr, a.k_max, nullptr, nullptr, nullptr,
+                                     nullptr);
+        }
+        wsync();
+        if (lane == 0)
+            __hip_atomic_store(&a.done[slot], (uint64_t)tk + 1, __ATOMIC_RELEASE,
+                               __HIP_MEMORY_SCOPE_SYSTEM);
+        wsync();
+    }
+}
+
+__global__ void k_serve_reset(ServeDev* dv) {
+    if (threadIdx.x == 0 && blockIdx.x == 0) dv->stop = 0u;
 }
 
 }  // namespace dev
@@ -1527,4 +1754,373 @@ extern "C" void aqr_plan_free(aqr_plan* p) {
     if (p->exec) (void)hipGraphExecDestroy(p->exec);
     if (p->capture_stream) (void)hipStreamDestroy(p->capture_stream);
     delete p;
+}
+
+// ===========================================================================
+// serving
+// ===========================================================================
+
+struct aqr_server {
+    const aqr_index* ix = nullptr;
+    aqr_server_params prm{};
+    dev::ServeArgs args{};
+    int blocks = 0, wpb = 4;
+    size_t lds = 0;
+    hipStream_t stream = nullptr;
+    dev::ServeCtl* ctl = nullptr;  // pinned, coherent
+    float* req_q = nullptr;
+    int32_t* req_slot = nullptr;
+    int32_t* req_k = nullptr;
+    int32_t* req_ef = nullptr;
+    int32_t* res_id = nullptr;
+    float* res_dist = nullptr;
+    uint64_t* done = nullptr;
+    uint64_t next_ticket = 0;
+    std::vector<uint64_t> slot_ticket;  // sequence number in the slot, or ~0 when free
+    std::vector<int32_t> free_slots;
+    bool launched = false;
+    std::mutex mu;
+    hipError_t (*launch_fn)(aqr_server*) = nullptr;
+};
+
+namespace {
+
+constexpr uint64_t kFree = ~0ull;
+constexpr int kSlotBits = 22;  // ticket = sequence << 22 | slot
+
+template <int CPL, int S, int C8, int CF>
+hipError_t serve_launch_t(aqr_server* sv) {
+    constexpr int U = CPL >= 4 ? 1 : 4 / CPL;
+    auto kern = dev::k_serve<CPL, U, S, C8, CF>;
+    static std::atomic<int> lds_set{0};
+    if ((int)sv->lds > lds_set.load()) {
+        hipError_t e = hipFuncSetAttribute((const void*)kern,
+                                           hipFuncAttributeMaxDynamicSharedMemorySize,
+                                           (int)sv->lds);
+        if (e != hipSuccess) return e;
+        lds_set.store((int)sv->lds);
+    }
+    if (sv->blocks <= 0) {
+        int per_cu = 0;
+        hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(
+            &per_cu, kern, sv->wpb * dev::kWave, sv->lds);
+        if (e != hipSuccess) return e;
+        // every block must be resident at once: workers only leave after
+        // the dispatcher (block 0) raises the stop flag
+        sv->blocks = std::max(1, per_cu) * std::max(1, sv->ix->num_cu);
+    }
+    hipLaunchKernelGGL(dev::k_serve_reset, dim3(1), dim3(64), 0, sv->stream, sv->args.dev);
+    hipLaunchKernelGGL(kern, dim3(sv->blocks), dim3(sv->wpb * dev::kWave), sv->lds, sv->stream,
+                       sv->args);
+    return hipGetLastError();
+}
+
+template <int CPL, int S>
+hipError_t (*pick_serve_cf(int c8, int cf))(aqr_server*) {
+    if (c8 == 1) {
+        switch (cf) {
+            case 1: return serve_launch_t<CPL, S, 1, 1>;
+            case 2: return serve_launch_t<CPL, S, 1, 2>;
+            case 4: return serve_launch_t<CPL, S, 1, 4>;
+            default: return nullptr;
+        }
+    }
+    return nullptr;
+}
+
+template <int CPL>
+hipError_t (*pick_serve_s(int slots, int c8, int cf))(aqr_server*) {
+    switch (slots) {
+        case 1: return pick_serve_cf<CPL, 1>(c8, cf);
+        case 2: return pick_serve_cf<CPL, 2>(c8, cf);
+        case 4: return pick_serve_cf<CPL, 4>(c8, cf);
+        case 8: return pick_serve_cf<CPL, 8>(c8, cf);
+        default: return nullptr;
+    }
+}
+
+// (re)launch the persistent kernel when it is not running
+aqr_status serve_ensure_running(aqr_server* sv) {
+    if (sv->launched) {
+        const hipError_t q = hipStreamQuery(sv->stream);
+        if (q == hipErrorNotReady) return AQR_OK;
+        if (q != hipSuccess) return hip_fail(q, "aqr_server: kernel");
+    }
+    const hipError_t e = sv->launch_fn(sv);
+    if (e != hipSuccess) return hip_fail(e, "aqr_server: launch");
+    sv->launched = true;
+    return AQR_OK;
+}
+
+}  // namespace
+
+extern "C" size_t aqr_server_workspace_size(void) { return 256; }
+
+extern "C" aqr_status aqr_server_create(const aqr_index* ix, const aqr_server_params* prm,
+                                        void* ws, size_t ws_bytes, aqr_server** out) {
+    try {
+        clear_error();
+        if (!ix || !prm || !ws || !out) return fail(AQR_ERR_INVALID_ARG, "aqr_server_create: null pointer");
+        if (ws_bytes < aqr_server_workspace_size())
+            return fail(AQR_ERR_OOM, "aqr_server_create: workspace too small");
+        if (prm->ring < 1 || prm->ring > (1 << 22) || prm->k_max < 1 || prm->k_max > 1024 ||
+            prm->ef_max < 1 || prm->ef_max > 512 || prm->m_ef < 1 || prm->n_rerank < 0)
+            return fail(AQR_ERR_INVALID_ARG, "aqr_server_create: parameter out of range");
+        const Idx& v = ix->v;
+        const int nch8 = v.dp / 16, nchf = v.xs / 4;
+        const int c8 = cpl_for(nch8), cf = cpl_for(nchf);
+        if (c8 != 1 || cf > 4)
+            return fail(AQR_ERR_INVALID_ARG, "aqr_server_create: serving supports d <= 1024");
+        if (v.s0 > 256) return fail(AQR_ERR_INVALID_ARG, "aqr_server_create: rows above 256 entries");
+        const int efm = std::max(prm->ef_max, prm->k_max);
+        int slots = 1;
+        while (slots * 64 < efm) slots <<= 1;
+        if (slots > 8) return fail(AQR_ERR_INVALID_ARG, "aqr_server_create: ef_max above 512");
+        int vb = prm->visited_log2 > 0 ? prm->visited_log2 : 9;
+        const int idb = std::max(v.idbits, vb + 1);
+        if (idb - vb > 15) vb = idb - 15;
+        const int nc_max = std::min(efm, std::max(prm->k_max, efm / prm->m_ef));
+        aqr_server* sv = new aqr_server();
+        sv->ix = ix;
+        sv->prm = *prm;
+        sv->wpb = prm->waves_per_block > 0 ? prm->waves_per_block : 4;
+        if (sv->wpb > 4) {
+            delete sv;
+            return fail(AQR_ERR_INVALID_ARG, "aqr_server_create: waves_per_block above 4");
+        }
+        dev::SearchLds sl{slots * 64,
+                          std::max(v.s0, v.s1) <= 64 ? 64 : (std::max(v.s0, v.s1) + 63) / 64 * 64,
+                          vb, v.xs, v.dp};
+        const size_t search_lds = sl.bytes();
+        dev::RerankArgs& r = sv->args.r;
+        r.ix = v;
+        r.nc_cap = (nc_max + 15) / 16 * 16;
+        r.r_cap = r.nc_cap + (prm->k_max + 15) / 16 * 16;
+        r.n_rerank = prm->n_rerank;
+        r.out_stride = prm->k_max;
+        r.tau_gap = prm->tau_gap;
+        r.tau_ratio = prm->tau_ratio;
+        r.eps = prm->eps;
+        r.force_et = -1;
+        r.nch8 = nch8;
+        r.lg8 = pow2_lg_for(nch8);
+        r.nchf = nchf;
+        r.lgf = pow2_lg_for(nchf);
+        dev::RerankLds rl{r.nc_cap, r.r_cap, v.xs};
+        const size_t wave_lds = search_lds + rl.bytes();
+        sv->lds = wave_lds * sv->wpb;
+        if (sv->lds > ix->max_lds) {
+            delete sv;
+            return fail(AQR_ERR_INVALID_ARG, "aqr_server_create: LDS per block exceeds the device limit");
+        }
+        dev::SearchArgs& sa = sv->args.s;
+        sa.ix = v;
+        sa.m_ef = prm->m_ef;
+        sa.ef_cap = slots * 64;
+        sa.out_stride = nc_max;
+        sa.vb = vb;
+        sa.mode = 2;
+        sa.nch = nch8;
+        sa.lg = pow2_lg_for(nch8);
+        sa.wave_lds = wave_lds;
+        sv->args.search_lds = search_lds;
+        sv->args.ring = prm->ring;
+        sv->args.k_max = prm->k_max;
+        sv->args.nc_max = nc_max;
+        sv->args.idle_ticks = (uint64_t)std::max(1, prm->idle_ms) * 100000ull;
+        switch (c8) {
+            default: sv->launch_fn = pick_serve_s<1>(slots, c8, cf); break;
+        }
+        if (!sv->launch_fn) {
+            delete sv;
+            return fail(AQR_ERR_INVALID_ARG, "aqr_server_create: unsupported row geometry");
+        }
+        // pinned, coherent host memory for the ring and the control block
+        const size_t R = (size_t)prm->ring;
+        struct Alloc {
+            void** p;
+            size_t bytes;
+        } al[] = {
+            {(void**)&sv->ctl, sizeof(dev::ServeCtl)},
+            {(void**)&sv->req_slot, R * sizeof(int32_t)},
+            {(void**)&sv->req_q, R * v.d * sizeof(float)},
+            {(void**)&sv->req_k, R * sizeof(int32_t)},
+            {(void**)&sv->req_ef, R * sizeof(int32_t)},
+            {(void**)&sv->res_id, R * prm->k_max * sizeof(int32_t)},
+            {(void**)&sv->res_dist, R * prm->k_max * sizeof(float)},
+            {(void**)&sv->done, R * sizeof(uint64_t)},
+        };
+        for (const Alloc& x : al) {
+            hipError_t e = hipHostMalloc(x.p, x.bytes, hipHostMallocCoherent | hipHostMallocMapped);
+            if (e != hipSuccess) {
+                *x.p = nullptr;
+                aqr_server_destroy(sv);
+                return hip_fail(e, "aqr_server_create: pinned host memory");
+            }
+            std::memset(*x.p, 0, x.bytes);
+        }
+        sv->args.ctl = sv->ctl;
+        sv->args.req_slot = sv->req_slot;
+        sv->args.req_q = sv->req_q;
+        sv->args.req_k = sv->req_k;
+        sv->args.req_ef = sv->req_ef;
+        sv->args.res_id = sv->res_id;
+        sv->args.res_dist = sv->res_dist;
+        sv->args.done = sv->done;
+        sv->args.dev = reinterpret_cast<dev::ServeDev*>(ws);
+        sv->slot_ticket.assign(R, kFree);
+        sv->free_slots.resize(R);
+        for (size_t i = 0; i < R; ++i) sv->free_slots[i] = (int32_t)(R - 1 - i);
+        hipError_t e = hipStreamCreateWithFlags(&sv->stream, hipStreamNonBlocking);
+        if (e != hipSuccess) {
+            sv->stream = nullptr;
+            aqr_server_destroy(sv);
+            return hip_fail(e, "aqr_server_create: stream");
+        }
+        dev::ServeDev zero{};
+        e = hipMemcpyAsync(ws, &zero, sizeof(zero), hipMemcpyHostToDevice, sv->stream);
+        if (e == hipSuccess) e = hipStreamSynchronize(sv->stream);
+        if (e != hipSuccess) {
+            aqr_server_destroy(sv);
+            return hip_fail(e, "aqr_server_create: workspace init");
+        }
+        *out = sv;
+        return AQR_OK;
+    } catch (...) {
+        return fail(AQR_ERR_OOM, "aqr_server_create: out of host memory");
+    }
+}
+
+extern "C" aqr_status aqr_server_submit(aqr_server* sv, const float* q, int32_t k, int32_t ef,
+                                        uint64_t* ticket) {
+    try {
+        clear_error();
+        if (!sv || !q || !ticket) return fail(AQR_ERR_INVALID_ARG, "aqr_server_submit: null pointer");
+        if (k < 1 || k > sv->prm.k_max || std::max(ef, k) > std::max(sv->prm.ef_max, sv->prm.k_max))
+            return fail(AQR_ERR_INVALID_ARG, "aqr_server_submit: k or ef outside the server's limits");
+        std::lock_guard<std::mutex> lk(sv->mu);
+        if (sv->free_slots.empty()) return fail(AQR_ERR_BUSY, "aqr_server_submit: ring full");
+        // With a free slot, fewer than `ring` requests are outstanding, and
+        // requests are claimed in sequence order, so the queue entry of
+        // sequence t (t mod ring) was consumed by sequence t - ring already.
+        const uint64_t t = sv->next_ticket;
+        const int32_t slot = sv->free_slots.back();
+        sv->free_slots.pop_back();
+        const int32_t d = sv->ix->v.d;
+        std::memcpy(sv->req_q + (size_t)slot * d, q, sizeof(float) * d);
+        sv->req_k[slot] = k;
+        sv->req_ef[slot] = ef;
+        sv->req_slot[t % (uint64_t)sv->prm.ring] = slot;
+        sv->slot_ticket[slot] = t;
+        sv->next_ticket = t + 1;
+        __atomic_store_n(&sv->ctl->tail, t + 1, __ATOMIC_RELEASE);
+        *ticket = (t << kSlotBits) | (uint64_t)slot;
+        return serve_ensure_running(sv);
+    } catch (...) {
+        return fail(AQR_ERR_STATE, "aqr_server_submit: unexpected failure");
+    }
+}
+
+extern "C" aqr_status aqr_server_poll(aqr_server* sv, uint64_t ticket, int32_t* out_id,
+                                      float* out_dist, int32_t* is_done) {
+    try {
+        clear_error();
+        if (!sv || !is_done) return fail(AQR_ERR_INVALID_ARG, "aqr_server_poll: null pointer");
+        std::lock_guard<std::mutex> lk(sv->mu);
+        const uint64_t slot = ticket & ((1ull << kSlotBits) - 1);
+        const uint64_t seq = ticket >> kSlotBits;
+        if (slot >= (uint64_t)sv->prm.ring || sv->slot_ticket[slot] != seq)
+            return fail(AQR_ERR_STATE, "aqr_server_poll: unknown or already collected ticket");
+        if (__atomic_load_n(&sv->done[slot], __ATOMIC_ACQUIRE) != seq + 1) {
+            *is_done = 0;
+            return serve_ensure_running(sv);
+        }
+        const int32_t km = sv->prm.k_max;
+        if (out_id) std::memcpy(out_id, sv->res_id + slot * km, sizeof(int32_t) * km);
+        if (out_dist) std::memcpy(out_dist, sv->res_dist + slot * km, sizeof(float) * km);
+        sv->slot_ticket[slot] = kFree;
+        sv->free_slots.push_back((int32_t)slot);
+        *is_done = 1;
+        return AQR_OK;
+    } catch (...) {
+        return fail(AQR_ERR_STATE, "aqr_server_poll: unexpected failure");
+    }
+}
+
+extern "C" aqr_status aqr_server_stop(aqr_server* sv) {
+    clear_error();
+    if (!sv) return fail(AQR_ERR_INVALID_ARG, "aqr_server_stop: null server");
+    std::lock_guard<std::mutex> lk(sv->mu);
+    if (!sv->launched) return AQR_OK;
+    __atomic_store_n(&sv->ctl->stop, 1u, __ATOMIC_RELEASE);
+    const hipError_t e = hipStreamSynchronize(sv->stream);
+    __atomic_store_n(&sv->ctl->stop, 0u, __ATOMIC_RELEASE);
+    sv->launched = false;
+    if (e != hipSuccess) return hip_fail(e, "aqr_server_stop");
+    return AQR_OK;
+}
+
+extern "C" void aqr_server_destroy(aqr_server* sv) {
+    if (!sv) return;
+    if (sv->launched) (void)aqr_server_stop(sv);
+    if (sv->stream) (void)hipStreamDestroy(sv->stream);
+    void* ptrs[] = {sv->ctl, sv->req_slot, sv->req_q, sv->req_k, sv->req_ef, sv->res_id, sv->res_dist, sv->done};
+    for (void* p : ptrs)
+        if (p) (void)hipHostFree(p);
+    delete sv;
+}
+
+// Native trace replay: request i arrives at arrival_s[i] (seconds from the
+// start); it is submitted at that time (or as soon as a ring slot is free)
+// and its latency runs from its arrival to the poll that finds it done.
+extern "C" aqr_status aqr_server_replay(aqr_server* sv, int64_t n, const double* arrival_s,
+                                        const float* Q, const int32_t* k, const int32_t* ef,
+                                        int32_t* out_id, float* out_dist, double* latency_s,
+                                        double* wall_s) {
+    try {
+        clear_error();
+        if (!sv || !arrival_s || !Q || !k || !ef || !latency_s)
+            return fail(AQR_ERR_INVALID_ARG, "aqr_server_replay: null pointer");
+        const int32_t d = sv->ix->v.d, km = sv->prm.k_max;
+        using clk = std::chrono::steady_clock;
+        const auto t0 = clk::now();
+        auto now_s = [&] { return std::chrono::duration<double>(clk::now() - t0).count(); };
+        std::vector<uint64_t> tick(n, kFree);
+        std::vector<int64_t> pending;  // submitted, not yet done
+        pending.reserve(sv->prm.ring);
+        int64_t next = 0, finished = 0;
+        std::vector<int32_t> ids(km);
+        std::vector<float> dd(km);
+        while (finished < n) {
+            const double t = now_s();
+            while (next < n && arrival_s[next] <= t) {
+                uint64_t tk = 0;
+                const aqr_status st = aqr_server_submit(sv, Q + next * d, k[next], ef[next], &tk);
+                if (st == AQR_ERR_BUSY) break;
+                if (st != AQR_OK) return st;
+                tick[next] = tk;
+                pending.push_back(next);
+                ++next;
+            }
+            for (size_t i = 0; i < pending.size();) {
+                const int64_t r = pending[i];
+                int32_t ok = 0;
+                const aqr_status st = aqr_server_poll(sv, tick[r], out_id ? out_id + r * km : ids.data(),
+                                                      out_dist ? out_dist + r * km : dd.data(), &ok);
+                if (st != AQR_OK) return st;
+                if (ok) {
+                    latency_s[r] = now_s() - arrival_s[r];
+                    ++finished;
+                    pending[i] = pending.back();
+                    pending.pop_back();
+                } else {
+                    ++i;
+                }
+            }
+        }
+        if (wall_s) *wall_s = now_s();
+        return AQR_OK;
+    } catch (...) {
+        return fail(AQR_ERR_STATE, "aqr_server_replay: unexpected failure");
+    }
 }

@@ -347,3 +347,18 @@ def test_fp32_baseline_matches_oracle(orc, small):
             # tie within rounding; such a query may take another path
             diverged += 1
         assert diverged <= 2, diverged
+
+
+@pytest.mark.parametrize("d", [100, 20])
+def test_ragged_dimension_pipeline(orc, d):
+    # d not a multiple of 16: code rows carry zero padding up to d_pad, which
+    # must add nothing to Stage-1, Stage-2 or Stage-3 distances
+    X, Q = W.tiny(4000, d, seed=30 + d, clusters=6, nq=60)
+    index = make_index(orc, X, 12, 80)
+    s1 = run_stage1(index, Q, 10, 96)
+    o, _ = oracle_stage1(orc, index, Q, 10, 96)
+    compare_stage1(s1, o, Q.shape[0])
+    gr = _rerank_gpu(index, s1, 10)
+    check_rerank(orc, index, Q, s1, 10, gr)
+    gr = _rerank_gpu(index, s1, 10, force_et=0, n_rerank=20)
+    check_rerank(orc, index, Q, s1, 10, gr, force_et=0, n_rerank=20)

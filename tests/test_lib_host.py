@@ -174,3 +174,21 @@ def test_null_handles_are_rejected(L):
     assert L.aqr_index_bind(None, None, None, None, None, 0, None, C.byref(C.c_void_p())) == \
         aqr.INVALID_ARG
     assert L.aqr_build(None, 1, 1, None, None, None, C.byref(C.c_void_p())) == aqr.INVALID_ARG
+
+
+def test_server_entry_points_reject_bad_arguments(L):
+    import ctypes as C
+    h = C.c_void_p()
+    p = aqr.ServerParams(ring=8, k_max=10, ef_max=64, m_ef=3, n_rerank=28, tau_gap=0.01,
+                         tau_ratio=1.008, eps=1e-6)
+    assert L.aqr_server_workspace_size() >= 24
+    assert L.aqr_server_create(None, C.byref(p), None, 0, C.byref(h)) == aqr.INVALID_ARG
+    assert b"null" in L.aqr_last_error()
+    t = C.c_uint64()
+    assert L.aqr_server_submit(None, None, 1, 1, C.byref(t)) == aqr.INVALID_ARG
+    done = C.c_int32()
+    assert L.aqr_server_poll(None, 0, None, None, C.byref(done)) == aqr.INVALID_ARG
+    assert L.aqr_server_stop(None) == aqr.INVALID_ARG
+    assert L.aqr_server_replay(None, 0, None, None, None, None, None, None, None, None) == \
+        aqr.INVALID_ARG
+    L.aqr_server_destroy(None)
