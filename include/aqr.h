@@ -387,11 +387,14 @@ void aqr_server_destroy(aqr_server* s);
  * Replay an arrival trace from the host: request i (query Q[i], k[i], ef[i])
  * arrives at arrival_s[i] seconds after the start and is submitted then, or
  * as soon as a slot frees up; latency_s[i] runs from its arrival to the poll
- * that finds it complete.  out_id/out_dist (nullable): [n][k_max].
+ * that finds it complete; service_s[i] (nullable) is the device time from
+ * the wave's claim of the request to its completion.  out_id/out_dist
+ * (nullable): [n][k_max].
  */
 aqr_status aqr_server_replay(aqr_server* s, int64_t n, const double* arrival_s, const float* Q,
                              const int32_t* k, const int32_t* ef, int32_t* out_id,
-                             float* out_dist, double* latency_s, double* wall_s);
+                             float* out_dist, double* latency_s, double* service_s,
+                             double* wall_s);
 
 #ifdef __cplusplus
 }

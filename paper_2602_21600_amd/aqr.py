@@ -125,7 +125,7 @@ _SIGS = [
     ("aqr_server_poll", _i32, [_vp, C.c_uint64, _vp, _vp, C.POINTER(_i32)]),
     ("aqr_server_stop", _i32, [_vp]),
     ("aqr_server_destroy", None, [_vp]),
-    ("aqr_server_replay", _i32, [_vp, _i64, _vp, _vp, _vp, _vp, _vp, _vp, _vp,
+    ("aqr_server_replay", _i32, [_vp, _i64, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp,
                                  C.POINTER(C.c_double)]),
 ]
 
@@ -564,8 +564,9 @@ class Server(_Handle):
     def stop(self):
         _check(lib().aqr_server_stop(self.ptr))
 
-    def replay(self, arrival_s, Q, k, ef):
-        """Replay an arrival trace natively; returns (ids, dists, latency_s, wall_s)."""
+    def replay(self, arrival_s, Q, k, ef, service=False):
+        """Replay an arrival trace natively; returns (ids, dists, latency_s, wall_s),
+        plus the per-request device service times when service=True."""
         n = len(arrival_s)
         arr = np.ascontiguousarray(arrival_s, np.float64)
         Q = np.ascontiguousarray(Q, np.float32)
@@ -574,8 +575,11 @@ class Server(_Handle):
         ids = np.empty((n, self.k_max), np.int32)
         dist = np.empty((n, self.k_max), np.float32)
         lat = np.empty(n, np.float64)
+        svc = np.empty(n, np.float64) if service else None
         wall = C.c_double()
         _check(lib().aqr_server_replay(self.ptr, n, _np_ptr(arr), _np_ptr(Q), _np_ptr(k),
                                        _np_ptr(ef), _np_ptr(ids), _np_ptr(dist), _np_ptr(lat),
-                                       C.byref(wall)))
+                                       _np_ptr(svc), C.byref(wall)))
+        if service:
+            return ids, dist, lat, wall.value, svc
         return ids, dist, lat, wall.value

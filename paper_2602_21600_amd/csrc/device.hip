@@ -37,7 +37,9 @@
 #include <climits>
 #include <cmath>
 #include <cstring>
+#include <limits>
 #include <mutex>
+#include <thread>
 #include <new>
 #include <vector>
 
@@ -750,7 +752,7 @@ __device__ __forceinline__ float asym_chunk(uint4 x, const float (&qr)[16], cons
 // whole wave.  qf: the FP32 query (xs floats, LDS); ids: the nc Stage-1
 // candidates (LDS); A, As, Rk, Rs, kind, kinds: LDS scratch; outputs are
 // the query's rows (out_stride entries) and optional taps.
-template <int CPL8, int CPLF>
+template <int CPL8, int CPLF, bool SYS = false>
 __device__ __forceinline__ void rerank_query(const RerankArgs& a, const int lane, const int k,
                                              int nc, const float* qf, const uint32_t* ids,
                                              uint64_t* A, uint64_t* As, uint64_t* Rk,
@@ -860,15 +862,19 @@ __device__ __forceinline__ void rerank_query(const RerankArgs& a, const int lane
     }
     wsync();
     for (int t = lane; t < out_stride; t += kWave) {
-        if (t < k && t < nr) {
-            out_id[t] = (int32_t)(uint32_t)Rs[t];
-            out_dist[t] = __uint_as_float((uint32_t)(Rs[t] >> 32));
-            if (out_kind) out_kind[t] = kinds[t];
+        const bool v = t < k && t < nr;
+        const int32_t oi = v ? (int32_t)(uint32_t)Rs[t] : -1;
+        const uint32_t od = v ? (uint32_t)(Rs[t] >> 32) : 0x7F800000u;
+        if constexpr (SYS) {
+            // pinned host memory: write through the GPU caches
+            __hip_atomic_store(out_id + t, oi, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+            __hip_atomic_store(reinterpret_cast<uint32_t*>(out_dist) + t, od, __ATOMIC_RELAXED,
+                               __HIP_MEMORY_SCOPE_SYSTEM);
         } else {
-            out_id[t] = -1;
-            out_dist[t] = __builtin_huge_valf();
-            if (out_kind) out_kind[t] = 0;
+            out_id[t] = oi;
+            out_dist[t] = __uint_as_float(od);
         }
+        if (out_kind) out_kind[t] = v ? kinds[t] : 0;
     }
     if (a_id_out) {
         for (int t = lane; t < nc; t += kWave) {
@@ -964,9 +970,10 @@ struct ServeDev {
 };
 
 struct ServeCtl {       // pinned host memory
-    uint64_t tail;
-    uint32_t stop;
+    uint64_t tail;      // requests published by the host
+    uint32_t stop;      // host asks the kernel to leave
     uint32_t pad;
+    uint64_t exited;    // epoch of the last launch whose dispatcher has left
 };
 
 struct ServeArgs {
@@ -977,6 +984,7 @@ struct ServeArgs {
     int32_t k_max;
     int32_t nc_max;
     uint64_t idle_ticks;
+    uint64_t epoch;
     const int32_t* req_slot;  // [ring]: slot of ticket t at t mod ring
     const float* req_q;     // [ring][d]
     const int32_t* req_k;   // [ring]
@@ -984,16 +992,37 @@ struct ServeArgs {
     int32_t* res_id;        // [ring][k_max]
     float* res_dist;        // [ring][k_max]
     uint64_t* done;         // [ring]
+    uint32_t* svc;          // [ring]: device service time of the request (100 MHz ticks)
     ServeCtl* ctl;
     ServeDev* dev;
 };
 
-__device__ __forceinline__ uint64_t ld_sys_acq(const uint64_t* p) {
-    return __hip_atomic_load(p, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_SYSTEM);
+// Synchronisation of the serving loop.  The spin loops use relaxed atomics
+// only: acquire and release at agent or system scope maintain the per-XCD L2
+// caches (invalidate / write back), and thousands of spinning waves doing that
+// would starve the searching ones.  Ordering comes from dependencies instead:
+//  - request data in pinned host memory is read with system-scope relaxed
+//    loads (they bypass the GPU caches), at addresses that depend on the
+//    claimed sequence number, which depends on the mirrored tail, which was
+//    read after the host published the data;
+//  - results are written with system-scope relaxed stores (write-through),
+//    and the wave waits for every store to complete before it writes the done
+//    flag.
+__device__ __forceinline__ uint64_t ld_sys(const uint64_t* p) {
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
 }
-__device__ __forceinline__ uint64_t ld_agent_acq(const uint64_t* p) {
-    return __hip_atomic_load(p, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
+__device__ __forceinline__ uint32_t ld_sys32(const uint32_t* p) {
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
 }
+__device__ __forceinline__ uint64_t ld_agent(const uint64_t* p) {
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+template <class T>
+__device__ __forceinline__ void st_sys(T* p, T v) {
+    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+}
+// wait until every memory operation this wave issued has completed
+__device__ __forceinline__ void wait_mem() { asm volatile("s_waitcnt vmcnt(0)" ::: "memory"); }
 
 template <int CPL, int U, int S, int CPL8, int CPLF>
 __global__ __launch_bounds__(256) void k_serve(ServeArgs a) {
@@ -1005,23 +1034,26 @@ __global__ __launch_bounds__(256) void k_serve(ServeArgs a) {
     ServeDev* dv = a.dev;
 
     if (blockIdx.x == 0 && wave == 0) {
-        // dispatcher
+        // dispatcher: mirror the host's publication counter into device memory
         if (lane == 0) {
-            uint64_t last = ld_agent_acq(&dv->tail);
+            uint64_t last = ld_agent(&dv->tail);
             uint64_t since = __builtin_amdgcn_s_memrealtime();
             for (;;) {
-                const uint64_t t = ld_sys_acq(&a.ctl->tail);
+                const uint64_t t = ld_sys(&a.ctl->tail);
                 if (t > last) {
-                    __hip_atomic_store(&dv->tail, t, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+                    __hip_atomic_store(&dv->tail, t, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
                     last = t;
                 }
-                const uint32_t stop =
-                    __hip_atomic_load(&a.ctl->stop, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_SYSTEM);
-                const uint64_t h = ld_agent_acq(&dv->head);
+                const uint32_t stop = ld_sys32(&a.ctl->stop);
+                const uint64_t h = ld_agent(&dv->head);
                 const uint64_t now = __builtin_amdgcn_s_memrealtime();
                 if (h < last) since = now;  // unclaimed work: not idle
                 if (stop != 0u || now - since > a.idle_ticks) {
-                    __hip_atomic_store(&dv->stop, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+                    // the final tail is visible before the stop flag
+                    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+                    __hip_atomic_store(&dv->stop, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                    // tell the host: requests published from now on need a relaunch
+                    st_sys(&a.ctl->exited, a.epoch);
                     break;
                 }
                 __builtin_amdgcn_s_sleep(8);
@@ -1052,56 +1084,60 @@ __global__ __launch_bounds__(256) void k_serve(ServeArgs a) {
     uint8_t* kind = reinterpret_cast<uint8_t*>(Rs + r_cap);
     uint8_t* kinds = kind + r_cap;
     uint32_t* rids = reinterpret_cast<uint32_t*>(kinds + r_cap);
-
     const Geo g = make_geo(sa.lg, sa.nch, lane);
     VisCache vis{visb, sa.vb, max(ix.idbits, sa.vb + 1)};
-    int backoff = 1;
 
     for (;;) {
-        // claim the next published request (every lane runs the claim; lane
-        // 0's outcome is taken)
-        int64_t t = -1;
-        int quit = 0;
-        if (lane == 0) {
-            const uint64_t h = ld_agent_acq(&dv->head);
-            const uint64_t tl = ld_agent_acq(&dv->tail);
-            if (h < tl) {
-                uint64_t expect = h;
-                if (__hip_atomic_compare_exchange_strong(&dv->head, &expect, h + 1,
-                                                         __ATOMIC_ACQ_REL, __ATOMIC_RELAXED,
-                                                         __HIP_MEMORY_SCOPE_AGENT))
-                    t = (int64_t)h;
-            } else if (__hip_atomic_load(&dv->stop, __ATOMIC_ACQUIRE,
-                                         __HIP_MEMORY_SCOPE_AGENT) != 0u) {
-                // stop is raised only after the last tail was mirrored
-                if (ld_agent_acq(&dv->head) >= ld_agent_acq(&dv->tail)) quit = 1;
-            }
-        }
+        // take the next sequence number (one atomic add per request; lane 0
+        // adds, every lane reads the old value after the branch has joined),
+        // then wait until the host has published it
+        uint64_t t = 0;
+        if (lane == 0)
+            t = __hip_atomic_fetch_add(&dv->head, (uint64_t)1, __ATOMIC_RELAXED,
+                                       __HIP_MEMORY_SCOPE_AGENT);
         wsync();
-        // all lanes are active again: readfirstlane takes lane 0's values
-        quit = uni(quit);
-        if (quit) break;
-        const int64_t tk = (int64_t)uni64((uint64_t)t);
-        if (tk < 0) {
-            // nothing published: back off (about 0.4 to 3.4 us)
+        const uint64_t tk = uni64(t);
+        int quit = 0;
+        int backoff = 1;
+        for (;;) {
+            uint64_t tl = 0;
+            uint32_t st = 0;
+            if (lane == 0) {
+                tl = ld_agent(&dv->tail);
+                if (tl <= tk) {
+                    st = __hip_atomic_load(&dv->stop, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                    if (st != 0u) {
+                        // the dispatcher published its final tail before raising stop
+                        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+                        tl = ld_agent(&dv->tail);
+                    }
+                }
+            }
+            wsync();
+            const uint64_t tlu = uni64(tl);
+            if (tlu > tk) break;           // published: serve it
+            if (uni((int)st) != 0) {       // never published: leave
+                quit = 1;
+                break;
+            }
             for (int i = 0; i < backoff; ++i) __builtin_amdgcn_s_sleep(16);
-            backoff = min(backoff * 2, 8);
-            continue;
+            backoff = min(backoff * 2, 8);  // about 0.4 to 3.4 us
         }
-        backoff = 1;
-        // the request's data was written before the host's release of tail
-        (void)ld_sys_acq(&a.ctl->tail);
-        const int slot = uni(a.req_slot[tk % a.ring]);
+        if (quit) break;
+        const uint64_t t_claim = __builtin_amdgcn_s_memrealtime();
+        const int slot =
+            uni((int)ld_sys32(reinterpret_cast<const uint32_t*>(a.req_slot) + tk % a.ring));
         if (slot < 0 || slot >= a.ring) continue;  // not written by aqr_server_submit
-        const int k = a.req_k[slot];
-        const int ef = a.req_ef[slot];
+        const int k = uni((int)ld_sys32(reinterpret_cast<const uint32_t*>(a.req_k) + slot));
+        const int ef = uni((int)ld_sys32(reinterpret_cast<const uint32_t*>(a.req_ef) + slot));
         const int efe = max(ef, k);
         const int nc = min(max(efe / sa.m_ef, k), efe);
         int bad = uni((k < 1 || k > a.k_max || efe > ef_cap || nc > a.nc_max) ? 1 : 0);
         if (!bad) {
             bool nonfinite = false;
+            const uint32_t* rq = reinterpret_cast<const uint32_t*>(a.req_q) + (int64_t)slot * ix.d;
             for (int j = lane; j < ix.xs; j += kWave) {
-                const float v = j < ix.d ? a.req_q[(int64_t)slot * ix.d + j] : 0.0f;
+                const float v = j < ix.d ? __uint_as_float(ld_sys32(rq + j)) : 0.0f;
                 nonfinite |= !__builtin_isfinite(v);
                 qf[j] = v;
             }
@@ -1109,10 +1145,11 @@ __global__ __launch_bounds__(256) void k_serve(ServeArgs a) {
         }
         int32_t* oid = a.res_id + (int64_t)slot * a.k_max;
         float* od = a.res_dist + (int64_t)slot * a.k_max;
+        // the row is k entries long (the host pads it to k_max)
         if (bad) {
-            for (int j = lane; j < a.k_max; j += kWave) {
-                oid[j] = -1;
-                od[j] = __builtin_huge_valf();
+            for (int j = lane; j < max(1, min(k, a.k_max)); j += kWave) {
+                st_sys(oid + j, -1);
+                st_sys(reinterpret_cast<uint32_t*>(od) + j, 0x7F800000u);
             }
         } else {
             // Stage 1 writes its N_c candidates into the search part; the
@@ -1122,20 +1159,27 @@ __global__ __launch_bounds__(256) void k_serve(ServeArgs a) {
             const int cnt = uni(*reinterpret_cast<const int*>(st_id));
             for (int j = lane; j < cnt; j += kWave) rids[j] = (uint32_t)mk[j];
             wsync();
-            rerank_query<CPL8, CPLF>(a.r, lane, k, cnt, qf, rids, A, As, Rk, Rs, kind, kinds,
-                                     oid, od, nullptr, a.k_max, nullptr, nullptr, nullptr,
-                                     nullptr);
+            rerank_query<CPL8, CPLF, true>(a.r, lane, k, cnt, qf, rids, A, As, Rk, Rs, kind,
+                                           kinds, oid, od, nullptr, k, nullptr, nullptr,
+                                           nullptr, nullptr);
         }
-        wsync();
         if (lane == 0)
-            __hip_atomic_store(&a.done[slot], (uint64_t)tk + 1, __ATOMIC_RELEASE,
-                               __HIP_MEMORY_SCOPE_SYSTEM);
+            st_sys(a.svc + slot, (uint32_t)(__builtin_amdgcn_s_memrealtime() - t_claim));
+        wait_mem();  // the row is in host memory before the flag
+        wsync();
+        if (lane == 0) st_sys(a.done + slot, (uint64_t)tk + 1);
         wsync();
     }
 }
 
+// Before a (re)launch: every request below the mirrored tail has been
+// served, and sequence numbers taken beyond it by workers that left were
+// never published, so numbering restarts at the tail.
 __global__ void k_serve_reset(ServeDev* dv) {
-    if (threadIdx.x == 0 && blockIdx.x == 0) dv->stop = 0u;
+    if (threadIdx.x == 0 && blockIdx.x == 0) {
+        dv->stop = 0u;
+        dv->head = dv->tail;
+    }
 }
 
 }  // namespace dev
@@ -1775,9 +1819,11 @@ struct aqr_server {
     int32_t* res_id = nullptr;
     float* res_dist = nullptr;
     uint64_t* done = nullptr;
+    uint32_t* svc = nullptr;
     uint64_t next_ticket = 0;
     std::vector<uint64_t> slot_ticket;  // sequence number in the slot, or ~0 when free
     std::vector<int32_t> free_slots;
+    std::vector<int32_t> slot_k;  // k of the request in the slot
     bool launched = false;
     std::mutex mu;
     hipError_t (*launch_fn)(aqr_server*) = nullptr;
@@ -1839,16 +1885,74 @@ hipError_t (*pick_serve_s(int slots, int c8, int cf))(aqr_server*) {
     }
 }
 
-// (re)launch the persistent kernel when it is not running
+// (Re)launch the persistent kernel when it is not running.  A running
+// kernel's dispatcher writes its epoch into ctl->exited when it leaves; a
+// request published after that is picked up by the relaunch made here on the
+// next submit or poll.
 aqr_status serve_ensure_running(aqr_server* sv) {
     if (sv->launched) {
-        const hipError_t q = hipStreamQuery(sv->stream);
-        if (q == hipErrorNotReady) return AQR_OK;
+        if (__atomic_load_n(&sv->ctl->exited, __ATOMIC_ACQUIRE) != sv->args.epoch) return AQR_OK;
+        const hipError_t q = hipStreamSynchronize(sv->stream);  // workers drain
         if (q != hipSuccess) return hip_fail(q, "aqr_server: kernel");
+        sv->launched = false;
     }
+    sv->args.epoch += 1;
     const hipError_t e = sv->launch_fn(sv);
     if (e != hipSuccess) return hip_fail(e, "aqr_server: launch");
     sv->launched = true;
+    return AQR_OK;
+}
+
+// Both below run with sv->mu held.
+aqr_status serve_submit_locked(aqr_server* sv, const float* q, int32_t k, int32_t ef,
+                               uint64_t* ticket) {
+    if (k < 1 || k > sv->prm.k_max || std::max(ef, k) > std::max(sv->prm.ef_max, sv->prm.k_max))
+        return fail(AQR_ERR_INVALID_ARG, "aqr_server_submit: k or ef outside the server's limits");
+    if (sv->free_slots.empty()) return fail(AQR_ERR_BUSY, "aqr_server_submit: ring full");
+    // With a free slot, fewer than `ring` requests are outstanding, and
+    // requests are claimed in sequence order, so the queue entry of sequence
+    // t (t mod ring) was consumed by sequence t - ring already.
+    const uint64_t t = sv->next_ticket;
+    const int32_t slot = sv->free_slots.back();
+    sv->free_slots.pop_back();
+    const int32_t d = sv->ix->v.d;
+    std::memcpy(sv->req_q + (size_t)slot * d, q, sizeof(float) * d);
+    sv->req_k[slot] = k;
+    sv->req_ef[slot] = ef;
+    sv->slot_k[slot] = k;
+    sv->req_slot[t % (uint64_t)sv->prm.ring] = slot;
+    sv->slot_ticket[slot] = t;
+    sv->next_ticket = t + 1;
+    __atomic_store_n(&sv->ctl->tail, t + 1, __ATOMIC_RELEASE);
+    *ticket = (t << kSlotBits) | (uint64_t)slot;
+    return serve_ensure_running(sv);
+}
+
+aqr_status serve_poll_locked(aqr_server* sv, uint64_t ticket, int32_t* out_id, float* out_dist,
+                             int32_t* is_done, uint32_t* svc_ticks = nullptr,
+                             bool relaunch = true) {
+    const uint64_t slot = ticket & ((1ull << kSlotBits) - 1);
+    const uint64_t seq = ticket >> kSlotBits;
+    if (slot >= (uint64_t)sv->prm.ring || sv->slot_ticket[slot] != seq)
+        return fail(AQR_ERR_STATE, "aqr_server_poll: unknown or already collected ticket");
+    if (__atomic_load_n(&sv->done[slot], __ATOMIC_ACQUIRE) != seq + 1) {
+        *is_done = 0;
+        return relaunch ? serve_ensure_running(sv) : AQR_OK;
+    }
+    // the device wrote the first k entries of the row; pad the rest
+    const int32_t km = sv->prm.k_max, k = sv->slot_k[slot];
+    if (out_id) {
+        std::memcpy(out_id, sv->res_id + slot * km, sizeof(int32_t) * k);
+        for (int32_t j = k; j < km; ++j) out_id[j] = -1;
+    }
+    if (out_dist) {
+        std::memcpy(out_dist, sv->res_dist + slot * km, sizeof(float) * k);
+        for (int32_t j = k; j < km; ++j) out_dist[j] = std::numeric_limits<float>::infinity();
+    }
+    if (svc_ticks) *svc_ticks = sv->svc[slot];
+    sv->slot_ticket[slot] = kFree;
+    sv->free_slots.push_back((int32_t)slot);
+    *is_done = 1;
     return AQR_OK;
 }
 
@@ -1949,6 +2053,7 @@ extern "C" aqr_status aqr_server_create(const aqr_index* ix, const aqr_server_pa
             {(void**)&sv->res_id, R * prm->k_max * sizeof(int32_t)},
             {(void**)&sv->res_dist, R * prm->k_max * sizeof(float)},
             {(void**)&sv->done, R * sizeof(uint64_t)},
+            {(void**)&sv->svc, R * sizeof(uint32_t)},
         };
         for (const Alloc& x : al) {
             hipError_t e = hipHostMalloc(x.p, x.bytes, hipHostMallocCoherent | hipHostMallocMapped);
@@ -1967,8 +2072,10 @@ extern "C" aqr_status aqr_server_create(const aqr_index* ix, const aqr_server_pa
         sv->args.res_id = sv->res_id;
         sv->args.res_dist = sv->res_dist;
         sv->args.done = sv->done;
+        sv->args.svc = sv->svc;
         sv->args.dev = reinterpret_cast<dev::ServeDev*>(ws);
         sv->slot_ticket.assign(R, kFree);
+        sv->slot_k.assign(R, 0);
         sv->free_slots.resize(R);
         for (size_t i = 0; i < R; ++i) sv->free_slots[i] = (int32_t)(R - 1 - i);
         hipError_t e = hipStreamCreateWithFlags(&sv->stream, hipStreamNonBlocking);
@@ -1996,26 +2103,8 @@ extern "C" aqr_status aqr_server_submit(aqr_server* sv, const float* q, int32_t 
     try {
         clear_error();
         if (!sv || !q || !ticket) return fail(AQR_ERR_INVALID_ARG, "aqr_server_submit: null pointer");
-        if (k < 1 || k > sv->prm.k_max || std::max(ef, k) > std::max(sv->prm.ef_max, sv->prm.k_max))
-            return fail(AQR_ERR_INVALID_ARG, "aqr_server_submit: k or ef outside the server's limits");
         std::lock_guard<std::mutex> lk(sv->mu);
-        if (sv->free_slots.empty()) return fail(AQR_ERR_BUSY, "aqr_server_submit: ring full");
-        // With a free slot, fewer than `ring` requests are outstanding, and
-        // requests are claimed in sequence order, so the queue entry of
-        // sequence t (t mod ring) was consumed by sequence t - ring already.
-        const uint64_t t = sv->next_ticket;
-        const int32_t slot = sv->free_slots.back();
-        sv->free_slots.pop_back();
-        const int32_t d = sv->ix->v.d;
-        std::memcpy(sv->req_q + (size_t)slot * d, q, sizeof(float) * d);
-        sv->req_k[slot] = k;
-        sv->req_ef[slot] = ef;
-        sv->req_slot[t % (uint64_t)sv->prm.ring] = slot;
-        sv->slot_ticket[slot] = t;
-        sv->next_ticket = t + 1;
-        __atomic_store_n(&sv->ctl->tail, t + 1, __ATOMIC_RELEASE);
-        *ticket = (t << kSlotBits) | (uint64_t)slot;
-        return serve_ensure_running(sv);
+        return serve_submit_locked(sv, q, k, ef, ticket);
     } catch (...) {
         return fail(AQR_ERR_STATE, "aqr_server_submit: unexpected failure");
     }
@@ -2027,21 +2116,7 @@ extern "C" aqr_status aqr_server_poll(aqr_server* sv, uint64_t ticket, int32_t* 
         clear_error();
         if (!sv || !is_done) return fail(AQR_ERR_INVALID_ARG, "aqr_server_poll: null pointer");
         std::lock_guard<std::mutex> lk(sv->mu);
-        const uint64_t slot = ticket & ((1ull << kSlotBits) - 1);
-        const uint64_t seq = ticket >> kSlotBits;
-        if (slot >= (uint64_t)sv->prm.ring || sv->slot_ticket[slot] != seq)
-            return fail(AQR_ERR_STATE, "aqr_server_poll: unknown or already collected ticket");
-        if (__atomic_load_n(&sv->done[slot], __ATOMIC_ACQUIRE) != seq + 1) {
-            *is_done = 0;
-            return serve_ensure_running(sv);
-        }
-        const int32_t km = sv->prm.k_max;
-        if (out_id) std::memcpy(out_id, sv->res_id + slot * km, sizeof(int32_t) * km);
-        if (out_dist) std::memcpy(out_dist, sv->res_dist + slot * km, sizeof(float) * km);
-        sv->slot_ticket[slot] = kFree;
-        sv->free_slots.push_back((int32_t)slot);
-        *is_done = 1;
-        return AQR_OK;
+        return serve_poll_locked(sv, ticket, out_id, out_dist, is_done);
     } catch (...) {
         return fail(AQR_ERR_STATE, "aqr_server_poll: unexpected failure");
     }
@@ -2064,7 +2139,8 @@ extern "C" void aqr_server_destroy(aqr_server* sv) {
     if (!sv) return;
     if (sv->launched) (void)aqr_server_stop(sv);
     if (sv->stream) (void)hipStreamDestroy(sv->stream);
-    void* ptrs[] = {sv->ctl, sv->req_slot, sv->req_q, sv->req_k, sv->req_ef, sv->res_id, sv->res_dist, sv->done};
+    void* ptrs[] = {sv->ctl,    sv->req_slot, sv->req_q, sv->req_k, sv->req_ef,
+                    sv->res_id, sv->res_dist, sv->done,  sv->svc};
     for (void* p : ptrs)
         if (p) (void)hipHostFree(p);
     delete sv;
@@ -2076,16 +2152,18 @@ extern "C" void aqr_server_destroy(aqr_server* sv) {
 extern "C" aqr_status aqr_server_replay(aqr_server* sv, int64_t n, const double* arrival_s,
                                         const float* Q, const int32_t* k, const int32_t* ef,
                                         int32_t* out_id, float* out_dist, double* latency_s,
-                                        double* wall_s) {
+                                        double* service_s, double* wall_s) {
     try {
         clear_error();
         if (!sv || !arrival_s || !Q || !k || !ef || !latency_s)
             return fail(AQR_ERR_INVALID_ARG, "aqr_server_replay: null pointer");
+        if (n < 0) return fail(AQR_ERR_INVALID_ARG, "aqr_server_replay: negative count");
+        std::lock_guard<std::mutex> lk(sv->mu);
         const int32_t d = sv->ix->v.d, km = sv->prm.k_max;
         using clk = std::chrono::steady_clock;
         const auto t0 = clk::now();
         auto now_s = [&] { return std::chrono::duration<double>(clk::now() - t0).count(); };
-        std::vector<uint64_t> tick(n, kFree);
+        std::vector<uint64_t> tick((size_t)n, kFree);
         std::vector<int64_t> pending;  // submitted, not yet done
         pending.reserve(sv->prm.ring);
         int64_t next = 0, finished = 0;
@@ -2095,27 +2173,40 @@ extern "C" aqr_status aqr_server_replay(aqr_server* sv, int64_t n, const double*
             const double t = now_s();
             while (next < n && arrival_s[next] <= t) {
                 uint64_t tk = 0;
-                const aqr_status st = aqr_server_submit(sv, Q + next * d, k[next], ef[next], &tk);
+                const aqr_status st = serve_submit_locked(sv, Q + next * d, k[next], ef[next], &tk);
                 if (st == AQR_ERR_BUSY) break;
                 if (st != AQR_OK) return st;
                 tick[next] = tk;
                 pending.push_back(next);
                 ++next;
             }
+            bool waiting = false;
             for (size_t i = 0; i < pending.size();) {
                 const int64_t r = pending[i];
                 int32_t ok = 0;
-                const aqr_status st = aqr_server_poll(sv, tick[r], out_id ? out_id + r * km : ids.data(),
-                                                      out_dist ? out_dist + r * km : dd.data(), &ok);
+                uint32_t ticks = 0;
+                const aqr_status st =
+                    serve_poll_locked(sv, tick[r], out_id ? out_id + r * km : ids.data(),
+                                      out_dist ? out_dist + r * km : dd.data(), &ok, &ticks, false);
                 if (st != AQR_OK) return st;
                 if (ok) {
                     latency_s[r] = now_s() - arrival_s[r];
+                    if (service_s) service_s[r] = ticks * 1e-8;  // 100 MHz
                     ++finished;
                     pending[i] = pending.back();
                     pending.pop_back();
                 } else {
+                    waiting = true;
                     ++i;
                 }
+            }
+            if (waiting) {
+                const aqr_status st = serve_ensure_running(sv);
+                if (st != AQR_OK) return st;
+            } else if (next < n) {
+                // nothing in flight: wait for the next arrival (spin for the last 50 us)
+                const double wait = arrival_s[next] - now_s() - 50e-6;
+                if (wait > 0) std::this_thread::sleep_for(std::chrono::duration<double>(wait));
             }
         }
         if (wall_s) *wall_s = now_s();

@@ -1,5 +1,6 @@
-"""Autotuner of the batch launch: waves per block, visited-cache size and
-re-rank waves per block, chosen by timing a sample batch through libaqr.
+"""Autotuner of the batch launch: waves per block, resident waves per CU,
+visited-cache size and re-rank waves per block, chosen by timing a sample
+batch through libaqr.
 
 The search result does not depend on these choices (only the speed does);
 the tests check that.  Results are cached in a JSON file keyed by the index
@@ -15,6 +16,9 @@ from . import aqr
 SEARCH_WPB = (1, 2, 4)
 VISITED_LOG2 = (8, 9, 10)
 RERANK_WPB = (2, 4)
+# resident search waves per CU: 0 = as many as occupancy allows, else the
+# persistent grid is cut to this many waves per CU
+WAVES_PER_CU = (0, 8)
 
 
 def _key(ix, ef_max, k_max, device_name):
@@ -47,8 +51,11 @@ def autotune(ix, Q, k, ef, k_max, ef_max, cache_path=None, reps=3, log=None):
         except ValueError:
             pass
     table = []
-    for wpb, vb, rwpb in itertools.product(SEARCH_WPB, VISITED_LOG2, RERANK_WPB):
-        tuning = dict(waves_per_block=wpb, visited_log2=vb, rerank_waves_per_block=rwpb)
+    n_cu = torch.cuda.get_device_properties(torch.cuda.current_device()).multi_processor_count
+    for wpb, vb, rwpb, wpc in itertools.product(SEARCH_WPB, VISITED_LOG2, RERANK_WPB,
+                                                WAVES_PER_CU):
+        tuning = dict(waves_per_block=wpb, visited_log2=vb, rerank_waves_per_block=rwpb,
+                      blocks=(n_cu * wpc) // wpb if wpc else 0)
         try:
             ms = time_config(ix, Q, k, ef, k_max, ef_max, tuning, reps)
         except aqr.AqrError as e:

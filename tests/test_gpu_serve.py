@@ -130,9 +130,10 @@ def test_serve_replay_trace(small):
     arrivals = W.poisson_arrivals(20000.0, nq, seed=7)
     sv = aqr.Server(small["ix"], K_MAX, EF_MAX, ring=256)
     try:
-        ids, dist, lat, wall = sv.replay(arrivals, Q, k, ef)
+        ids, dist, lat, wall, svc = sv.replay(arrivals, Q, k, ef, service=True)
     finally:
         sv.stop()
     for q in range(nq):
         check_row(ids[q], dist[q], ref, q)
     assert np.all(lat > 0) and wall >= arrivals[-1]
+    assert np.all(svc > 0) and np.all(svc <= lat + 1e-3)

@@ -189,6 +189,6 @@ def test_server_entry_points_reject_bad_arguments(L):
     done = C.c_int32()
     assert L.aqr_server_poll(None, 0, None, None, C.byref(done)) == aqr.INVALID_ARG
     assert L.aqr_server_stop(None) == aqr.INVALID_ARG
-    assert L.aqr_server_replay(None, 0, None, None, None, None, None, None, None, None) == \
-        aqr.INVALID_ARG
+    assert L.aqr_server_replay(None, 0, None, None, None, None, None, None, None, None,
+                               None) == aqr.INVALID_ARG
     L.aqr_server_destroy(None)
