@@ -538,7 +538,7 @@ def build_index(args, wl, X, threads):
         t_quant = time.perf_counter() - t
         t = time.perf_counter()
         g = aqr.aqr_build(codes, d, qz, threads=threads,
-                          level_u=W.level_draws(args.workload, n))
+                          level_u=W.level_draws(args.workload, n), progress=20)
         t_build = time.perf_counter() - t
         if cache:
             os.makedirs(cache, exist_ok=True)

@@ -118,7 +118,7 @@ typedef struct aqr_bparams {
     int32_t M;             /* connectivity; <= 0 takes M_i of the quantiser */
     int32_t efc;           /* construction depth; <= 0 takes ef^c of the quantiser */
     int32_t threads;       /* 1 = sequential and deterministic, 0 = all hardware threads */
-    int32_t reserved;
+    int32_t progress;      /* > 0: a line on stderr after each 1/progress of the points */
     uint64_t seed;         /* level draws when level_u is NULL (SplitMix64) */
 } aqr_bparams;
 
@@ -342,7 +342,7 @@ void aqr_plan_free(aqr_plan* plan);
 typedef struct aqr_server_params {
     int32_t ring;         /* request slots (the admission limit) */
     int32_t k_max;        /* largest k accepted (row length of a result) */
-    int32_t ef_max;       /* largest ef accepted (<= 512; sizes the LDS of every wave) */
+    int32_t ef_max;       /* largest ef accepted (<= 1024; sizes the LDS of every wave) */
     int32_t m_ef;         /* ef multiplier of N_c */
     int32_t n_rerank;     /* N_rerank */
     float tau_gap, tau_ratio, eps;  /* early termination (Table 3 row "0.97+": 0.010, 1.008) */

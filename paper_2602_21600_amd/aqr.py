@@ -38,7 +38,7 @@ class QInfo(C.Structure):
 
 class BParams(C.Structure):
     _fields_ = [("M", C.c_int32), ("efc", C.c_int32), ("threads", C.c_int32),
-                ("reserved", C.c_int32), ("seed", C.c_uint64)]
+                ("progress", C.c_int32), ("seed", C.c_uint64)]
 
 
 class GInfo(C.Structure):
@@ -275,10 +275,10 @@ def aqr_quantizer_create(info, mn, mx, scale):
     return Quantizer(h.value)
 
 
-def aqr_build(codes, d, qz, M=0, efc=0, threads=0, seed=0, level_u=None):
+def aqr_build(codes, d, qz, M=0, efc=0, threads=0, seed=0, level_u=None, progress=0):
     codes = np.ascontiguousarray(codes, np.uint8)
     n = codes.shape[0]
-    bp = BParams(M=M, efc=efc, threads=threads, reserved=0, seed=seed)
+    bp = BParams(M=M, efc=efc, threads=threads, progress=progress, seed=seed)
     lu = None if level_u is None else np.ascontiguousarray(level_u, np.float64)
     h = C.c_void_p()
     _check(lib().aqr_build(_np_ptr(codes), n, d, qz.ptr, C.byref(bp), _np_ptr(lu), C.byref(h)))

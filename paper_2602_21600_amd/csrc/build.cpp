@@ -16,6 +16,8 @@
 // the entry-point lock for its whole duration.
 #include <algorithm>
 #include <atomic>
+#include <cstdio>
+#include <chrono>
 #include <cmath>
 #include <cstring>
 #include <mutex>
@@ -268,9 +270,23 @@ extern "C" aqr_status aqr_build(const uint8_t* codes, int64_t n, int32_t d,
         g->L = g->level[0];
         const int T = host_threads(p->threads);
         Builder B(*g, codes, qz->info.d_pad, T > 1);
+        const int64_t step = p->progress > 0 ? std::max<int64_t>(1, n / p->progress) : 0;
+        const auto t0 = std::chrono::steady_clock::now();
+        auto report = [&](int64_t i) {
+            if (step && i % step == 0) {
+                const double s =
+                    std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+                std::fprintf(stderr, "[aqr_build] %lld / %lld points inserted, %.1f s\n",
+                             (long long)i, (long long)n, s);
+                std::fflush(stderr);
+            }
+        };
         if (T <= 1 || n < 2) {
             Visited vis(n);
-            for (int64_t i = 1; i < n; ++i) B.insert((uint32_t)i, vis);
+            for (int64_t i = 1; i < n; ++i) {
+                B.insert((uint32_t)i, vis);
+                report(i);
+            }
         } else {
             std::atomic<int64_t> next{1};
             parallel_for_threads(T, [&](int) {
@@ -279,6 +295,7 @@ extern "C" aqr_status aqr_build(const uint8_t* codes, int64_t n, int32_t d,
                     int64_t i = next.fetch_add(1);
                     if (i >= n) break;
                     B.insert((uint32_t)i, vis);
+                    report(i);
                 }
             });
         }

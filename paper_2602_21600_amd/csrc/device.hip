@@ -127,6 +127,37 @@ __device__ __forceinline__ uint32_t wave_sum_u32(uint32_t v) {
     return v;
 }
 
+// Sum over aligned groups of G lanes (G a power of two <= 64), result in
+// every lane of the group.  Steps inside a row of 16 lanes use DPP lane
+// permutes (quad swaps, then the half-row and row mirrors); wider groups
+// finish with LDS-routed permutes.  Every step pairs lanes symmetrically, so
+// all lanes of a group hold the same value, also in floating point.
+template <int CTRL>
+__device__ __forceinline__ uint32_t dpp_t(uint32_t v) {
+    return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, CTRL, 0xF, 0xF, false);
+}
+constexpr int kDppXor1 = 0xB1;        // quad_perm [1,0,3,2]
+constexpr int kDppXor2 = 0x4E;        // quad_perm [2,3,0,1]
+constexpr int kDppHalfMirror = 0x141; // lane i <-> 7 - i in each group of 8
+constexpr int kDppMirror = 0x140;     // lane i <-> 15 - i in each row of 16
+
+__device__ __forceinline__ uint32_t group_sum_u32(uint32_t v, int G) {
+    if (G >= 2) v += dpp_t<kDppXor1>(v);
+    if (G >= 4) v += dpp_t<kDppXor2>(v);
+    if (G >= 8) v += dpp_t<kDppHalfMirror>(v);
+    if (G >= 16) v += dpp_t<kDppMirror>(v);
+    for (int m = 16; m < G; m <<= 1) v += shfl_xor_u32(v, m);
+    return v;
+}
+__device__ __forceinline__ float group_sum_f32(float v, int G) {
+    if (G >= 2) v += __uint_as_float(dpp_t<kDppXor1>(__float_as_uint(v)));
+    if (G >= 4) v += __uint_as_float(dpp_t<kDppXor2>(__float_as_uint(v)));
+    if (G >= 8) v += __uint_as_float(dpp_t<kDppHalfMirror>(__float_as_uint(v)));
+    if (G >= 16) v += __uint_as_float(dpp_t<kDppMirror>(__float_as_uint(v)));
+    for (int m = 16; m < G; m <<= 1) v += shfl_xor_f32(v, m);
+    return v;
+}
+
 __device__ __forceinline__ uint32_t dot4(uint32_t a, uint32_t b, uint32_t c) {
     return __builtin_amdgcn_udot4(a, b, c, false);
 }
@@ -169,8 +200,8 @@ struct Rows<false> {
     }
     __device__ static __forceinline__ uint32_t zero() { return 0u; }
     __device__ static __forceinline__ uint32_t add(uint32_t a, uint32_t b) { return a + b; }
-    __device__ static __forceinline__ uint32_t xor_shfl(uint32_t v, int m) {
-        return shfl_xor_u32(v, m);
+    __device__ static __forceinline__ uint32_t group_sum(uint32_t v, int G) {
+        return group_sum_u32(v, G);
     }
     // key distance bits from the reduced partial and |q|^2
     __device__ static __forceinline__ uint32_t dbits(uint32_t s, uint32_t qq) { return qq + s; }
@@ -197,7 +228,7 @@ struct Rows<true> {
     }
     __device__ static __forceinline__ float zero() { return 0.0f; }
     __device__ static __forceinline__ float add(float a, float b) { return a + b; }
-    __device__ static __forceinline__ float xor_shfl(float v, int m) { return shfl_xor_f32(v, m); }
+    __device__ static __forceinline__ float group_sum(float v, int G) { return group_sum_f32(v, G); }
     __device__ static __forceinline__ uint32_t dbits(float s, uint32_t) { return __float_as_uint(s); }
 };
 
@@ -243,7 +274,7 @@ __device__ __forceinline__ void eval_rows(const Idx& ix, const uint32_t* ids, in
             typename R::Acc s = R::zero();
 #pragma unroll
             for (int c = 0; c < CPL; ++c) s = R::add(s, R::part(x[u][c], qv[c]));
-            for (int m = g.G >> 1; m >= 1; m >>= 1) s = R::add(s, R::xor_shfl(s, m));
+            s = R::group_sum(s, g.G);
             const int r = r0 + u * g.rpp + g.grp;
             if (g.sub == 0 && r < nn)
                 keys[r] = ((uint64_t)R::dbits(s, qq) << 32) | (uint64_t)id[u];
@@ -324,19 +355,19 @@ __device__ __forceinline__ uint64_t readlane64(uint64_t v, int l) {
 
 // Stage 1 of one valid query, run by the whole wave.
 //
-// The result list W (at most ef_cap = 64*S keys, sorted) and its expanded
-// flags live in LDS.  A merge loads W into registers striped (entry i is
-// slot i/64 of lane i%64, invalid entries ~0), ranks each admitted key
-// against it and checks it for an equal key with 64-bit compares and
-// ballots, then scatters W and the admitted keys to their merged positions
-// in place.  Keeping W out of registers between merges keeps the register
-// peak at the distance phase, which sets the number of waves per CU.
+// The result list W (at most ef_cap keys, sorted) and its expanded flags
+// live in LDS.  A merge finds each admitted key's place in W by bisection
+// (one lane per key), drops keys already in W, ranks the admitted keys among
+// themselves, then shifts the W entries above the lowest insertion point
+// slot by slot (64 entries per slot, last slot first) and writes the
+// admitted keys into the gaps.  Only the slots at or above the lowest
+// insertion point are touched, and W is never held in registers.
 //
 // Every branch that steers a loop is on a wave-uniform value (a ballot, a
 // popcount or a readfirstlane), and every single-lane block is closed by a
 // wave barrier before the next loop control, so all lanes stay converged at
 // each cross-lane operation.
-template <bool F32, int CPL, int U, int S>
+template <bool F32, int CPL, int U>
 __device__ __forceinline__ void search_query(const SearchArgs& a, const int64_t q, const int efe,
                                              const int nc, const int lane, const Geo& g,
                                              const VisCache& vis, uint64_t* mk, uint8_t* mf,
@@ -473,63 +504,51 @@ __device__ __forceinline__ void search_query(const SearchArgs& a, const int64_t 
             const uint64_t key = j < nn ? st_key[j] : ~0ull;
             uint64_t A = ballot(key < bound);
             if (A == 0) continue;
-            uint64_t w[S];
-            uint32_t wfl = 0;
-#pragma unroll
-            for (int s = 0; s < S; ++s) {
-                const int i = s * kWave + lane;
-                w[s] = i < wsize ? mk[i] : ~0ull;
-                wfl |= (i < wsize && mf[i]) ? (1u << s) : 0u;
+            // entries of W below the key, by bisection of the sorted list
+            int lo = 0;
+            for (int step = 1 << (31 - __builtin_clz((unsigned)wsize)); step > 0; step >>= 1) {
+                const int p = lo + step - 1;
+                if (p < wsize && mk[p] < key) lo += step;
             }
-            int posW = 0, rankA = 0;
-            uint32_t sh[S];
-#pragma unroll
-            for (int s = 0; s < S; ++s) sh[s] = 0;
-            uint64_t dupm = 0;
-            for (uint64_t it = A; it != 0; it &= it - 1) {
-                const int t = (int)__builtin_ctzll(it);
-                const uint64_t kt = readlane64(key, t);
-                int r = 0;
-                uint64_t eq = 0;
-#pragma unroll
-                for (int s = 0; s < S; ++s) {
-                    r += __popcll(ballot(w[s] < kt));
-                    eq |= ballot(w[s] == kt);
-                }
-                if (eq != 0) {
-                    dupm |= 1ull << t;  // already in W: a forgotten node scored again
-                } else {
-                    if (lane == t) posW = r;
-#pragma unroll
-                    for (int s = 0; s < S; ++s) sh[s] += kt < w[s] ? 1u : 0u;
-                    rankA += kt < key ? 1 : 0;
-                }
-            }
-            A &= ~dupm;
+            // a key already in W (a node the visited cache forgot) is dropped
+            A &= ~ballot(lo < wsize && mk[lo] == key);
             const int m_adm = __popcll(A);
             if (m_adm == 0) continue;
             n_adm += m_adm;
             const bool mine = ((A >> lane) & 1ull) != 0;
-            const int pos = posW + rankA;
-            // W entry i moves to i + (admitted keys below it); an admitted key
-            // to (W entries below it) + (admitted keys below it).  All of W is
-            // in registers, so the scatter can overwrite the LDS copy.
+            int rankA = 0;
+            int lo_min = INT_MAX;
+            for (uint64_t it = A; it != 0; it &= it - 1) {
+                const int t = (int)__builtin_ctzll(it);
+                rankA += readlane64(key, t) < key ? 1 : 0;
+                lo_min = min(lo_min, __builtin_amdgcn_readlane(lo, t));
+            }
+            const int pos = lo + rankA;
+            // W entry i moves up by the number of admitted keys with lower
+            // bound <= i.  Slots are moved from the last one down: an entry
+            // only moves up and past the slots already moved, and each slot
+            // is read whole before it is written.
             wsync();
-#pragma unroll
-            for (int s = 0; s < S; ++s) {
-                const int i = s * kWave + lane;
-                const int p = i + (int)sh[s];
-                if (i < wsize && p < efe) {
-                    mk[p] = w[s];
-                    mf[p] = (uint8_t)((wfl >> s) & 1u);
+            for (int sl = (wsize - 1) >> 6; sl >= (lo_min >> 6); --sl) {
+                const int i = sl * kWave + lane;
+                const bool v = i < wsize && i >= lo_min;
+                const uint64_t w = v ? mk[i] : 0ull;
+                const uint8_t f = v ? mf[i] : (uint8_t)0;
+                int sh = 0;
+                for (uint64_t it = A; it != 0; it &= it - 1)
+                    sh += __builtin_amdgcn_readlane(lo, (int)__builtin_ctzll(it)) <= i ? 1 : 0;
+                const int p = i + sh;
+                if (v && p < efe) {
+                    mk[p] = w;
+                    mf[p] = f;
                 }
             }
             if (mine && pos < efe) {
                 mk[pos] = key;
                 mf[pos] = 0;
             }
-            const int pm = uni(wave_min_i32(mine ? pos : INT_MAX));
-            first = min(first, pm);
+            // the smallest admitted key has rank 0: its position is lo_min
+            first = min(first, lo_min);
             wsize = min(efe, wsize + m_adm);
             wsync();
         }
@@ -571,7 +590,7 @@ __device__ __forceinline__ void search_query(const SearchArgs& a, const int64_t 
     }
 }
 
-template <bool F32, int CPL, int U, int S>
+template <bool F32, int CPL, int U>
 __global__ __launch_bounds__(256) void k_search(SearchArgs a) {
     extern __shared__ __align__(16) unsigned char smem[];
     const int lane = lane_id();
@@ -637,7 +656,7 @@ __global__ __launch_bounds__(256) void k_search(SearchArgs a) {
                     }
                 }
             } else {
-                search_query<F32, CPL, U, S>(a, q, efe, nc, lane, g, vis, mk, mf, st_id, st_key,
+                search_query<F32, CPL, U>(a, q, efe, nc, lane, g, vis, mk, mf, st_id, st_key,
                                              visb, qf, qc);
             }
         }
@@ -793,7 +812,7 @@ __device__ __forceinline__ void rerank_query(const RerankArgs& a, const int lane
                     s += asym_chunk(x, qr[c], mr[c], sr[c]);
                 }
             }
-            for (int m = g.G >> 1; m >= 1; m >>= 1) s += shfl_xor_f32(s, m);
+            s = group_sum_f32(s, g.G);
             if (g.sub == 0 && r < nc) A[r] = ((uint64_t)__float_as_uint(s) << 32) | id;
         }
     }
@@ -838,7 +857,7 @@ __device__ __forceinline__ void rerank_query(const RerankArgs& a, const int lane
                 if (id != kNone && ch < g.nch)
                     s += Rows<true>::part(Rows<true>::load(ix, id, ch), qv[c]);
             }
-            for (int m = g.G >> 1; m >= 1; m >>= 1) s += shfl_xor_f32(s, m);
+            s = group_sum_f32(s, g.G);
             if (g.sub == 0 && r < nrr) {
                 Rk[r] = ((uint64_t)__float_as_uint(s) << 32) | id;
                 kind[r] = 1;
@@ -1024,7 +1043,7 @@ __device__ __forceinline__ void st_sys(T* p, T v) {
 // wait until every memory operation this wave issued has completed
 __device__ __forceinline__ void wait_mem() { asm volatile("s_waitcnt vmcnt(0)" ::: "memory"); }
 
-template <int CPL, int U, int S, int CPL8, int CPLF>
+template <int CPL, int U, int CPL8, int CPLF>
 __global__ __launch_bounds__(256) void k_serve(ServeArgs a) {
     extern __shared__ __align__(16) unsigned char smem[];
     const int lane = lane_id();
@@ -1154,7 +1173,7 @@ __global__ __launch_bounds__(256) void k_serve(ServeArgs a) {
         } else {
             // Stage 1 writes its N_c candidates into the search part; the
             // re-rank reads them from there
-            search_query<false, CPL, U, S>(sa, 0, efe, nc, lane, g, vis, mk, mf, st_id, st_key,
+            search_query<false, CPL, U>(sa, 0, efe, nc, lane, g, vis, mk, mf, st_id, st_key,
                                            visb, qf, qc);
             const int cnt = uni(*reinterpret_cast<const int*>(st_id));
             for (int j = lane; j < cnt; j += kWave) rids[j] = (uint32_t)mk[j];
@@ -1373,12 +1392,12 @@ extern "C" size_t aqr_search_workspace_size(void) { return 256; }
 
 namespace {
 
-template <bool F32, int CPL, int S>
-hipError_t launch_search_s(dev::SearchArgs& a, int blocks, int wpb, size_t lds, int ncu,
-                           hipStream_t s) {
-    // 16-byte loads in flight per lane in the distance phase: 4 for code rows, 2 for FP32 rows
-    constexpr int U = CPL >= 4 ? 1 : 4 / CPL / (F32 ? 2 : 1) > 0 ? 4 / CPL / (F32 ? 2 : 1) : 1;
-    auto kern = dev::k_search<F32, CPL, U, S>;
+template <bool F32, int CPL>
+hipError_t launch_search_cpl(dev::SearchArgs& a, int blocks, int wpb, size_t lds, int ncu,
+                             hipStream_t s) {
+    // 16-byte loads in flight per lane in the distance phase
+    constexpr int U = CPL >= 2 ? 1 : 2;
+    auto kern = dev::k_search<F32, CPL, U>;
     // the dynamic-LDS limit is raised once per size, outside any stream capture
     static std::atomic<int> lds_set{0};
     hipError_t e = hipSuccess;
@@ -1398,22 +1417,6 @@ hipError_t launch_search_s(dev::SearchArgs& a, int blocks, int wpb, size_t lds, 
     }
     hipLaunchKernelGGL(kern, dim3(blocks), dim3(wpb * dev::kWave), lds, s, a);
     return hipGetLastError();
-}
-
-template <bool F32, int CPL>
-hipError_t launch_search_cpl(dev::SearchArgs& a, int blocks, int wpb, size_t lds, int ncu,
-                             hipStream_t s) {
-    switch (a.ef_cap / 64) {
-        case 1: return launch_search_s<F32, CPL, 1>(a, blocks, wpb, lds, ncu, s);
-        case 2: return launch_search_s<F32, CPL, 2>(a, blocks, wpb, lds, ncu, s);
-        case 3:
-        case 4: return launch_search_s<F32, CPL, 4>(a, blocks, wpb, lds, ncu, s);
-        case 5:
-        case 6:
-        case 7:
-        case 8: return launch_search_s<F32, CPL, 8>(a, blocks, wpb, lds, ncu, s);
-        default: return launch_search_s<F32, CPL, 16>(a, blocks, wpb, lds, ncu, s);
-    }
 }
 
 template <bool F32>
@@ -1474,9 +1477,8 @@ aqr_status run_search(const aqr_index* ix, const float* Q, int64_t nq, const int
         return fail(AQR_ERR_INVALID_ARG, std::string(who) + ": waves_per_block must be 1, 2 or 4");
     if (v.s0 > 256)
         return fail(AQR_ERR_INVALID_ARG, std::string(who) + ": layer-0 rows above 256 entries are not supported");
-    int slots = 1;  // result-list slots per lane: a power of two >= ef_max / 64
-    while (slots * 64 < sp->ef_max) slots <<= 1;
-    dev::SearchLds sl{slots * 64,
+    const int ef_cap = (sp->ef_max + 63) / 64 * 64;  // W capacity: whole 64-entry slots
+    dev::SearchLds sl{ef_cap,
                       std::max(v.s0, v.s1) <= 64 ? 64 : (std::max(v.s0, v.s1) + 63) / 64 * 64, vb,
                       v.xs, v.dp};
     const size_t wl = sl.bytes();
@@ -1834,10 +1836,10 @@ namespace {
 constexpr uint64_t kFree = ~0ull;
 constexpr int kSlotBits = 22;  // ticket = sequence << 22 | slot
 
-template <int CPL, int S, int C8, int CF>
+template <int CPL, int C8, int CF>
 hipError_t serve_launch_t(aqr_server* sv) {
-    constexpr int U = CPL >= 4 ? 1 : 4 / CPL;
-    auto kern = dev::k_serve<CPL, U, S, C8, CF>;
+    constexpr int U = CPL >= 2 ? 1 : 2;
+    auto kern = dev::k_serve<CPL, U, C8, CF>;
     static std::atomic<int> lds_set{0};
     if ((int)sv->lds > lds_set.load()) {
         hipError_t e = hipFuncSetAttribute((const void*)kern,
@@ -1861,26 +1863,12 @@ hipError_t serve_launch_t(aqr_server* sv) {
     return hipGetLastError();
 }
 
-template <int CPL, int S>
-hipError_t (*pick_serve_cf(int c8, int cf))(aqr_server*) {
-    if (c8 == 1) {
-        switch (cf) {
-            case 1: return serve_launch_t<CPL, S, 1, 1>;
-            case 2: return serve_launch_t<CPL, S, 1, 2>;
-            case 4: return serve_launch_t<CPL, S, 1, 4>;
-            default: return nullptr;
-        }
-    }
-    return nullptr;
-}
-
-template <int CPL>
-hipError_t (*pick_serve_s(int slots, int c8, int cf))(aqr_server*) {
-    switch (slots) {
-        case 1: return pick_serve_cf<CPL, 1>(c8, cf);
-        case 2: return pick_serve_cf<CPL, 2>(c8, cf);
-        case 4: return pick_serve_cf<CPL, 4>(c8, cf);
-        case 8: return pick_serve_cf<CPL, 8>(c8, cf);
+hipError_t (*pick_serve(int c8, int cf))(aqr_server*) {
+    if (c8 != 1) return nullptr;
+    switch (cf) {
+        case 1: return serve_launch_t<1, 1, 1>;
+        case 2: return serve_launch_t<1, 1, 2>;
+        case 4: return serve_launch_t<1, 1, 4>;
         default: return nullptr;
     }
 }
@@ -1968,7 +1956,7 @@ extern "C" aqr_status aqr_server_create(const aqr_index* ix, const aqr_server_pa
         if (ws_bytes < aqr_server_workspace_size())
             return fail(AQR_ERR_OOM, "aqr_server_create: workspace too small");
         if (prm->ring < 1 || prm->ring > (1 << 22) || prm->k_max < 1 || prm->k_max > 1024 ||
-            prm->ef_max < 1 || prm->ef_max > 512 || prm->m_ef < 1 || prm->n_rerank < 0)
+            prm->ef_max < 1 || prm->ef_max > 1024 || prm->m_ef < 1 || prm->n_rerank < 0)
             return fail(AQR_ERR_INVALID_ARG, "aqr_server_create: parameter out of range");
         const Idx& v = ix->v;
         const int nch8 = v.dp / 16, nchf = v.xs / 4;
@@ -1977,9 +1965,7 @@ extern "C" aqr_status aqr_server_create(const aqr_index* ix, const aqr_server_pa
             return fail(AQR_ERR_INVALID_ARG, "aqr_server_create: serving supports d <= 1024");
         if (v.s0 > 256) return fail(AQR_ERR_INVALID_ARG, "aqr_server_create: rows above 256 entries");
         const int efm = std::max(prm->ef_max, prm->k_max);
-        int slots = 1;
-        while (slots * 64 < efm) slots <<= 1;
-        if (slots > 8) return fail(AQR_ERR_INVALID_ARG, "aqr_server_create: ef_max above 512");
+        const int ef_cap = (efm + 63) / 64 * 64;
         int vb = prm->visited_log2 > 0 ? prm->visited_log2 : 9;
         const int idb = std::max(v.idbits, vb + 1);
         if (idb - vb > 15) vb = idb - 15;
@@ -1992,7 +1978,7 @@ extern "C" aqr_status aqr_server_create(const aqr_index* ix, const aqr_server_pa
             delete sv;
             return fail(AQR_ERR_INVALID_ARG, "aqr_server_create: waves_per_block above 4");
         }
-        dev::SearchLds sl{slots * 64,
+        dev::SearchLds sl{ef_cap,
                           std::max(v.s0, v.s1) <= 64 ? 64 : (std::max(v.s0, v.s1) + 63) / 64 * 64,
                           vb, v.xs, v.dp};
         const size_t search_lds = sl.bytes();
@@ -2020,7 +2006,7 @@ extern "C" aqr_status aqr_server_create(const aqr_index* ix, const aqr_server_pa
         dev::SearchArgs& sa = sv->args.s;
         sa.ix = v;
         sa.m_ef = prm->m_ef;
-        sa.ef_cap = slots * 64;
+        sa.ef_cap = ef_cap;
         sa.out_stride = nc_max;
         sa.vb = vb;
         sa.mode = 2;
@@ -2032,9 +2018,7 @@ extern "C" aqr_status aqr_server_create(const aqr_index* ix, const aqr_server_pa
         sv->args.k_max = prm->k_max;
         sv->args.nc_max = nc_max;
         sv->args.idle_ticks = (uint64_t)std::max(1, prm->idle_ms) * 100000ull;
-        switch (c8) {
-            default: sv->launch_fn = pick_serve_s<1>(slots, c8, cf); break;
-        }
+        sv->launch_fn = pick_serve(c8, cf);
         if (!sv->launch_fn) {
             delete sv;
             return fail(AQR_ERR_INVALID_ARG, "aqr_server_create: unsupported row geometry");
