@@ -158,6 +158,40 @@ __device__ __forceinline__ float group_sum_f32(float v, int G) {
     return v;
 }
 
+// Sum over aligned groups of 2^LG lanes, known at compile time; the sum is
+// complete in the last lane of each group (lanes G-1, 2G-1, ...).  Inside a
+// row of 16 the butterfly above leaves it in every lane; across rows the
+// row broadcasts add row 0 into row 1 and row 2 into row 3, then rows 0-1
+// into row 3.
+constexpr int kDppBcast15 = 0x142;    // lane 15 of each row to the next row
+constexpr int kDppBcast31 = 0x143;    // lane 31 to rows 2 and 3
+template <int LG>
+__device__ __forceinline__ uint32_t gsum_u32(uint32_t v) {
+    if constexpr (LG >= 1) v += dpp_t<kDppXor1>(v);
+    if constexpr (LG >= 2) v += dpp_t<kDppXor2>(v);
+    if constexpr (LG >= 3) v += dpp_t<kDppHalfMirror>(v);
+    if constexpr (LG >= 4) v += dpp_t<kDppMirror>(v);
+    if constexpr (LG >= 5)
+        v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, kDppBcast15, 0xA, 0xF, false);
+    if constexpr (LG >= 6)
+        v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, kDppBcast31, 0xC, 0xF, false);
+    return v;
+}
+template <int LG>
+__device__ __forceinline__ float gsum_f32(float v) {
+    if constexpr (LG >= 1) v += __uint_as_float(dpp_t<kDppXor1>(__float_as_uint(v)));
+    if constexpr (LG >= 2) v += __uint_as_float(dpp_t<kDppXor2>(__float_as_uint(v)));
+    if constexpr (LG >= 3) v += __uint_as_float(dpp_t<kDppHalfMirror>(__float_as_uint(v)));
+    if constexpr (LG >= 4) v += __uint_as_float(dpp_t<kDppMirror>(__float_as_uint(v)));
+    if constexpr (LG >= 5)
+        v += __uint_as_float((uint32_t)__builtin_amdgcn_update_dpp(
+            0, (int)__float_as_uint(v), kDppBcast15, 0xA, 0xF, false));
+    if constexpr (LG >= 6)
+        v += __uint_as_float((uint32_t)__builtin_amdgcn_update_dpp(
+            0, (int)__float_as_uint(v), kDppBcast31, 0xC, 0xF, false));
+    return v;
+}
+
 __device__ __forceinline__ uint32_t dot4(uint32_t a, uint32_t b, uint32_t c) {
     return __builtin_amdgcn_udot4(a, b, c, false);
 }
@@ -200,8 +234,9 @@ struct Rows<false> {
     }
     __device__ static __forceinline__ uint32_t zero() { return 0u; }
     __device__ static __forceinline__ uint32_t add(uint32_t a, uint32_t b) { return a + b; }
-    __device__ static __forceinline__ uint32_t group_sum(uint32_t v, int G) {
-        return group_sum_u32(v, G);
+    template <int LG>
+    __device__ static __forceinline__ uint32_t gsum(uint32_t v) {
+        return gsum_u32<LG>(v);
     }
     // key distance bits from the reduced partial and |q|^2
     __device__ static __forceinline__ uint32_t dbits(uint32_t s, uint32_t qq) { return qq + s; }
@@ -228,7 +263,10 @@ struct Rows<true> {
     }
     __device__ static __forceinline__ float zero() { return 0.0f; }
     __device__ static __forceinline__ float add(float a, float b) { return a + b; }
-    __device__ static __forceinline__ float group_sum(float v, int G) { return group_sum_f32(v, G); }
+    template <int LG>
+    __device__ static __forceinline__ float gsum(float v) {
+        return gsum_f32<LG>(v);
+    }
     __device__ static __forceinline__ uint32_t dbits(float s, uint32_t) { return __float_as_uint(s); }
 };
 
@@ -248,35 +286,42 @@ __device__ __forceinline__ Geo make_geo(int lg, int nch, int lane) {
 }
 
 // Score nn rows whose ids are ids[0..nn) (LDS); keys[r] = (dist bits << 32) | id.
-template <bool F32, int CPL, int U>
+// Rows are spread over groups of 2^LG lanes, one 16-byte chunk per lane and
+// CPL chunks per lane.  There are no divergent branches: rows past nn and
+// chunks past the row read row 0 / chunk 0 (valid memory) and are masked out
+// of the sum, and ids[] is read up to one pass past nn (the caller's array
+// has that slack).
+template <bool F32, int CPL, int U, int LG>
 __device__ __forceinline__ void eval_rows(const Idx& ix, const uint32_t* ids, int nn,
                                           uint64_t* keys, const uint4 (&qv)[CPL], uint32_t qq,
-                                          const Geo& g) {
+                                          const int lane, const int nch) {
     using R = Rows<F32>;
-    for (int r0 = 0; r0 < nn; r0 += g.rpp * U) {
+    constexpr int G = 1 << LG, RPP = kWave >> LG;
+    const int sub = lane & (G - 1), grp = lane >> LG;
+    for (int r0 = 0; r0 < nn; r0 += RPP * U) {
         uint4 x[U][CPL];
         uint32_t id[U];
 #pragma unroll
         for (int u = 0; u < U; ++u) {
-            const int r = r0 + u * g.rpp + g.grp;
-            id[u] = r < nn ? ids[r] : kNone;
+            const int r = r0 + u * RPP + grp;
+            id[u] = r < nn ? ids[r] : 0u;
 #pragma unroll
             for (int c = 0; c < CPL; ++c) {
-                const int ch = g.sub + c * g.G;
-                if (id[u] != kNone && ch < g.nch)
-                    x[u][c] = R::load(ix, id[u], ch);
-                else
-                    x[u][c] = make_uint4(0u, 0u, 0u, 0u);
+                const int ch = sub + c * G;
+                x[u][c] = R::load(ix, id[u], ch < nch ? ch : 0);
             }
         }
 #pragma unroll
         for (int u = 0; u < U; ++u) {
             typename R::Acc s = R::zero();
 #pragma unroll
-            for (int c = 0; c < CPL; ++c) s = R::add(s, R::part(x[u][c], qv[c]));
-            s = R::group_sum(s, g.G);
-            const int r = r0 + u * g.rpp + g.grp;
-            if (g.sub == 0 && r < nn)
+            for (int c = 0; c < CPL; ++c) {
+                const typename R::Acc t = R::part(x[u][c], qv[c]);
+                s = R::add(s, sub + c * G < nch ? t : R::zero());
+            }
+            s = R::template gsum<LG>(s);
+            const int r = r0 + u * RPP + grp;
+            if (sub == G - 1 && r < nn)
                 keys[r] = ((uint64_t)R::dbits(s, qq) << 32) | (uint64_t)id[u];
         }
     }
@@ -367,9 +412,9 @@ __device__ __forceinline__ uint64_t readlane64(uint64_t v, int l) {
 // popcount or a readfirstlane), and every single-lane block is closed by a
 // wave barrier before the next loop control, so all lanes stay converged at
 // each cross-lane operation.
-template <bool F32, int CPL, int U>
+template <bool F32, int CPL, int U, int LG, bool TAPS>
 __device__ __forceinline__ void search_query(const SearchArgs& a, const int64_t q, const int efe,
-                                             const int nc, const int lane, const Geo& g,
+                                             const int nc, const int lane,
                                              const VisCache& vis, uint64_t* mk, uint8_t* mf,
                                              uint32_t* st_id, uint64_t* st_key, uint64_t* visb,
                                              float* qf, uint8_t* qc) {
@@ -388,8 +433,8 @@ __device__ __forceinline__ void search_query(const SearchArgs& a, const int64_t 
     uint4 qv[CPL];
 #pragma unroll
     for (int c = 0; c < CPL; ++c) {
-        const int ch = g.sub + c * g.G;
-        if (ch < g.nch)
+        const int ch = (lane & ((1 << LG) - 1)) + (c << LG);
+        if (ch < a.nch)
             qv[c] = F32 ? reinterpret_cast<const uint4*>(qf)[ch]
                         : reinterpret_cast<const uint4*>(qc)[ch];
         else
@@ -403,7 +448,7 @@ __device__ __forceinline__ void search_query(const SearchArgs& a, const int64_t 
     uint32_t cur = ix.ep;
     if (lane == 0) st_id[0] = cur;
     wsync();
-    eval_rows<F32, CPL, U>(ix, st_id, 1, st_key, qv, qq, g);
+    eval_rows<F32, CPL, U, LG>(ix, st_id, 1, st_key, qv, qq, lane, a.nch);
     wsync();
     uint64_t curkey = uni64(st_key[0]);
     for (int l = ix.L; l >= 1; --l) {
@@ -417,7 +462,7 @@ __device__ __forceinline__ void search_query(const SearchArgs& a, const int64_t 
                 cnt += __popcll(m);
             }
             wsync();
-            eval_rows<F32, CPL, U>(ix, st_id, cnt, st_key, qv, qq, g);
+            eval_rows<F32, CPL, U, LG>(ix, st_id, cnt, st_key, qv, qq, lane, a.nch);
             wsync();
             n_up += cnt;
             ++n_upx;
@@ -451,7 +496,8 @@ __device__ __forceinline__ void search_query(const SearchArgs& a, const int64_t 
         int idx = -1;
         for (int b0 = first & ~(kWave - 1); b0 < wsize; b0 += kWave) {
             const int i = b0 + lane;
-            const uint64_t m = ballot(i >= first && i < wsize && mf[i] == 0);
+            const uint8_t f = mf[i];  // inside W's capacity (whole 64-entry slots)
+            const uint64_t m = ballot(i >= first && i < wsize && f == 0);
             if (m) {
                 idx = b0 + (int)__builtin_ctzll(m);
                 break;
@@ -464,7 +510,7 @@ __device__ __forceinline__ void search_query(const SearchArgs& a, const int64_t 
         wsync();
         if (lane == 0) {
             mf[idx] = 1;
-            if (a.taps.expanded && (int)n_exp < a.taps.cap)
+            if (TAPS && a.taps.expanded && (int)n_exp < a.taps.cap)
                 a.taps.expanded[q * a.taps.cap + n_exp] = c;
         }
         wsync();
@@ -488,14 +534,14 @@ __device__ __forceinline__ void search_query(const SearchArgs& a, const int64_t 
         wsync();
         nn = uni(nn);
         if (nn == 0) continue;
-        if (a.taps.evaluated) {
+        if (TAPS && a.taps.evaluated) {
             for (int j = lane; j < nn; j += kWave) {
                 const int p = (int)n_eval + j;
                 if (p < a.taps.cap) a.taps.evaluated[q * a.taps.cap + p] = st_id[j];
             }
         }
         n_eval += nn;
-        eval_rows<F32, CPL, U>(ix, st_id, nn, st_key, qv, qq, g);
+        eval_rows<F32, CPL, U, LG>(ix, st_id, nn, st_key, qv, qq, lane, a.nch);
         wsync();
         // merge the scored neighbours, 64 at a time
         for (int b0 = 0; b0 < nn; b0 += kWave) {
@@ -576,7 +622,7 @@ __device__ __forceinline__ void search_query(const SearchArgs& a, const int64_t 
             a.out_D[q * a.out_stride + i] = v ? (uint32_t)(key >> 32) : 0x7F800000u;
         }
     }
-    if (a.taps.counts && lane == 0) {
+    if (TAPS && a.taps.counts && lane == 0) {
         const uint64_t t_end = __builtin_amdgcn_s_memrealtime();
         uint32_t* cq = a.taps.counts + q * 8;
         cq[0] = n_exp;
@@ -590,7 +636,7 @@ __device__ __forceinline__ void search_query(const SearchArgs& a, const int64_t 
     }
 }
 
-template <bool F32, int CPL, int U>
+template <bool F32, int CPL, int U, int LG, bool TAPS>
 __global__ __launch_bounds__(256) void k_search(SearchArgs a) {
     extern __shared__ __align__(16) unsigned char smem[];
     const int lane = lane_id();
@@ -609,7 +655,6 @@ __global__ __launch_bounds__(256) void k_search(SearchArgs a) {
     float* qf = reinterpret_cast<float*>(visb + ((size_t)1 << a.vb));
     uint8_t* qc = reinterpret_cast<uint8_t*>(qf + ix.xs);
 
-    const Geo g = make_geo(a.lg, a.nch, lane);
     VisCache vis{visb, a.vb, max(ix.idbits, a.vb + 1)};
 
     for (;;) {
@@ -656,7 +701,7 @@ __global__ __launch_bounds__(256) void k_search(SearchArgs a) {
                     }
                 }
             } else {
-                search_query<F32, CPL, U>(a, q, efe, nc, lane, g, vis, mk, mf, st_id, st_key,
+                search_query<F32, CPL, U, LG, TAPS>(a, q, efe, nc, lane, vis, mk, mf, st_id, st_key,
                                              visb, qf, qc);
             }
         }
@@ -1043,7 +1088,7 @@ __device__ __forceinline__ void st_sys(T* p, T v) {
 // wait until every memory operation this wave issued has completed
 __device__ __forceinline__ void wait_mem() { asm volatile("s_waitcnt vmcnt(0)" ::: "memory"); }
 
-template <int CPL, int U, int CPL8, int CPLF>
+template <int CPL, int U, int LG, int CPL8, int CPLF>
 __global__ __launch_bounds__(256) void k_serve(ServeArgs a) {
     extern __shared__ __align__(16) unsigned char smem[];
     const int lane = lane_id();
@@ -1103,7 +1148,6 @@ __global__ __launch_bounds__(256) void k_serve(ServeArgs a) {
     uint8_t* kind = reinterpret_cast<uint8_t*>(Rs + r_cap);
     uint8_t* kinds = kind + r_cap;
     uint32_t* rids = reinterpret_cast<uint32_t*>(kinds + r_cap);
-    const Geo g = make_geo(sa.lg, sa.nch, lane);
     VisCache vis{visb, sa.vb, max(ix.idbits, sa.vb + 1)};
 
     for (;;) {
@@ -1173,7 +1217,7 @@ __global__ __launch_bounds__(256) void k_serve(ServeArgs a) {
         } else {
             // Stage 1 writes its N_c candidates into the search part; the
             // re-rank reads them from there
-            search_query<false, CPL, U>(sa, 0, efe, nc, lane, g, vis, mk, mf, st_id, st_key,
+            search_query<false, CPL, U, LG, false>(sa, 0, efe, nc, lane, vis, mk, mf, st_id, st_key,
                                            visb, qf, qc);
             const int cnt = uni(*reinterpret_cast<const int*>(st_id));
             for (int j = lane; j < cnt; j += kWave) rids[j] = (uint32_t)mk[j];
@@ -1392,20 +1436,22 @@ extern "C" size_t aqr_search_workspace_size(void) { return 256; }
 
 namespace {
 
-template <bool F32, int CPL>
-hipError_t launch_search_cpl(dev::SearchArgs& a, int blocks, int wpb, size_t lds, int ncu,
-                             hipStream_t s) {
+template <bool F32, int CPL, int LG>
+hipError_t launch_search_k(dev::SearchArgs& a, int blocks, int wpb, size_t lds, int ncu,
+                           hipStream_t s) {
     // 16-byte loads in flight per lane in the distance phase
     constexpr int U = CPL >= 2 ? 1 : 2;
-    auto kern = dev::k_search<F32, CPL, U>;
-    // the dynamic-LDS limit is raised once per size, outside any stream capture
-    static std::atomic<int> lds_set{0};
+    const bool taps = a.taps.expanded || a.taps.evaluated || a.taps.counts;
+    auto kern = taps ? dev::k_search<F32, CPL, U, LG, true> : dev::k_search<F32, CPL, U, LG, false>;
+    // the dynamic-LDS limit is raised once per size and kernel, outside any stream capture
+    static std::atomic<int> lds_set[2] = {0, 0};
+    std::atomic<int>& ls = lds_set[taps ? 1 : 0];
     hipError_t e = hipSuccess;
-    if ((int)lds > lds_set.load()) {
+    if ((int)lds > ls.load()) {
         e = hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize,
                                 (int)lds);
         if (e != hipSuccess) return e;
-        lds_set.store((int)lds);
+        ls.store((int)lds);
     }
     if (blocks <= 0) {
         int per_cu = 0;
@@ -1419,22 +1465,31 @@ hipError_t launch_search_cpl(dev::SearchArgs& a, int blocks, int wpb, size_t lds
     return hipGetLastError();
 }
 
+// Row geometry: CPL 16-byte chunks per lane, groups of 2^lg lanes per row
+// (lg >= 2; with CPL > 1 a row spans the wave).
 template <bool F32>
-hipError_t launch_search(dev::SearchArgs& a, int cpl, int blocks, int wpb, size_t lds, int ncu,
-                         hipStream_t s) {
+hipError_t launch_search(dev::SearchArgs& a, int cpl, int lg, int blocks, int wpb, size_t lds,
+                         int ncu, hipStream_t s) {
+    if (cpl == 1) {
+        switch (lg) {
+            case 2: return launch_search_k<F32, 1, 2>(a, blocks, wpb, lds, ncu, s);
+            case 3: return launch_search_k<F32, 1, 3>(a, blocks, wpb, lds, ncu, s);
+            case 4: return launch_search_k<F32, 1, 4>(a, blocks, wpb, lds, ncu, s);
+            case 5: return launch_search_k<F32, 1, 5>(a, blocks, wpb, lds, ncu, s);
+            default: return launch_search_k<F32, 1, 6>(a, blocks, wpb, lds, ncu, s);
+        }
+    }
     if constexpr (F32) {
         switch (cpl) {
-            case 1: return launch_search_cpl<F32, 1>(a, blocks, wpb, lds, ncu, s);
-            case 2: return launch_search_cpl<F32, 2>(a, blocks, wpb, lds, ncu, s);
-            case 4: return launch_search_cpl<F32, 4>(a, blocks, wpb, lds, ncu, s);
-            case 8: return launch_search_cpl<F32, 8>(a, blocks, wpb, lds, ncu, s);
-            default: return launch_search_cpl<F32, 16>(a, blocks, wpb, lds, ncu, s);
+            case 2: return launch_search_k<F32, 2, 6>(a, blocks, wpb, lds, ncu, s);
+            case 4: return launch_search_k<F32, 4, 6>(a, blocks, wpb, lds, ncu, s);
+            case 8: return launch_search_k<F32, 8, 6>(a, blocks, wpb, lds, ncu, s);
+            default: return launch_search_k<F32, 16, 6>(a, blocks, wpb, lds, ncu, s);
         }
     } else {
         switch (cpl) {
-            case 1: return launch_search_cpl<F32, 1>(a, blocks, wpb, lds, ncu, s);
-            case 2: return launch_search_cpl<F32, 2>(a, blocks, wpb, lds, ncu, s);
-            default: return launch_search_cpl<F32, 4>(a, blocks, wpb, lds, ncu, s);
+            case 2: return launch_search_k<F32, 2, 6>(a, blocks, wpb, lds, ncu, s);
+            default: return launch_search_k<F32, 4, 6>(a, blocks, wpb, lds, ncu, s);
         }
     }
 }
@@ -1500,7 +1555,7 @@ aqr_status run_search(const aqr_index* ix, const float* Q, int64_t nq, const int
     a.mode = f32 ? 1 : 0;
     const int nch = f32 ? v.xs / 4 : v.dp / 16;
     a.nch = nch;
-    a.lg = pow2_lg_for(nch);
+    a.lg = std::max(2, pow2_lg_for(nch));
     a.wave_lds = wl;
     a.out_id = out_id;
     a.out_D = out_D;
@@ -1519,8 +1574,8 @@ aqr_status run_search(const aqr_index* ix, const float* Q, int64_t nq, const int
     const int cpl = cpl_for(nch);
     if (cpl > 16) return fail(AQR_ERR_INVALID_ARG, std::string(who) + ": row too wide");
     if (!f32 && cpl > 4) return fail(AQR_ERR_INVALID_ARG, std::string(who) + ": code row too wide");
-    e = f32 ? launch_search<true>(a, cpl, sp->blocks, wpb, lds, ix->num_cu, s)
-            : launch_search<false>(a, cpl, sp->blocks, wpb, lds, ix->num_cu, s);
+    e = f32 ? launch_search<true>(a, cpl, a.lg, sp->blocks, wpb, lds, ix->num_cu, s)
+            : launch_search<false>(a, cpl, a.lg, sp->blocks, wpb, lds, ix->num_cu, s);
     if (e != hipSuccess) return hip_fail(e, who);
     return AQR_OK;
 }
@@ -1836,10 +1891,10 @@ namespace {
 constexpr uint64_t kFree = ~0ull;
 constexpr int kSlotBits = 22;  // ticket = sequence << 22 | slot
 
-template <int CPL, int C8, int CF>
+template <int CPL, int LG, int C8, int CF>
 hipError_t serve_launch_t(aqr_server* sv) {
     constexpr int U = CPL >= 2 ? 1 : 2;
-    auto kern = dev::k_serve<CPL, U, C8, CF>;
+    auto kern = dev::k_serve<CPL, U, LG, C8, CF>;
     static std::atomic<int> lds_set{0};
     if ((int)sv->lds > lds_set.load()) {
         hipError_t e = hipFuncSetAttribute((const void*)kern,
@@ -1863,13 +1918,24 @@ hipError_t serve_launch_t(aqr_server* sv) {
     return hipGetLastError();
 }
 
-hipError_t (*pick_serve(int c8, int cf))(aqr_server*) {
-    if (c8 != 1) return nullptr;
+template <int LG>
+hipError_t (*pick_serve_cf(int cf))(aqr_server*) {
     switch (cf) {
-        case 1: return serve_launch_t<1, 1, 1>;
-        case 2: return serve_launch_t<1, 1, 2>;
-        case 4: return serve_launch_t<1, 1, 4>;
+        case 1: return serve_launch_t<1, LG, 1, 1>;
+        case 2: return serve_launch_t<1, LG, 1, 2>;
+        case 4: return serve_launch_t<1, LG, 1, 4>;
         default: return nullptr;
+    }
+}
+
+hipError_t (*pick_serve(int c8, int lg, int cf))(aqr_server*) {
+    if (c8 != 1) return nullptr;
+    switch (lg) {
+        case 2: return pick_serve_cf<2>(cf);
+        case 3: return pick_serve_cf<3>(cf);
+        case 4: return pick_serve_cf<4>(cf);
+        case 5: return pick_serve_cf<5>(cf);
+        default: return pick_serve_cf<6>(cf);
     }
 }
 
@@ -2011,14 +2077,14 @@ extern "C" aqr_status aqr_server_create(const aqr_index* ix, const aqr_server_pa
         sa.vb = vb;
         sa.mode = 2;
         sa.nch = nch8;
-        sa.lg = pow2_lg_for(nch8);
+        sa.lg = std::max(2, pow2_lg_for(nch8));
         sa.wave_lds = wave_lds;
         sv->args.search_lds = search_lds;
         sv->args.ring = prm->ring;
         sv->args.k_max = prm->k_max;
         sv->args.nc_max = nc_max;
         sv->args.idle_ticks = (uint64_t)std::max(1, prm->idle_ms) * 100000ull;
-        sv->launch_fn = pick_serve(c8, cf);
+        sv->launch_fn = pick_serve(c8, sa.lg, cf);
         if (!sv->launch_fn) {
             delete sv;
             return fail(AQR_ERR_INVALID_ARG, "aqr_server_create: unsupported row geometry");
