@@ -349,6 +349,19 @@ struct VisCache {
         if (!hit) b[bucket] = (w << 16) | e;
         return hit;
     }
+    // Whole-wave form: lanes with nothing to insert (an invalid id, or a
+    // hit) write the spare bucket 2^vb instead of branching around the store.
+    __device__ __forceinline__ bool test_insert_if(uint32_t id, bool valid) const {
+        const uint32_t mask = B >= 32 ? 0xFFFFFFFFu : ((1u << B) - 1u);
+        const uint32_t h = ((valid ? id : 0u) * 0x9E3779B1u) & mask;
+        const uint32_t bucket = h >> (B - vb);
+        const uint32_t e = (h & ((1u << (B - vb)) - 1u)) | 0x8000u;
+        const uint64_t w = b[bucket];
+        const bool hit = ((uint32_t)(w & 0xFFFFu) == e) | ((uint32_t)((w >> 16) & 0xFFFFu) == e) |
+                         ((uint32_t)((w >> 32) & 0xFFFFu) == e) | ((uint32_t)(w >> 48) == e);
+        b[valid && !hit ? bucket : (1u << vb)] = (w << 16) | e;
+        return hit;
+    }
 };
 
 // ---------------------------------------------------------------------------
@@ -356,19 +369,23 @@ struct VisCache {
 // ---------------------------------------------------------------------------
 struct SearchLds {
     int ef_cap, st_cap, vb, xs, dp;
-    __host__ __device__ size_t bytes() const {
-        size_t o = 0;
-        o += (size_t)ef_cap * 8;           // merge buffer: keys
-        o += (size_t)ef_cap;               // merge buffer: expanded flags
-        o = (o + 7) & ~(size_t)7;
-        o += (size_t)st_cap * (4 + 8);     // new neighbour ids and their keys
-        o += ((size_t)8 << vb);            // visited buckets
-        o += (size_t)xs * 4;               // FP32 query
-        o += (size_t)dp;                   // query codes
-        o = (o + 15) & ~(size_t)15;
-        return o;
-    }
+    // Each array has one spare entry past its end (W: index ef_cap; the
+    // neighbour ids: index st_cap, which is the first key slot; the visited
+    // buckets: index 2^vb): lanes with nothing to store write there, so
+    // stores need no divergent branch.
+    __host__ __device__ static size_t r16(size_t o) { return (o + 15) & ~(size_t)15; }
+    __host__ __device__ size_t off_mf() const { return (size_t)(ef_cap + 1) * 8; }
+    __host__ __device__ size_t off_st() const { return r16(off_mf() + ef_cap + 1); }
+    __host__ __device__ size_t off_sk() const { return off_st() + (size_t)st_cap * 4; }
+    __host__ __device__ size_t off_vis() const { return off_sk() + (size_t)st_cap * 8; }
+    __host__ __device__ size_t off_qf() const { return r16(off_vis() + ((size_t)8 << vb) + 16); }
+    __host__ __device__ size_t off_qc() const { return off_qf() + (size_t)xs * 4; }
+    __host__ __device__ size_t bytes() const { return r16(off_qc() + (size_t)dp); }
 };
+
+__device__ __forceinline__ int st_cap_of(int s0, int s1) {
+    return max(s0, s1) <= 64 ? 64 : ((max(s0, s1) + 63) / 64) * 64;
+}
 
 struct SearchArgs {
     Idx ix;
@@ -419,6 +436,8 @@ __device__ __forceinline__ void search_query(const SearchArgs& a, const int64_t 
                                              uint32_t* st_id, uint64_t* st_key, uint64_t* visb,
                                              float* qf, uint8_t* qc) {
     const Idx& ix = a.ix;
+    const int st_cap = st_cap_of(ix.s0, ix.s1);  // index of the spare neighbour-id entry
+    const int ef_cap = a.ef_cap;                 // index of the spare W entry
     uint32_t qq = 0;
     if (!F32) {
         uint32_t part = 0;
@@ -458,7 +477,7 @@ __device__ __forceinline__ void search_query(const SearchArgs& a, const int64_t 
             for (int b0 = 0; b0 < ix.s1; b0 += kWave) {
                 uint32_t e = (b0 + lane < ix.s1) ? row[b0 + lane] : kNone;
                 uint64_t m = ballot(e != kNone);
-                if (e != kNone) st_id[cnt + below(m)] = e;
+                st_id[e != kNone ? cnt + below(m) : st_cap] = e;
                 cnt += __popcll(m);
             }
             wsync();
@@ -508,26 +527,28 @@ __device__ __forceinline__ void search_query(const SearchArgs& a, const int64_t 
         const uint32_t c = (uint32_t)uni64(mk[idx]);
         first = idx + 1;
         wsync();
-        if (lane == 0) {
-            mf[idx] = 1;
-            if (TAPS && a.taps.expanded && (int)n_exp < a.taps.cap)
-                a.taps.expanded[q * a.taps.cap + n_exp] = c;
-        }
+        mf[idx] = 1;  // every lane stores the same byte
+        if (TAPS && lane == 0 && a.taps.expanded && (int)n_exp < a.taps.cap)
+            a.taps.expanded[q * a.taps.cap + n_exp] = c;
         wsync();
         ++n_exp;
         // unvisited neighbours of c
         const uint32_t* row = ix.adj0 + (int64_t)c * ix.s0;
         uint32_t e[4];
 #pragma unroll
-        for (int b = 0; b < 4; ++b)
-            e[b] = (b < nad && b * kWave + lane < ix.s0) ? row[b * kWave + lane] : kNone;
+        for (int b = 0; b < 4; ++b) {
+            const int j = b * kWave + lane;
+            const uint32_t v = b < nad ? row[j < ix.s0 ? j : 0] : kNone;
+            e[b] = j < ix.s0 ? v : kNone;
+        }
         int nn = 0;
 #pragma unroll
         for (int b = 0; b < 4; ++b) {
             if (b < nad) {
-                const bool isnew = e[b] != kNone && !vis.test_insert(e[b]);
+                const bool valid = e[b] != kNone;
+                const bool isnew = !vis.test_insert_if(e[b], valid) && valid;
                 const uint64_t m = ballot(isnew);
-                if (isnew) st_id[nn + below(m)] = e[b];
+                st_id[isnew ? nn + below(m) : st_cap] = e[b];
                 nn += __popcll(m);
             }
         }
@@ -554,10 +575,12 @@ __device__ __forceinline__ void search_query(const SearchArgs& a, const int64_t 
             int lo = 0;
             for (int step = 1 << (31 - __builtin_clz((unsigned)wsize)); step > 0; step >>= 1) {
                 const int p = lo + step - 1;
-                if (p < wsize && mk[p] < key) lo += step;
+                const uint64_t w = mk[p < wsize ? p : 0];
+                lo += (p < wsize && w < key) ? step : 0;
             }
             // a key already in W (a node the visited cache forgot) is dropped
-            A &= ~ballot(lo < wsize && mk[lo] == key);
+            const uint64_t wl = mk[lo < wsize ? lo : 0];
+            A &= ~ballot(lo < wsize && wl == key);
             const int m_adm = __popcll(A);
             if (m_adm == 0) continue;
             n_adm += m_adm;
@@ -578,21 +601,19 @@ __device__ __forceinline__ void search_query(const SearchArgs& a, const int64_t 
             for (int sl = (wsize - 1) >> 6; sl >= (lo_min >> 6); --sl) {
                 const int i = sl * kWave + lane;
                 const bool v = i < wsize && i >= lo_min;
-                const uint64_t w = v ? mk[i] : 0ull;
-                const uint8_t f = v ? mf[i] : (uint8_t)0;
+                const uint64_t w = mk[i];  // inside W's capacity
+                const uint8_t f = mf[i];
                 int sh = 0;
                 for (uint64_t it = A; it != 0; it &= it - 1)
                     sh += __builtin_amdgcn_readlane(lo, (int)__builtin_ctzll(it)) <= i ? 1 : 0;
                 const int p = i + sh;
-                if (v && p < efe) {
-                    mk[p] = w;
-                    mf[p] = f;
-                }
+                const int dst = v && p < efe ? p : ef_cap;  // others write the spare entry
+                mk[dst] = w;
+                mf[dst] = f;
             }
-            if (mine && pos < efe) {
-                mk[pos] = key;
-                mf[pos] = 0;
-            }
+            const int dst = mine && pos < efe ? pos : ef_cap;
+            mk[dst] = key;
+            mf[dst] = 0;
             // the smallest admitted key has rank 0: its position is lo_min
             first = min(first, lo_min);
             wsize = min(efe, wsize + m_adm);
@@ -642,18 +663,15 @@ __global__ __launch_bounds__(256) void k_search(SearchArgs a) {
     const int lane = lane_id();
     const int wave = threadIdx.x / kWave;
     const Idx& ix = a.ix;
-    const int ef_cap = a.ef_cap;
-    const int st_cap = max(ix.s0, ix.s1) <= 64 ? 64 : ((max(ix.s0, ix.s1) + 63) / 64) * 64;
-
+    const SearchLds L{a.ef_cap, st_cap_of(ix.s0, ix.s1), a.vb, ix.xs, ix.dp};
     unsigned char* base = smem + (size_t)wave * a.wave_lds;
     uint64_t* mk = reinterpret_cast<uint64_t*>(base);
-    uint8_t* mf = reinterpret_cast<uint8_t*>(mk + ef_cap);
-    const size_t off = ((size_t)ef_cap * 9 + 7) & ~(size_t)7;
-    uint32_t* st_id = reinterpret_cast<uint32_t*>(base + off);
-    uint64_t* st_key = reinterpret_cast<uint64_t*>(base + off + (size_t)st_cap * 4);
-    uint64_t* visb = st_key + st_cap;
-    float* qf = reinterpret_cast<float*>(visb + ((size_t)1 << a.vb));
-    uint8_t* qc = reinterpret_cast<uint8_t*>(qf + ix.xs);
+    uint8_t* mf = base + L.off_mf();
+    uint32_t* st_id = reinterpret_cast<uint32_t*>(base + L.off_st());
+    uint64_t* st_key = reinterpret_cast<uint64_t*>(base + L.off_sk());
+    uint64_t* visb = reinterpret_cast<uint64_t*>(base + L.off_vis());
+    float* qf = reinterpret_cast<float*>(base + L.off_qf());
+    uint8_t* qc = base + L.off_qc();
 
     VisCache vis{visb, a.vb, max(ix.idbits, a.vb + 1)};
 
@@ -680,7 +698,7 @@ __global__ __launch_bounds__(256) void k_search(SearchArgs a) {
                 nc = k;
             }
             int bad =
-                uni((k < 1 || efe > ef_cap || nc < 1 || nc > a.out_stride || nc > efe) ? 1 : 0);
+                uni((k < 1 || efe > a.ef_cap || nc < 1 || nc > a.out_stride || nc > efe) ? 1 : 0);
             if (!bad) {
                 // load the FP32 query into LDS (zero padded); reject non-finite values
                 bool nonfinite = false;
@@ -1130,15 +1148,14 @@ __global__ __launch_bounds__(256) void k_serve(ServeArgs a) {
     // search part's FP32 query buffer throughout
     unsigned char* base = smem + (size_t)wave * sa.wave_lds;
     const int ef_cap = sa.ef_cap;
-    const int st_cap = max(ix.s0, ix.s1) <= 64 ? 64 : ((max(ix.s0, ix.s1) + 63) / 64) * 64;
+    const SearchLds L{ef_cap, st_cap_of(ix.s0, ix.s1), sa.vb, ix.xs, ix.dp};
     uint64_t* mk = reinterpret_cast<uint64_t*>(base);
-    uint8_t* mf = reinterpret_cast<uint8_t*>(mk + ef_cap);
-    const size_t off = ((size_t)ef_cap * 9 + 7) & ~(size_t)7;
-    uint32_t* st_id = reinterpret_cast<uint32_t*>(base + off);
-    uint64_t* st_key = reinterpret_cast<uint64_t*>(base + off + (size_t)st_cap * 4);
-    uint64_t* visb = st_key + st_cap;
-    float* qf = reinterpret_cast<float*>(visb + ((size_t)1 << sa.vb));
-    uint8_t* qc = reinterpret_cast<uint8_t*>(qf + ix.xs);
+    uint8_t* mf = base + L.off_mf();
+    uint32_t* st_id = reinterpret_cast<uint32_t*>(base + L.off_st());
+    uint64_t* st_key = reinterpret_cast<uint64_t*>(base + L.off_sk());
+    uint64_t* visb = reinterpret_cast<uint64_t*>(base + L.off_vis());
+    float* qf = reinterpret_cast<float*>(base + L.off_qf());
+    uint8_t* qc = base + L.off_qc();
     unsigned char* rb = base + a.search_lds;
     const int nc_cap = a.r.nc_cap, r_cap = a.r.r_cap;
     uint64_t* A = reinterpret_cast<uint64_t*>(rb);
