@@ -213,6 +213,12 @@ def search_bytes(cnt_big, nq, d, d_pad, s0, s1, nc_total):
     return code, adj, io
 
 
+def finite_or_none(x):
+    """JSON has no infinities: thresholds that switch early termination off
+    are reported as null."""
+    return x if x is None or np.isfinite(x) else None
+
+
 def rerank_by_name(name):
     return next(c for c in RERANK_CONFIGS if c[0] == name)
 
@@ -365,7 +371,7 @@ def bench_batched(args, torch, aqr, W, wl, dev, threads):
                         f"with k in {{1,10,100}} and ef in {{16,...,512}} in one captured launch",
             "n": n, "d": d, "nq": nq, "M0": wl.M0, "efc0": wl.efc0, "M_i": ginfo["M"],
             "delta": round(info["delta"], 6), "rerank": cfg[0], "n_rerank": nrr,
-            "tau_gap": tg, "tau_ratio": tr, "tuning": best,
+            "tau_gap": finite_or_none(tg), "tau_ratio": finite_or_none(tr), "tuning": best,
             "recall@min(k,10)": round(float(rq.mean()), 5), "recall_by_k": rec_by_k,
             "recall@10_by_ef": rec_by_ef, "global_batch": nq,
             "parallelism": "single GPU, one wavefront per query, persistent",
@@ -390,7 +396,7 @@ def bench_batched(args, torch, aqr, W, wl, dev, threads):
         "device_hip_sha": source_sha(),
         "wall_s": round(time.perf_counter() - t_all, 1),
     })
-    print(json.dumps(out), flush=True)
+    print(json.dumps(out, allow_nan=False), flush=True)
 
 
 def bench_serving(args, torch, aqr, W, wl, dev, threads):
@@ -495,7 +501,7 @@ def bench_serving(args, torch, aqr, W, wl, dev, threads):
                         f"{head['load']} of the server's saturation rate",
             "n": n, "d": d, "M0": wl.M0, "efc0": wl.efc0, "M_i": ginfo["M"],
             "delta": round(info["delta"], 6), "ef": ef98, "rerank": cfg[0], "n_rerank": nrr,
-            "tau_gap": tg, "tau_ratio": tr, "ring": args.ring, "k_max": k_max,
+            "tau_gap": finite_or_none(tg), "tau_ratio": finite_or_none(tr), "ring": args.ring, "k_max": k_max,
             "ef_max": ef_max, "parallelism": "single GPU, resident persistent server kernel",
         },
         "latency_ms": {"p50": head["p50_ms"], "p99": head["p99_ms"],
@@ -509,7 +515,7 @@ def bench_serving(args, torch, aqr, W, wl, dev, threads):
         "device_hip_sha": source_sha(),
         "wall_s": round(time.perf_counter() - t_all, 1),
     })
-    print(json.dumps(out), flush=True)
+    print(json.dumps(out, allow_nan=False), flush=True)
 
 
 def build_index(args, wl, X, threads):
@@ -576,6 +582,10 @@ def main():
     ap.add_argument("--rerank", default=None,
                     help="re-rank setting (--profile: default no-et; batched: table3)")
     ap.add_argument("--tune-sample", type=int, default=20000)
+    ap.add_argument("--no-tune", dest="tune", action="store_false",
+                    help="skip the launch-shape tuning of the timed search")
+    ap.add_argument("--vb", type=int, default=0, help="visited_log2 of the timed search (skips tuning)")
+    ap.add_argument("--wpb", type=int, default=0, help="waves per block of the timed search (skips tuning)")
     ap.add_argument("--ring", type=int, default=4096, help="serving: request slots")
     ap.add_argument("--loads", default="0.1,0.5,0.8,0.9",
                     help="serving: offered loads as fractions of the saturation rate")
@@ -666,9 +676,23 @@ def main():
         if fp_pick is None:
             fp_pick = (efs[-1], fp_table[-1][1])
 
-    # ---- timed AQR path ----
+    # ---- tuning (results do not depend on it) and the timed AQR path ----
     ef_a = aqr_pick[0]
-    runner = AqrRunner(aqr, ix, nq, k, ef_a, dev, rerank=aqr_pick[2])
+    tuning = {"visited_log2": 0, "waves_per_block": 0}
+    if args.vb or args.wpb:
+        tuning = {"visited_log2": args.vb, "waves_per_block": args.wpb}
+    elif args.tune and not args.profile:
+        best_ms = None
+        for vb in (6, 7, 8, 9):
+            for wpb in (2, 4):
+                r = AqrRunner(aqr, ix, nq, k, ef_a, dev, visited_log2=vb, waves_per_block=wpb,
+                              rerank=aqr_pick[2])
+                ms_t, _ = timed(torch, lambda m: r.search_only(Qd), 3, 1)
+                log(f"tune visited_log2={vb} waves_per_block={wpb}: {ms_t:.3f} ms")
+                if best_ms is None or ms_t < best_ms:
+                    best_ms, tuning = ms_t, {"visited_log2": vb, "waves_per_block": wpb}
+        log(f"tuning picked {tuning}")
+    runner = AqrRunner(aqr, ix, nq, k, ef_a, dev, rerank=aqr_pick[2], **tuning)
 
     def aqr_step(marks):
         if marks:
@@ -712,7 +736,9 @@ def main():
     reeval = float(cnt[:, 1].sum() / max(1, cnt_big[:, 1].sum()) - 1.0)
     lat_us = cnt[:, 5] / 100.0  # 100 MHz real-time clock
     sha = source_sha()
-    traffic = traffic_from_profile(f"search_u8_{args.workload}_ef{ef_a}", sha)
+    prof_name = (f"search_u8_{args.workload}_ef{ef_a}_vb{tuning['visited_log2']}"
+                 f"_wpb{tuning['waves_per_block']}")
+    traffic = traffic_from_profile(prof_name, sha)
 
     copy_info = None
     if args.profile:
@@ -805,14 +831,15 @@ def main():
             "n": n, "d": d, "nq": nq, "k": k, "ef": ef_a, "M0": wl.M0, "efc0": wl.efc0,
             "M_i": ginfo["M"], "delta": round(info["delta"], 6), "m_ef": 3,
             "rerank": aqr_pick[2][0], "n_rerank": aqr_pick[2][1],
-            "tau_gap": aqr_pick[2][2], "tau_ratio": aqr_pick[2][3],
-            "recall@10": round(aqr_pick[1], 5),
+            "tau_gap": finite_or_none(aqr_pick[2][2]),
+            "tau_ratio": finite_or_none(aqr_pick[2][3]),
+            "recall@10": finite_or_none(round(aqr_pick[1], 5)), "tuning": tuning,
             "global_batch": nq, "parallelism": "single GPU, one wavefront per query",
         },
         "roofline": {
             "bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
             "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-            "traffic": traffic,
+            "traffic": traffic, "traffic_profile": prof_name,
             "kernel": "k_search (Stage 1, 8-bit codes)",
             "kernel_ms": round(search_ms, 4),
             "alg_bytes_per_launch": alg_bytes,
@@ -834,7 +861,7 @@ def main():
         "copy_kernel": copy_info,
         "wall_s": round(time.perf_counter() - t_all, 1),
     }
-    print(json.dumps(out), flush=True)
+    print(json.dumps(out, allow_nan=False), flush=True)
 
 
 if __name__ == "__main__":

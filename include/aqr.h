@@ -192,7 +192,7 @@ typedef struct aqr_sparams {
     int32_t m_ef;         /* ef multiplier when nc is not given (Table 3: 2 or 3) */
     int32_t waves_per_block; /* 0 = library default */
     int32_t blocks;       /* persistent grid size, 0 = fill the device */
-    int32_t visited_log2; /* log2 of visited-cache buckets (4 ids each), 0 = default */
+    int32_t visited_log2; /* log2 of visited-cache buckets (4 ids each), 0 = 7 */
     const int32_t* order; /* device, nullable: work order of the queries (a permutation) */
 } aqr_sparams;
 
@@ -347,7 +347,7 @@ typedef struct aqr_server_params {
     int32_t n_rerank;     /* N_rerank */
     float tau_gap, tau_ratio, eps;  /* early termination (Table 3 row "0.97+": 0.010, 1.008) */
     int32_t waves_per_block;        /* 0 = 4 */
-    int32_t visited_log2;           /* 0 = default */
+    int32_t visited_log2;           /* 0 = 7 */
     int32_t idle_ms;      /* the kernel exits after this long without unclaimed requests */
     int32_t reserved;
 } aqr_server_params;

@@ -1540,7 +1540,7 @@ aqr_status run_search(const aqr_index* ix, const float* Q, int64_t nq, const int
     if (taps && (taps->expanded || taps->evaluated) && taps->cap < 1)
         return fail(AQR_ERR_INVALID_ARG, std::string(who) + ": taps->cap must be >= 1");
     const Idx& v = ix->v;
-    int vb = sp->visited_log2 > 0 ? sp->visited_log2 : 9;
+    int vb = sp->visited_log2 > 0 ? sp->visited_log2 : 7;
     if (vb < 4 || vb > 14) return fail(AQR_ERR_INVALID_ARG, std::string(who) + ": visited_log2 out of [4, 14]");
     const int idb = std::max(v.idbits, vb + 1);
     if (idb - vb > 15) vb = idb - 15;  // keep the stored remainder within 15 bits
@@ -2049,7 +2049,7 @@ extern "C" aqr_status aqr_server_create(const aqr_index* ix, const aqr_server_pa
         if (v.s0 > 256) return fail(AQR_ERR_INVALID_ARG, "aqr_server_create: rows above 256 entries");
         const int efm = std::max(prm->ef_max, prm->k_max);
         const int ef_cap = (efm + 63) / 64 * 64;
-        int vb = prm->visited_log2 > 0 ? prm->visited_log2 : 9;
+        int vb = prm->visited_log2 > 0 ? prm->visited_log2 : 7;
         const int idb = std::max(v.idbits, vb + 1);
         if (idb - vb > 15) vb = idb - 15;
         const int nc_max = std::min(efm, std::max(prm->k_max, efm / prm->m_ef));

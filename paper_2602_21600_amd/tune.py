@@ -14,7 +14,7 @@ import time
 from . import aqr
 
 SEARCH_WPB = (1, 2, 4)
-VISITED_LOG2 = (8, 9, 10)
+VISITED_LOG2 = (6, 7, 8, 9)
 RERANK_WPB = (2, 4)
 # resident search waves per CU: 0 = as many as occupancy allows, else the
 # persistent grid is cut to this many waves per CU
