@@ -217,7 +217,7 @@ size_t aqr_search_workspace_size(void);
  * N_c = clamp(floor(ef_eff / m_ef), k, ef_eff), ef_eff = max(ef, k)).
  * Each query is encoded (Section 3.2, same rounding as aqr_quantize),
  * descends the upper layers greedily and searches layer 0 with ef_eff
- * (Alg. 2 l.4-7).  Outputs (device): cand_id and cand_D [nq][out_stride]
+ * (Section 3.2 Stage 1, Algorithm 2).  Outputs (device): cand_id and cand_D [nq][out_stride]
  * hold the first N_c entries of the result list, ascending by (D, id), where
  * D = sum_j (q^_j - x^_j)^2 is the exact integer code distance (the paper's
  * d^q is s_dist * D); cand_cnt[nq] = number written, or -1 for a query with
@@ -257,7 +257,7 @@ typedef struct aqr_rtaps {
 } aqr_rtaps;
 
 /*
- * Stages 2-3 for nq queries (Alg. 2 l.9-24), on the Stage-1 lists
+ * Stages 2-3 for nq queries (Section 3.2, Algorithm 2), on the Stage-1 lists
  * cand_id/cand_cnt (device, stride nc_stride) and the FP32 queries Q:
  *   d^a = sum_j (q_j - x~_j)^2 with x~_j = fl32(fl32(x^_j / scale_j) + min_j),
  *   A = candidates sorted by (d^a, id);

@@ -1,20 +1,22 @@
 // device.hip -- gfx950 kernels and device-side entry points of libaqr.
 //
-// Query path of AQR-HNSW (Section 3.2, Alg. 2) on an MI355X:
+// Query path of AQR-HNSW (Section 3.2, Algorithm 2) on an MI355X:
 //   * k_search: one wavefront per query in a persistent loop (queries are
 //     pulled from an atomic counter).  Per query: encode the FP32 query to
-//     8-bit codes (Alg. 2 l.4), greedy descent through the upper layers,
-//     then the layer-0 search with width ef (Alg. 2 l.6-7).  The same kernel
-//     instantiated on FP32 rows is the baseline HNSW search.
+//     8-bit codes, greedy descent through the upper layers, then the layer-0
+//     search with width ef (Stage 1).  The same kernel instantiated on FP32
+//     rows is the baseline HNSW search.
 //   * k_rerank: one wavefront per query: asymmetric distances on decoded
 //     codes, sort, early termination, exact FP32 distances on the survivors
-//     and assembly of the top k (Alg. 2 l.9-24).
+//     and assembly of the top k (Stages 2 and 3).
+//   * k_serve: the same per-query code in a resident kernel fed from a ring
+//     of requests in pinned host memory.
 //
 // Layer-0 search form.  The result list W is one sorted array of (D, id)
-// keys in LDS with an "expanded" flag per entry; the next node to expand is
-// the nearest unexpanded entry and the search ends when none is left.  All
-// unvisited neighbours of one expansion are scored together and merged into
-// W as one batch (keys below the current bound, W kept at ef entries).
+// keys in LDS whose low bit is an "expanded" flag; the next node to expand
+// is the nearest unexpanded entry and the search ends when none is left.
+// All unvisited neighbours of one expansion are scored together and merged
+// into W as one batch (keys below the current bound, W kept at ef entries).
 // The visited set is an LDS cache that may forget ids but never reports an
 // id it has not seen.  Under the strict (D, id) order these choices give
 // the same expansions, the same distinct visited set and the same result
@@ -24,10 +26,10 @@
 //
 // Distances.  Code rows are read 16 bytes per lane; a row is spread over G
 // lanes (G = 16-byte chunks of the row, rounded up to a power of two, at
-// most 64) so one wave reads 64/G rows per pass, each row one contiguous
-// segment.  The 8-bit squared distance is exact in uint32 as
+// least 4 and at most 64) so one wave reads 64/G rows per pass, each row one
+// contiguous segment.  The 8-bit squared distance is exact in uint32 as
 // |q|^2 + sum(x*x - 2 q*x) with the 4 x u8 dot product instruction, reduced
-// across the G lanes by butterfly shuffles.  FP32 rows use fused
+// across the G lanes by DPP lane permutes.  FP32 rows use fused
 // multiply-add on direct differences.
 #include <hip/hip_runtime.h>
 
@@ -285,7 +287,8 @@ __device__ __forceinline__ Geo make_geo(int lg, int nch, int lane) {
     return g;
 }
 
-// Score nn rows whose ids are ids[0..nn) (LDS); keys[r] = (dist bits << 32) | id.
+// Score nn rows whose ids are ids[0..nn) (LDS); keys[r] = (dist bits << 32) | (id << 1): the
+// low bit is left free for the expanded flag of W, and keys still order by (distance, id).
 // Rows are spread over groups of 2^LG lanes, one 16-byte chunk per lane and
 // CPL chunks per lane.  There are no divergent branches: rows past nn and
 // chunks past the row read row 0 / chunk 0 (valid memory) and are masked out
@@ -322,7 +325,7 @@ __device__ __forceinline__ void eval_rows(const Idx& ix, const uint32_t* ids, in
             s = R::template gsum<LG>(s);
             const int r = r0 + u * RPP + grp;
             if (sub == G - 1 && r < nn)
-                keys[r] = ((uint64_t)R::dbits(s, qq) << 32) | (uint64_t)id[u];
+                keys[r] = ((uint64_t)R::dbits(s, qq) << 32) | ((uint64_t)id[u] << 1);
         }
     }
 }
@@ -369,13 +372,13 @@ struct VisCache {
 // ---------------------------------------------------------------------------
 struct SearchLds {
     int ef_cap, st_cap, vb, xs, dp;
-    // Each array has one spare entry past its end (W: index ef_cap; the
-    // neighbour ids: index st_cap, which is the first key slot; the visited
-    // buckets: index 2^vb): lanes with nothing to store write there, so
-    // stores need no divergent branch.
+    // W holds keys whose low bit is the expanded flag.  Each array has one
+    // spare entry past its end (W: index ef_cap; the neighbour ids: index
+    // st_cap, which is the first key slot; the visited buckets: index 2^vb):
+    // lanes with nothing to store write there, so stores need no divergent
+    // branch.
     __host__ __device__ static size_t r16(size_t o) { return (o + 15) & ~(size_t)15; }
-    __host__ __device__ size_t off_mf() const { return (size_t)(ef_cap + 1) * 8; }
-    __host__ __device__ size_t off_st() const { return r16(off_mf() + ef_cap + 1); }
+    __host__ __device__ size_t off_st() const { return r16((size_t)(ef_cap + 1) * 8); }
     __host__ __device__ size_t off_sk() const { return off_st() + (size_t)st_cap * 4; }
     __host__ __device__ size_t off_vis() const { return off_sk() + (size_t)st_cap * 8; }
     __host__ __device__ size_t off_qf() const { return r16(off_vis() + ((size_t)8 << vb) + 16); }
@@ -417,10 +420,10 @@ __device__ __forceinline__ uint64_t readlane64(uint64_t v, int l) {
 
 // Stage 1 of one valid query, run by the whole wave.
 //
-// The result list W (at most ef_cap keys, sorted) and its expanded flags
-// live in LDS.  A merge finds each admitted key's place in W by bisection
-// (one lane per key), drops keys already in W, ranks the admitted keys among
-// themselves, then shifts the W entries above the lowest insertion point
+// The result list W (at most ef_cap keys, sorted, expanded flag in the low
+// bit) lives in LDS.  A merge finds each admitted key's place in W by
+// bisection (one lane per key), drops keys already in W, ranks the admitted
+// keys among themselves, then shifts the W entries above the lowest insertion point
 // slot by slot (64 entries per slot, last slot first) and writes the
 // admitted keys into the gaps.  Only the slots at or above the lowest
 // insertion point are touched, and W is never held in registers.
@@ -432,7 +435,7 @@ __device__ __forceinline__ uint64_t readlane64(uint64_t v, int l) {
 template <bool F32, int CPL, int U, int LG, bool TAPS>
 __device__ __forceinline__ void search_query(const SearchArgs& a, const int64_t q, const int efe,
                                              const int nc, const int lane,
-                                             const VisCache& vis, uint64_t* mk, uint8_t* mf,
+                                             const VisCache& vis, uint64_t* mk,
                                              uint32_t* st_id, uint64_t* st_key, uint64_t* visb,
                                              float* qf, uint8_t* qc) {
     const Idx& ix = a.ix;
@@ -490,7 +493,7 @@ __device__ __forceinline__ void search_query(const SearchArgs& a, const int64_t 
             best = uni64(wave_min_u64(best));
             if (best < curkey) {
                 curkey = best;
-                cur = (uint32_t)best;
+                cur = (uint32_t)best >> 1;
             } else {
                 break;
             }
@@ -502,9 +505,8 @@ __device__ __forceinline__ void search_query(const SearchArgs& a, const int64_t 
     for (int i = lane; i < (1 << a.vb); i += kWave) visb[i] = 0ull;
     wsync();
     if (lane == 0) {
-        vis.test_insert((uint32_t)curkey);
+        vis.test_insert((uint32_t)curkey >> 1);
         mk[0] = curkey;
-        mf[0] = 0;
     }
     wsync();
     int wsize = 1;
@@ -515,8 +517,8 @@ __device__ __forceinline__ void search_query(const SearchArgs& a, const int64_t 
         int idx = -1;
         for (int b0 = first & ~(kWave - 1); b0 < wsize; b0 += kWave) {
             const int i = b0 + lane;
-            const uint8_t f = mf[i];  // inside W's capacity (whole 64-entry slots)
-            const uint64_t m = ballot(i >= first && i < wsize && f == 0);
+            const uint64_t w = mk[i];  // inside W's capacity (whole 64-entry slots)
+            const uint64_t m = ballot(i >= first && i < wsize && (w & 1ull) == 0);
             if (m) {
                 idx = b0 + (int)__builtin_ctzll(m);
                 break;
@@ -524,10 +526,11 @@ __device__ __forceinline__ void search_query(const SearchArgs& a, const int64_t 
         }
         idx = uni(idx);
         if (idx < 0) break;
-        const uint32_t c = (uint32_t)uni64(mk[idx]);
+        const uint64_t kc = uni64(mk[idx]);
+        const uint32_t c = (uint32_t)kc >> 1;
         first = idx + 1;
         wsync();
-        mf[idx] = 1;  // every lane stores the same byte
+        mk[idx] = kc | 1ull;  // expanded; every lane stores the same value
         if (TAPS && lane == 0 && a.taps.expanded && (int)n_exp < a.taps.cap)
             a.taps.expanded[q * a.taps.cap + n_exp] = c;
         wsync();
@@ -580,7 +583,7 @@ __device__ __forceinline__ void search_query(const SearchArgs& a, const int64_t 
             }
             // a key already in W (a node the visited cache forgot) is dropped
             const uint64_t wl = mk[lo < wsize ? lo : 0];
-            A &= ~ballot(lo < wsize && wl == key);
+            A &= ~ballot(lo < wsize && (wl | 1ull) == (key | 1ull));
             const int m_adm = __popcll(A);
             if (m_adm == 0) continue;
             n_adm += m_adm;
@@ -602,18 +605,15 @@ __device__ __forceinline__ void search_query(const SearchArgs& a, const int64_t 
                 const int i = sl * kWave + lane;
                 const bool v = i < wsize && i >= lo_min;
                 const uint64_t w = mk[i];  // inside W's capacity
-                const uint8_t f = mf[i];
                 int sh = 0;
                 for (uint64_t it = A; it != 0; it &= it - 1)
                     sh += __builtin_amdgcn_readlane(lo, (int)__builtin_ctzll(it)) <= i ? 1 : 0;
                 const int p = i + sh;
                 const int dst = v && p < efe ? p : ef_cap;  // others write the spare entry
                 mk[dst] = w;
-                mf[dst] = f;
             }
             const int dst = mine && pos < efe ? pos : ef_cap;
             mk[dst] = key;
-            mf[dst] = 0;
             // the smallest admitted key has rank 0: its position is lo_min
             first = min(first, lo_min);
             wsize = min(efe, wsize + m_adm);
@@ -631,7 +631,7 @@ __device__ __forceinline__ void search_query(const SearchArgs& a, const int64_t 
     } else if (a.mode == 0) {
         for (int i = lane; i < cnt; i += kWave) {
             const uint64_t key = mk[i];
-            a.out_id[q * a.out_stride + i] = (uint32_t)key;
+            a.out_id[q * a.out_stride + i] = (uint32_t)key >> 1;
             a.out_D[q * a.out_stride + i] = (uint32_t)(key >> 32);
         }
         if (lane == 0) a.out_cnt[q] = cnt;
@@ -639,7 +639,7 @@ __device__ __forceinline__ void search_query(const SearchArgs& a, const int64_t 
         for (int i = lane; i < a.out_stride; i += kWave) {
             const bool v = i < cnt;
             const uint64_t key = v ? mk[i] : ~0ull;
-            a.out_id[q * a.out_stride + i] = v ? (uint32_t)key : kNone;
+            a.out_id[q * a.out_stride + i] = v ? (uint32_t)key >> 1 : kNone;
             a.out_D[q * a.out_stride + i] = v ? (uint32_t)(key >> 32) : 0x7F800000u;
         }
     }
@@ -666,7 +666,6 @@ __global__ __launch_bounds__(256) void k_search(SearchArgs a) {
     const SearchLds L{a.ef_cap, st_cap_of(ix.s0, ix.s1), a.vb, ix.xs, ix.dp};
     unsigned char* base = smem + (size_t)wave * a.wave_lds;
     uint64_t* mk = reinterpret_cast<uint64_t*>(base);
-    uint8_t* mf = base + L.off_mf();
     uint32_t* st_id = reinterpret_cast<uint32_t*>(base + L.off_st());
     uint64_t* st_key = reinterpret_cast<uint64_t*>(base + L.off_sk());
     uint64_t* visb = reinterpret_cast<uint64_t*>(base + L.off_vis());
@@ -719,7 +718,7 @@ __global__ __launch_bounds__(256) void k_search(SearchArgs a) {
                     }
                 }
             } else {
-                search_query<F32, CPL, U, LG, TAPS>(a, q, efe, nc, lane, vis, mk, mf, st_id, st_key,
+                search_query<F32, CPL, U, LG, TAPS>(a, q, efe, nc, lane, vis, mk, st_id, st_key,
                                              visb, qf, qc);
             }
         }
@@ -888,7 +887,7 @@ __device__ __forceinline__ void rerank_query(const RerankArgs& a, const int lane
         As[r] = v;
     }
     wsync();
-    // early termination (Alg. 2 l.15-17)
+    // early termination (Section 3.2, Algorithm 2)
     int et = 0;
     if (nc > k) {
         const float dk = __uint_as_float((uint32_t)(As[k - 1] >> 32));
@@ -1150,7 +1149,6 @@ __global__ __launch_bounds__(256) void k_serve(ServeArgs a) {
     const int ef_cap = sa.ef_cap;
     const SearchLds L{ef_cap, st_cap_of(ix.s0, ix.s1), sa.vb, ix.xs, ix.dp};
     uint64_t* mk = reinterpret_cast<uint64_t*>(base);
-    uint8_t* mf = base + L.off_mf();
     uint32_t* st_id = reinterpret_cast<uint32_t*>(base + L.off_st());
     uint64_t* st_key = reinterpret_cast<uint64_t*>(base + L.off_sk());
     uint64_t* visb = reinterpret_cast<uint64_t*>(base + L.off_vis());
@@ -1234,10 +1232,10 @@ __global__ __launch_bounds__(256) void k_serve(ServeArgs a) {
         } else {
             // Stage 1 writes its N_c candidates into the search part; the
             // re-rank reads them from there
-            search_query<false, CPL, U, LG, false>(sa, 0, efe, nc, lane, vis, mk, mf, st_id, st_key,
+            search_query<false, CPL, U, LG, false>(sa, 0, efe, nc, lane, vis, mk, st_id, st_key,
                                            visb, qf, qc);
             const int cnt = uni(*reinterpret_cast<const int*>(st_id));
-            for (int j = lane; j < cnt; j += kWave) rids[j] = (uint32_t)mk[j];
+            for (int j = lane; j < cnt; j += kWave) rids[j] = (uint32_t)mk[j] >> 1;
             wsync();
             rerank_query<CPL8, CPLF, true>(a.r, lane, k, cnt, qf, rids, A, As, Rk, Rs, kind,
                                            kinds, oid, od, nullptr, k, nullptr, nullptr,
@@ -1456,8 +1454,8 @@ namespace {
 template <bool F32, int CPL, int LG>
 hipError_t launch_search_k(dev::SearchArgs& a, int blocks, int wpb, size_t lds, int ncu,
                            hipStream_t s) {
-    // 16-byte loads in flight per lane in the distance phase
-    constexpr int U = CPL >= 2 ? 1 : 2;
+    // rows in flight per lane group in the distance phase
+    constexpr int U = CPL >= 4 ? 1 : 2;
     const bool taps = a.taps.expanded || a.taps.evaluated || a.taps.counts;
     auto kern = taps ? dev::k_search<F32, CPL, U, LG, true> : dev::k_search<F32, CPL, U, LG, false>;
     // the dynamic-LDS limit is raised once per size and kernel, outside any stream capture
@@ -1487,6 +1485,12 @@ hipError_t launch_search_k(dev::SearchArgs& a, int blocks, int wpb, size_t lds, 
 template <bool F32>
 hipError_t launch_search(dev::SearchArgs& a, int cpl, int lg, int blocks, int wpb, size_t lds,
                          int ncu, hipStream_t s) {
+    // code rows of 8 or 16 chunks: two chunks per lane on half the lanes
+    // (fewer group reductions and row bookkeeping per scored row)
+    if (!F32 && cpl == 1 && lg >= 3 && lg <= 4) {
+        if (lg == 3) return launch_search_k<F32, 2, 2>(a, blocks, wpb, lds, ncu, s);
+        return launch_search_k<F32, 2, 3>(a, blocks, wpb, lds, ncu, s);
+    }
     if (cpl == 1) {
         switch (lg) {
             case 2: return launch_search_k<F32, 1, 2>(a, blocks, wpb, lds, ncu, s);
