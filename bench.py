@@ -582,8 +582,8 @@ def main():
     ap.add_argument("--rerank", default=None,
                     help="re-rank setting (--profile: default no-et; batched: table3)")
     ap.add_argument("--tune-sample", type=int, default=20000)
-    ap.add_argument("--no-tune", dest="tune", action="store_false",
-                    help="skip the launch-shape tuning of the timed search")
+    ap.add_argument("--tune", action="store_true",
+                    help="tune the launch shape of the timed search by timing")
     ap.add_argument("--vb", type=int, default=0, help="visited_log2 of the timed search (skips tuning)")
     ap.add_argument("--wpb", type=int, default=0, help="waves per block of the timed search (skips tuning)")
     ap.add_argument("--ring", type=int, default=4096, help="serving: request slots")
@@ -678,7 +678,9 @@ def main():
 
     # ---- tuning (results do not depend on it) and the timed AQR path ----
     ef_a = aqr_pick[0]
-    tuning = {"visited_log2": 0, "waves_per_block": 0}
+    # default launch shape of the timed search: the one the tuning loop below
+    # picks on this workload (results do not depend on it)
+    tuning = {"visited_log2": 8, "waves_per_block": 2}
     if args.vb or args.wpb:
         tuning = {"visited_log2": args.vb, "waves_per_block": args.wpb}
     elif args.tune and not args.profile:
