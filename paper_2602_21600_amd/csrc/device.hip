@@ -372,18 +372,21 @@ struct VisCache {
 // ---------------------------------------------------------------------------
 struct SearchLds {
     int ef_cap, st_cap, vb, xs, dp;
-    // W holds keys whose low bit is the expanded flag.  Each array has one
-    // spare entry past its end (W: index ef_cap; the neighbour ids: index
-    // st_cap, which is the first key slot; the visited buckets: index 2^vb):
-    // lanes with nothing to store write there, so stores need no divergent
-    // branch.
+    // Layout of one wave: [FP32 query | query codes | W | neighbour ids |
+    // their keys | visited buckets].  W holds keys whose low bit is the
+    // expanded flag.  Each array has one spare entry past its end (W: index
+    // ef_cap; the neighbour ids: index st_cap, which is the first key slot;
+    // the visited buckets: index 2^vb): lanes with nothing to store write
+    // there, so stores need no divergent branch.  The query comes first so
+    // that the serving kernel can reuse everything after it for Stages 2-3.
     __host__ __device__ static size_t r16(size_t o) { return (o + 15) & ~(size_t)15; }
-    __host__ __device__ size_t off_st() const { return r16((size_t)(ef_cap + 1) * 8); }
+    __host__ __device__ size_t off_qf() const { return 0; }
+    __host__ __device__ size_t off_qc() const { return (size_t)xs * 4; }
+    __host__ __device__ size_t off_mk() const { return r16(off_qc() + (size_t)dp); }
+    __host__ __device__ size_t off_st() const { return r16(off_mk() + (size_t)(ef_cap + 1) * 8); }
     __host__ __device__ size_t off_sk() const { return off_st() + (size_t)st_cap * 4; }
     __host__ __device__ size_t off_vis() const { return off_sk() + (size_t)st_cap * 8; }
-    __host__ __device__ size_t off_qf() const { return r16(off_vis() + ((size_t)8 << vb) + 16); }
-    __host__ __device__ size_t off_qc() const { return off_qf() + (size_t)xs * 4; }
-    __host__ __device__ size_t bytes() const { return r16(off_qc() + (size_t)dp); }
+    __host__ __device__ size_t bytes() const { return r16(off_vis() + ((size_t)8 << vb) + 16); }
 };
 
 __device__ __forceinline__ int st_cap_of(int s0, int s1) {
@@ -665,7 +668,7 @@ __global__ __launch_bounds__(256) void k_search(SearchArgs a) {
     const Idx& ix = a.ix;
     const SearchLds L{a.ef_cap, st_cap_of(ix.s0, ix.s1), a.vb, ix.xs, ix.dp};
     unsigned char* base = smem + (size_t)wave * a.wave_lds;
-    uint64_t* mk = reinterpret_cast<uint64_t*>(base);
+    uint64_t* mk = reinterpret_cast<uint64_t*>(base + L.off_mk());
     uint32_t* st_id = reinterpret_cast<uint32_t*>(base + L.off_st());
     uint64_t* st_key = reinterpret_cast<uint64_t*>(base + L.off_sk());
     uint64_t* visb = reinterpret_cast<uint64_t*>(base + L.off_vis());
@@ -1060,7 +1063,6 @@ struct ServeCtl {       // pinned host memory
 struct ServeArgs {
     SearchArgs s;       // Idx, m_ef, ef_cap, vb, geometry, wave_lds (search part)
     RerankArgs r;       // geometry and thresholds of the re-rank part
-    size_t search_lds;  // bytes of the search part of one wave's LDS
     int32_t ring;
     int32_t k_max;
     int32_t nc_max;
@@ -1105,8 +1107,11 @@ __device__ __forceinline__ void st_sys(T* p, T v) {
 // wait until every memory operation this wave issued has completed
 __device__ __forceinline__ void wait_mem() { asm volatile("s_waitcnt vmcnt(0)" ::: "memory"); }
 
+// Register budget for three waves per SIMD: the search and re-rank phases
+// of a worker are never live at once, and without the hint the compiler
+// keeps more registers than three waves allow.
 template <int CPL, int U, int LG, int CPL8, int CPLF>
-__global__ __launch_bounds__(256) void k_serve(ServeArgs a) {
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k_serve(ServeArgs a) {
     extern __shared__ __align__(16) unsigned char smem[];
     const int lane = lane_id();
     const int wave = threadIdx.x / kWave;
@@ -1143,26 +1148,28 @@ __global__ __launch_bounds__(256) void k_serve(ServeArgs a) {
         return;
     }
 
-    // worker LDS: [search part | re-rank part]; the query stays in the
-    // search part's FP32 query buffer throughout
+    // worker LDS: the search layout; the FP32 query stays at its start
     unsigned char* base = smem + (size_t)wave * sa.wave_lds;
     const int ef_cap = sa.ef_cap;
     const SearchLds L{ef_cap, st_cap_of(ix.s0, ix.s1), sa.vb, ix.xs, ix.dp};
-    uint64_t* mk = reinterpret_cast<uint64_t*>(base);
+    uint64_t* mk = reinterpret_cast<uint64_t*>(base + L.off_mk());
     uint32_t* st_id = reinterpret_cast<uint32_t*>(base + L.off_st());
     uint64_t* st_key = reinterpret_cast<uint64_t*>(base + L.off_sk());
     uint64_t* visb = reinterpret_cast<uint64_t*>(base + L.off_vis());
     float* qf = reinterpret_cast<float*>(base + L.off_qf());
     uint8_t* qc = base + L.off_qc();
-    unsigned char* rb = base + a.search_lds;
+    // Stages 2-3 reuse everything after the query: the candidate ids are
+    // copied out of W (each 64-id chunk is read before it is written, and the
+    // id array starts where W starts, so no unread key is overwritten)
+    unsigned char* rb = base + L.off_mk();
     const int nc_cap = a.r.nc_cap, r_cap = a.r.r_cap;
-    uint64_t* A = reinterpret_cast<uint64_t*>(rb);
+    uint32_t* rids = reinterpret_cast<uint32_t*>(rb);
+    uint64_t* A = reinterpret_cast<uint64_t*>(rb + (size_t)nc_cap * 4);
     uint64_t* As = A + nc_cap;
     uint64_t* Rk = As + nc_cap;
     uint64_t* Rs = Rk + r_cap;
     uint8_t* kind = reinterpret_cast<uint8_t*>(Rs + r_cap);
     uint8_t* kinds = kind + r_cap;
-    uint32_t* rids = reinterpret_cast<uint32_t*>(kinds + r_cap);
     VisCache vis{visb, sa.vb, max(ix.idbits, sa.vb + 1)};
 
     for (;;) {
@@ -1706,7 +1713,8 @@ extern "C" aqr_status aqr_rerank(const aqr_index* ix, const float* Q, int64_t nq
         a.ccnt = cand_cnt;
         a.nc_stride = nc_stride;
         a.nc_cap = (nc_stride + 15) / 16 * 16;
-        a.r_cap = a.nc_cap + (rp->out_stride + 15) / 16 * 16;
+        // R holds the exact entries plus the fill from A: at most nc entries
+        a.r_cap = a.nc_cap;
         a.kq = k;
         a.n_rerank = rp->n_rerank;
         a.out_stride = rp->out_stride;
@@ -2069,10 +2077,11 @@ extern "C" aqr_status aqr_server_create(const aqr_index* ix, const aqr_server_pa
                           std::max(v.s0, v.s1) <= 64 ? 64 : (std::max(v.s0, v.s1) + 63) / 64 * 64,
                           vb, v.xs, v.dp};
         const size_t search_lds = sl.bytes();
+        const size_t qpart = sl.off_mk();
         dev::RerankArgs& r = sv->args.r;
         r.ix = v;
         r.nc_cap = (nc_max + 15) / 16 * 16;
-        r.r_cap = r.nc_cap + (prm->k_max + 15) / 16 * 16;
+        r.r_cap = r.nc_cap;  // R never exceeds the candidate count
         r.n_rerank = prm->n_rerank;
         r.out_stride = prm->k_max;
         r.tau_gap = prm->tau_gap;
@@ -2083,8 +2092,9 @@ extern "C" aqr_status aqr_server_create(const aqr_index* ix, const aqr_server_pa
         r.lg8 = pow2_lg_for(nch8);
         r.nchf = nchf;
         r.lgf = pow2_lg_for(nchf);
-        dev::RerankLds rl{r.nc_cap, r.r_cap, v.xs};
-        const size_t wave_lds = search_lds + rl.bytes();
+        // Stages 2-3 overlay the search arrays after the query
+        const size_t rr = (size_t)r.nc_cap * 4 + (size_t)r.nc_cap * 16 + (size_t)r.r_cap * 18;
+        const size_t wave_lds = dev::SearchLds::r16(qpart + std::max(search_lds - qpart, rr));
         sv->lds = wave_lds * sv->wpb;
         if (sv->lds > ix->max_lds) {
             delete sv;
@@ -2100,7 +2110,6 @@ extern "C" aqr_status aqr_server_create(const aqr_index* ix, const aqr_server_pa
         sa.nch = nch8;
         sa.lg = std::max(2, pow2_lg_for(nch8));
         sa.wave_lds = wave_lds;
-        sv->args.search_lds = search_lds;
         sv->args.ring = prm->ring;
         sv->args.k_max = prm->k_max;
         sv->args.nc_max = nc_max;
