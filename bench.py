@@ -680,7 +680,7 @@ def main():
     ef_a = aqr_pick[0]
     # default launch shape of the timed search: the one the tuning loop below
     # picks on this workload (results do not depend on it)
-    tuning = {"visited_log2": 8, "waves_per_block": 2}
+    tuning = {"visited_log2": 7, "waves_per_block": 4}
     if args.vb or args.wpb:
         tuning = {"visited_log2": args.vb, "waves_per_block": args.wpb}
     elif args.tune and not args.profile:
