@@ -592,11 +592,13 @@ __device__ __forceinline__ void search_query(const SearchArgs& a, const int64_t 
             n_adm += m_adm;
             const bool mine = ((A >> lane) & 1ull) != 0;
             int rankA = 0;
-            int lo_min = INT_MAX;
+            int lo_min = INT_MAX, lo_max = -1;
             for (uint64_t it = A; it != 0; it &= it - 1) {
                 const int t = (int)__builtin_ctzll(it);
                 rankA += readlane64(key, t) < key ? 1 : 0;
-                lo_min = min(lo_min, __builtin_amdgcn_readlane(lo, t));
+                const int lt = __builtin_amdgcn_readlane(lo, t);
+                lo_min = min(lo_min, lt);
+                lo_max = max(lo_max, lt);
             }
             const int pos = lo + rankA;
             // W entry i moves up by the number of admitted keys with lower
@@ -608,9 +610,13 @@ __device__ __forceinline__ void search_query(const SearchArgs& a, const int64_t 
                 const int i = sl * kWave + lane;
                 const bool v = i < wsize && i >= lo_min;
                 const uint64_t w = mk[i];  // inside W's capacity
-                int sh = 0;
-                for (uint64_t it = A; it != 0; it &= it - 1)
-                    sh += __builtin_amdgcn_readlane(lo, (int)__builtin_ctzll(it)) <= i ? 1 : 0;
+                // a slot wholly above every insertion point moves by m_adm
+                int sh = m_adm;
+                if (lo_max > sl * kWave) {
+                    sh = 0;
+                    for (uint64_t it = A; it != 0; it &= it - 1)
+                        sh += __builtin_amdgcn_readlane(lo, (int)__builtin_ctzll(it)) <= i ? 1 : 0;
+                }
                 const int p = i + sh;
                 const int dst = v && p < efe ? p : ef_cap;  // others write the spare entry
                 mk[dst] = w;
