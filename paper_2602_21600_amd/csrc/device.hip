@@ -120,10 +120,6 @@ __device__ __forceinline__ uint64_t wave_min_u64(uint64_t v) {
     }
     return v;
 }
-__device__ __forceinline__ int wave_min_i32(int v) {
-    for (int m = 32; m >= 1; m >>= 1) v = min(v, __shfl_xor(v, m, kWave));
-    return v;
-}
 __device__ __forceinline__ uint32_t wave_sum_u32(uint32_t v) {
     for (int m = 32; m >= 1; m >>= 1) v += shfl_xor_u32(v, m);
     return v;
@@ -143,14 +139,6 @@ constexpr int kDppXor2 = 0x4E;        // quad_perm [2,3,0,1]
 constexpr int kDppHalfMirror = 0x141; // lane i <-> 7 - i in each group of 8
 constexpr int kDppMirror = 0x140;     // lane i <-> 15 - i in each row of 16
 
-__device__ __forceinline__ uint32_t group_sum_u32(uint32_t v, int G) {
-    if (G >= 2) v += dpp_t<kDppXor1>(v);
-    if (G >= 4) v += dpp_t<kDppXor2>(v);
-    if (G >= 8) v += dpp_t<kDppHalfMirror>(v);
-    if (G >= 16) v += dpp_t<kDppMirror>(v);
-    for (int m = 16; m < G; m <<= 1) v += shfl_xor_u32(v, m);
-    return v;
-}
 __device__ __forceinline__ float group_sum_f32(float v, int G) {
     if (G >= 2) v += __uint_as_float(dpp_t<kDppXor1>(__float_as_uint(v)));
     if (G >= 4) v += __uint_as_float(dpp_t<kDppXor2>(__float_as_uint(v)));
