@@ -1107,11 +1107,11 @@ __device__ __forceinline__ void st_sys(T* p, T v) {
 // wait until every memory operation this wave issued has completed
 __device__ __forceinline__ void wait_mem() { asm volatile("s_waitcnt vmcnt(0)" ::: "memory"); }
 
-// Register budget for three waves per SIMD: the search and re-rank phases
-// of a worker are never live at once, and without the hint the compiler
-// keeps more registers than three waves allow.
+// Register budget for four waves per SIMD: the search and re-rank phases of
+// a worker are never live at once; without the hint the compiler keeps more
+// registers than three waves allow (a few values spill at four).
 template <int CPL, int U, int LG, int CPL8, int CPLF>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k_serve(ServeArgs a) {
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k_serve(ServeArgs a) {
     extern __shared__ __align__(16) unsigned char smem[];
     const int lane = lane_id();
     const int wave = threadIdx.x / kWave;
