@@ -10,7 +10,9 @@
  *                  search), device
  *   aqr_rerank     Alg. 2 stages 2-3 (asymmetric distances, early
  *                  termination, exact FP32 re-rank, assembly), device
- * plus the baseline FP32 HNSW search on the same graph and support calls.
+ * plus the baseline FP32 HNSW search on the same graph, batch plans (one
+ * captured launch of uneven queries) and a serving loop (a resident kernel
+ * with continuous admission).
  *
  * Conventions
  *   - Every call returns an aqr_status; aqr_last_error() gives a message for
@@ -24,6 +26,8 @@
  *     as void*, NULL = default stream).  Arguments are validated on the host
  *     before any launch; a device fault surfaces at the caller's next
  *     synchronisation.
+ *   - A batch call with nq = 0 returns AQR_OK without launching anything;
+ *     its buffers may then be NULL.
  *   - Keys: every ordering is by (distance, id), id ascending on ties.
  *   - A bound index is read-only; concurrent calls on different streams are
  *     allowed when each call has its own workspace and outputs.

@@ -1534,10 +1534,11 @@ aqr_status run_search(const aqr_index* ix, const float* Q, int64_t nq, const int
                       size_t ws_bytes, const aqr_taps* taps, void* stream, bool f32,
                       const char* who) {
     clear_error();
-    if (!ix || !sp || !k || !ef || !out_id || !out_D || !ws || (!f32 && !out_cnt))
-        return fail(AQR_ERR_INVALID_ARG, std::string(who) + ": null pointer");
+    if (!ix || !sp) return fail(AQR_ERR_INVALID_ARG, std::string(who) + ": null pointer");
     if (nq < 0) return fail(AQR_ERR_INVALID_ARG, std::string(who) + ": nq < 0");
-    if (nq == 0) return AQR_OK;
+    if (nq == 0) return AQR_OK;  // an empty batch needs no buffers
+    if (!k || !ef || !out_id || !out_D || !ws || (!f32 && !out_cnt))
+        return fail(AQR_ERR_INVALID_ARG, std::string(who) + ": null pointer");
     if (!Q) return fail(AQR_ERR_INVALID_ARG, std::string(who) + ": null queries");
     if (nq > (int64_t)INT32_MAX) return fail(AQR_ERR_INVALID_ARG, std::string(who) + ": nq too large");
     if (sp->ef_max < 1 || sp->ef_max > 1024)
@@ -1639,9 +1640,10 @@ extern "C" aqr_status aqr_search_fp32(const aqr_index* ix, const float* Q, int64
 extern "C" aqr_status aqr_encode_queries(const aqr_index* ix, const float* Q, int64_t nq,
                                          uint8_t* qcodes, void* stream) {
     clear_error();
-    if (!ix || !qcodes) return fail(AQR_ERR_INVALID_ARG, "aqr_encode_queries: null pointer");
+    if (!ix) return fail(AQR_ERR_INVALID_ARG, "aqr_encode_queries: null pointer");
     if (nq < 0) return fail(AQR_ERR_INVALID_ARG, "aqr_encode_queries: nq < 0");
     if (nq == 0) return AQR_OK;
+    if (!qcodes) return fail(AQR_ERR_INVALID_ARG, "aqr_encode_queries: null pointer");
     if (!Q) return fail(AQR_ERR_INVALID_ARG, "aqr_encode_queries: null queries");
     hipLaunchKernelGGL(dev::k_encode, dim3((unsigned)nq), dim3(128), 0, (hipStream_t)stream,
                        ix->v, Q, nq, qcodes);
@@ -1687,10 +1689,11 @@ extern "C" aqr_status aqr_rerank(const aqr_index* ix, const float* Q, int64_t nq
                                  const aqr_rtaps* taps, void* stream) {
     try {
         clear_error();
-        if (!ix || !rp || !cand_id || !cand_cnt || !k || !out_id || !out_dist)
-            return fail(AQR_ERR_INVALID_ARG, "aqr_rerank: null pointer");
+        if (!ix || !rp) return fail(AQR_ERR_INVALID_ARG, "aqr_rerank: null pointer");
         if (nq < 0) return fail(AQR_ERR_INVALID_ARG, "aqr_rerank: nq < 0");
-        if (nq == 0) return AQR_OK;
+        if (nq == 0) return AQR_OK;  // an empty batch needs no buffers
+        if (!cand_id || !cand_cnt || !k || !out_id || !out_dist)
+            return fail(AQR_ERR_INVALID_ARG, "aqr_rerank: null pointer");
         if (!Q) return fail(AQR_ERR_INVALID_ARG, "aqr_rerank: null queries");
         if (nc_stride < 1 || nc_stride > 1024)
             return fail(AQR_ERR_INVALID_ARG, "aqr_rerank: nc_stride must be in [1, 1024]");

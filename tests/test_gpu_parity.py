@@ -131,7 +131,7 @@ def test_query_encoding_bit_exact(orc, small):
                                   orc.encode(Q, small["min"], small["scale"], stride=128))
 
 
-@pytest.mark.parametrize("ef", [10, 64, 210, 512])
+@pytest.mark.parametrize("ef", [10, 64, 210, 512, 1000])
 def test_stage1_bit_exact_small(orc, small, ef):
     Q = small["Q"]
     cap = 1 << 15
@@ -394,3 +394,21 @@ def test_wide_rows_pipeline(orc):
     assert len(same) >= nq - 2
     for q in same:
         np.testing.assert_allclose(odist.cpu().numpy()[q], rd[q], rtol=RTOL)
+
+
+def test_empty_batches(orc, small):
+    # nq = 0 is accepted by every batch entry point and launches nothing
+    torch = _torch()
+    from paper_2602_21600_amd import aqr
+    z = torch.zeros((0, small["d"]), dtype=torch.float32, device="cuda")
+    zi = torch.zeros(0, dtype=torch.int32, device="cuda")
+    cid = torch.zeros((0, 21), dtype=torch.int32, device="cuda")
+    ws = torch.zeros(aqr.aqr_search_workspace_size(), dtype=torch.uint8, device="cuda")
+    aqr.aqr_search(small["ix"], z, zi, zi, cid, cid.clone(), zi.clone(), ws, 64, 21)
+    out_id = torch.zeros((0, 10), dtype=torch.int32, device="cuda")
+    out_d = torch.zeros((0, 10), dtype=torch.float32, device="cuda")
+    aqr.aqr_rerank(small["ix"], z, cid, zi, zi, out_id, out_d)
+    aqr.aqr_search_fp32(small["ix"], z, zi, zi, out_id, out_d, ws, 64, 10)
+    plan = aqr.BatchPlan(small["ix"], 8, 10, 64, use_graph=False)
+    plan.launch(0)
+    torch.cuda.synchronize()
