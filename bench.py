@@ -574,7 +574,7 @@ def main():
     ap.add_argument("--n", type=int, default=None, help="base subset (testing only)")
     ap.add_argument("--nq", type=int, default=None)
     ap.add_argument("--efs", default=None, help="comma-separated ef sweep")
-    ap.add_argument("--cpu-sample", type=int, default=2000)
+    ap.add_argument("--cpu-sample", type=int, default=10000)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--profile", action="store_true",
                     help="skip sweeps and the CPU leg; time the AQR path at --ef")
@@ -614,7 +614,7 @@ def main():
     threads = threads if threads > 0 else min(16, os.cpu_count() or 1)
     args.loads = [float(x) for x in args.loads.split(",")]
     if args.workload == "batched":
-        if args.cpu_sample == 2000:
+        if args.cpu_sample == 10000:
             args.cpu_sample = 300
         return bench_batched(args, torch, aqr, W, wl, dev, threads)
     if args.workload == "serving":
