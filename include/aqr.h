@@ -368,8 +368,10 @@ size_t aqr_server_workspace_size(void);
  * start on the next free wave.  One wave mirrors the host's publication
  * counter into device memory; the kernel leaves after idle_ms without
  * unclaimed requests or on aqr_server_stop, and submit/poll relaunch it when
- * needed.  ws: caller-owned device workspace (aqr_server_workspace_size()
- * bytes) for the claim counters.  Each request runs Stage 1 and Stages 2-3
+ * needed.  While the kernel runs, its blocks hold most of the device; other
+ * work on the device runs in what they leave free, and aqr_server_stop (or
+ * idle_ms of quiet) releases it.  ws: caller-owned device workspace
+ * (aqr_server_workspace_size() bytes) for the claim counters.  Each request runs Stage 1 and Stages 2-3
  * with the same code as aqr_search/aqr_rerank, so its result equals the
  * batch result for the same query, k and ef.
  */
