@@ -803,6 +803,13 @@ def main():
                "kind": "oracle",
                "sample": f"first {S} of the {nq} queries, same index, ef={ef_a}, k={k}; "
                          f"encode + Stage 1 + Stages 2-3 in FP64"}
+        # the same oracle on one thread, on a tenth of the sample
+        S1 = max(1, S // 10)
+        orc.set_threads(1)
+        t = time.perf_counter()
+        orc.query(index, Q[:S1], k, ef_a, n_rerank=nrr_, tau_gap=tg_, tau_ratio=tr_)
+        cpu["one_thread_value"] = round(S1 / (time.perf_counter() - t), 1)
+        orc.set_threads(threads)
         s1 = ref["stage1"]
         gid = runner.plan.cand_id[:S].cpu().numpy().view(np.uint32)
         gcnt = runner.plan.cand_cnt[:S].cpu().numpy()

@@ -1458,11 +1458,9 @@ extern "C" size_t aqr_search_workspace_size(void) { return 256; }
 
 namespace {
 
-template <bool F32, int CPL, int LG>
+template <bool F32, int CPL, int U, int LG>
 hipError_t launch_search_k(dev::SearchArgs& a, int blocks, int wpb, size_t lds, int ncu,
                            hipStream_t s) {
-    // rows in flight per lane group in the distance phase
-    constexpr int U = CPL >= 4 ? 1 : 2;
     const bool taps = a.taps.expanded || a.taps.evaluated || a.taps.counts;
     auto kern = taps ? dev::k_search<F32, CPL, U, LG, true> : dev::k_search<F32, CPL, U, LG, false>;
     // the dynamic-LDS limit is raised once per size and kernel, outside any stream capture
@@ -1487,38 +1485,58 @@ hipError_t launch_search_k(dev::SearchArgs& a, int blocks, int wpb, size_t lds, 
     return hipGetLastError();
 }
 
-// Row geometry: CPL 16-byte chunks per lane, groups of 2^lg lanes per row
-// (lg >= 2; with CPL > 1 a row spans the wave).
+// Row geometry by row width (nch 16-byte chunks): CPL chunks per lane on
+// groups of 2^LG lanes (CPL * 2^LG >= nch), U rows per group in flight.
+// Short rows take two chunks per lane on narrow groups; wide rows take four
+// (codes) or eight (FP32) chunks per lane, so that a pass of the wave still
+// scores several rows: one wave works on one query, and with few queries in
+// a batch the number of rows in flight per wave sets the latency.
 template <bool F32>
-hipError_t launch_search(dev::SearchArgs& a, int cpl, int lg, int blocks, int wpb, size_t lds,
-                         int ncu, hipStream_t s) {
-    // code rows of 8 or 16 chunks: two chunks per lane on half the lanes
-    // (fewer group reductions and row bookkeeping per scored row)
-    if (!F32 && cpl == 1 && lg >= 3 && lg <= 4) {
-        if (lg == 3) return launch_search_k<F32, 2, 2>(a, blocks, wpb, lds, ncu, s);
-        return launch_search_k<F32, 2, 3>(a, blocks, wpb, lds, ncu, s);
-    }
-    if (cpl == 1) {
-        switch (lg) {
-            case 2: return launch_search_k<F32, 1, 2>(a, blocks, wpb, lds, ncu, s);
-            case 3: return launch_search_k<F32, 1, 3>(a, blocks, wpb, lds, ncu, s);
-            case 4: return launch_search_k<F32, 1, 4>(a, blocks, wpb, lds, ncu, s);
-            case 5: return launch_search_k<F32, 1, 5>(a, blocks, wpb, lds, ncu, s);
-            default: return launch_search_k<F32, 1, 6>(a, blocks, wpb, lds, ncu, s);
+hipError_t launch_search(dev::SearchArgs& a, int nch, int blocks, int wpb, size_t lds, int ncu,
+                         hipStream_t s) {
+    auto lg_for = [](int groups) {  // smallest lg with 2^lg >= groups, at least 2
+        int lg = 2;
+        while ((1 << lg) < groups) ++lg;
+        return lg;
+    };
+    if constexpr (!F32) {
+        if (nch <= 16) {  // up to 256 bytes: 2 chunks per lane, 2 rows in flight
+            switch (lg_for((nch + 1) / 2)) {
+                case 2: return launch_search_k<F32, 2, 2, 2>(a, blocks, wpb, lds, ncu, s);
+                default: return launch_search_k<F32, 2, 2, 3>(a, blocks, wpb, lds, ncu, s);
+            }
         }
-    }
-    if constexpr (F32) {
-        switch (cpl) {
-            case 2: return launch_search_k<F32, 2, 6>(a, blocks, wpb, lds, ncu, s);
-            case 4: return launch_search_k<F32, 4, 6>(a, blocks, wpb, lds, ncu, s);
-            case 8: return launch_search_k<F32, 8, 6>(a, blocks, wpb, lds, ncu, s);
-            default: return launch_search_k<F32, 16, 6>(a, blocks, wpb, lds, ncu, s);
+        if (nch <= 64) {  // up to 1 KB: 4 chunks per lane, 2 rows in flight
+            switch (lg_for((nch + 3) / 4)) {
+                case 3: return launch_search_k<F32, 4, 2, 3>(a, blocks, wpb, lds, ncu, s);
+                default: return launch_search_k<F32, 4, 2, 4>(a, blocks, wpb, lds, ncu, s);
+            }
         }
+        if (nch <= 128) return launch_search_k<F32, 4, 1, 5>(a, blocks, wpb, lds, ncu, s);
+        return launch_search_k<F32, 4, 1, 6>(a, blocks, wpb, lds, ncu, s);
     } else {
-        switch (cpl) {
-            case 2: return launch_search_k<F32, 2, 6>(a, blocks, wpb, lds, ncu, s);
-            default: return launch_search_k<F32, 4, 6>(a, blocks, wpb, lds, ncu, s);
+        if (nch <= 16) {  // up to 64 floats: 2 chunks per lane
+            switch (lg_for((nch + 1) / 2)) {
+                case 2: return launch_search_k<F32, 2, 2, 2>(a, blocks, wpb, lds, ncu, s);
+                default: return launch_search_k<F32, 2, 2, 3>(a, blocks, wpb, lds, ncu, s);
+            }
         }
+        if (nch <= 64) {  // up to 256 floats: 2 chunks per lane on up to 32 lanes
+            switch (lg_for((nch + 1) / 2)) {
+                case 4: return launch_search_k<F32, 2, 2, 4>(a, blocks, wpb, lds, ncu, s);
+                default: return launch_search_k<F32, 2, 2, 5>(a, blocks, wpb, lds, ncu, s);
+            }
+        }
+        if (nch <= 256) {  // up to 1,024 floats: 8 chunks per lane on up to 32 lanes
+            switch (lg_for((nch + 7) / 8)) {
+                case 2:
+                case 3:
+                case 4: return launch_search_k<F32, 8, 2, 4>(a, blocks, wpb, lds, ncu, s);
+                default: return launch_search_k<F32, 8, 2, 5>(a, blocks, wpb, lds, ncu, s);
+            }
+        }
+        if (nch <= 512) return launch_search_k<F32, 8, 1, 6>(a, blocks, wpb, lds, ncu, s);
+        return launch_search_k<F32, 16, 1, 6>(a, blocks, wpb, lds, ncu, s);
     }
 }
 
@@ -1603,8 +1621,8 @@ aqr_status run_search(const aqr_index* ix, const float* Q, int64_t nq, const int
     const int cpl = cpl_for(nch);
     if (cpl > 16) return fail(AQR_ERR_INVALID_ARG, std::string(who) + ": row too wide");
     if (!f32 && cpl > 4) return fail(AQR_ERR_INVALID_ARG, std::string(who) + ": code row too wide");
-    e = f32 ? launch_search<true>(a, cpl, a.lg, sp->blocks, wpb, lds, ix->num_cu, s)
-            : launch_search<false>(a, cpl, a.lg, sp->blocks, wpb, lds, ix->num_cu, s);
+    e = f32 ? launch_search<true>(a, nch, sp->blocks, wpb, lds, ix->num_cu, s)
+            : launch_search<false>(a, nch, sp->blocks, wpb, lds, ix->num_cu, s);
     if (e != hipSuccess) return hip_fail(e, who);
     return AQR_OK;
 }

@@ -412,3 +412,16 @@ def test_empty_batches(orc, small):
     plan = aqr.BatchPlan(small["ix"], 8, 10, 64, use_graph=False)
     plan.launch(0)
     torch.cuda.synchronize()
+
+
+def test_bench_ground_truth_matches_oracle(orc, small):
+    # the bench's exact kNN (FP32 screening on the GPU, FP64 re-score) equals
+    # the oracle's FP64 brute force, ids up to ties
+    import bench
+    X, Q = small["X"], small["Q"]
+    gi, gd = bench.ground_truth(X, Q, 10, "cuda:0", chunk=4096)
+    ri, rd = orc.knn_f32(X, Q, 10)
+    np.testing.assert_allclose(gd, rd, rtol=1e-12)
+    for q in range(Q.shape[0]):
+        for t in np.nonzero(gi[q] != ri[q])[0]:
+            assert np.sum(np.abs(rd[q] - rd[q, t]) <= 1e-12 * rd[q, t]) >= 2, (q, t)
