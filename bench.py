@@ -142,10 +142,11 @@ class AqrRunner:
 
 
 class Fp32Runner:
-    def __init__(self, aqr, ix, nq, k, ef, device):
+    def __init__(self, aqr, ix, nq, k, ef, device, visited_log2=0, waves_per_block=0):
         import torch
         self.aqr = aqr
         self.ix = ix
+        self.sp = dict(visited_log2=visited_log2, waves_per_block=waves_per_block)
         self.k_ = k
         self.ef_ = max(ef, k)
         self.k = torch.full((nq,), k, dtype=torch.int32, device=device)
@@ -156,7 +157,7 @@ class Fp32Runner:
 
     def step(self, Qd, taps=None):
         self.aqr.aqr_search_fp32(self.ix, Qd, self.k, self.ef, self.out_id, self.out_d, self.ws,
-                                 self.ef_, self.k_, taps=taps)
+                                 self.ef_, self.k_, taps=taps, **self.sp)
         return self.out_id, self.out_d
 
 
@@ -685,11 +686,15 @@ def main():
         tuning = {"visited_log2": args.vb, "waves_per_block": args.wpb}
     elif args.tune and not args.profile:
         best_ms = None
-        for vb in (6, 7, 8, 9):
-            for wpb in (2, 4):
-                r = AqrRunner(aqr, ix, nq, k, ef_a, dev, visited_log2=vb, waves_per_block=wpb,
-                              rerank=aqr_pick[2])
-                ms_t, _ = timed(torch, lambda m: r.search_only(Qd), 3, 1)
+        for vb in (6, 7, 8, 9, 10, 12):
+            for wpb in (1, 2, 4):
+                try:
+                    r = AqrRunner(aqr, ix, nq, k, ef_a, dev, visited_log2=vb,
+                                  waves_per_block=wpb, rerank=aqr_pick[2])
+                    ms_t, _ = timed(torch, lambda m: r.search_only(Qd), 3, 1)
+                except aqr.AqrError as e:  # LDS limit of the device
+                    log(f"tune visited_log2={vb} waves_per_block={wpb}: skipped ({e})")
+                    continue
                 log(f"tune visited_log2={vb} waves_per_block={wpb}: {ms_t:.3f} ms")
                 if best_ms is None or ms_t < best_ms:
                     best_ms, tuning = ms_t, {"visited_log2": vb, "waves_per_block": wpb}
@@ -757,7 +762,24 @@ def main():
     fp = None
     if fp_pick is not None:
         ef_f = fp_pick[0]
-        frun = Fp32Runner(aqr, ix, nq, k, ef_f, dev)
+        # the baseline gets the same launch-shape treatment as the AQR search
+        fp_tuning = dict(tuning)
+        if args.tune and not args.profile and not (args.vb or args.wpb):
+            best_ms = None
+            for vb in (6, 7, 8, 9, 10, 12):
+                for wpb in (1, 2, 4):
+                    try:
+                        r = Fp32Runner(aqr, ix, nq, k, ef_f, dev, visited_log2=vb,
+                                       waves_per_block=wpb)
+                        ms_t, _ = timed(torch, lambda m: r.step(Qd), 3, 1)
+                    except aqr.AqrError as e:
+                        log(f"tune fp32 visited_log2={vb} waves_per_block={wpb}: skipped ({e})")
+                        continue
+                    log(f"tune fp32 visited_log2={vb} waves_per_block={wpb}: {ms_t:.3f} ms")
+                    if best_ms is None or ms_t < best_ms:
+                        best_ms, fp_tuning = ms_t, {"visited_log2": vb, "waves_per_block": wpb}
+            log(f"fp32 tuning picked {fp_tuning}")
+        frun = Fp32Runner(aqr, ix, nq, k, ef_f, dev, **fp_tuning)
 
         def fp_step(marks):
             if marks:
@@ -777,6 +799,7 @@ def main():
         fp_bytes = int((cf[:, 1].sum() + cf[:, 2].sum() + nq) * xs * 4 +
                        cf[:, 0].sum() * s0 * 4 + cf[:, 4].sum() * s1 * 4 + nq * (4 * d + 8 * k))
         fp = {"value": round(nq / (ms_fp / 1e3), 1), "unit": "queries/s", "ef": ef_f,
+              "tuning": fp_tuning,
               "recall@10": round(fp_pick[1], 5), "ms_per_step": round(ms_fp, 4),
               "kernel_ms": round(per_fp[0], 4),
               "achieved_GBps": round(fp_bytes / (per_fp[0] / 1e3) / 1e9, 1),

@@ -1488,8 +1488,8 @@ hipError_t launch_search_k(dev::SearchArgs& a, int blocks, int wpb, size_t lds, 
 // Row geometry by row width (nch 16-byte chunks): CPL chunks per lane on
 // groups of 2^LG lanes (CPL * 2^LG >= nch), U rows per group in flight.
 // Short rows take two chunks per lane on narrow groups; wide rows take four
-// (codes) or eight (FP32) chunks per lane, so that a pass of the wave still
-// scores several rows: one wave works on one query, and with few queries in
+// or eight chunks per lane, so that a pass of the wave still scores several
+// rows: one wave works on one query, and with few queries in
 // a batch the number of rows in flight per wave sets the latency.
 template <bool F32>
 hipError_t launch_search(dev::SearchArgs& a, int nch, int blocks, int wpb, size_t lds, int ncu,
@@ -1506,14 +1506,12 @@ hipError_t launch_search(dev::SearchArgs& a, int nch, int blocks, int wpb, size_
                 default: return launch_search_k<F32, 2, 2, 3>(a, blocks, wpb, lds, ncu, s);
             }
         }
-        if (nch <= 64) {  // up to 1 KB: 4 chunks per lane, 2 rows in flight
-            switch (lg_for((nch + 3) / 4)) {
-                case 3: return launch_search_k<F32, 4, 2, 3>(a, blocks, wpb, lds, ncu, s);
-                default: return launch_search_k<F32, 4, 2, 4>(a, blocks, wpb, lds, ncu, s);
-            }
-        }
-        if (nch <= 128) return launch_search_k<F32, 4, 1, 5>(a, blocks, wpb, lds, ncu, s);
-        return launch_search_k<F32, 4, 1, 6>(a, blocks, wpb, lds, ncu, s);
+        if (nch <= 32)  // up to 512 bytes: 4 chunks per lane, 2 rows in flight
+            return launch_search_k<F32, 4, 2, 3>(a, blocks, wpb, lds, ncu, s);
+        if (nch <= 64)  // up to 1 KB: 8 chunks per lane, 2 rows in flight
+            return launch_search_k<F32, 8, 2, 3>(a, blocks, wpb, lds, ncu, s);
+        if (nch <= 128) return launch_search_k<F32, 8, 1, 4>(a, blocks, wpb, lds, ncu, s);
+        return launch_search_k<F32, 8, 1, 5>(a, blocks, wpb, lds, ncu, s);
     } else {
         if (nch <= 16) {  // up to 64 floats: 2 chunks per lane
             switch (lg_for((nch + 1) / 2)) {
