@@ -121,6 +121,10 @@ struct Builder {
         std::priority_queue<uint64_t, std::vector<uint64_t>, std::greater<uint64_t>> C;
         std::priority_queue<uint64_t> W;
         vis.next();
+        // The point being inserted is never its own candidate. A concurrent
+        // insert can link it into a list before its own layer-0 search runs;
+        // in a sequential build this mark changes nothing.
+        vis.test_set(q);
         for (uint64_t e : eps) {
             if (vis.test_set(key_id(e))) continue;
             C.push(e);
@@ -173,10 +177,19 @@ struct Builder {
     void add_link(uint32_t x, uint32_t y, int32_t layer) {
         std::unique_lock<std::mutex> lk(lock_of(x), std::defer_lock);
         if (concurrent) lk.lock();
+        link_locked(x, y, layer);
+    }
+    // Caller holds x's lock. Self links and entries already present are
+    // skipped; neither occurs in a sequential build.
+    void link_locked(uint32_t x, uint32_t y, int32_t layer) {
+        if (y == x) return;
         int32_t cap;
         uint32_t* r = nbrs(x, layer, cap);
         int32_t cnt = 0;
-        while (cnt < cap && r[cnt] != kNone) ++cnt;
+        while (cnt < cap && r[cnt] != kNone) {
+            if (r[cnt] == y) return;
+            ++cnt;
+        }
         if (cnt < cap) {
             r[cnt] = y;
             return;
@@ -211,7 +224,12 @@ struct Builder {
                 if (concurrent) lk.lock();
                 int32_t cap;
                 uint32_t* row = nbrs(i, lc, cap);
-                for (int32_t t = 0; t < r; ++t) row[t] = sel[t];
+                // Links that concurrent inserts appended to i's list meanwhile
+                // are merged after the selection, not overwritten; the list is
+                // empty here in a sequential build.
+                std::vector<uint32_t> prior(row, row + cap);
+                for (int32_t t = 0; t < cap; ++t) row[t] = t < r ? sel[t] : kNone;
+                for (int32_t t = 0; t < cap && prior[t] != kNone; ++t) link_locked(i, prior[t], lc);
             }
             for (int32_t t = 0; t < r; ++t) add_link(sel[t], i, lc);
             eps = W;
