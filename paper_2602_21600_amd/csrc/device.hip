@@ -1941,7 +1941,7 @@ constexpr int kSlotBits = 22;  // ticket = sequence << 22 | slot
 
 template <int CPL, int LG, int C8, int CF>
 hipError_t serve_launch_t(aqr_server* sv) {
-    constexpr int U = CPL >= 2 ? 1 : 2;
+    constexpr int U = 2;
     auto kern = dev::k_serve<CPL, U, LG, C8, CF>;
     static std::atomic<int> lds_set{0};
     if ((int)sv->lds > lds_set.load()) {
@@ -1966,25 +1966,25 @@ hipError_t serve_launch_t(aqr_server* sv) {
     return hipGetLastError();
 }
 
-template <int LG>
+template <int CPL, int LG>
 hipError_t (*pick_serve_cf(int cf))(aqr_server*) {
     switch (cf) {
-        case 1: return serve_launch_t<1, LG, 1, 1>;
-        case 2: return serve_launch_t<1, LG, 1, 2>;
-        case 4: return serve_launch_t<1, LG, 1, 4>;
+        case 1: return serve_launch_t<CPL, LG, 1, 1>;
+        case 2: return serve_launch_t<CPL, LG, 1, 2>;
+        case 4: return serve_launch_t<CPL, LG, 1, 4>;
         default: return nullptr;
     }
 }
 
-hipError_t (*pick_serve(int c8, int lg, int cf))(aqr_server*) {
-    if (c8 != 1) return nullptr;
-    switch (lg) {
-        case 2: return pick_serve_cf<2>(cf);
-        case 3: return pick_serve_cf<3>(cf);
-        case 4: return pick_serve_cf<4>(cf);
-        case 5: return pick_serve_cf<5>(cf);
-        default: return pick_serve_cf<6>(cf);
-    }
+// Code-row geometry of the serving worker's Stage 1, by row width (nch
+// 16-byte chunks, at most 64): the batch kernel's rule with at most four
+// chunks per lane.
+hipError_t (*pick_serve(int nch, int cf))(aqr_server*) {
+    if (nch <= 8) return pick_serve_cf<2, 2>(cf);
+    if (nch <= 16) return pick_serve_cf<2, 3>(cf);
+    if (nch <= 32) return pick_serve_cf<4, 3>(cf);
+    if (nch <= 64) return pick_serve_cf<4, 4>(cf);
+    return nullptr;
 }
 
 // (Re)launch the persistent kernel when it is not running.  A running
@@ -2133,7 +2133,7 @@ extern "C" aqr_status aqr_server_create(const aqr_index* ix, const aqr_server_pa
         sv->args.k_max = prm->k_max;
         sv->args.nc_max = nc_max;
         sv->args.idle_ticks = (uint64_t)std::max(1, prm->idle_ms) * 100000ull;
-        sv->launch_fn = pick_serve(c8, sa.lg, cf);
+        sv->launch_fn = c8 == 1 ? pick_serve(nch8, cf) : nullptr;
         if (!sv->launch_fn) {
             delete sv;
             return fail(AQR_ERR_INVALID_ARG, "aqr_server_create: unsupported row geometry");
