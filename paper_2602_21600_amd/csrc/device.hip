@@ -275,47 +275,62 @@ __device__ __forceinline__ Geo make_geo(int lg, int nch, int lane) {
     return g;
 }
 
-// Score nn rows whose ids are ids[0..nn) (LDS); keys[r] = (dist bits << 32) | (id << 1): the
-// low bit is left free for the expanded flag of W, and keys still order by (distance, id).
-// Rows are spread over groups of 2^LG lanes, one 16-byte chunk per lane and
-// CPL chunks per lane.  There are no divergent branches: rows past nn and
-// chunks past the row read row 0 / chunk 0 (valid memory) and are masked out
-// of the sum, and ids[] is read up to one pass past nn (the caller's array
-// has that slack).
+// Score rows ids[r0 .. r0 + US * RPP) that lie below nn (ids in LDS); keys[r] =
+// (dist bits << 32) | (id << 1): the low bit is left free for the expanded
+// flag of W, and keys still order by (distance, id).  Rows are spread over
+// groups of 2^LG lanes, one 16-byte chunk per lane and CPL chunks per lane;
+// the US row sets of a pass are loaded before any is scored.  There are no
+// divergent branches: rows past nn and chunks past the row read row 0 /
+// chunk 0 (valid memory) and are masked out of the sum.
+template <bool F32, int CPL, int US, int LG>
+__device__ __forceinline__ void eval_pass(const Idx& ix, const uint32_t* ids, int nn, int r0,
+                                          uint64_t* keys, const uint4 (&qv)[CPL], uint32_t qq,
+                                          const int sub, const int grp, const int nch) {
+    using R = Rows<F32>;
+    constexpr int G = 1 << LG, RPP = kWave >> LG;
+    uint4 x[US][CPL];
+    uint32_t id[US];
+#pragma unroll
+    for (int u = 0; u < US; ++u) {
+        const int r = r0 + u * RPP + grp;
+        id[u] = r < nn ? ids[r] : 0u;
+#pragma unroll
+        for (int c = 0; c < CPL; ++c) {
+            const int ch = sub + c * G;
+            x[u][c] = R::load(ix, id[u], ch < nch ? ch : 0);
+        }
+    }
+#pragma unroll
+    for (int u = 0; u < US; ++u) {
+        typename R::Acc s = R::zero();
+#pragma unroll
+        for (int c = 0; c < CPL; ++c) {
+            const typename R::Acc t = R::part(x[u][c], qv[c]);
+            s = R::add(s, sub + c * G < nch ? t : R::zero());
+        }
+        s = R::template gsum<LG>(s);
+        const int r = r0 + u * RPP + grp;
+        if (sub == G - 1 && r < nn)
+            keys[r] = ((uint64_t)R::dbits(s, qq) << 32) | ((uint64_t)id[u] << 1);
+    }
+}
+
+// Score nn rows: passes of U row sets while the last set of a pass still
+// holds rows, then single-set passes for the rest, so a short list (at most
+// one set of rows) costs one set, not U.
 template <bool F32, int CPL, int U, int LG>
 __device__ __forceinline__ void eval_rows(const Idx& ix, const uint32_t* ids, int nn,
                                           uint64_t* keys, const uint4 (&qv)[CPL], uint32_t qq,
                                           const int lane, const int nch) {
-    using R = Rows<F32>;
     constexpr int G = 1 << LG, RPP = kWave >> LG;
     const int sub = lane & (G - 1), grp = lane >> LG;
-    for (int r0 = 0; r0 < nn; r0 += RPP * U) {
-        uint4 x[U][CPL];
-        uint32_t id[U];
-#pragma unroll
-        for (int u = 0; u < U; ++u) {
-            const int r = r0 + u * RPP + grp;
-            id[u] = r < nn ? ids[r] : 0u;
-#pragma unroll
-            for (int c = 0; c < CPL; ++c) {
-                const int ch = sub + c * G;
-                x[u][c] = R::load(ix, id[u], ch < nch ? ch : 0);
-            }
-        }
-#pragma unroll
-        for (int u = 0; u < U; ++u) {
-            typename R::Acc s = R::zero();
-#pragma unroll
-            for (int c = 0; c < CPL; ++c) {
-                const typename R::Acc t = R::part(x[u][c], qv[c]);
-                s = R::add(s, sub + c * G < nch ? t : R::zero());
-            }
-            s = R::template gsum<LG>(s);
-            const int r = r0 + u * RPP + grp;
-            if (sub == G - 1 && r < nn)
-                keys[r] = ((uint64_t)R::dbits(s, qq) << 32) | ((uint64_t)id[u] << 1);
-        }
+    int r0 = 0;
+    if constexpr (U > 1) {
+        for (; nn - r0 > RPP * (U - 1); r0 += RPP * U)
+            eval_pass<F32, CPL, U, LG>(ix, ids, nn, r0, keys, qv, qq, sub, grp, nch);
     }
+    for (; r0 < nn; r0 += RPP)
+        eval_pass<F32, CPL, 1, LG>(ix, ids, nn, r0, keys, qv, qq, sub, grp, nch);
 }
 
 // ---------------------------------------------------------------------------
@@ -565,13 +580,17 @@ __device__ __forceinline__ void search_query(const SearchArgs& a, const int64_t 
             const uint64_t key = j < nn ? st_key[j] : ~0ull;
             uint64_t A = ballot(key < bound);
             if (A == 0) continue;
-            // entries of W below the key, by bisection of the sorted list
+            // entries of W below the key, by bisection of the sorted list:
+            // the key's count lies in [lo, lo + n] and n shrinks by its
+            // half each step (the same on every lane), so every read is
+            // inside W and no lane branches
             int lo = 0;
-            for (int step = 1 << (31 - __builtin_clz((unsigned)wsize)); step > 0; step >>= 1) {
-                const int p = lo + step - 1;
-                const uint64_t w = mk[p < wsize ? p : 0];
-                lo += (p < wsize && w < key) ? step : 0;
+            for (int n = wsize; n > 1;) {
+                const int half = n >> 1;
+                lo = mk[lo + half] < key ? lo + half : lo;
+                n -= half;
             }
+            lo += mk[lo] < key ? 1 : 0;
             // a key already in W (a node the visited cache forgot) is dropped
             const uint64_t wl = mk[lo < wsize ? lo : 0];
             A &= ~ballot(lo < wsize && (wl | 1ull) == (key | 1ull));
