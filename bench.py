@@ -665,7 +665,10 @@ def main():
         gt_ids, gt_d = ground_truth(X, Q, k, dev)
     Qd = torch.from_numpy(Q).to(dev)
 
-    efs = [int(e) for e in args.efs.split(",")] if args.efs else list(wl.ef) + [384, 512]
+    # the workload's ef list, then finer steps above it, so the cheapest ef that
+    # reaches the recall target is found for both searches alike
+    efs = ([int(e) for e in args.efs.split(",")] if args.efs else
+           sorted(set(wl.ef) | {288, 320, 352, 384, 448, 512}))
 
     def recall_of(ids):
         return recall_at(ids.cpu().numpy(), X, Q, gt_ids, gt_d, k)

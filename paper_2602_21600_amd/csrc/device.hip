@@ -521,18 +521,20 @@ __device__ __forceinline__ void search_query(const SearchArgs& a, const int64_t 
     for (;;) {
         // nearest unexpanded entry of W
         int idx = -1;
+        uint64_t kc = 0;
         for (int b0 = first & ~(kWave - 1); b0 < wsize; b0 += kWave) {
             const int i = b0 + lane;
             const uint64_t w = mk[i];  // inside W's capacity (whole 64-entry slots)
             const uint64_t m = ballot(i >= first && i < wsize && (w & 1ull) == 0);
             if (m) {
-                idx = b0 + (int)__builtin_ctzll(m);
+                const int t = (int)__builtin_ctzll(m);
+                idx = b0 + t;
+                kc = readlane64(w, t);
                 break;
             }
         }
         idx = uni(idx);
         if (idx < 0) break;
-        const uint64_t kc = uni64(mk[idx]);
         const uint32_t c = (uint32_t)kc >> 1;
         first = idx + 1;
         wsync();
@@ -590,9 +592,14 @@ __device__ __forceinline__ void search_query(const SearchArgs& a, const int64_t 
                 lo = mk[lo + half] < key ? lo + half : lo;
                 n -= half;
             }
-            lo += mk[lo] < key ? 1 : 0;
-            // a key already in W (a node the visited cache forgot) is dropped
-            const uint64_t wl = mk[lo < wsize ? lo : 0];
+            // The last step reads W[lo] and W[lo + 1] together (lo + 1 <=
+            // wsize <= ef_cap: inside the array, the spare entry at worst).
+            // The entry at the key's place shows whether the key is already
+            // in W (a node the visited cache forgot); such a key is dropped.
+            const uint64_t w0 = mk[lo], w1 = mk[lo + 1];
+            const bool past = w0 < key;
+            lo += past ? 1 : 0;
+            const uint64_t wl = past ? w1 : w0;
             A &= ~ballot(lo < wsize && (wl | 1ull) == (key | 1ull));
             const int m_adm = __popcll(A);
             if (m_adm == 0) continue;
