@@ -910,6 +910,8 @@ def main():
             "alg_bytes_per_launch": alg_bytes,
             "code_bytes": code_bytes, "adjacency_bytes": adj_bytes, "io_bytes": io_bytes,
             "reevaluation_overhead": round(reeval, 4),
+            "expansions_per_query": round(float(cnt[:, 0].mean()), 2),
+            "evaluations_per_query": round(float(cnt[:, 1].mean()), 1),
         },
         "rerank_ms": round(rerank_ms, 4),
         "latency_us": {"p50": round(float(np.percentile(lat_us, 50)), 2),
