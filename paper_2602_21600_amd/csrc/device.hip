@@ -315,22 +315,40 @@ __device__ __forceinline__ void eval_pass(const Idx& ix, const uint32_t* ids, in
     }
 }
 
-// Score nn rows: passes of U row sets while the last set of a pass still
-// holds rows, then single-set passes for the rest, so a short list (at most
-// one set of rows) costs one set, not U.
+// Score nn rows in passes of as many row sets as the remaining rows need, at
+// most U, so a short list costs as many sets as it fills, not U.
 template <bool F32, int CPL, int U, int LG>
 __device__ __forceinline__ void eval_rows(const Idx& ix, const uint32_t* ids, int nn,
                                           uint64_t* keys, const uint4 (&qv)[CPL], uint32_t qq,
                                           const int lane, const int nch) {
     constexpr int G = 1 << LG, RPP = kWave >> LG;
     const int sub = lane & (G - 1), grp = lane >> LG;
-    int r0 = 0;
-    if constexpr (U > 1) {
-        for (; nn - r0 > RPP * (U - 1); r0 += RPP * U)
-            eval_pass<F32, CPL, U, LG>(ix, ids, nn, r0, keys, qv, qq, sub, grp, nch);
-    }
-    for (; r0 < nn; r0 += RPP)
+    for (int r0 = 0; r0 < nn;) {
+        const int sets = min(U, (nn - r0 + RPP - 1) / RPP);  // wave-uniform
+        if constexpr (U >= 4) {
+            if (sets == 4) {
+                eval_pass<F32, CPL, (U >= 4 ? 4 : 1), LG>(ix, ids, nn, r0, keys, qv, qq, sub, grp, nch);
+                r0 += 4 * RPP;
+                continue;
+            }
+        }
+        if constexpr (U >= 3) {
+            if (sets == 3) {
+                eval_pass<F32, CPL, (U >= 3 ? 3 : 1), LG>(ix, ids, nn, r0, keys, qv, qq, sub, grp, nch);
+                r0 += 3 * RPP;
+                continue;
+            }
+        }
+        if constexpr (U >= 2) {
+            if (sets == 2) {
+                eval_pass<F32, CPL, (U >= 2 ? 2 : 1), LG>(ix, ids, nn, r0, keys, qv, qq, sub, grp, nch);
+                r0 += 2 * RPP;
+                continue;
+            }
+        }
         eval_pass<F32, CPL, 1, LG>(ix, ids, nn, r0, keys, qv, qq, sub, grp, nch);
+        r0 += RPP;
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -1516,10 +1534,12 @@ hipError_t launch_search_k(dev::SearchArgs& a, int blocks, int wpb, size_t lds, 
 // Short rows take two chunks per lane on narrow groups; wide rows take four
 // or eight chunks per lane, so that a pass of the wave still scores several
 // rows: one wave works on one query, and with few queries in
-// a batch the number of rows in flight per wave sets the latency.
+// a batch the number of rows in flight per wave sets the latency.  A batch
+// of at most one wave per SIMD (lat) leaves registers to spare, so wide
+// rows then keep four row sets in flight instead of two (128 VGPRs of rows).
 template <bool F32>
 hipError_t launch_search(dev::SearchArgs& a, int nch, int blocks, int wpb, size_t lds, int ncu,
-                         hipStream_t s) {
+                         hipStream_t s, bool lat) {
     auto lg_for = [](int groups) {  // smallest lg with 2^lg >= groups, at least 2
         int lg = 2;
         while ((1 << lg) < groups) ++lg;
@@ -1534,8 +1554,9 @@ hipError_t launch_search(dev::SearchArgs& a, int nch, int blocks, int wpb, size_
         }
         if (nch <= 32)  // up to 512 bytes: 4 chunks per lane, 2 rows in flight
             return launch_search_k<F32, 4, 2, 3>(a, blocks, wpb, lds, ncu, s);
-        if (nch <= 64)  // up to 1 KB: 8 chunks per lane, 2 rows in flight
-            return launch_search_k<F32, 8, 2, 3>(a, blocks, wpb, lds, ncu, s);
+        if (nch <= 64)  // up to 1 KB: 8 chunks per lane, 2 (lat: 4) rows in flight
+            return lat ? launch_search_k<F32, 8, 4, 3>(a, blocks, wpb, lds, ncu, s)
+                       : launch_search_k<F32, 8, 2, 3>(a, blocks, wpb, lds, ncu, s);
         if (nch <= 128) return launch_search_k<F32, 8, 1, 4>(a, blocks, wpb, lds, ncu, s);
         return launch_search_k<F32, 8, 1, 5>(a, blocks, wpb, lds, ncu, s);
     } else {
@@ -1555,8 +1576,12 @@ hipError_t launch_search(dev::SearchArgs& a, int nch, int blocks, int wpb, size_
             switch (lg_for((nch + 7) / 8)) {
                 case 2:
                 case 3:
-                case 4: return launch_search_k<F32, 8, 2, 4>(a, blocks, wpb, lds, ncu, s);
-                default: return launch_search_k<F32, 8, 2, 5>(a, blocks, wpb, lds, ncu, s);
+                case 4:
+                    return lat ? launch_search_k<F32, 8, 4, 4>(a, blocks, wpb, lds, ncu, s)
+                               : launch_search_k<F32, 8, 2, 4>(a, blocks, wpb, lds, ncu, s);
+                default:
+                    return lat ? launch_search_k<F32, 8, 4, 5>(a, blocks, wpb, lds, ncu, s)
+                               : launch_search_k<F32, 8, 2, 5>(a, blocks, wpb, lds, ncu, s);
             }
         }
         if (nch <= 512) return launch_search_k<F32, 8, 1, 6>(a, blocks, wpb, lds, ncu, s);
@@ -1645,8 +1670,9 @@ aqr_status run_search(const aqr_index* ix, const float* Q, int64_t nq, const int
     const int cpl = cpl_for(nch);
     if (cpl > 16) return fail(AQR_ERR_INVALID_ARG, std::string(who) + ": row too wide");
     if (!f32 && cpl > 4) return fail(AQR_ERR_INVALID_ARG, std::string(who) + ": code row too wide");
-    e = f32 ? launch_search<true>(a, nch, sp->blocks, wpb, lds, ix->num_cu, s)
-            : launch_search<false>(a, nch, sp->blocks, wpb, lds, ix->num_cu, s);
+    const bool lat = nq <= (int64_t)ix->num_cu * 4;  // at most one wave per SIMD
+    e = f32 ? launch_search<true>(a, nch, sp->blocks, wpb, lds, ix->num_cu, s, lat)
+            : launch_search<false>(a, nch, sp->blocks, wpb, lds, ix->num_cu, s, lat);
     if (e != hipSuccess) return hip_fail(e, who);
     return AQR_OK;
 }

@@ -364,13 +364,15 @@ def test_ragged_dimension_pipeline(orc, d):
     check_rerank(orc, index, Q, s1, 10, gr, force_et=0, n_rerank=20)
 
 
-def test_wide_rows_pipeline(orc):
-    # 960-dimensional rows (the GIST-1M shape, M_0 = 32): code rows span a
-    # whole wave (64 lanes of 16 bytes, reduced across the four rows of 16
-    # lanes) and FP32 rows take four chunks per lane
+@pytest.mark.parametrize("nq", [40, 1100])
+def test_wide_rows_pipeline(orc, nq):
+    # 960-dimensional rows (the GIST-1M shape, M_0 = 32): code rows take 8
+    # chunks per lane on 8-lane groups and FP32 rows 8 chunks per lane on
+    # 32-lane groups.  A batch of at most one wave per SIMD (40 queries)
+    # keeps four row sets in flight, a larger one (1,100 queries) two.
     torch = _torch()
     from paper_2602_21600_amd import aqr
-    X, Q = W.tiny(2500, 960, seed=77, clusters=6, nq=40)
+    X, Q = W.tiny(2500, 960, seed=77, clusters=6, nq=nq)
     index = make_index(orc, X, 32, 60)
     s1 = run_stage1(index, Q, 10, 128, tap_cap=1 << 14)
     o, _ = oracle_stage1(orc, index, Q, 10, 128, tap_cap=1 << 14)
@@ -380,7 +382,6 @@ def test_wide_rows_pipeline(orc):
         np.testing.assert_array_equal(s1["expanded"][q, :ne], o["expanded"][q, :ne])
     gr = _rerank_gpu(index, s1, 10, force_et=0, n_rerank=40)
     check_rerank(orc, index, Q, s1, 10, gr, force_et=0, n_rerank=40)
-    nq = Q.shape[0]
     Qd = torch.from_numpy(Q).cuda()
     kd = torch.full((nq,), 10, dtype=torch.int32, device="cuda")
     efd = torch.full((nq,), 96, dtype=torch.int32, device="cuda")
@@ -390,8 +391,10 @@ def test_wide_rows_pipeline(orc):
     aqr.aqr_search_fp32(index["ix"], Qd, kd, efd, oid, odist, ws, 96, 10)
     torch.cuda.synchronize()
     rid, rd = orc.search_f32(index["graph"], X, Q, 96, 10)
+    # FP32 against FP64 distances may order a near-tie differently and so
+    # take another path: a few queries in fifty may differ
     same = [q for q in range(nq) if np.array_equal(oid.cpu().numpy()[q], rid[q])]
-    assert len(same) >= nq - 2
+    assert len(same) >= nq - max(2, nq // 50)
     for q in same:
         np.testing.assert_allclose(odist.cpu().numpy()[q], rd[q], rtol=RTOL)
 
