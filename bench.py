@@ -615,7 +615,7 @@ def main():
                     help="re-rank setting (--profile: default no-et; batched: table3)")
     ap.add_argument("--tune-sample", type=int, default=20000)
     ap.add_argument("--tune", action="store_true",
-                    help="tune the launch shape of the timed search by timing")
+                    help="tune the launch shapes of the timed searches (AQR and FP32) by timing")
     ap.add_argument("--vb", type=int, default=0, help="visited_log2 of the timed search (skips tuning)")
     ap.add_argument("--wpb", type=int, default=0, help="waves per block of the timed search (skips tuning)")
     ap.add_argument("--ring", type=int, default=4096, help="serving: request slots")
@@ -713,19 +713,19 @@ def main():
 
     # ---- tuning (results do not depend on it) and the timed AQR path ----
     ef_a = aqr_pick[0]
-    # default launch shape of the timed search: the one the tuning loop below
-    # picks on this workload (results do not depend on it)
-    tuning = {"visited_log2": 7, "waves_per_block": 4}
+    # launch shape of the timed search without --tune: the one the tuning
+    # loop below picks on the default workload (results do not depend on it)
+    tuning = {"visited_log2": 8, "waves_per_block": 4}
     if args.vb or args.wpb:
         tuning = {"visited_log2": args.vb, "waves_per_block": args.wpb}
     elif args.tune and not args.profile:
         best_ms = None
-        for vb in (6, 7, 8, 9, 10, 12):
+        for vb in (6, 7, 8, 9, 10, 11, 12):
             for wpb in (1, 2, 4):
                 try:
                     r = AqrRunner(aqr, ix, nq, k, ef_a, dev, visited_log2=vb,
                                   waves_per_block=wpb, rerank=aqr_pick[2])
-                    ms_t, _ = timed(torch, lambda m: r.search_only(Qd), 3, 1)
+                    ms_t, _ = timed(torch, lambda m: r.search_only(Qd), 5, 1)
                 except aqr.AqrError as e:  # LDS limit of the device
                     log(f"tune visited_log2={vb} waves_per_block={wpb}: skipped ({e})")
                     continue
@@ -796,16 +796,19 @@ def main():
     fp = None
     if fp_pick is not None:
         ef_f = fp_pick[0]
-        # the baseline gets the same launch-shape treatment as the AQR search
-        fp_tuning = dict(tuning)
+        # the baseline gets the same launch-shape treatment as the AQR search:
+        # without --tune, the shape the tuning loop picks for it on the default
+        # workload (FP32 rows are 4x the bytes, so a larger visited cache pays)
+        fp_tuning = ({"visited_log2": args.vb, "waves_per_block": args.wpb}
+                     if (args.vb or args.wpb) else {"visited_log2": 10, "waves_per_block": 4})
         if args.tune and not args.profile and not (args.vb or args.wpb):
             best_ms = None
-            for vb in (6, 7, 8, 9, 10, 12):
+            for vb in (6, 7, 8, 9, 10, 11, 12):
                 for wpb in (1, 2, 4):
                     try:
                         r = Fp32Runner(aqr, ix, nq, k, ef_f, dev, visited_log2=vb,
                                        waves_per_block=wpb)
-                        ms_t, _ = timed(torch, lambda m: r.step(Qd), 3, 1)
+                        ms_t, _ = timed(torch, lambda m: r.step(Qd), 5, 1)
                     except aqr.AqrError as e:
                         log(f"tune fp32 visited_log2={vb} waves_per_block={wpb}: skipped ({e})")
                         continue

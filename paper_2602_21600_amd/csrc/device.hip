@@ -710,13 +710,15 @@ void k_search(SearchArgs a) {
     const int lane = lane_id();
     const int wave = threadIdx.x / kWave;
     const Idx& ix = a.ix;
-    const SearchLds L{a.ef_cap, st_cap_of(ix.s0, ix.s1), a.vb, ix.xs, ix.dp};
+    // The 8-bit search encodes the query straight from global memory, so its
+    // layout has no FP32 query (xs 0); the FP32 search keeps it in LDS.
+    const SearchLds L{a.ef_cap, st_cap_of(ix.s0, ix.s1), a.vb, F32 ? ix.xs : 0, ix.dp};
     unsigned char* base = smem + (size_t)wave * a.wave_lds;
     uint64_t* mk = reinterpret_cast<uint64_t*>(base + L.off_mk());
     uint32_t* st_id = reinterpret_cast<uint32_t*>(base + L.off_st());
     uint64_t* st_key = reinterpret_cast<uint64_t*>(base + L.off_sk());
     uint64_t* visb = reinterpret_cast<uint64_t*>(base + L.off_vis());
-    float* qf = reinterpret_cast<float*>(base + L.off_qf());
+    float* qlds = reinterpret_cast<float*>(base + L.off_qf());
     uint8_t* qc = base + L.off_qc();
 
     VisCache vis{visb, a.vb, max(ix.idbits, a.vb + 1)};
@@ -745,13 +747,15 @@ void k_search(SearchArgs a) {
             }
             int bad =
                 uni((k < 1 || efe > a.ef_cap || nc < 1 || nc > a.out_stride || nc > efe) ? 1 : 0);
+            float* qf = F32 ? qlds : const_cast<float*>(a.Q + q * ix.d);
             if (!bad) {
-                // load the FP32 query into LDS (zero padded); reject non-finite values
+                // reject non-finite values; the FP32 search copies the query
+                // into LDS (zero padded)
                 bool nonfinite = false;
                 for (int j = lane; j < ix.xs; j += kWave) {
                     const float v = j < ix.d ? a.Q[q * ix.d + j] : 0.0f;
                     nonfinite |= !__builtin_isfinite(v);
-                    qf[j] = v;
+                    if (F32) qf[j] = v;
                 }
                 bad = uni(ballot(nonfinite) != 0 ? 1 : 0);
             }
@@ -1631,7 +1635,7 @@ aqr_status run_search(const aqr_index* ix, const float* Q, int64_t nq, const int
     const int ef_cap = (sp->ef_max + 63) / 64 * 64;  // W capacity: whole 64-entry slots
     dev::SearchLds sl{ef_cap,
                       std::max(v.s0, v.s1) <= 64 ? 64 : (std::max(v.s0, v.s1) + 63) / 64 * 64, vb,
-                      v.xs, v.dp};
+                      f32 ? v.xs : 0, v.dp};  // the 8-bit search keeps no FP32 query in LDS
     const size_t wl = sl.bytes();
     const size_t lds = wl * wpb;
     if (lds > ix->max_lds)
