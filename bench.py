@@ -188,6 +188,16 @@ class Fp32Runner:
         return self.out_id, self.out_d
 
 
+def spin_up(torch, fn, seconds=0.5):
+    """Run fn(None) back to back for about `seconds`, so that an idle GPU's
+    clock has ramped up before launch shapes are compared by timing."""
+    t0 = time.perf_counter()
+    while time.perf_counter() - t0 < seconds:
+        for _ in range(8):
+            fn(None)
+        torch.cuda.synchronize()
+
+
 def timed(torch, fn, steps, warmup, kernel_events=None):
     """Run warmup then `steps` timed calls; returns (ms_per_step, per-kernel ms)."""
     for _ in range(warmup):
@@ -347,17 +357,36 @@ def bench_batched(args, torch, aqr, W, wl, dev, threads):
     out_d = torch.empty((nq, k_max), dtype=torch.float32, device=dev)
     ws = torch.zeros(aqr.aqr_search_workspace_size(), dtype=torch.uint8, device=dev)
 
+    # the baseline's launch shape is tuned on the same batch, as the AQR plan's is
+    fp_sp, best_fp = {}, None
+    spin_up(torch, lambda m: aqr.aqr_search_fp32(ix, Qd, kd, efd, out_id, out_d, ws, ef_max,
+                                                 k_max, order=b["order"]))
+    for vb in (7, 8, 9, 10, 11):
+        for wpb in (1, 2, 4):
+            cand = dict(visited_log2=vb, waves_per_block=wpb)
+            try:
+                ms_t, _ = timed(torch, lambda m: aqr.aqr_search_fp32(
+                    ix, Qd, kd, efd, out_id, out_d, ws, ef_max, k_max, order=b["order"], **cand),
+                    2, 1)
+            except aqr.AqrError as e:  # LDS limit of the device
+                log(f"tune fp32 {cand}: skipped ({e})")
+                continue
+            if best_fp is None or ms_t < best_fp:
+                best_fp, fp_sp = ms_t, cand
+    log(f"fp32 tuning picked {fp_sp}")
+
     def fp_step(marks):
         if marks:
             marks[0].record()
-        aqr.aqr_search_fp32(ix, Qd, kd, efd, out_id, out_d, ws, ef_max, k_max, order=b["order"])
+        aqr.aqr_search_fp32(ix, Qd, kd, efd, out_id, out_d, ws, ef_max, k_max, order=b["order"],
+                            **fp_sp)
         if marks:
             marks[1].record()
 
     log("timing FP32 HNSW on the same batch")
     ms_fp, per_fp = timed(torch, fp_step, args.steps, args.warmup, kernel_events=2)
     rq_fp = recall_per_query(out_id.cpu().numpy(), X, Q, gt_ids, gt_d, kk)
-    fp = {"value": round(nq / (ms_fp / 1e3), 1), "unit": "queries/s",
+    fp = {"value": round(nq / (ms_fp / 1e3), 1), "unit": "queries/s", "tuning": fp_sp,
           "ms_per_step": round(ms_fp, 4), "recall@min(k,10)": round(float(rq_fp.mean()), 5),
           "recall@10_by_ef": {int(v): round(float(rq_fp[k10 & (efq == v)].mean()), 5)
                               for v in np.unique(efq)}}
@@ -601,7 +630,9 @@ def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
-    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--warmup", type=int, default=200,
+                    help="untimed steps before each timed region: an idle GPU sits at a low "
+                         "clock and needs a fraction of a second of steady load to leave it")
     ap.add_argument("--workload", default="sift1m")
     ap.add_argument("--n", type=int, default=None, help="base subset (testing only)")
     ap.add_argument("--nq", type=int, default=None)
@@ -613,7 +644,9 @@ def main():
     ap.add_argument("--ef", type=int, default=None)
     ap.add_argument("--rerank", default=None,
                     help="re-rank setting (--profile: default no-et; batched: table3)")
-    ap.add_argument("--tune-sample", type=int, default=20000)
+    ap.add_argument("--tune-sample", type=int, default=100_000,
+                    help="batched: queries timed per launch shape (shapes that win on a small "
+                         "sample can lose on the whole batch, whose occupancy matters more)")
     ap.add_argument("--tune", action="store_true",
                     help="tune the launch shapes of the timed searches (AQR and FP32) by timing")
     ap.add_argument("--vb", type=int, default=0, help="visited_log2 of the timed search (skips tuning)")
@@ -720,6 +753,8 @@ def main():
         tuning = {"visited_log2": args.vb, "waves_per_block": args.wpb}
     elif args.tune and not args.profile:
         best_ms = None
+        r0 = AqrRunner(aqr, ix, nq, k, ef_a, dev, rerank=aqr_pick[2], **tuning)
+        spin_up(torch, lambda m: r0.search_only(Qd))
         for vb in (6, 7, 8, 9, 10, 11, 12):
             for wpb in (1, 2, 4):
                 try:
@@ -803,6 +838,8 @@ def main():
                      if (args.vb or args.wpb) else {"visited_log2": 10, "waves_per_block": 4})
         if args.tune and not args.profile and not (args.vb or args.wpb):
             best_ms = None
+            r0 = Fp32Runner(aqr, ix, nq, k, ef_f, dev, **fp_tuning)
+            spin_up(torch, lambda m: r0.step(Qd))
             for vb in (6, 7, 8, 9, 10, 11, 12):
                 for wpb in (1, 2, 4):
                     try:

@@ -40,8 +40,10 @@
 #include <cmath>
 #include <cstring>
 #include <limits>
+#include <map>
 #include <mutex>
 #include <thread>
+#include <utility>
 #include <new>
 #include <vector>
 
@@ -1522,10 +1524,26 @@ hipError_t launch_search_k(dev::SearchArgs& a, int blocks, int wpb, size_t lds, 
         ls.store((int)lds);
     }
     if (blocks <= 0) {
+        // Resident blocks per CU for this kernel, block size and LDS size,
+        // asked of the runtime once and kept: the query is not free, and a
+        // launch that waits on it leaves the device idle.
+        static std::mutex occ_mu;
+        static std::map<std::pair<int, int>, int> occ[2];
+        const std::pair<int, int> key{wpb, (int)lds};
         int per_cu = 0;
-        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, wpb * dev::kWave, lds);
-        if (e != hipSuccess) return e;
-        blocks = std::max(1, per_cu) * std::max(1, ncu);
+        {
+            std::lock_guard<std::mutex> lk(occ_mu);
+            auto it = occ[taps ? 1 : 0].find(key);
+            if (it != occ[taps ? 1 : 0].end()) per_cu = it->second;
+        }
+        if (per_cu == 0) {
+            e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, wpb * dev::kWave, lds);
+            if (e != hipSuccess) return e;
+            per_cu = std::max(1, per_cu);
+            std::lock_guard<std::mutex> lk(occ_mu);
+            occ[taps ? 1 : 0][key] = per_cu;
+        }
+        blocks = per_cu * std::max(1, ncu);
         const int64_t need = (a.nq + wpb - 1) / wpb;
         if ((int64_t)blocks > need) blocks = (int)std::max<int64_t>(1, need);
     }

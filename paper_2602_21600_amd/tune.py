@@ -14,7 +14,7 @@ import time
 from . import aqr
 
 SEARCH_WPB = (1, 2, 4)
-VISITED_LOG2 = (6, 7, 8, 9)
+VISITED_LOG2 = (6, 7, 8, 9, 10)
 RERANK_WPB = (2, 4)
 # resident search waves per CU: 0 = as many as occupancy allows, else the
 # persistent grid is cut to this many waves per CU
@@ -38,6 +38,19 @@ def time_config(ix, Q, k, ef, k_max, ef_max, tuning, reps=3):
     return (time.perf_counter() - t) * 1e3 / reps
 
 
+def spin_up(ix, Q, k, ef, k_max, ef_max, seconds=0.5):
+    """Keep the device busy for about `seconds` with the default launch shape:
+    an idle GPU runs at a low clock, and configurations timed before the clock
+    has ramped up would look slower than they are."""
+    import torch
+    plan = aqr.BatchPlan(ix, Q.shape[0], k_max, ef_max, use_graph=False, tuning={})
+    n = plan.load(Q, k, ef)
+    t0 = time.perf_counter()
+    while time.perf_counter() - t0 < seconds:
+        plan.launch(n)
+        torch.cuda.synchronize()
+
+
 def autotune(ix, Q, k, ef, k_max, ef_max, cache_path=None, reps=3, log=None):
     """Returns (best tuning dict, table of (tuning, ms))."""
     import torch
@@ -51,6 +64,7 @@ def autotune(ix, Q, k, ef, k_max, ef_max, cache_path=None, reps=3, log=None):
         except ValueError:
             pass
     table = []
+    spin_up(ix, Q, k, ef, k_max, ef_max)
     n_cu = torch.cuda.get_device_properties(torch.cuda.current_device()).multi_processor_count
     for wpb, vb, rwpb, wpc in itertools.product(SEARCH_WPB, VISITED_LOG2, RERANK_WPB,
                                                 WAVES_PER_CU):
