@@ -514,7 +514,7 @@ def bench_serving(args, torch, aqr, W, wl, dev, threads):
         del plan
 
     sv = aqr.Server(ix, k_max, ef_max, ring=args.ring, n_rerank=nrr, tau_gap=tg, tau_ratio=tr,
-                    idle_ms=200)
+                    idle_ms=200, visited_log2=args.serve_vb)
     results = {}
     try:
         # warm up the server (kernel launch, caches)
@@ -652,6 +652,8 @@ def main():
     ap.add_argument("--vb", type=int, default=0, help="visited_log2 of the timed search (skips tuning)")
     ap.add_argument("--wpb", type=int, default=0, help="waves per block of the timed search (skips tuning)")
     ap.add_argument("--ring", type=int, default=4096, help="serving: request slots")
+    ap.add_argument("--serve-vb", type=int, default=0,
+                    help="serving: visited_log2 of the server kernel (0: the library default)")
     ap.add_argument("--loads", default="0.1,0.5,0.8,0.9",
                     help="serving: offered loads as fractions of the saturation rate")
     ap.add_argument("--serve-seconds", type=float, default=1.0)

@@ -351,7 +351,9 @@ typedef struct aqr_server_params {
     int32_t n_rerank;     /* N_rerank */
     float tau_gap, tau_ratio, eps;  /* early termination (Table 3 row "0.97+": 0.010, 1.008) */
     int32_t waves_per_block;        /* 0 = 4 */
-    int32_t visited_log2;           /* 0 = 7 */
+    int32_t visited_log2;           /* 0 = 9: the serving kernel runs four waves per SIMD,
+                                       so its LDS has room for the larger cache; values
+                                       below idbits - 15 are raised to it */
     int32_t idle_ms;      /* the kernel exits after this long without unclaimed requests */
     int32_t reserved;
 } aqr_server_params;

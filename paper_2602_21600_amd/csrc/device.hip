@@ -2154,7 +2154,7 @@ extern "C" aqr_status aqr_server_create(const aqr_index* ix, const aqr_server_pa
         if (v.s0 > 256) return fail(AQR_ERR_INVALID_ARG, "aqr_server_create: rows above 256 entries");
         const int efm = std::max(prm->ef_max, prm->k_max);
         const int ef_cap = (efm + 63) / 64 * 64;
-        int vb = prm->visited_log2 > 0 ? prm->visited_log2 : 7;
+        int vb = prm->visited_log2 > 0 ? prm->visited_log2 : 9;  // four waves per SIMD leave room
         const int idb = std::max(v.idbits, vb + 1);
         if (idb - vb > 15) vb = idb - 15;
         const int nc_max = std::min(efm, std::max(prm->k_max, efm / prm->m_ef));
