@@ -598,13 +598,18 @@ def build_index(args, wl, X, threads):
                   upper_off=arr["upper_off"], upper_adj=arr["upper_adj"], ep=meta["ep"])
         g = aqr.aqr_graph_import(gx)
     else:
-        log(f"quantize n={n} d={d} threads={threads}")
+        # --sq8: the paper's plain scalar-quantisation baseline, min/max bounds
+        # (P_max = 0) and a graph at the configured M_0 and ef_0^c, with no
+        # density adaptation
+        p_max = 0.0 if args.sq8 else 0.01
+        log(f"quantize n={n} d={d} threads={threads} p_max={p_max}")
         t = time.perf_counter()
         qz, codes = aqr.aqr_quantize(X, aqr.default_qparams(M0=wl.M0, efc0=wl.efc0,
-                                                            threads=threads))
+                                                            p_max=p_max, threads=threads))
         t_quant = time.perf_counter() - t
         t = time.perf_counter()
         g = aqr.aqr_build(codes, d, qz, threads=threads,
+                          M=wl.M0 if args.sq8 else 0, efc=wl.efc0 if args.sq8 else 0,
                           level_u=W.level_draws(args.workload, n), progress=20)
         t_build = time.perf_counter() - t
         if cache:
@@ -658,6 +663,9 @@ def main():
                     help="serving: offered loads as fractions of the saturation rate")
     ap.add_argument("--serve-seconds", type=float, default=1.0)
     ap.add_argument("--cache", default=None, help="directory to save/load the built index")
+    ap.add_argument("--sq8", action="store_true",
+                    help="plain 8-bit scalar quantisation (P_max = 0) and a plain HNSW graph at "
+                         "M_0 and ef_0^c: the paper's scalar-quantisation baseline")
     ap.add_argument("--copy-mib", type=int, default=256,
                     help="size of the plain copy kernel timed in --profile mode")
     args = ap.parse_args()
@@ -814,7 +822,8 @@ def main():
     reeval = float(cnt[:, 1].sum() / max(1, cnt_big[:, 1].sum()) - 1.0)
     lat_us = cnt[:, 5] / 100.0  # 100 MHz real-time clock
     sha = source_sha()
-    prof_name = (f"search_u8_{args.workload}_ef{ef_a}_vb{tuning['visited_log2']}"
+    prof_name = (f"search_{'sq8' if args.sq8 else 'u8'}_{args.workload}_ef{ef_a}"
+                 f"_vb{tuning['visited_log2']}"
                  f"_wpb{tuning['waves_per_block']}")
     traffic = traffic_from_profile(prof_name, sha)
 
@@ -937,7 +946,8 @@ def main():
         "data": "synthetic",
         "config": {
             "workload": f"{args.workload}: {n:,} x {d} FP32 L2, {wl.n_clusters}-cluster "
-                        f"Gaussian mixture; {nq:,} queries; k={k}",
+                        f"Gaussian mixture; {nq:,} queries; k={k}"
+                        + ("; plain SQ8 baseline (P_max 0, graph at M_0)" if args.sq8 else ""),
             "n": n, "d": d, "nq": nq, "k": k, "ef": ef_a, "M0": wl.M0, "efc0": wl.efc0,
             "M_i": ginfo["M"], "delta": round(info["delta"], 6), "m_ef": 3,
             "rerank": aqr_pick[2][0], "n_rerank": aqr_pick[2][1],
