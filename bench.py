@@ -513,6 +513,41 @@ def bench_serving(args, torch, aqr, W, wl, dev, threads):
         log(f"batch capacity {name}: {batch_qps[name]:,.0f} QPS")
         del plan
 
+    # Stage-1 roofline of the fixed stream run as one batch: the 8-bit search
+    # kernel alone, timed with HIP events, against its algorithmic bytes from
+    # distinct-evaluation counts (a run with a large visited cache)
+    s_run = AqrRunner(aqr, ix, nq, 10, ef98, dev, rerank=cfg)
+    spin_up(torch, lambda m: s_run.search_only(Qd))
+
+    def s_step(marks):
+        if marks:
+            marks[0].record()
+        s_run.search_only(Qd)
+        if marks:
+            marks[1].record()
+
+    _, per_s = timed(torch, s_step, 5, 2, kernel_events=2)
+    s_ms = per_s[0]
+    counts = torch.zeros((nq, 8), dtype=torch.int32, device=dev)
+    AqrRunner(aqr, ix, nq, 10, ef98, dev, visited_log2=14, waves_per_block=1,
+              rerank=cfg).search_only(Qd, taps=dict(cap=0, counts=counts))
+    torch.cuda.synchronize()
+    cnt_big = counts.cpu().numpy().astype(np.int64)
+    s0 = (2 * ginfo["M"] + 15) // 16 * 16
+    s1 = (ginfo["M"] + 15) // 16 * 16
+    nc_total = int(s_run.plan.cand_cnt[:nq].sum().item())
+    code_b, adj_b, io_b = search_bytes(cnt_big, nq, d, info["d_pad"], s0, s1, nc_total)
+    s_alg = code_b + adj_b + io_b
+    s_achieved = s_alg / (s_ms / 1e3) / 1e9
+    log(f"Stage-1 batch of the fixed stream: {s_ms:.3f} ms, {s_achieved:,.0f} GB/s algorithmic")
+    serve_roofline = {
+        "bound": "hbm", "achieved": round(s_achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+        "frac": round(s_achieved / HBM_PEAK_GBS, 4), "traffic": None,
+        "kernel": f"k_search (Stage 1, 8-bit codes) on the fixed stream as one batch of {nq:,}",
+        "kernel_ms": round(s_ms, 4), "alg_bytes_per_launch": s_alg, "code_bytes": code_b,
+        "adjacency_bytes": adj_b, "io_bytes": io_b,
+    }
+
     sv = aqr.Server(ix, k_max, ef_max, ring=args.ring, n_rerank=nrr, tau_gap=tg, tau_ratio=tr,
                     idle_ms=200, visited_log2=args.serve_vb)
     results = {}
@@ -569,7 +604,7 @@ def bench_serving(args, torch, aqr, W, wl, dev, threads):
                        "what": "arrival to completion seen by the host, queueing included"},
         "serving": results,
         "calibration": sweep,
-        "roofline": None,
+        "roofline": serve_roofline,
         "cpu_baseline": None,
         "build_s": {"quantize": t_quant and round(t_quant, 1),
                     "graph": t_build and round(t_build, 1)},
