@@ -700,13 +700,14 @@ __device__ __forceinline__ void search_query(const SearchArgs& a, const int64_t 
     }
 }
 
-// Register budget: seven waves per SIMD for code rows (a few spilled values
-// cost less than the lost wave); the FP32 rows keep the compiler's choice.
-template <bool F32, int CPL>
-constexpr int search_waves_per_eu() { return F32 || CPL > 2 ? 1 : 7; }
+// Register budget: seven waves per SIMD for code rows of up to 16 chunks (a
+// few spilled values cost less than the lost wave); wider rows and the FP32
+// rows keep the compiler's choice.
+template <bool F32, int CPL, int LG>
+constexpr int search_waves_per_eu() { return !F32 && (CPL << LG) <= 16 ? 7 : 1; }
 
 template <bool F32, int CPL, int U, int LG, bool TAPS>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(search_waves_per_eu<F32, CPL>())))
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(search_waves_per_eu<F32, CPL, LG>())))
 void k_search(SearchArgs a) {
     extern __shared__ __align__(16) unsigned char smem[];
     const int lane = lane_id();
