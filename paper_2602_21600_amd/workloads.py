@@ -17,6 +17,11 @@ here.  These generators stand in for their shapes with Gaussian mixtures:
   serving  10,000,000 x 96, L2, 1,024 clusters with log-uniform weights in
            [1, 100], std log-uniform [0.05, 1.0]; M=16, efC=200; Poisson
            arrivals with k in {1,10,100} and ef log-uniform in [16, 512]
+  fmnist   60,000 x 784 (Fashion-MNIST shape), L2, 10 clusters (one per
+           class) with equal weights; each cluster varies along 16 random
+           directions of its own (scale log-uniform [0.3, 1.0]) plus noise of
+           std 0.02, so pixels are correlated as in images; values clipped to
+           >= 0 (zero background); 10,000 queries; M=16, efC=200; k=10, ef 16..256
 
 Cluster centres are N(0, I_d).  Samples are drawn in FP64 from NumPy's PCG64
 generator and stored as FP32.  Seeds: base 1000*c+1, queries 1000*c+2,
@@ -64,6 +69,9 @@ WORKLOADS = {
                         False, False, True, 24, 200, (1, 10, 100), (16, 32, 64, 128, 256, 512)),
     "serving": Workload("serving", 5, 10_000_000, 96, 100_000, 1024, "loguniform", 100.0, 0.05,
                         1.0, False, False, False, 16, 200, (1, 10, 100), (16, 512)),
+    "fmnist": Workload("fmnist", 6, 60_000, 784, 10_000, 10, "equal", 0.0, 0.3, 1.0, False, True,
+                       False, 16, 200, (10,), (16, 24, 32, 48, 64, 96, 128, 192, 256),
+                       extra={"latent": 16, "noise": 0.02}),
 }
 
 
@@ -89,19 +97,33 @@ def _mixture(w: Workload, rng: np.random.Generator):
     else:
         raise ValueError(w.sizes)
     weights = weights / weights.sum()
-    return centres, std, weights
+    basis = None
+    r = w.extra.get("latent", 0)
+    if r:
+        # low-rank clusters: each has its own random basis of r directions
+        basis = rng.standard_normal((c, w.d, r)) / np.sqrt(r)
+    return centres, std, weights, basis
 
 
 def _draw(w: Workload, seed: int, count: int) -> np.ndarray:
     mix_rng = np.random.default_rng(1000 * w.number)
-    centres, std, weights = _mixture(w, mix_rng)
+    centres, std, weights, basis = _mixture(w, mix_rng)
     rng = np.random.default_rng(seed)
     out = np.empty((count, w.d), np.float32)
     for s in range(0, count, _BLOCK):
         e = min(count, s + _BLOCK)
         labels = rng.choice(w.n_clusters, size=_BLOCK, p=weights)[: e - s]
-        z = rng.standard_normal((_BLOCK, w.d))[: e - s]
-        x = centres[labels] + std[labels] * z
+        if basis is None:
+            z = rng.standard_normal((_BLOCK, w.d))[: e - s]
+            x = centres[labels] + std[labels] * z
+        else:
+            # centre + std * (basis @ latent) + small independent noise
+            u = rng.standard_normal((_BLOCK, basis.shape[2]))[: e - s]
+            z = rng.standard_normal((_BLOCK, w.d))[: e - s]
+            x = centres[labels] + w.extra["noise"] * z
+            for c in np.unique(labels):
+                m = labels == c
+                x[m] += std[c] * (u[m] @ basis[c].T)
         if w.clip_nonneg:
             np.maximum(x, 0.0, out=x)
         if w.cosine:

@@ -71,6 +71,20 @@ def test_quantize_small_workload_matches_oracle(orc):
     np.testing.assert_array_equal(codes, orc.encode(X, ref["min"], ref["scale"], stride=128))
 
 
+def test_quantize_image_like_rows_match_oracle(orc):
+    # 784 dimensions with about half the values zero (the Fashion-MNIST
+    # shape): many dimensions have a zero lower bound, some are almost
+    # constant
+    X = W.base("fmnist", 3000)
+    assert 0.3 < float((X == 0).mean()) < 0.7
+    qz, codes, ref = _train_both(orc, X)
+    info = aqr.aqr_quantizer_info(qz)
+    assert info["delta"] == ref["delta"]
+    np.testing.assert_array_equal(info["min"], ref["min"])
+    np.testing.assert_array_equal(info["max"], ref["max"])
+    np.testing.assert_array_equal(codes, orc.encode(X, ref["min"], ref["scale"], stride=784))
+
+
 def test_quantize_encode_only(orc):
     X, Y = W.tiny(800, 16, seed=2, nq=50)
     qz, codes = aqr.aqr_quantize(X, aqr.default_qparams())
