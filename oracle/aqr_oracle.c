@@ -869,7 +869,10 @@ int32_t orc_search_f32(const float* X, int64_t n, int32_t d, int32_t M, const in
  *   Stage 3: n_rr = min(|A|, k) under ET, else min(|A|, max(N_rerank, k));
  *            exact d^e = sum_j (q_j - x_j)^2 in FP64 for A[0..n_rr).
  *   Assembly: R = exact entries, then A[n_rr..] with their d^a while
- *            |R| < k; sorted by (distance, id); top k; padding (-1, +inf).
+ *            |R| < k (assembly 0, "as needed to ensure at least k"), or
+ *            all of A[n_rr..] (assembly 1, the union reading of R_exact
+ *            with the remaining candidates); sorted by (distance, id); top
+ *            k; padding (-1, +inf).
  * a_order (optional, [nq][nc_stride]): if given, replaces the Stage-2 sort
  * with this externally supplied order of the candidates (must be a
  * permutation of the candidate list).
@@ -881,7 +884,7 @@ int32_t orc_rerank(const float* X, const uint8_t* codes, int64_t n, int32_t d, i
                    const float* mn, const float* scale, const float* Q, int64_t nq,
                    const uint32_t* cand_id, const int32_t* cand_cnt, int32_t nc_stride,
                    const int32_t* k, int32_t k_stride, int32_t n_rerank, double tau_gap,
-                   double tau_ratio, double eps, const int32_t* force_et,
+                   double tau_ratio, double eps, const int32_t* force_et, int32_t assembly,
                    const uint32_t* a_order, int32_t* out_id, double* out_dist, uint8_t* out_kind,
                    uint32_t* a_id, double* a_dist, uint8_t* et_out, int32_t* nrr_out) {
     (void)n;
@@ -955,8 +958,9 @@ int32_t orc_rerank(const float* X, const uint8_t* codes, int64_t n, int32_t d, i
                 Rk[nr] = 1;
                 nr++;
             }
-            /* assembly: fill from A only while fewer than k results */
-            for (int32_t t = nrr; t < nc && nr < kq; t++) {
+            /* assembly: fill from A only while fewer than k results, or
+             * (union) take every remaining candidate */
+            for (int32_t t = nrr; t < nc && (assembly == 1 || nr < kq); t++) {
                 R[nr] = A[t];
                 Rk[nr] = 2;
                 nr++;

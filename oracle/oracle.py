@@ -69,7 +69,7 @@ def _load():
                                    _i32, _f32p, _i64, _i32p, _i32p, _i32, _i32p, _f64p, _vp]
     lib.orc_search_f32.restype = _i32
     lib.orc_rerank.argtypes = [_f32p, _u8p, _i64, _i32, _i32, _f32p, _f32p, _f32p, _i64, _u32p,
-                               _i32p, _i32, _i32p, _i32, _i32, _f64, _f64, _f64, _vp, _vp,
+                               _i32p, _i32, _i32p, _i32, _i32, _f64, _f64, _f64, _vp, _i32, _vp,
                                _i32p, _f64p, _vp, _vp, _vp, _vp, _vp]
     lib.orc_rerank.restype = _i32
     lib.orc_knn_f32.argtypes = [_f32p, _i64, _i32, _f32p, _i64, _i32, _i32p, _f64p]
@@ -272,8 +272,15 @@ def search_f32(graph, X, Q, ef_eff, k, k_stride=None, with_visits=False):
 
 
 def rerank(X, codes, mn, scale, Q, cand_id, cand_cnt, k, n_rerank=28, tau_gap=0.010,
-           tau_ratio=1.008, eps=1e-6, force_et=None, a_order=None, k_stride=None, taps=False):
-    """Stages 2-3, early termination and assembly.  Returns a dict."""
+           tau_ratio=1.008, eps=1e-6, force_et=None, a_order=None, k_stride=None, taps=False,
+           assembly=0):
+    """Stages 2-3, early termination and assembly.  Returns a dict.
+
+    assembly 0 fills R from A only while it holds fewer than k entries (the
+    reading "as needed to ensure at least k"); 1 joins every remaining
+    candidate of A to the exact results (the union reading)."""
+    if assembly not in (0, 1):
+        raise ValueError("assembly must be 0 (fill) or 1 (union)")
     X = np.ascontiguousarray(X, np.float32)
     n, d = X.shape
     codes = np.ascontiguousarray(codes, np.uint8)
@@ -300,7 +307,8 @@ def rerank(X, codes, mn, scale, Q, cand_id, cand_cnt, k, n_rerank=28, tau_gap=0.
     _check(_load().orc_rerank(X, codes, n, d, stride, np.ascontiguousarray(mn, np.float32),
                               np.ascontiguousarray(scale, np.float32), Q, nq, cand_id, cand_cnt,
                               nc_stride, k, k_stride, int(n_rerank), float(tau_gap),
-                              float(tau_ratio), float(eps), _ptr(fe), _ptr(ao), oid, od, _ptr(ok),
+                              float(tau_ratio), float(eps), _ptr(fe), int(assembly), _ptr(ao),
+                              oid, od, _ptr(ok),
                               _ptr(aid), _ptr(ad), _ptr(et), _ptr(nrr)), "rerank")
     res = dict(id=oid, dist=od, kind=ok)
     if taps:
@@ -335,7 +343,7 @@ def knn_codes(codes, d, qcodes, k):
 # --------------------------------------------------------------------------
 
 def query(index, Q, k, ef, m_ef=3, n_rerank=28, tau_gap=0.010, tau_ratio=1.008, eps=1e-6,
-          taps=False):
+          taps=False, assembly=0):
     """index: dict with X, codes, d, min, scale, graph.  Returns a dict."""
     Q = np.ascontiguousarray(Q, np.float32)
     nq = Q.shape[0]
@@ -349,7 +357,8 @@ def query(index, Q, k, ef, m_ef=3, n_rerank=28, tau_gap=0.010, tau_ratio=1.008, 
     s1 = search_codes(index["graph"], index["codes"], index["d"], qc, efe, nc,
                       tap_cap=(65536 if taps else 0))
     rr = rerank(index["X"], index["codes"], index["min"], index["scale"], Q, s1["cand_id"],
-                s1["cand_cnt"], k, n_rerank, tau_gap, tau_ratio, eps, taps=taps)
+                s1["cand_cnt"], k, n_rerank, tau_gap, tau_ratio, eps, taps=taps,
+                assembly=assembly)
     rr["stage1"] = s1
     rr["qcodes"] = qc
     return rr

@@ -193,6 +193,51 @@ def test_assembly_padding_ties_and_kinds(orc):
     assert rr["nrr"][0] == 3 and rr["et"][0] == 0
 
 
+def test_assembly_union_hand_case(orc):
+    # d = 1, decoded x~ = code: d^a = 1, 4, 9, 16 for ids 0..3.  The exact
+    # vectors differ (5, 6, 0.5, 0.25): d^e = 25, 36, 0.25, 0.0625.  ET forced
+    # on with k = 2 re-ranks ids 0 and 1 only.  Fill mode stops at k exact
+    # results; the union reading lets the approximate 9 and 16 of ids 2 and 3
+    # win over the exact 25 and 36.
+    codes = np.array([[1], [2], [3], [4]], np.uint8)
+    mn = np.zeros(1, np.float32)
+    sc = np.ones(1, np.float32)
+    X = np.array([[5.0], [6.0], [0.5], [0.25]], np.float32)
+    Q = np.zeros((1, 1), np.float32)
+    cid = np.array([[0, 1, 2, 3]], np.uint32)
+    cnt = np.array([4], np.int32)
+    fill = orc.rerank(X, codes, mn, sc, Q, cid, cnt, 2, force_et=1, taps=True)
+    assert fill["id"][0].tolist() == [0, 1] and fill["dist"][0].tolist() == [25.0, 36.0]
+    assert fill["kind"][0].tolist() == [1, 1] and fill["nrr"][0] == 2
+    union = orc.rerank(X, codes, mn, sc, Q, cid, cnt, 2, force_et=1, taps=True, assembly=1)
+    assert union["id"][0].tolist() == [2, 3] and union["dist"][0].tolist() == [9.0, 16.0]
+    assert union["kind"][0].tolist() == [2, 2]
+    with pytest.raises(ValueError):
+        orc.rerank(X, codes, mn, sc, Q, cid, cnt, 2, assembly=2)
+
+
+def test_assembly_union_properties(orc):
+    # on a random index: the union's k-th distance never exceeds fill's (it
+    # chooses from a superset); every approximate entry carries its Stage-2
+    # distance; with every candidate re-ranked the two readings agree
+    ix = _index(orc, n=300, d=12)
+    qc = orc.encode(ix["Q"], ix["min"], ix["scale"], stride=ix["codes"].shape[1])
+    s1 = orc.search_codes(ix["graph"], ix["codes"], ix["d"], qc, 60, 20)
+    args = (ix["X"], ix["codes"], ix["min"], ix["scale"], ix["Q"], s1["cand_id"], s1["cand_cnt"], 5)
+    fill = orc.rerank(*args, n_rerank=5, force_et=1, taps=True)
+    union = orc.rerank(*args, n_rerank=5, force_et=1, taps=True, assembly=1)
+    assert np.all(union["dist"][:, -1] <= fill["dist"][:, -1])
+    assert np.any(union["kind"] == 2)
+    for q in range(ix["Q"].shape[0]):
+        da = dict(zip(union["a_id"][q].tolist(), union["a_dist"][q].tolist()))
+        for t in np.nonzero(union["kind"][q] == 2)[0]:
+            assert union["dist"][q, t] == da[int(union["id"][q, t])]
+    full_f = orc.rerank(*args, n_rerank=60, force_et=0)
+    full_u = orc.rerank(*args, n_rerank=60, force_et=0, assembly=1)
+    np.testing.assert_array_equal(full_f["id"], full_u["id"])
+    np.testing.assert_array_equal(full_f["dist"], full_u["dist"])
+
+
 def test_rerank_from_supplied_order(orc):
     # a supplied A order replaces the Stage-2 sort: with ET forced on and k=1
     # only the first supplied candidate is re-ranked
