@@ -250,7 +250,11 @@ typedef struct aqr_rparams {
     float eps;            /* epsilon of gap and ratio (1e-6) */
     int32_t force_et;     /* -1 automatic, 0 never, 1 always */
     int32_t waves_per_block; /* 0 = library default */
-    int32_t reserved;
+    int32_t assembly;     /* Alg. 2 assembly, two readings: 0 fills R with the next
+                             candidates of A (with their d^a) only while it holds fewer
+                             than k results; 1 joins every candidate of A not re-ranked
+                             to the exact results and keeps the k smallest.  Other
+                             values: AQR_ERR_INVALID_ARG */
 } aqr_rparams;
 
 typedef struct aqr_rtaps {

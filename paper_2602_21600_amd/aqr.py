@@ -60,7 +60,7 @@ class Taps(C.Structure):
 class RParams(C.Structure):
     _fields_ = [("n_rerank", C.c_int32), ("out_stride", C.c_int32), ("tau_gap", C.c_float),
                 ("tau_ratio", C.c_float), ("eps", C.c_float), ("force_et", C.c_int32),
-                ("waves_per_block", C.c_int32), ("reserved", C.c_int32)]
+                ("waves_per_block", C.c_int32), ("assembly", C.c_int32)]
 
 
 class RTaps(C.Structure):
@@ -380,10 +380,10 @@ def aqr_encode_queries(ix, Q, qcodes, stream=None):
 
 def aqr_rerank(ix, Q, cand_id, cand_cnt, k, out_id, out_dist, out_kind=None, n_rerank=28,
                tau_gap=0.010, tau_ratio=1.008, eps=1e-6, force_et=-1, out_stride=None,
-               waves_per_block=0, taps=None, stream=None):
+               waves_per_block=0, taps=None, stream=None, assembly=0):
     out_stride = out_id.shape[1] if out_stride is None else out_stride
     rp = RParams(n_rerank=n_rerank, out_stride=out_stride, tau_gap=tau_gap, tau_ratio=tau_ratio,
-                 eps=eps, force_et=force_et, waves_per_block=waves_per_block, reserved=0)
+                 eps=eps, force_et=force_et, waves_per_block=waves_per_block, assembly=assembly)
     rt = None
     if taps is not None:
         rt = RTaps(a_id=_dev_ptr(taps.get("a_id")), a_dist=_dev_ptr(taps.get("a_dist")),
@@ -407,7 +407,7 @@ class QueryPlan:
 
     def __init__(self, ix, nq, k_max, ef_max, m_ef=3, n_rerank=28, tau_gap=0.010,
                  tau_ratio=1.008, eps=1e-6, nc_max=None, visited_log2=0, waves_per_block=0,
-                 blocks=0):
+                 blocks=0, assembly=0):
         import torch
         self.ix = ix
         self.nq = nq
@@ -415,7 +415,8 @@ class QueryPlan:
         self.ef_max = max(ef_max, k_max)
         self.m_ef = m_ef
         self.nc_max = nc_max or min(self.ef_max, max(k_max, self.ef_max // m_ef))
-        self.rr = dict(n_rerank=n_rerank, tau_gap=tau_gap, tau_ratio=tau_ratio, eps=eps)
+        self.rr = dict(n_rerank=n_rerank, tau_gap=tau_gap, tau_ratio=tau_ratio, eps=eps,
+                       assembly=assembly)
         self.sp = dict(visited_log2=visited_log2, waves_per_block=waves_per_block, blocks=blocks)
         dev = ix.arena.device
         self.cand_id = torch.empty((nq, self.nc_max), dtype=torch.int32, device=dev)
@@ -469,7 +470,7 @@ class BatchPlan:
 
     def __init__(self, ix, nq_max, k_max, ef_max, m_ef=3, n_rerank=28, tau_gap=0.010,
                  tau_ratio=1.008, eps=1e-6, longest_first=True, use_graph=True, counts=False,
-                 tuning=None):
+                 tuning=None, assembly=0):
         import torch
         tuning = dict(tuning or {})
         dev = ix.arena.device
@@ -498,7 +499,7 @@ class BatchPlan:
                   order=None)
         rp = dict(n_rerank=n_rerank, out_stride=k_max, tau_gap=tau_gap, tau_ratio=tau_ratio,
                   eps=eps, force_et=-1, waves_per_block=tuning.get("rerank_waves_per_block", 0),
-                  reserved=0)
+                  assembly=assembly)
         self.plan = aqr_plan_create(ix, sp, rp, self.bufs, use_graph)
 
     def load(self, Q, k, ef):

@@ -844,6 +844,7 @@ struct RerankArgs {
     int32_t out_stride;
     float tau_gap, tau_ratio, eps;
     int32_t force_et;
+    int32_t assembly;    // 0: fill from A while fewer than k; 1: union with the rest of A
     int32_t lg8, nch8;   // geometry of code rows
     int32_t lgf, nchf;   // geometry of FP32 rows
     size_t wave_lds;
@@ -980,8 +981,9 @@ __device__ __forceinline__ void rerank_query(const RerankArgs& a, const int lane
             }
         }
     }
-    // assembly: fill from A while fewer than k
-    const int fill = max(0, min(nc - nrr, k - nrr));
+    // assembly: fill from A while fewer than k, or (union) join every
+    // remaining candidate of A with its d^a; R holds at most nc entries
+    const int fill = a.assembly == 1 ? nc - nrr : max(0, min(nc - nrr, k - nrr));
     for (int t = lane; t < fill; t += kWave) {
         Rk[nrr + t] = As[nrr + t];
         kind[nrr + t] = 2;
@@ -1791,6 +1793,8 @@ extern "C" aqr_status aqr_rerank(const aqr_index* ix, const float* Q, int64_t nq
         if (rp->out_stride < 1 || rp->out_stride > 1024)
             return fail(AQR_ERR_INVALID_ARG, "aqr_rerank: out_stride must be in [1, 1024]");
         if (rp->n_rerank < 0) return fail(AQR_ERR_INVALID_ARG, "aqr_rerank: n_rerank < 0");
+        if (rp->assembly != 0 && rp->assembly != 1)
+            return fail(AQR_ERR_INVALID_ARG, "aqr_rerank: assembly must be 0 (fill) or 1 (union)");
         if (!(rp->eps >= 0.0f) || std::isnan(rp->tau_gap) || std::isnan(rp->tau_ratio))
             return fail(AQR_ERR_INVALID_ARG, "aqr_rerank: bad thresholds");
         if (taps && ((taps->a_id == nullptr) != (taps->a_dist == nullptr)))
@@ -1816,6 +1820,7 @@ extern "C" aqr_status aqr_rerank(const aqr_index* ix, const float* Q, int64_t nq
         a.tau_ratio = rp->tau_ratio;
         a.eps = rp->eps;
         a.force_et = rp->force_et < 0 ? -1 : (rp->force_et ? 1 : 0);
+        a.assembly = rp->assembly;
         a.nch8 = v.dp / 16;
         a.lg8 = pow2_lg_for(a.nch8);
         a.nchf = v.xs / 4;
@@ -2182,6 +2187,7 @@ extern "C" aqr_status aqr_server_create(const aqr_index* ix, const aqr_server_pa
         r.tau_ratio = prm->tau_ratio;
         r.eps = prm->eps;
         r.force_et = -1;
+        r.assembly = 0;  // the server fills from A (the default reading)
         r.nch8 = nch8;
         r.lg8 = pow2_lg_for(nch8);
         r.nchf = nchf;
