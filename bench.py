@@ -137,6 +137,9 @@ RERANK_CONFIGS = [
 ]
 
 
+ASSEMBLY = 0  # re-rank assembly: 0 fill (default reading), 1 union (--assembly union)
+
+
 class AqrRunner:
     def __init__(self, aqr, ix, nq, k, ef, device, visited_log2=0, waves_per_block=0,
                  rerank=RERANK_CONFIGS[0]):
@@ -147,7 +150,7 @@ class AqrRunner:
         _, nrr, tg, tr = rerank
         self.plan = aqr.QueryPlan(ix, nq, k, max(ef, k), visited_log2=visited_log2,
                                   waves_per_block=waves_per_block, n_rerank=nrr, tau_gap=tg,
-                                  tau_ratio=tr)
+                                  tau_ratio=tr, assembly=ASSEMBLY)
         self.k = torch.full((nq,), k, dtype=torch.int32, device=device)
         self.ef = torch.full((nq,), ef, dtype=torch.int32, device=device)
 
@@ -698,12 +701,17 @@ def main():
                     help="serving: offered loads as fractions of the saturation rate")
     ap.add_argument("--serve-seconds", type=float, default=1.0)
     ap.add_argument("--cache", default=None, help="directory to save/load the built index")
+    ap.add_argument("--assembly", choices=("fill", "union"), default="fill",
+                    help="re-rank assembly: fill from A while fewer than k (default), or the "
+                         "union of the exact results with the rest of A")
     ap.add_argument("--sq8", action="store_true",
                     help="plain 8-bit scalar quantisation (P_max = 0) and a plain HNSW graph at "
                          "M_0 and ef_0^c: the paper's scalar-quantisation baseline")
     ap.add_argument("--copy-mib", type=int, default=256,
                     help="size of the plain copy kernel timed in --profile mode")
     args = ap.parse_args()
+    global ASSEMBLY
+    ASSEMBLY = 1 if args.assembly == "union" else 0
 
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1",
@@ -940,7 +948,8 @@ def main():
         log(f"CPU oracle on {S} queries with {orc.get_threads()} threads")
         t = time.perf_counter()
         _, nrr_, tg_, tr_ = aqr_pick[2]
-        ref = orc.query(index, Q[:S], k, ef_a, n_rerank=nrr_, tau_gap=tg_, tau_ratio=tr_)
+        ref = orc.query(index, Q[:S], k, ef_a, n_rerank=nrr_, tau_gap=tg_, tau_ratio=tr_,
+                        assembly=ASSEMBLY)
         dt = time.perf_counter() - t
         cpu = {"value": round(S / dt, 1), "unit": "queries/s", "cores": orc.get_threads(),
                "kind": "oracle",
@@ -950,7 +959,8 @@ def main():
         S1 = max(1, S // 10)
         orc.set_threads(1)
         t = time.perf_counter()
-        orc.query(index, Q[:S1], k, ef_a, n_rerank=nrr_, tau_gap=tg_, tau_ratio=tr_)
+        orc.query(index, Q[:S1], k, ef_a, n_rerank=nrr_, tau_gap=tg_, tau_ratio=tr_,
+                  assembly=ASSEMBLY)
         cpu["one_thread_value"] = round(S1 / (time.perf_counter() - t), 1)
         orc.set_threads(threads)
         s1 = ref["stage1"]
@@ -986,6 +996,7 @@ def main():
             "n": n, "d": d, "nq": nq, "k": k, "ef": ef_a, "M0": wl.M0, "efc0": wl.efc0,
             "M_i": ginfo["M"], "delta": round(info["delta"], 6), "m_ef": 3,
             "rerank": aqr_pick[2][0], "n_rerank": aqr_pick[2][1],
+            "assembly": "union" if ASSEMBLY else "fill",
             "tau_gap": finite_or_none(aqr_pick[2][2]),
             "tau_ratio": finite_or_none(aqr_pick[2][3]),
             "recall@10": finite_or_none(round(aqr_pick[1], 5)), "tuning": tuning,
