@@ -688,6 +688,127 @@ int32_t orc_build(const uint8_t* codes, int64_t n, int32_t d, int32_t stride, in
     return 0;
 }
 
+/*
+ * Batched construction over the 8-bit codes: the same insertion step as
+ * orc_build, in an order that lets a GPU search many insertions at once.
+ *   Seed: every point below seed_n and every point with level >= 1 is
+ *         inserted as in orc_build, in increasing id order.
+ *   Batches: the other points (level 0) follow in increasing id order, in
+ *         consecutive chunks of min(batch, max(1, floor(inserted / 8)))
+ *         points, where inserted counts the points already in the graph.
+ *         Every point of a chunk searches the graph as it stood before the
+ *         chunk (greedy descent on the upper layers, then layer 0 with
+ *         width efc), selects M neighbours with the heuristic and takes them
+ *         as its layer-0 list; then each adds the reverse links, in id order.
+ * With seed_n = n this is orc_build; with batch = 1 it is orc_build over the
+ * points in the order (seed points, then the rest).
+ */
+int32_t orc_build_batched(const uint8_t* codes, int64_t n, int32_t d, int32_t stride, int32_t M,
+                          int32_t efc, const int32_t* level, int64_t seed_n, int32_t batch,
+                          uint32_t* adj0, const int64_t* upper_off, uint32_t* upper_adj,
+                          int32_t* out2) {
+    if (!codes || !level || !adj0 || !upper_off || !out2 || n < 1 || M < 2 || efc < 1 ||
+        seed_n < 1 || batch < 1)
+        return -1;
+    graph g;
+    g.n = n;
+    g.M = M;
+    g.cap0 = 2 * M;
+    g.cap1 = M;
+    g.level = (int32_t*)level;
+    g.adj0 = adj0;
+    g.upper_off = (int64_t*)upper_off;
+    g.upper_adj = upper_adj;
+    for (int64_t i = 0; i < n * g.cap0; i++) adj0[i] = ORC_NONE;
+    for (int64_t i = 0; i < upper_off[n] * g.cap1; i++) upper_adj[i] = ORC_NONE;
+    space sp = {SP_CODES, d, stride, codes, NULL};
+    visited v;
+    olist W;
+    okey* eps = (okey*)malloc((size_t)(efc + 2) * sizeof(okey));
+    uint32_t* sel = (uint32_t*)malloc((size_t)(batch > 0 ? batch : 1) * M * sizeof(uint32_t));
+    int32_t* nsel = (int32_t*)malloc((size_t)batch * sizeof(int32_t));
+    uint32_t* chunk = (uint32_t*)malloc((size_t)batch * sizeof(uint32_t));
+    if (vis_init(&v, n) || ol_init(&W, efc + 2) || !eps || !sel || !nsel || !chunk) return -1;
+    g.ep = 0;
+    g.L = level[0];
+    int64_t inserted = 1;
+    /* seed: ids below seed_n and every upper-level point, in id order */
+    for (int64_t i = 1; i < n; i++) {
+        if (i >= seed_n && level[i] == 0) continue;
+        const void* q = sp_point(&sp, (uint32_t)i);
+        int32_t li = level[i];
+        okey cur = {sp_dist_q(&sp, q, g.ep), g.ep};
+        for (int32_t lc = g.L; lc > li; lc--) {
+            if (search_layer(&g, &sp, q, &cur, 1, 1, lc, &v, &W, NULL)) return -1;
+            vis_reset(&v);
+            cur = W.a[0];
+        }
+        int32_t n_eps = 1;
+        eps[0] = cur;
+        for (int32_t lc = li < g.L ? li : g.L; lc >= 0; lc--) {
+            if (search_layer(&g, &sp, q, eps, n_eps, efc, lc, &v, &W, NULL)) return -1;
+            vis_reset(&v);
+            int32_t r = select_heuristic(&sp, W.a, W.n, M, sel);
+            int32_t cap;
+            uint32_t* row = nbr_row(&g, (uint32_t)i, lc, &cap);
+            for (int32_t t = 0; t < r; t++) row[t] = sel[t];
+            for (int32_t t = 0; t < r; t++)
+                if (add_link(&g, &sp, sel[t], (uint32_t)i, lc)) return -1;
+            n_eps = (int32_t)W.n;
+            for (int32_t t = 0; t < n_eps; t++) eps[t] = W.a[t];
+        }
+        if (li > g.L) {
+            g.L = li;
+            g.ep = (uint32_t)i;
+        }
+        inserted++;
+    }
+    /* batches of the remaining level-0 points */
+    int64_t next = seed_n;
+    for (;;) {
+        int64_t want = inserted / 8;
+        if (want < 1) want = 1;
+        if (want > batch) want = batch;
+        int32_t nb = 0;
+        while (next < n && nb < want) {
+            if (level[next] == 0) chunk[nb++] = (uint32_t)next;
+            next++;
+        }
+        if (nb == 0) break;
+        /* search and select against the graph as it stood before the chunk */
+        for (int32_t b = 0; b < nb; b++) {
+            const void* q = sp_point(&sp, chunk[b]);
+            okey cur = {sp_dist_q(&sp, q, g.ep), g.ep};
+            for (int32_t lc = g.L; lc > 0; lc--) {
+                if (search_layer(&g, &sp, q, &cur, 1, 1, lc, &v, &W, NULL)) return -1;
+                vis_reset(&v);
+                cur = W.a[0];
+            }
+            if (search_layer(&g, &sp, q, &cur, 1, efc, 0, &v, &W, NULL)) return -1;
+            vis_reset(&v);
+            nsel[b] = select_heuristic(&sp, W.a, W.n, M, sel + (size_t)b * M);
+        }
+        for (int32_t b = 0; b < nb; b++) {
+            int32_t cap;
+            uint32_t* row = nbr_row(&g, chunk[b], 0, &cap);
+            for (int32_t t = 0; t < nsel[b]; t++) row[t] = sel[(size_t)b * M + t];
+        }
+        for (int32_t b = 0; b < nb; b++)
+            for (int32_t t = 0; t < nsel[b]; t++)
+                if (add_link(&g, &sp, sel[(size_t)b * M + t], chunk[b], 0)) return -1;
+        inserted += nb;
+    }
+    out2[0] = (int32_t)g.ep;
+    out2[1] = g.L;
+    free(eps);
+    free(sel);
+    free(nsel);
+    free(chunk);
+    ol_free(&W);
+    vis_free(&v);
+    return 0;
+}
+
 /* ------------------------------------------------------------------------ */
 /* Section 3.2, Alg. 2: search                                               */
 /* ------------------------------------------------------------------------ */

@@ -60,6 +60,9 @@ def _load():
     lib.orc_build.argtypes = [_u8p, _i64, _i32, _i32, _i32, _i32, _i32p, _u32p, _i64p, _u32p,
                               _i32p]
     lib.orc_build.restype = _i32
+    lib.orc_build_batched.argtypes = [_u8p, _i64, _i32, _i32, _i32, _i32, _i32p, _i64, _i32,
+                                      _u32p, _i64p, _u32p, _i32p]
+    lib.orc_build_batched.restype = _i32
     lib.orc_param_map.argtypes = [_i32, _i32, _i32, _i32p]
     lib.orc_search_codes.argtypes = [_u8p, _i64, _i32, _i32, _i32, _i32p, _u32p, _i64p, _u32p,
                                      _u32, _i32, _u8p, _i64, _i32p, _i32p, _i32, _u32p, _u32p,
@@ -202,6 +205,22 @@ def build(codes, d, M, efc, level):
     out2 = np.zeros(2, np.int32)
     _check(_load().orc_build(codes, n, d, stride, int(M), int(efc), level, adj0, off, upper,
                              out2), "build")
+    return dict(n=n, M=int(M), level=level, adj0=adj0, upper_off=off, upper_adj=upper,
+                ep=int(out2[0]), L=int(out2[1]))
+
+
+def build_batched(codes, d, M, efc, level, seed_n, batch):
+    """Batched HNSW build (seed points in order, then chunks of level-0
+    points that each search the graph as it stood before the chunk)."""
+    codes = np.ascontiguousarray(codes, np.uint8)
+    n, stride = codes.shape
+    level = np.ascontiguousarray(level, np.int32)
+    off = upper_offsets(level)
+    adj0 = np.zeros((n, 2 * M), np.uint32)
+    upper = np.zeros((max(int(off[-1]), 1), M), np.uint32)
+    out2 = np.zeros(2, np.int32)
+    _check(_load().orc_build_batched(codes, n, d, stride, int(M), int(efc), level, int(seed_n),
+                                     int(batch), adj0, off, upper, out2), "build_batched")
     return dict(n=n, M=int(M), level=level, adj0=adj0, upper_off=off, upper_adj=upper,
                 ep=int(out2[0]), L=int(out2[1]))
 

@@ -139,3 +139,59 @@ def test_build_is_deterministic(orc):
     for k in ("adj0", "upper_adj", "upper_off"):
         np.testing.assert_array_equal(g1[k], g2[k])
     assert (g1["ep"], g1["L"]) == (g2["ep"], g2["L"])
+
+
+def _codes(orc, n, d, seed):
+    X, Q = W.tiny(n, d, seed=seed, clusters=6, nq=40)
+    tr = orc.train(X, p_max=0.01)
+    stride = (d + 15) // 16 * 16
+    return X, Q, tr, orc.encode(X, tr["min"], tr["scale"], stride=stride)
+
+
+def _same_graph(a, b):
+    for key in ("adj0", "upper_adj", "upper_off", "level"):
+        np.testing.assert_array_equal(a[key], b[key])
+    assert (a["ep"], a["L"]) == (b["ep"], b["L"])
+
+
+def test_batched_build_with_everything_seeded_is_sequential(orc):
+    X, _, _, codes = _codes(orc, 1200, 16, 3)
+    lv = orc.levels(W.level_draws("small", 1200), 10)
+    _same_graph(orc.build_batched(codes, 16, 10, 40, lv, seed_n=1200, batch=64),
+                orc.build(codes, 16, 10, 40, lv))
+
+
+def test_batched_build_with_unit_chunks_is_sequential(orc):
+    # every upper-level point lies below seed_n, so the seed is the prefix
+    # [0, seed_n) and chunks of one point continue in id order: the batched
+    # build must then be the sequential build
+    n, M = 1500, 10
+    X, _, _, codes = _codes(orc, n, 16, 4)
+    lv = orc.levels(W.level_draws("small", n), M)
+    seed_n = 300
+    lv[seed_n:] = 0
+    lv[0] = max(lv[0], 1)
+    _same_graph(orc.build_batched(codes, 16, M, 40, lv, seed_n=seed_n, batch=1),
+                orc.build(codes, 16, M, 40, lv))
+
+
+def test_batched_build_chunks_differ_but_keep_invariants_and_recall(orc):
+    # chunks of up to 1/8 of the graph: points of a chunk do not see each
+    # other, so the graph differs from the sequential one, but it keeps the
+    # invariants and finds the exact neighbours about as often
+    n, M, efc, d = 3000, 12, 60, 24
+    X, Q, tr, codes = _codes(orc, n, d, 5)
+    lv = orc.levels(W.level_draws("small", n), M)
+    gb = orc.build_batched(codes, d, M, efc, lv, seed_n=200, batch=256)
+    gs = orc.build(codes, d, M, efc, lv)
+    check_invariants(gb, M)
+    assert not np.array_equal(gb["adj0"], gs["adj0"])
+    qc = orc.encode(Q, tr["min"], tr["scale"], stride=codes.shape[1])
+    truth, _ = orc.knn_codes(codes, d, qc, 10)
+    rec = []
+    for g in (gb, gs):
+        s1 = orc.search_codes(g, codes, d, qc, 40, 40)
+        hits = [len(set(s1["cand_id"][q, :10].tolist()) & set(truth[q].tolist()))
+                for q in range(Q.shape[0])]
+        rec.append(np.mean(hits) / 10)
+    assert rec[0] >= rec[1] - 0.02, rec
