@@ -165,6 +165,28 @@ aqr_status aqr_graph_import(int64_t n, int32_t M, const int32_t* level, const ui
                             aqr_graph** g);
 void aqr_graph_free(aqr_graph* g);
 
+/*
+ * Batched construction with the layer-0 searches on the current device
+ * (the insertion step of Alg. 1 and HNSW, reordered so that many insertions
+ * search at once).  First the seed is inserted on the host as aqr_build
+ * does: every point below seed_n and every point with level >= 1, in id
+ * order (threads == 1: sequential and deterministic).  The other points
+ * (level 0) follow in id order in chunks of min(batch, max(1, floor(m / 8)))
+ * points, m = points already in the graph.  Every point of a chunk searches
+ * the graph as it stood before the chunk on the device (greedy descent, then
+ * layer 0 with width efc), selects M neighbours with the heuristic and takes
+ * them as its layer-0 list; the reverse links are added in id order (on the
+ * host, different target nodes in parallel).  Given the seed, the result
+ * does not depend on threads.  codes: host, n x d_pad; X: host FP32 n x d,
+ * the vectors the codes encode (the device search encodes them again).  The
+ * call allocates and frees device memory for the index and the chunks
+ * (hipMalloc) and waits for its work; seed_n >= n is aqr_build.  Levels and
+ * p as in aqr_build; efc <= 1024.
+ */
+aqr_status aqr_build_batched(const uint8_t* codes, const float* X, int64_t n, int32_t d,
+                             const aqr_quantizer* qz, const aqr_bparams* p, const double* level_u,
+                             int64_t seed_n, int32_t batch, aqr_graph** out);
+
 /* ------------------------------------------------------------------------ */
 /* device index                                                              */
 /* ------------------------------------------------------------------------ */

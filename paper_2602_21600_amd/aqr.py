@@ -100,6 +100,8 @@ _SIGS = [
     ("aqr_quantizer_create", _i32, [C.POINTER(QInfo), _vp, _vp, _vp, C.POINTER(_vp)]),
     ("aqr_quantizer_free", None, [_vp]),
     ("aqr_build", _i32, [_vp, _i64, _i32, _vp, C.POINTER(BParams), _vp, C.POINTER(_vp)]),
+    ("aqr_build_batched", _i32, [_vp, _vp, _i64, _i32, _vp, C.POINTER(BParams), _vp, _i64, _i32,
+                                 C.POINTER(_vp)]),
     ("aqr_graph_info", _i32, [_vp, C.POINTER(GInfo)]),
     ("aqr_graph_export", _i32, [_vp, _vp, _vp, _vp, _vp]),
     ("aqr_graph_import", _i32, [_i64, _i32, _vp, _vp, _vp, _vp, _u32, C.POINTER(_vp)]),
@@ -282,6 +284,24 @@ def aqr_build(codes, d, qz, M=0, efc=0, threads=0, seed=0, level_u=None, progres
     lu = None if level_u is None else np.ascontiguousarray(level_u, np.float64)
     h = C.c_void_p()
     _check(lib().aqr_build(_np_ptr(codes), n, d, qz.ptr, C.byref(bp), _np_ptr(lu), C.byref(h)))
+    return Graph(h.value)
+
+
+def aqr_build_batched(codes, X, d, qz, M=0, efc=0, threads=0, seed=0, level_u=None, progress=0,
+                      seed_n=None, batch=16384):
+    """Batched build with the chunk searches on the device (aqr_build_batched).
+    seed_n defaults to max(20000, n / 64)."""
+    codes = np.ascontiguousarray(codes, np.uint8)
+    X = np.ascontiguousarray(X, np.float32)
+    n = codes.shape[0]
+    if X.shape != (n, d):
+        raise ValueError("X must be n x d")
+    seed_n = max(20000, n // 64) if seed_n is None else int(seed_n)
+    bp = BParams(M=M, efc=efc, threads=threads, progress=progress, seed=seed)
+    lu = None if level_u is None else np.ascontiguousarray(level_u, np.float64)
+    h = C.c_void_p()
+    _check(lib().aqr_build_batched(_np_ptr(codes), _np_ptr(X), n, d, qz.ptr, C.byref(bp),
+                                   _np_ptr(lu), seed_n, int(batch), C.byref(h)))
     return Graph(h.value)
 
 

@@ -247,78 +247,146 @@ struct Builder {
 
 using namespace aqr;
 
+namespace aqr {
+
+// Levels for every point, then insertion of the seed: every point below
+// seed_n and every point with level >= 1, in id order (seed_n >= n: all
+// points, the plain build).  Level-0 points at or above seed_n are left
+// unlinked for link_chunk.
+aqr_status build_seeded(const uint8_t* codes, int64_t n, int32_t d, const aqr_quantizer* qz,
+                        const aqr_bparams* p, const double* level_u, int64_t seed_n,
+                        const char* who, aqr_graph** out) {
+    const std::string w(who);
+    if (!codes || !qz || !p || !out) return fail(AQR_ERR_INVALID_ARG, w + ": null pointer");
+    if (n < 1 || n > (int64_t)0xFFFFFFFEu) return fail(AQR_ERR_INVALID_ARG, w + ": n out of range");
+    if (d != qz->info.d) return fail(AQR_ERR_INVALID_ARG, w + ": d does not match the quantiser");
+    const int32_t M = p->M > 0 ? p->M : qz->info.M;
+    const int32_t efc = p->efc > 0 ? p->efc : qz->info.efc;
+    if (M < 2 || M > 512 || efc < 1)
+        return fail(AQR_ERR_INVALID_ARG, w + ": M must be in [2, 512] and efc >= 1");
+    aqr_graph* g = new aqr_graph();
+    g->n = n;
+    g->M = M;
+    g->efc = efc;
+    g->level.resize(n);
+    const double mL = 1.0 / std::log((double)M);
+    uint64_t state = p->seed;
+    for (int64_t i = 0; i < n; ++i) {
+        double u;
+        if (level_u) {
+            u = level_u[i];
+            if (!(u > 0.0 && u <= 1.0)) {
+                delete g;
+                return fail(AQR_ERR_INVALID_ARG, w + ": level draws must lie in (0, 1]");
+            }
+        } else {
+            u = (double)((splitmix64(state) >> 11) + 1) * 0x1.0p-53;
+        }
+        g->level[i] = (int32_t)std::floor(-std::log(u) * mL);
+    }
+    g->upper_off.assign(n + 1, 0);
+    for (int64_t i = 0; i < n; ++i) g->upper_off[i + 1] = g->upper_off[i] + g->level[i];
+    g->adj0.assign((size_t)n * 2 * M, AQR_NONE);
+    g->upper_adj.assign((size_t)std::max<int64_t>(g->upper_off[n], 1) * M, AQR_NONE);
+    g->ep = 0;
+    g->L = g->level[0];
+    std::vector<uint32_t> S;  // seed points after point 0, in id order
+    for (int64_t i = 1; i < n; ++i)
+        if (i < seed_n || g->level[i] > 0) S.push_back((uint32_t)i);
+    const int T = host_threads(p->threads);
+    Builder B(*g, codes, qz->info.d_pad, T > 1);
+    const int64_t ns = (int64_t)S.size();
+    const int64_t step = p->progress > 0 ? std::max<int64_t>(1, ns / p->progress) : 0;
+    const auto t0 = std::chrono::steady_clock::now();
+    auto report = [&](int64_t i) {
+        if (step && i % step == 0) {
+            const double sec =
+                std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+            std::fprintf(stderr, "[%s] %lld / %lld points inserted, %.1f s\n", who,
+                         (long long)(i + 1), (long long)(ns + 1), sec);
+            std::fflush(stderr);
+        }
+    };
+    if (T <= 1 || ns < 1) {
+        Visited vis(n);
+        for (int64_t i = 0; i < ns; ++i) {
+            B.insert(S[i], vis);
+            report(i);
+        }
+    } else {
+        std::atomic<int64_t> next{0};
+        parallel_for_threads(T, [&](int) {
+            Visited vis(n);
+            for (;;) {
+                int64_t i = next.fetch_add(1);
+                if (i >= ns) break;
+                B.insert(S[i], vis);
+                report(i);
+            }
+        });
+    }
+    *out = g;
+    return AQR_OK;
+}
+
+// One chunk of the batched build: ids (ascending) with their layer-0
+// candidates (keys (D << 32) | id, ascending, cnt[b] of them at row b of a
+// [nb][stride] array), each from a search of the graph as it stood before
+// the chunk.  Selects M neighbours per point with the heuristic, sets the
+// points' layer-0 lists, then adds the reverse links: the links into one
+// node are applied in id order (as a sequential pass in id order would),
+// and different nodes in parallel.  dirty receives every id whose layer-0
+// list changed.
+void link_chunk(aqr_graph* g, const uint8_t* codes, int32_t dp, const uint32_t* ids, int32_t nb,
+                const uint64_t* cand, int32_t stride, const int32_t* cnt, int threads,
+                std::vector<uint32_t>& dirty) {
+    const int32_t M = g->M;
+    Builder B(*g, codes, dp, false);
+    std::vector<uint32_t> sel((size_t)nb * M);
+    std::vector<int32_t> ns(nb, 0);
+    const int T = std::max(1, std::min(threads, (int)std::max(1, nb / 64)));
+    std::atomic<int32_t> nx{0};
+    parallel_for_threads(T, [&](int) {
+        for (;;) {
+            const int32_t b = nx.fetch_add(1);
+            if (b >= nb) break;
+            ns[b] = B.heuristic(cand + (size_t)b * stride, (size_t)std::max(0, cnt[b]), M,
+                                &sel[(size_t)b * M]);
+            uint32_t* row = g->adj0.data() + (int64_t)ids[b] * 2 * M;
+            for (int32_t t = 0; t < 2 * M; ++t) row[t] = t < ns[b] ? sel[(size_t)b * M + t] : kNone;
+        }
+    });
+    std::vector<uint64_t> pr;  // (target << 32) | b, b in id order
+    for (int32_t b = 0; b < nb; ++b)
+        for (int32_t t = 0; t < ns[b]; ++t) pr.push_back(((uint64_t)sel[(size_t)b * M + t] << 32) | (uint32_t)b);
+    std::sort(pr.begin(), pr.end());
+    std::vector<size_t> grp;
+    for (size_t i = 0; i < pr.size(); ++i)
+        if (i == 0 || (pr[i] >> 32) != (pr[i - 1] >> 32)) grp.push_back(i);
+    grp.push_back(pr.size());
+    const int64_t ng = (int64_t)grp.size() - 1;
+    std::atomic<int64_t> gx{0};
+    const int T2 = std::max(1, std::min(threads, (int)std::max<int64_t>(1, ng / 64)));
+    parallel_for_threads(T2, [&](int) {
+        for (;;) {
+            const int64_t k = gx.fetch_add(1);
+            if (k >= ng) break;
+            for (size_t i = grp[k]; i < grp[k + 1]; ++i)
+                B.link_locked((uint32_t)(pr[i] >> 32), ids[(uint32_t)pr[i]], 0);
+        }
+    });
+    dirty.assign(ids, ids + nb);
+    for (int64_t k = 0; k < ng; ++k) dirty.push_back((uint32_t)(pr[grp[k]] >> 32));
+}
+
+}  // namespace aqr
+
 extern "C" aqr_status aqr_build(const uint8_t* codes, int64_t n, int32_t d,
                                 const aqr_quantizer* qz, const aqr_bparams* p,
                                 const double* level_u, aqr_graph** out) {
     try {
         clear_error();
-        if (!codes || !qz || !p || !out) return fail(AQR_ERR_INVALID_ARG, "aqr_build: null pointer");
-        if (n < 1 || n > (int64_t)0xFFFFFFFEu)
-            return fail(AQR_ERR_INVALID_ARG, "aqr_build: n out of range");
-        if (d != qz->info.d) return fail(AQR_ERR_INVALID_ARG, "aqr_build: d does not match the quantiser");
-        const int32_t M = p->M > 0 ? p->M : qz->info.M;
-        const int32_t efc = p->efc > 0 ? p->efc : qz->info.efc;
-        if (M < 2 || M > 512 || efc < 1)
-            return fail(AQR_ERR_INVALID_ARG, "aqr_build: M must be in [2, 512] and efc >= 1");
-        aqr_graph* g = new aqr_graph();
-        g->n = n;
-        g->M = M;
-        g->efc = efc;
-        g->level.resize(n);
-        const double mL = 1.0 / std::log((double)M);
-        uint64_t state = p->seed;
-        for (int64_t i = 0; i < n; ++i) {
-            double u;
-            if (level_u) {
-                u = level_u[i];
-                if (!(u > 0.0 && u <= 1.0)) {
-                    delete g;
-                    return fail(AQR_ERR_INVALID_ARG, "aqr_build: level draws must lie in (0, 1]");
-                }
-            } else {
-                u = (double)((splitmix64(state) >> 11) + 1) * 0x1.0p-53;
-            }
-            g->level[i] = (int32_t)std::floor(-std::log(u) * mL);
-        }
-        g->upper_off.assign(n + 1, 0);
-        for (int64_t i = 0; i < n; ++i) g->upper_off[i + 1] = g->upper_off[i] + g->level[i];
-        g->adj0.assign((size_t)n * 2 * M, AQR_NONE);
-        g->upper_adj.assign((size_t)std::max<int64_t>(g->upper_off[n], 1) * M, AQR_NONE);
-        g->ep = 0;
-        g->L = g->level[0];
-        const int T = host_threads(p->threads);
-        Builder B(*g, codes, qz->info.d_pad, T > 1);
-        const int64_t step = p->progress > 0 ? std::max<int64_t>(1, n / p->progress) : 0;
-        const auto t0 = std::chrono::steady_clock::now();
-        auto report = [&](int64_t i) {
-            if (step && i % step == 0) {
-                const double s =
-                    std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
-                std::fprintf(stderr, "[aqr_build] %lld / %lld points inserted, %.1f s\n",
-                             (long long)i, (long long)n, s);
-                std::fflush(stderr);
-            }
-        };
-        if (T <= 1 || n < 2) {
-            Visited vis(n);
-            for (int64_t i = 1; i < n; ++i) {
-                B.insert((uint32_t)i, vis);
-                report(i);
-            }
-        } else {
-            std::atomic<int64_t> next{1};
-            parallel_for_threads(T, [&](int) {
-                Visited vis(n);
-                for (;;) {
-                    int64_t i = next.fetch_add(1);
-                    if (i >= n) break;
-                    B.insert((uint32_t)i, vis);
-                    report(i);
-                }
-            });
-        }
-        *out = g;
-        return AQR_OK;
+        return build_seeded(codes, n, d, qz, p, level_u, n, "aqr_build", out);
     } catch (const std::bad_alloc&) {
         return fail(AQR_ERR_OOM, "aqr_build: out of host memory");
     } catch (...) {

@@ -41,6 +41,7 @@
 #include <cstring>
 #include <limits>
 #include <map>
+#include <memory>
 #include <mutex>
 #include <thread>
 #include <utility>
@@ -778,6 +779,17 @@ void k_search(SearchArgs a) {
         }
         wsync();
     }
+}
+
+// Batched build: write changed layer-0 rows (width entries each) into the
+// device adjacency (row stride s0); rows[] are node ids below n, checked on
+// the host.
+__global__ void k_scatter_rows(uint32_t* adj0, int32_t s0, const uint32_t* rows,
+                               const uint32_t* data, int32_t nrows, int32_t width) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= (int64_t)nrows * width) return;
+    const int64_t r = i / width, c = i - r * width;
+    adj0[(int64_t)rows[r] * s0 + c] = data[i];
 }
 
 __global__ void k_reset(int32_t* counter) {
@@ -2393,5 +2405,180 @@ extern "C" aqr_status aqr_server_replay(aqr_server* sv, int64_t n, const double*
         return AQR_OK;
     } catch (...) {
         return fail(AQR_ERR_STATE, "aqr_server_replay: unexpected failure");
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Batched graph construction with the layer-0 searches on the device
+// ---------------------------------------------------------------------------
+extern "C" aqr_status aqr_build_batched(const uint8_t* codes, const float* X, int64_t n, int32_t d,
+                                        const aqr_quantizer* qz, const aqr_bparams* p,
+                                        const double* level_u, int64_t seed_n, int32_t batch,
+                                        aqr_graph** out) {
+    const char* who = "aqr_build_batched";
+    void* arena = nullptr;
+    std::vector<void*> bufs;
+    aqr_index* ix = nullptr;
+    auto release = [&]() {
+        if (ix) aqr_index_free(ix);
+        for (void* b : bufs) (void)hipFree(b);
+        if (arena) (void)hipFree(arena);
+    };
+    try {
+        clear_error();
+        if (!X || !out) return fail(AQR_ERR_INVALID_ARG, "aqr_build_batched: null pointer");
+        if (seed_n < 1 || batch < 1)
+            return fail(AQR_ERR_INVALID_ARG, "aqr_build_batched: seed_n and batch must be >= 1");
+        aqr_graph* g0 = nullptr;
+        aqr_status st = build_seeded(codes, n, d, qz, p, level_u, std::min(seed_n, n), who, &g0);
+        if (st != AQR_OK) return st;
+        std::unique_ptr<aqr_graph> g(g0);
+        const int32_t M = g->M, efc = g->efc;
+        if (efc > 1024) return fail(AQR_ERR_INVALID_ARG, "aqr_build_batched: efc above 1024");
+        std::vector<uint32_t> R;  // level-0 points left for the chunks, in id order
+        for (int64_t i = seed_n; i < n; ++i)
+            if (g->level[i] == 0) R.push_back((uint32_t)i);
+        if (R.empty()) {
+            *out = g.release();
+            return AQR_OK;
+        }
+        const int T = host_threads(p->threads);
+        hipError_t e;
+        size_t bytes = 0;
+        if ((st = aqr_index_bytes(qz, g.get(), &bytes)) != AQR_OK) return st;
+        if ((e = hipMalloc(&arena, bytes)) != hipSuccess) {
+            release();
+            return hip_fail(e, "aqr_build_batched: device memory for the index");
+        }
+        if ((st = aqr_index_bind(qz, g.get(), codes, X, arena, bytes, nullptr, &ix)) != AQR_OK) {
+            release();
+            return st;
+        }
+        const int32_t B = (int32_t)std::min<int64_t>(batch, (int64_t)R.size());
+        const int64_t max_dirty = std::min<int64_t>((int64_t)B * (1 + M), n);
+        const int32_t s0 = ix->v.s0, W = 2 * M;
+        auto dalloc = [&](size_t b) -> void* {
+            void* ptr = nullptr;
+            if (hipMalloc(&ptr, std::max<size_t>(b, 256)) != hipSuccess) return nullptr;
+            bufs.push_back(ptr);
+            return ptr;
+        };
+        float* Qd = (float*)dalloc((size_t)B * d * 4);
+        int32_t* kd = (int32_t*)dalloc((size_t)B * 4);
+        int32_t* efd = (int32_t*)dalloc((size_t)B * 4);
+        int32_t* ncd = (int32_t*)dalloc((size_t)B * 4);
+        int32_t* cntd = (int32_t*)dalloc((size_t)B * 4);
+        uint32_t* cidd = (uint32_t*)dalloc((size_t)B * efc * 4);
+        uint32_t* cDd = (uint32_t*)dalloc((size_t)B * efc * 4);
+        void* ws = dalloc(aqr_search_workspace_size());
+        uint32_t* rowd = (uint32_t*)dalloc((size_t)max_dirty * 4);
+        uint32_t* datd = (uint32_t*)dalloc((size_t)max_dirty * W * 4);
+        for (void* b : bufs)
+            if (!b) {
+                release();
+                return fail(AQR_ERR_OOM, "aqr_build_batched: device memory for the chunks");
+            }
+        {
+            std::vector<int32_t> one(B, 1), wide(B, efc);
+            if ((e = hipMemcpy(kd, one.data(), (size_t)B * 4, hipMemcpyHostToDevice)) != hipSuccess ||
+                (e = hipMemcpy(efd, wide.data(), (size_t)B * 4, hipMemcpyHostToDevice)) != hipSuccess ||
+                (e = hipMemcpy(ncd, wide.data(), (size_t)B * 4, hipMemcpyHostToDevice)) != hipSuccess) {
+                release();
+                return hip_fail(e, "aqr_build_batched: copy");
+            }
+        }
+        aqr_sparams sp{};
+        sp.ef_max = efc;
+        sp.out_stride = efc;
+        sp.m_ef = 1;
+        std::vector<float> hq((size_t)B * d);
+        std::vector<uint32_t> hid((size_t)B * efc), hD((size_t)B * efc), dirty, hrow, hdat;
+        std::vector<int32_t> hcnt(B);
+        std::vector<uint64_t> keys((size_t)B * efc);
+        int64_t inserted = n - (int64_t)R.size();
+        const int32_t dp = qz->info.d_pad;
+        size_t pos = 0;
+        const auto t0 = std::chrono::steady_clock::now();
+        int64_t next_report = 0;
+        while (pos < R.size()) {
+            const int32_t nb = (int32_t)std::min<int64_t>(
+                std::min<int64_t>(batch, std::max<int64_t>(1, inserted / 8)),
+                (int64_t)(R.size() - pos));
+            const uint32_t* ids = R.data() + pos;
+            for (int32_t b = 0; b < nb; ++b)
+                std::memcpy(&hq[(size_t)b * d], X + (int64_t)ids[b] * d, sizeof(float) * d);
+            if ((e = hipMemcpy(Qd, hq.data(), (size_t)nb * d * 4, hipMemcpyHostToDevice)) != hipSuccess) {
+                release();
+                return hip_fail(e, "aqr_build_batched: copy");
+            }
+            st = run_search(ix, Qd, nb, kd, efd, ncd, &sp, cidd, cDd, cntd, ws,
+                            aqr_search_workspace_size(), nullptr, nullptr, false, who);
+            if (st != AQR_OK) {
+                release();
+                return st;
+            }
+            if ((e = hipMemcpy(hid.data(), cidd, (size_t)nb * efc * 4, hipMemcpyDeviceToHost)) != hipSuccess ||
+                (e = hipMemcpy(hD.data(), cDd, (size_t)nb * efc * 4, hipMemcpyDeviceToHost)) != hipSuccess ||
+                (e = hipMemcpy(hcnt.data(), cntd, (size_t)nb * 4, hipMemcpyDeviceToHost)) != hipSuccess) {
+                release();
+                return hip_fail(e, "aqr_build_batched: copy");
+            }
+            for (int32_t b = 0; b < nb; ++b) {
+                if (hcnt[b] < 1 || hcnt[b] > efc) {
+                    release();
+                    return fail(AQR_ERR_STATE, "aqr_build_batched: a chunk search returned no candidates");
+                }
+                for (int32_t t = 0; t < hcnt[b]; ++t) {
+                    const size_t o = (size_t)b * efc + t;
+                    keys[o] = ((uint64_t)hD[o] << 32) | hid[o];
+                }
+            }
+            link_chunk(g.get(), codes, dp, ids, nb, keys.data(), efc, hcnt.data(), T, dirty);
+            const int32_t nr = (int32_t)dirty.size();
+            if ((int64_t)nr > max_dirty) {
+                release();
+                return fail(AQR_ERR_STATE, "aqr_build_batched: more changed rows than staged");
+            }
+            hrow.assign(dirty.begin(), dirty.end());
+            hdat.resize((size_t)nr * W);
+            for (int32_t r = 0; r < nr; ++r) {
+                if ((int64_t)hrow[r] >= n) {
+                    release();
+                    return fail(AQR_ERR_STATE, "aqr_build_batched: row id out of range");
+                }
+                std::memcpy(&hdat[(size_t)r * W], &g->adj0[(size_t)hrow[r] * W], sizeof(uint32_t) * W);
+            }
+            if ((e = hipMemcpy(rowd, hrow.data(), (size_t)nr * 4, hipMemcpyHostToDevice)) != hipSuccess ||
+                (e = hipMemcpy(datd, hdat.data(), (size_t)nr * W * 4, hipMemcpyHostToDevice)) != hipSuccess) {
+                release();
+                return hip_fail(e, "aqr_build_batched: copy");
+            }
+            const int64_t tot = (int64_t)nr * W;
+            hipLaunchKernelGGL(dev::k_scatter_rows, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0,
+                               nullptr, const_cast<uint32_t*>(ix->v.adj0), s0, rowd, datd, nr, W);
+            if ((e = hipGetLastError()) != hipSuccess || (e = hipDeviceSynchronize()) != hipSuccess) {
+                release();
+                return hip_fail(e, "aqr_build_batched: row update");
+            }
+            pos += nb;
+            inserted += nb;
+            if (p->progress > 0 && (int64_t)pos >= next_report) {
+                const double sec =
+                    std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+                std::fprintf(stderr, "[%s] %lld / %lld chunked points linked, %.1f s\n", who,
+                             (long long)pos, (long long)R.size(), sec);
+                std::fflush(stderr);
+                next_report = (int64_t)pos + std::max<int64_t>(1, (int64_t)R.size() / p->progress);
+            }
+        }
+        release();
+        *out = g.release();
+        return AQR_OK;
+    } catch (const std::bad_alloc&) {
+        release();
+        return fail(AQR_ERR_OOM, "aqr_build_batched: out of host memory");
+    } catch (...) {
+        release();
+        return fail(AQR_ERR_STATE, "aqr_build_batched: unexpected failure");
     }
 }

@@ -45,6 +45,16 @@ struct Graph {
 struct aqr_quantizer : aqr::Quantizer {};
 struct aqr_graph : aqr::Graph {};
 
+namespace aqr {
+// Graph construction pieces shared with the device build (build.cpp).
+aqr_status build_seeded(const uint8_t* codes, int64_t n, int32_t d, const aqr_quantizer* qz,
+                        const aqr_bparams* p, const double* level_u, int64_t seed_n,
+                        const char* who, aqr_graph** out);
+void link_chunk(aqr_graph* g, const uint8_t* codes, int32_t dp, const uint32_t* ids, int32_t nb,
+                const uint64_t* cand, int32_t stride, const int32_t* cnt, int threads,
+                std::vector<uint32_t>& dirty);
+}  // namespace aqr
+
 #include <thread>
 
 namespace aqr {
