@@ -431,6 +431,7 @@ def bench_batched(args, torch, aqr, W, wl, dev, threads):
                         f"{wl.n_clusters}-cluster mixture with Pareto(1.5) sizes; {nq:,} queries "
                         f"with k in {{1,10,100}} and ef in {{16,...,512}} in one captured launch",
             "n": n, "d": d, "nq": nq, "M0": wl.M0, "efc0": wl.efc0, "M_i": ginfo["M"],
+            "graph_build": "batched, device searches" if args.gpu_build else "host",
             "delta": round(info["delta"], 6), "rerank": cfg[0], "n_rerank": nrr,
             "tau_gap": finite_or_none(tg), "tau_ratio": finite_or_none(tr), "tuning": best,
             "recall@min(k,10)": round(float(rq.mean()), 5), "recall_by_k": rec_by_k,
@@ -598,6 +599,7 @@ def bench_serving(args, torch, aqr, W, wl, dev, threads):
                         f"saturation rate; ef is the cheapest reaching recall@10 >= 0.98 in "
                         f"batch mode, else the best reachable (calibrated recall@10 {rec98})",
             "n": n, "d": d, "M0": wl.M0, "efc0": wl.efc0, "M_i": ginfo["M"],
+            "graph_build": "batched, device searches" if args.gpu_build else "host",
             "delta": round(info["delta"], 6), "ef": ef98, "recall@10": rec98,
             "rerank": cfg[0], "n_rerank": nrr,
             "tau_gap": finite_or_none(tg), "tau_ratio": finite_or_none(tr), "ring": args.ring, "k_max": k_max,
@@ -646,9 +648,15 @@ def build_index(args, wl, X, threads):
                                                             p_max=p_max, threads=threads))
         t_quant = time.perf_counter() - t
         t = time.perf_counter()
-        g = aqr.aqr_build(codes, d, qz, threads=threads,
-                          M=wl.M0 if args.sq8 else 0, efc=wl.efc0 if args.sq8 else 0,
-                          level_u=W.level_draws(args.workload, n), progress=20)
+        if args.gpu_build:
+            g = aqr.aqr_build_batched(codes, X, d, qz, threads=threads,
+                                      M=wl.M0 if args.sq8 else 0,
+                                      efc=wl.efc0 if args.sq8 else 0,
+                                      level_u=W.level_draws(args.workload, n), progress=20)
+        else:
+            g = aqr.aqr_build(codes, d, qz, threads=threads,
+                              M=wl.M0 if args.sq8 else 0, efc=wl.efc0 if args.sq8 else 0,
+                              level_u=W.level_draws(args.workload, n), progress=20)
         t_build = time.perf_counter() - t
         if cache:
             os.makedirs(cache, exist_ok=True)
@@ -704,6 +712,9 @@ def main():
     ap.add_argument("--assembly", choices=("fill", "union"), default="fill",
                     help="re-rank assembly: fill from A while fewer than k (default), or the "
                          "union of the exact results with the rest of A")
+    ap.add_argument("--host-build", dest="gpu_build", action="store_false",
+                    help="build the graph with the host builder (aqr_build) instead of the "
+                         "batched build whose chunk searches run on the GPU (aqr_build_batched)")
     ap.add_argument("--sq8", action="store_true",
                     help="plain 8-bit scalar quantisation (P_max = 0) and a plain HNSW graph at "
                          "M_0 and ef_0^c: the paper's scalar-quantisation baseline")
@@ -992,9 +1003,12 @@ def main():
         "config": {
             "workload": f"{args.workload}: {n:,} x {d} FP32 L2, {wl.n_clusters}-cluster "
                         f"Gaussian mixture; {nq:,} queries; k={k}"
-                        + ("; plain SQ8 baseline (P_max 0, graph at M_0)" if args.sq8 else ""),
+                        + ("; plain SQ8 baseline (P_max 0, graph at M_0)" if args.sq8 else "")
+                        + ("" if args.gpu_build else "; graph from the host build"),
             "n": n, "d": d, "nq": nq, "k": k, "ef": ef_a, "M0": wl.M0, "efc0": wl.efc0,
-            "M_i": ginfo["M"], "delta": round(info["delta"], 6), "m_ef": 3,
+            "M_i": ginfo["M"],
+            "graph_build": "batched, device searches" if args.gpu_build else "host",
+            "delta": round(info["delta"], 6), "m_ef": 3,
             "rerank": aqr_pick[2][0], "n_rerank": aqr_pick[2][1],
             "assembly": "union" if ASSEMBLY else "fill",
             "tau_gap": finite_or_none(aqr_pick[2][2]),
