@@ -333,13 +333,14 @@ aqr_status build_seeded(const uint8_t* codes, int64_t n, int32_t d, const aqr_qu
 // candidates (keys (D << 32) | id, ascending, cnt[b] of them at row b of a
 // [nb][stride] array), each from a search of the graph as it stood before
 // the chunk.  Selects M neighbours per point with the heuristic, sets the
-// points' layer-0 lists, then adds the reverse links: the links into one
-// node are applied in id order (as a sequential pass in id order would),
-// and different nodes in parallel.  dirty receives every id whose layer-0
-// list changed.
+// points' layer-0 lists, then adds the reverse links: thread t owns the
+// target nodes x with x % T == t and applies the links into them in the
+// order they were generated (id order, as a sequential pass would), so the
+// result does not depend on T.  dirty receives every id whose layer-0 list
+// changed; mark (n bytes, all zero) is scratch and left all zero.
 void link_chunk(aqr_graph* g, const uint8_t* codes, int32_t dp, const uint32_t* ids, int32_t nb,
                 const uint64_t* cand, int32_t stride, const int32_t* cnt, int threads,
-                std::vector<uint32_t>& dirty) {
+                std::vector<uint32_t>& dirty, std::vector<uint8_t>& mark) {
     const int32_t M = g->M;
     Builder B(*g, codes, dp, false);
     std::vector<uint32_t> sel((size_t)nb * M);
@@ -356,27 +357,26 @@ void link_chunk(aqr_graph* g, const uint8_t* codes, int32_t dp, const uint32_t* 
             for (int32_t t = 0; t < 2 * M; ++t) row[t] = t < ns[b] ? sel[(size_t)b * M + t] : kNone;
         }
     });
-    std::vector<uint64_t> pr;  // (target << 32) | b, b in id order
-    for (int32_t b = 0; b < nb; ++b)
-        for (int32_t t = 0; t < ns[b]; ++t) pr.push_back(((uint64_t)sel[(size_t)b * M + t] << 32) | (uint32_t)b);
-    std::sort(pr.begin(), pr.end());
-    std::vector<size_t> grp;
-    for (size_t i = 0; i < pr.size(); ++i)
-        if (i == 0 || (pr[i] >> 32) != (pr[i - 1] >> 32)) grp.push_back(i);
-    grp.push_back(pr.size());
-    const int64_t ng = (int64_t)grp.size() - 1;
-    std::atomic<int64_t> gx{0};
-    const int T2 = std::max(1, std::min(threads, (int)std::max<int64_t>(1, ng / 64)));
-    parallel_for_threads(T2, [&](int) {
-        for (;;) {
-            const int64_t k = gx.fetch_add(1);
-            if (k >= ng) break;
-            for (size_t i = grp[k]; i < grp[k + 1]; ++i)
-                B.link_locked((uint32_t)(pr[i] >> 32), ids[(uint32_t)pr[i]], 0);
-        }
+    const int T2 = std::max(1, threads);
+    std::vector<std::vector<uint32_t>> owned(T2);
+    parallel_for_threads(T2, [&](int t) {
+        for (int32_t b = 0; b < nb; ++b)
+            for (int32_t j = 0; j < ns[b]; ++j) {
+                const uint32_t x = sel[(size_t)b * M + j];
+                if ((int)(x % (uint32_t)T2) != t) continue;
+                B.link_locked(x, ids[b], 0);
+                if (!mark[x]) {
+                    mark[x] = 1;
+                    owned[t].push_back(x);
+                }
+            }
     });
     dirty.assign(ids, ids + nb);
-    for (int64_t k = 0; k < ng; ++k) dirty.push_back((uint32_t)(pr[grp[k]] >> 32));
+    for (auto& o : owned)
+        for (uint32_t x : o) {
+            dirty.push_back(x);
+            mark[x] = 0;
+        }
 }
 
 }  // namespace aqr

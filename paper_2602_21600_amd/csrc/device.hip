@@ -2495,16 +2495,24 @@ extern "C" aqr_status aqr_build_batched(const uint8_t* codes, const float* X, in
         std::vector<uint32_t> hid((size_t)B * efc), hD((size_t)B * efc), dirty, hrow, hdat;
         std::vector<int32_t> hcnt(B);
         std::vector<uint64_t> keys((size_t)B * efc);
+        std::vector<uint8_t> mark((size_t)n, 0);  // scratch of link_chunk
         int64_t inserted = n - (int64_t)R.size();
         const int32_t dp = qz->info.d_pad;
         size_t pos = 0;
         const auto t0 = std::chrono::steady_clock::now();
         int64_t next_report = 0;
+        double t_search = 0.0, t_link = 0.0, t_rows = 0.0;  // seconds, for the progress report
+        auto now = [] { return std::chrono::steady_clock::now(); };
+        auto secs = [](std::chrono::steady_clock::time_point a,
+                       std::chrono::steady_clock::time_point b) {
+            return std::chrono::duration<double>(b - a).count();
+        };
         while (pos < R.size()) {
             const int32_t nb = (int32_t)std::min<int64_t>(
                 std::min<int64_t>(batch, std::max<int64_t>(1, inserted / 8)),
                 (int64_t)(R.size() - pos));
             const uint32_t* ids = R.data() + pos;
+            const auto ta = now();
             for (int32_t b = 0; b < nb; ++b)
                 std::memcpy(&hq[(size_t)b * d], X + (int64_t)ids[b] * d, sizeof(float) * d);
             if ((e = hipMemcpy(Qd, hq.data(), (size_t)nb * d * 4, hipMemcpyHostToDevice)) != hipSuccess) {
@@ -2533,7 +2541,9 @@ extern "C" aqr_status aqr_build_batched(const uint8_t* codes, const float* X, in
                     keys[o] = ((uint64_t)hD[o] << 32) | hid[o];
                 }
             }
-            link_chunk(g.get(), codes, dp, ids, nb, keys.data(), efc, hcnt.data(), T, dirty);
+            const auto tb = now();
+            link_chunk(g.get(), codes, dp, ids, nb, keys.data(), efc, hcnt.data(), T, dirty, mark);
+            const auto tc = now();
             const int32_t nr = (int32_t)dirty.size();
             if ((int64_t)nr > max_dirty) {
                 release();
@@ -2560,13 +2570,17 @@ extern "C" aqr_status aqr_build_batched(const uint8_t* codes, const float* X, in
                 release();
                 return hip_fail(e, "aqr_build_batched: row update");
             }
+            t_search += secs(ta, tb);
+            t_link += secs(tb, tc);
+            t_rows += secs(tc, now());
             pos += nb;
             inserted += nb;
-            if (p->progress > 0 && (int64_t)pos >= next_report) {
-                const double sec =
-                    std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
-                std::fprintf(stderr, "[%s] %lld / %lld chunked points linked, %.1f s\n", who,
-                             (long long)pos, (long long)R.size(), sec);
+            if (p->progress > 0 && ((int64_t)pos >= next_report || pos == R.size())) {
+                std::fprintf(stderr,
+                             "[%s] %lld / %lld chunked points linked, %.1f s (device search "
+                             "%.1f s, host linking %.1f s, row upload %.1f s)\n",
+                             who, (long long)pos, (long long)R.size(), secs(t0, now()), t_search,
+                             t_link, t_rows);
                 std::fflush(stderr);
                 next_report = (int64_t)pos + std::max<int64_t>(1, (int64_t)R.size() / p->progress);
             }

@@ -52,7 +52,7 @@ aqr_status build_seeded(const uint8_t* codes, int64_t n, int32_t d, const aqr_qu
                         const char* who, aqr_graph** out);
 void link_chunk(aqr_graph* g, const uint8_t* codes, int32_t dp, const uint32_t* ids, int32_t nb,
                 const uint64_t* cand, int32_t stride, const int32_t* cnt, int threads,
-                std::vector<uint32_t>& dirty);
+                std::vector<uint32_t>& dirty, std::vector<uint8_t>& mark);
 }  // namespace aqr
 
 #include <thread>

@@ -96,3 +96,15 @@ def test_batched_build_rejects_bad_arguments(orc):
         aqr.aqr_build_batched(codes, X, 16, qz, seed_n=0)
     with pytest.raises(aqr.AqrError):
         aqr.aqr_build_batched(codes, X, 16, qz, batch=0)
+
+
+def test_batched_build_tiny_index_matches_oracle(orc):
+    # fewer points than a default seed, chunks of a few points from the start
+    _torch()
+    from paper_2602_21600_amd import aqr
+    X, _ = W.tiny(60, 8, seed=2, clusters=2)
+    qz, codes, info = _quantised(X, 4, 10)
+    u = 1.0 - np.random.default_rng(4).random(60)
+    g = aqr.aqr_build_batched(codes, X, 8, qz, threads=1, level_u=u, seed_n=20, batch=8)
+    og = orc.build_batched(codes, 8, info["M"], info["efc"], orc.levels(u, info["M"]), 20, 8)
+    _same(aqr.aqr_graph_export(g), og)
