@@ -431,7 +431,8 @@ def bench_batched(args, torch, aqr, W, wl, dev, threads):
                         f"{wl.n_clusters}-cluster mixture with Pareto(1.5) sizes; {nq:,} queries "
                         f"with k in {{1,10,100}} and ef in {{16,...,512}} in one captured launch",
             "n": n, "d": d, "nq": nq, "M0": wl.M0, "efc0": wl.efc0, "M_i": ginfo["M"],
-            "graph_build": "batched, device searches" if args.gpu_build else "host",
+            "graph_build": ("batched, device searches; quantiser density on the device"
+                            if args.gpu_build else "host"),
             "delta": round(info["delta"], 6), "rerank": cfg[0], "n_rerank": nrr,
             "tau_gap": finite_or_none(tg), "tau_ratio": finite_or_none(tr), "tuning": best,
             "recall@min(k,10)": round(float(rq.mean()), 5), "recall_by_k": rec_by_k,
@@ -599,7 +600,8 @@ def bench_serving(args, torch, aqr, W, wl, dev, threads):
                         f"saturation rate; ef is the cheapest reaching recall@10 >= 0.98 in "
                         f"batch mode, else the best reachable (calibrated recall@10 {rec98})",
             "n": n, "d": d, "M0": wl.M0, "efc0": wl.efc0, "M_i": ginfo["M"],
-            "graph_build": "batched, device searches" if args.gpu_build else "host",
+            "graph_build": ("batched, device searches; quantiser density on the device"
+                            if args.gpu_build else "host"),
             "delta": round(info["delta"], 6), "ef": ef98, "recall@10": rec98,
             "rerank": cfg[0], "n_rerank": nrr,
             "tau_gap": finite_or_none(tg), "tau_ratio": finite_or_none(tr), "ring": args.ring, "k_max": k_max,
@@ -642,10 +644,12 @@ def build_index(args, wl, X, threads):
         # (P_max = 0) and a graph at the configured M_0 and ef_0^c, with no
         # density adaptation
         p_max = 0.0 if args.sq8 else 0.01
-        log(f"quantize n={n} d={d} threads={threads} p_max={p_max}")
+        log(f"quantize n={n} d={d} threads={threads} p_max={p_max} "
+            f"density on the {'GPU' if args.gpu_build else 'host'}")
         t = time.perf_counter()
         qz, codes = aqr.aqr_quantize(X, aqr.default_qparams(M0=wl.M0, efc0=wl.efc0,
-                                                            p_max=p_max, threads=threads))
+                                                            p_max=p_max, threads=threads),
+                                     device=args.gpu_build)
         t_quant = time.perf_counter() - t
         t = time.perf_counter()
         if args.gpu_build:
@@ -713,8 +717,10 @@ def main():
                     help="re-rank assembly: fill from A while fewer than k (default), or the "
                          "union of the exact results with the rest of A")
     ap.add_argument("--host-build", dest="gpu_build", action="store_false",
-                    help="build the graph with the host builder (aqr_build) instead of the "
-                         "batched build whose chunk searches run on the GPU (aqr_build_batched)")
+                    help="train the quantiser and build the graph on the host (aqr_quantize, "
+                         "aqr_build) instead of with the density search and the batched "
+                         "build's chunk searches on the GPU (aqr_quantize_device, "
+                         "aqr_build_batched)")
     ap.add_argument("--sq8", action="store_true",
                     help="plain 8-bit scalar quantisation (P_max = 0) and a plain HNSW graph at "
                          "M_0 and ef_0^c: the paper's scalar-quantisation baseline")
@@ -1007,7 +1013,8 @@ def main():
                         + ("" if args.gpu_build else "; graph from the host build"),
             "n": n, "d": d, "nq": nq, "k": k, "ef": ef_a, "M0": wl.M0, "efc0": wl.efc0,
             "M_i": ginfo["M"],
-            "graph_build": "batched, device searches" if args.gpu_build else "host",
+            "graph_build": ("batched, device searches; quantiser density on the device"
+                            if args.gpu_build else "host"),
             "delta": round(info["delta"], 6), "m_ef": 3,
             "rerank": aqr_pick[2][0], "n_rerank": aqr_pick[2][1],
             "assembly": "union" if ASSEMBLY else "fill",

@@ -103,6 +103,33 @@ typedef struct aqr_quantizer aqr_quantizer;
 aqr_status aqr_quantize(const float* X, int64_t n, int32_t d, const aqr_qparams* p,
                         aqr_quantizer** qz, uint8_t* codes_out);
 
+/*
+ * aqr_quantize with the density search of Section 3.1 Stage 1 (the k_rho
+ * nearest neighbours of every sample point over all n points) on the current
+ * device; the rest of the training and the encoding run on the host.  Every
+ * distance is summed in the same FP64 order as on the host and the k smallest
+ * are summed in ascending order, so the quantiser and the codes are those of
+ * aqr_quantize bit for bit.  X stays a host array: the call copies it to
+ * device memory it allocates (n x d floats, hipMalloc) and frees before it
+ * returns, and waits for its work.  k_rho <= 64.  HIP failures give
+ * AQR_ERR_DEVICE; the other errors are those of aqr_quantize.
+ */
+aqr_status aqr_quantize_device(const float* X, int64_t n, int32_t d, const aqr_qparams* p,
+                               aqr_quantizer** qz, uint8_t* codes_out);
+
+/*
+ * The densities rho_i of Section 3.1 Stage 1 into rho (host, n doubles):
+ * 1 / (mean of the k_rho smallest squared L2 distances to the other points
+ * + eps), FP64; with n > p->sample_threshold only the points
+ * floor(s n / n_s), s < n_s = min(p->n_sample, n), are measured and every
+ * other point gets their mean.  device != 0 runs the neighbour search on the
+ * current device (as aqr_quantize_device), 0 on p->threads host threads;
+ * both give the same values.  Only p->k_rho (<= 64), n_sample,
+ * sample_threshold, eps and threads are read.
+ */
+aqr_status aqr_density(const float* X, int64_t n, int32_t d, const aqr_qparams* p,
+                       int32_t device, double* rho);
+
 /* Copy out the scalars and the per-dimension min_j, max_j, scale_j (each d
  * floats; any array pointer may be NULL). */
 aqr_status aqr_quantizer_info(const aqr_quantizer* qz, aqr_qinfo* info, float* min_out,

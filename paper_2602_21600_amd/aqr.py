@@ -96,6 +96,8 @@ _SIGS = [
     ("aqr_last_error", C.c_char_p, []),
     ("aqr_version", _i32, []),
     ("aqr_quantize", _i32, [_vp, _i64, _i32, C.POINTER(QParams), C.POINTER(_vp), _vp]),
+    ("aqr_quantize_device", _i32, [_vp, _i64, _i32, C.POINTER(QParams), C.POINTER(_vp), _vp]),
+    ("aqr_density", _i32, [_vp, _i64, _i32, C.POINTER(QParams), _i32, _vp]),
     ("aqr_quantizer_info", _i32, [_vp, C.POINTER(QInfo), _vp, _vp, _vp]),
     ("aqr_quantizer_create", _i32, [C.POINTER(QInfo), _vp, _vp, _vp, C.POINTER(_vp)]),
     ("aqr_quantizer_free", None, [_vp]),
@@ -241,16 +243,29 @@ def default_qparams(M0=16, efc0=200, p_max=0.01, threads=0):
                 p_max=p_max, M0=M0, efc0=efc0)
 
 
-def aqr_quantize(X, params=None, qz=None, codes=True):
-    """Train (qz None) or reuse a quantiser; returns (Quantizer, codes or None)."""
+def aqr_quantize(X, params=None, qz=None, codes=True, device=False):
+    """Train (qz None) or reuse a quantiser; returns (Quantizer, codes or None).
+    device=True: aqr_quantize_device (the density search on the current
+    device, same result)."""
     X = np.ascontiguousarray(X, np.float32)
     n, d = X.shape
     p = QParams(**(params or default_qparams()))
     h = C.c_void_p(qz.ptr if qz is not None else None)
     d_pad = (d + 15) // 16 * 16
     out = np.zeros((n, d_pad), np.uint8) if codes else None
-    _check(lib().aqr_quantize(_np_ptr(X), n, d, C.byref(p), C.byref(h), _np_ptr(out)))
+    fn = lib().aqr_quantize_device if device else lib().aqr_quantize
+    _check(fn(_np_ptr(X), n, d, C.byref(p), C.byref(h), _np_ptr(out)))
     return (qz if qz is not None else Quantizer(h.value)), out
+
+
+def aqr_density(X, params=None, device=False):
+    """Densities rho (n doubles) of the quantiser's Stage 1 (aqr_density)."""
+    X = np.ascontiguousarray(X, np.float32)
+    n, d = X.shape
+    p = QParams(**(params or default_qparams()))
+    rho = np.zeros(n, np.float64)
+    _check(lib().aqr_density(_np_ptr(X), n, d, C.byref(p), 1 if device else 0, _np_ptr(rho)))
+    return rho
 
 
 def aqr_quantizer_info(qz):

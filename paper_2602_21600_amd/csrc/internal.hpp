@@ -53,6 +53,11 @@ aqr_status build_seeded(const uint8_t* codes, int64_t n, int32_t d, const aqr_qu
 void link_chunk(aqr_graph* g, const uint8_t* codes, int32_t dp, const uint32_t* ids, int32_t nb,
                 const uint64_t* cand, int32_t stride, const int32_t* cnt, int threads,
                 std::vector<uint32_t>& dirty, std::vector<uint8_t>& mark);
+// Stage-1 densities on the current device (density.hip): for each of the m
+// sample rows S[s] of X (host, n x d), the FP64 sum in ascending order of the
+// k smallest squared distances to the other rows, into sums[s].
+aqr_status device_density_sums(const float* X, int64_t n, int32_t d, const int64_t* S, int64_t m,
+                               int32_t k, int T, double* sums);
 }  // namespace aqr
 
 #include <thread>

@@ -52,7 +52,7 @@ struct TopK {
 };
 
 aqr_status densities(const float* X, int64_t n, int32_t d, const aqr_qparams& p, int T,
-                     std::vector<double>& rho) {
+                     bool device, std::vector<double>& rho) {
     const int64_t ns = std::min<int64_t>(p.n_sample, n);
     const bool sampled = n > p.sample_threshold;
     const int64_t m = sampled ? ns : n;
@@ -61,7 +61,13 @@ aqr_status densities(const float* X, int64_t n, int32_t d, const aqr_qparams& p,
     std::vector<int64_t> S(m);
     for (int64_t s = 0; s < m; ++s) S[s] = sampled ? (s * n) / ns : s;
     rho.assign(n, 0.0);
-    const int64_t ntiles = (m + kTile - 1) / kTile;
+    if (device && k > 0) {
+        std::vector<double> sums(m);
+        aqr_status st = device_density_sums(X, n, d, S.data(), m, k, T, sums.data());
+        if (st != AQR_OK) return st;
+        for (int64_t s = 0; s < m; ++s) rho[S[s]] = 1.0 / (sums[s] / (double)k + p.eps);
+    }
+    const int64_t ntiles = device && k > 0 ? 0 : (m + kTile - 1) / kTile;
     std::atomic<int64_t> next{0};
     parallel_for_threads(T, [&](int) {
         std::vector<double> tileT((size_t)d * kTile);  // [dim][t]
@@ -160,9 +166,9 @@ bool all_finite(const float* X, int64_t count) {
 }
 
 aqr_status train(const float* X, int64_t n, int32_t d, const aqr_qparams& p, int T,
-                 Quantizer& q) {
+                 bool device, Quantizer& q) {
     std::vector<double> rho;
-    aqr_status st = densities(X, n, d, p, T, rho);
+    aqr_status st = densities(X, n, d, p, T, device, rho);
     if (st != AQR_OK) return st;
     double rmax = rho[0], rmin = rho[0];
     for (int64_t i = 1; i < n; ++i) {
@@ -226,39 +232,77 @@ aqr_status train(const float* X, int64_t n, int32_t d, const aqr_qparams& p, int
 
 using namespace aqr;
 
-extern "C" aqr_status aqr_quantize(const float* X, int64_t n, int32_t d, const aqr_qparams* p,
-                                   aqr_quantizer** qz, uint8_t* codes_out) {
+namespace {
+
+aqr_status quantize(const float* X, int64_t n, int32_t d, const aqr_qparams* p,
+                    aqr_quantizer** qz, uint8_t* codes_out, bool device, const char* who) {
+    const std::string w(who);
     try {
         clear_error();
-        if (!X || !qz) return fail(AQR_ERR_INVALID_ARG, "aqr_quantize: null pointer");
-        if (n < 1 || d < 1) return fail(AQR_ERR_INVALID_ARG, "aqr_quantize: n and d must be >= 1");
+        if (!X || !qz) return fail(AQR_ERR_INVALID_ARG, w + ": null pointer");
+        if (n < 1 || d < 1) return fail(AQR_ERR_INVALID_ARG, w + ": n and d must be >= 1");
         if (!all_finite(X, n * (int64_t)d))
-            return fail(AQR_ERR_INVALID_ARG, "aqr_quantize: non-finite input value");
+            return fail(AQR_ERR_INVALID_ARG, w + ": non-finite input value");
         aqr_quantizer* q = *qz;
         bool created = false;
         if (!q) {
-            if (!p) return fail(AQR_ERR_INVALID_ARG, "aqr_quantize: params required to train");
+            if (!p) return fail(AQR_ERR_INVALID_ARG, w + ": params required to train");
             if (p->k_rho < 1 || p->n_sample < 1 || !(p->eps > 0) || p->p_max < 0 ||
                 p->p_max > 0.5 || p->M0 < 2 || p->efc0 < 1)
-                return fail(AQR_ERR_INVALID_ARG, "aqr_quantize: parameter out of range");
+                return fail(AQR_ERR_INVALID_ARG, w + ": parameter out of range");
             q = new aqr_quantizer();
             created = true;
-            aqr_status st = train(X, n, d, *p, host_threads(p->threads), *q);
+            aqr_status st = train(X, n, d, *p, host_threads(p->threads), device, *q);
             if (st != AQR_OK) {
                 delete q;
                 return st;
             }
         } else if (q->info.d != d) {
-            return fail(AQR_ERR_INVALID_ARG, "aqr_quantize: d does not match the quantiser");
+            return fail(AQR_ERR_INVALID_ARG, w + ": d does not match the quantiser");
         }
         if (codes_out)
             encode_rows(X, n, d, q->info.d_pad, *q, codes_out, host_threads(p ? p->threads : 0));
         if (created) *qz = q;
         return AQR_OK;
     } catch (const std::bad_alloc&) {
-        return fail(AQR_ERR_OOM, "aqr_quantize: out of host memory");
+        return fail(AQR_ERR_OOM, w + ": out of host memory");
     } catch (...) {
-        return fail(AQR_ERR_STATE, "aqr_quantize: unexpected failure");
+        return fail(AQR_ERR_STATE, w + ": unexpected failure");
+    }
+}
+
+}  // namespace
+
+extern "C" aqr_status aqr_quantize(const float* X, int64_t n, int32_t d, const aqr_qparams* p,
+                                   aqr_quantizer** qz, uint8_t* codes_out) {
+    return quantize(X, n, d, p, qz, codes_out, false, "aqr_quantize");
+}
+
+extern "C" aqr_status aqr_quantize_device(const float* X, int64_t n, int32_t d,
+                                          const aqr_qparams* p, aqr_quantizer** qz,
+                                          uint8_t* codes_out) {
+    return quantize(X, n, d, p, qz, codes_out, true, "aqr_quantize_device");
+}
+
+extern "C" aqr_status aqr_density(const float* X, int64_t n, int32_t d, const aqr_qparams* p,
+                                  int32_t device, double* rho) {
+    try {
+        clear_error();
+        if (!X || !p || !rho) return fail(AQR_ERR_INVALID_ARG, "aqr_density: null pointer");
+        if (n < 1 || d < 1) return fail(AQR_ERR_INVALID_ARG, "aqr_density: n and d must be >= 1");
+        if (p->k_rho < 1 || p->n_sample < 1 || !(p->eps > 0))
+            return fail(AQR_ERR_INVALID_ARG, "aqr_density: parameter out of range");
+        if (!all_finite(X, n * (int64_t)d))
+            return fail(AQR_ERR_INVALID_ARG, "aqr_density: non-finite input value");
+        std::vector<double> r;
+        aqr_status st = densities(X, n, d, *p, host_threads(p->threads), device != 0, r);
+        if (st != AQR_OK) return st;
+        std::memcpy(rho, r.data(), sizeof(double) * (size_t)n);
+        return AQR_OK;
+    } catch (const std::bad_alloc&) {
+        return fail(AQR_ERR_OOM, "aqr_density: out of host memory");
+    } catch (...) {
+        return fail(AQR_ERR_STATE, "aqr_density: unexpected failure");
     }
 }
 

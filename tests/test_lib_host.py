@@ -85,6 +85,26 @@ def test_quantize_image_like_rows_match_oracle(orc):
     np.testing.assert_array_equal(codes, orc.encode(X, ref["min"], ref["scale"], stride=784))
 
 
+@pytest.mark.parametrize("n,d,k_rho,threshold", [(2500, 20, 10, 1000), (900, 13, 64, 10000),
+                                                 (3, 5, 10, 10000)])
+def test_host_density_matches_oracle(orc, n, d, k_rho, threshold):
+    X, _ = W.tiny(n, d, seed=n + k_rho, clusters=4) if n > 50 else (
+        np.random.default_rng(0).standard_normal((n, d)).astype(np.float32), None)
+    p = aqr.default_qparams()
+    p.update(k_rho=k_rho, n_sample=400, sample_threshold=threshold)
+    ref = orc.density(X, k_rho=k_rho, n_s=400, threshold=threshold)
+    np.testing.assert_array_equal(aqr.aqr_density(X, p), ref)
+
+
+def test_density_rejects_bad_parameters():
+    X = np.ones((10, 4), np.float32)
+    for bad in (dict(k_rho=0), dict(k_rho=65), dict(n_sample=0), dict(eps=0.0)):
+        p = aqr.default_qparams()
+        p.update(bad)
+        with pytest.raises(aqr.AqrError):
+            aqr.aqr_density(X, p)
+
+
 def test_quantize_encode_only(orc):
     X, Y = W.tiny(800, 16, seed=2, nq=50)
     qz, codes = aqr.aqr_quantize(X, aqr.default_qparams())
