@@ -681,6 +681,29 @@ def build_index(args, wl, X, threads):
     return qz, g, codes, info, ginfo, t_quant, t_build
 
 
+def bench_build(args, wl, threads):
+    """--build-only: quantiser and graph of the workload, timed on the host clock
+    around each call (the device parts wait for their own work)."""
+    from paper_2602_21600_amd import workloads as W
+    t_all = time.perf_counter()
+    log(f"generating {args.workload}")
+    X = W.base(args.workload, args.n)
+    n, d = X.shape
+    args.cache = None
+    _, _, _, info, ginfo, t_quant, t_build = build_index(args, wl, X, threads)
+    print(json.dumps({
+        "metric": "index build time (quantiser training + encoding + HNSW graph)",
+        "value": round(t_quant + t_build, 3), "unit": "s", "n_gpus": 1,
+        "higher_is_better": False, "data": "synthetic",
+        "config": {"workload": f"{args.workload}: {n:,} x {d} FP32 base set", "n": n, "d": d,
+                   "M0": wl.M0, "efc0": wl.efc0,
+                   "M_i": ginfo["M"], "efc": info["efc"], "host_threads": threads,
+                   "quantiser": "density on the device" if args.gpu_build else "host",
+                   "graph_build": "batched, device searches" if args.gpu_build else "host"},
+        "build_s": {"quantize": round(t_quant, 3), "graph": round(t_build, 3)},
+        "wall_s": round(time.perf_counter() - t_all, 1)}), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -724,6 +747,9 @@ def main():
     ap.add_argument("--sq8", action="store_true",
                     help="plain 8-bit scalar quantisation (P_max = 0) and a plain HNSW graph at "
                          "M_0 and ef_0^c: the paper's scalar-quantisation baseline")
+    ap.add_argument("--build-only", action="store_true",
+                    help="train the quantiser and build the graph of the workload, then print "
+                         "one JSON line with the build times (no search)")
     ap.add_argument("--copy-mib", type=int, default=256,
                     help="size of the plain copy kernel timed in --profile mode")
     args = ap.parse_args()
@@ -748,6 +774,8 @@ def main():
     threads = int(os.environ.get("OMP_NUM_THREADS", "0") or 0)
     threads = threads if threads > 0 else min(16, os.cpu_count() or 1)
     args.loads = [float(x) for x in args.loads.split(",")]
+    if args.build_only:
+        return bench_build(args, wl, threads)
     if args.workload == "batched":
         if args.cpu_sample == 10000:
             args.cpu_sample = 300
