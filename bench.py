@@ -29,6 +29,9 @@ if ROOT not in sys.path:
 
 HBM_PEAK_GBS = 8000.0
 TARGET_RECALL = 0.98
+# further points of the recall-QPS curve, each timed like the headline point
+CURVE_TARGETS = (0.90, 0.95, 0.99)
+CURVE_EXTRA_EF = (576, 640, 768, 896, 1024)
 
 
 def log(msg):
@@ -681,6 +684,73 @@ def build_index(args, wl, X, threads):
     return qz, g, codes, info, ginfo, t_quant, t_build
 
 
+def recall_qps_curve(args, torch, aqr, ix, Qd, nq, k, dev, efs, aqr_table, fp_table, tuning,
+                     fp_tuning, recall_of):
+    """For each of CURVE_TARGETS: the cheapest AQR setting (smallest ef, then
+    the re-rank settings in cost order) and the smallest FP32 ef whose recall
+    reaches it, each timed over args.steps steps; None where no swept ef
+    reaches the target."""
+    a_tab = list(aqr_table)
+    f_tab = list(fp_table)
+    more = sorted(set(efs) | set(CURVE_EXTRA_EF))
+    top = max(CURVE_TARGETS)
+
+    def a_first(t):
+        return next(((e, c, r) for e, c, r in a_tab if r >= t), None)
+
+    def f_first(t):
+        return next(((e, r) for e, r in f_tab if r >= t), None)
+
+    done_a = {(e, c) for e, c, _ in a_tab}
+    for ef in more:
+        if a_first(top) is not None:
+            break
+        for cfg in RERANK_CONFIGS:
+            if (ef, cfg[0]) in done_a:
+                continue
+            r = AqrRunner(aqr, ix, nq, k, ef, dev, rerank=cfg)
+            ids, _ = r.step(Qd)
+            torch.cuda.synchronize()
+            rec = recall_of(ids)
+            a_tab.append((ef, cfg[0], round(rec, 5)))
+            log(f"curve aqr ef={ef} rerank={cfg[0]} recall@10={rec:.4f}")
+            if rec >= top:
+                break
+    done_f = {e for e, _ in f_tab}
+    for ef in more:
+        if f_first(top) is not None:
+            break
+        if ef in done_f:
+            continue
+        r = Fp32Runner(aqr, ix, nq, k, ef, dev)
+        ids, _ = r.step(Qd)
+        torch.cuda.synchronize()
+        rec = recall_of(ids)
+        f_tab.append((ef, round(rec, 5)))
+        log(f"curve fp32 ef={ef} recall@10={rec:.4f}")
+    a_tab.sort(key=lambda t: (t[0], [c[0] for c in RERANK_CONFIGS].index(t[1])))
+    f_tab.sort()
+    out = []
+    for t in CURVE_TARGETS:
+        pa, pf = a_first(t), f_first(t)
+        pt = {"target": t, "aqr": None, "fp32": None, "speedup": None}
+        if pa is not None:
+            cfg = rerank_by_name(pa[1])
+            r = AqrRunner(aqr, ix, nq, k, pa[0], dev, rerank=cfg, **tuning)
+            ms, _ = timed(torch, lambda m: r.step(Qd), args.steps, 50)
+            pt["aqr"] = {"ef": pa[0], "rerank": pa[1], "recall@10": pa[2],
+                         "qps": round(nq / (ms / 1e3), 1)}
+        if pf is not None and fp_tuning is not None:
+            r = Fp32Runner(aqr, ix, nq, k, pf[0], dev, **fp_tuning)
+            ms, _ = timed(torch, lambda m: r.step(Qd), args.steps, 50)
+            pt["fp32"] = {"ef": pf[0], "recall@10": pf[1], "qps": round(nq / (ms / 1e3), 1)}
+        if pt["aqr"] and pt["fp32"]:
+            pt["speedup"] = round(pt["aqr"]["qps"] / pt["fp32"]["qps"], 3)
+        log(f"curve target {t}: {pt}")
+        out.append(pt)
+    return out
+
+
 def bench_build(args, wl, threads):
     """--build-only: quantiser and graph of the workload, timed on the host clock
     around each call (the device parts wait for their own work)."""
@@ -747,6 +817,9 @@ def main():
     ap.add_argument("--sq8", action="store_true",
                     help="plain 8-bit scalar quantisation (P_max = 0) and a plain HNSW graph at "
                          "M_0 and ef_0^c: the paper's scalar-quantisation baseline")
+    ap.add_argument("--no-curve", action="store_true",
+                    help="skip the recall-QPS curve at recall targets "
+                         + ", ".join(str(t) for t in CURVE_TARGETS))
     ap.add_argument("--build-only", action="store_true",
                     help="train the quantiser and build the graph of the workload, then print "
                          "one JSON line with the build times (no search)")
@@ -981,6 +1054,21 @@ def main():
               "sweep": fp_table}
         log(f"FP32 {fp['value']:,.0f} QPS at ef={ef_f}")
 
+    # ---- recall-QPS curve: the cheapest setting of each search at further
+    # recall targets, timed the same way (the sweeps above stop at 0.98, so
+    # they are continued for higher targets) ----
+    curve = None
+    if not args.profile and not args.no_curve:
+        curve = recall_qps_curve(args, torch, aqr, ix, Qd, nq, k, dev, efs, aqr_table, fp_table,
+                                 tuning, fp_tuning if fp is not None else None, recall_of)
+        curve.append({"target": TARGET_RECALL,
+                      "aqr": {"ef": ef_a, "rerank": aqr_pick[2][0],
+                              "recall@10": round(aqr_pick[1], 5), "qps": round(qps_aqr, 1)},
+                      "fp32": ({"ef": fp["ef"], "recall@10": fp["recall@10"],
+                                "qps": fp["value"]} if fp else None),
+                      "speedup": round(qps_aqr / fp["value"], 3) if fp else None})
+        curve.sort(key=lambda c: c["target"])
+
     # ---- CPU oracle baseline on a sample of the same queries ----
     cpu = None
     parity = None
@@ -1070,6 +1158,7 @@ def main():
         "fp32_hnsw": fp,
         "speedup_vs_fp32": (round(qps_aqr / fp["value"], 3) if fp else None),
         "aqr_sweep": aqr_table,
+        "recall_qps_curve": curve,
         "cpu_baseline": cpu,
         "parity_sample": parity,
         "build_s": {"quantize": t_quant and round(t_quant, 1),

@@ -2417,11 +2417,12 @@ extern "C" aqr_status aqr_build_batched(const uint8_t* codes, const float* X, in
                                         aqr_graph** out) {
     const char* who = "aqr_build_batched";
     void* arena = nullptr;
-    std::vector<void*> bufs;
+    std::vector<void*> bufs, hbufs;  // device buffers, pinned host staging
     aqr_index* ix = nullptr;
     auto release = [&]() {
         if (ix) aqr_index_free(ix);
         for (void* b : bufs) (void)hipFree(b);
+        for (void* b : hbufs) (void)hipHostFree(b);
         if (arena) (void)hipFree(arena);
     };
     try {
@@ -2478,6 +2479,25 @@ extern "C" aqr_status aqr_build_batched(const uint8_t* codes, const float* X, in
                 release();
                 return fail(AQR_ERR_OOM, "aqr_build_batched: device memory for the chunks");
             }
+        // pinned staging for the per-chunk copies (queries in, candidates out,
+        // changed rows in)
+        auto halloc = [&](size_t b) -> void* {
+            void* ptr = nullptr;
+            if (hipHostMalloc(&ptr, std::max<size_t>(b, 256)) != hipSuccess) return nullptr;
+            hbufs.push_back(ptr);
+            return ptr;
+        };
+        float* hq = (float*)halloc((size_t)B * d * 4);
+        uint32_t* hid = (uint32_t*)halloc((size_t)B * efc * 4);
+        uint32_t* hD = (uint32_t*)halloc((size_t)B * efc * 4);
+        int32_t* hcnt = (int32_t*)halloc((size_t)B * 4);
+        uint32_t* hrow = (uint32_t*)halloc((size_t)max_dirty * 4);
+        uint32_t* hdat = (uint32_t*)halloc((size_t)max_dirty * W * 4);
+        for (void* b : hbufs)
+            if (!b) {
+                release();
+                return fail(AQR_ERR_OOM, "aqr_build_batched: pinned host memory for the chunks");
+            }
         {
             std::vector<int32_t> one(B, 1), wide(B, efc);
             if ((e = hipMemcpy(kd, one.data(), (size_t)B * 4, hipMemcpyHostToDevice)) != hipSuccess ||
@@ -2491,9 +2511,7 @@ extern "C" aqr_status aqr_build_batched(const uint8_t* codes, const float* X, in
         sp.ef_max = efc;
         sp.out_stride = efc;
         sp.m_ef = 1;
-        std::vector<float> hq((size_t)B * d);
-        std::vector<uint32_t> hid((size_t)B * efc), hD((size_t)B * efc), dirty, hrow, hdat;
-        std::vector<int32_t> hcnt(B);
+        std::vector<uint32_t> dirty;
         std::vector<uint64_t> keys((size_t)B * efc);
         std::vector<uint8_t> mark((size_t)n, 0);  // scratch of link_chunk
         int64_t inserted = n - (int64_t)R.size();
@@ -2515,7 +2533,7 @@ extern "C" aqr_status aqr_build_batched(const uint8_t* codes, const float* X, in
             const auto ta = now();
             for (int32_t b = 0; b < nb; ++b)
                 std::memcpy(&hq[(size_t)b * d], X + (int64_t)ids[b] * d, sizeof(float) * d);
-            if ((e = hipMemcpy(Qd, hq.data(), (size_t)nb * d * 4, hipMemcpyHostToDevice)) != hipSuccess) {
+            if ((e = hipMemcpy(Qd, hq, (size_t)nb * d * 4, hipMemcpyHostToDevice)) != hipSuccess) {
                 release();
                 return hip_fail(e, "aqr_build_batched: copy");
             }
@@ -2525,9 +2543,9 @@ extern "C" aqr_status aqr_build_batched(const uint8_t* codes, const float* X, in
                 release();
                 return st;
             }
-            if ((e = hipMemcpy(hid.data(), cidd, (size_t)nb * efc * 4, hipMemcpyDeviceToHost)) != hipSuccess ||
-                (e = hipMemcpy(hD.data(), cDd, (size_t)nb * efc * 4, hipMemcpyDeviceToHost)) != hipSuccess ||
-                (e = hipMemcpy(hcnt.data(), cntd, (size_t)nb * 4, hipMemcpyDeviceToHost)) != hipSuccess) {
+            if ((e = hipMemcpy(hid, cidd, (size_t)nb * efc * 4, hipMemcpyDeviceToHost)) != hipSuccess ||
+                (e = hipMemcpy(hD, cDd, (size_t)nb * efc * 4, hipMemcpyDeviceToHost)) != hipSuccess ||
+                (e = hipMemcpy(hcnt, cntd, (size_t)nb * 4, hipMemcpyDeviceToHost)) != hipSuccess) {
                 release();
                 return hip_fail(e, "aqr_build_batched: copy");
             }
@@ -2542,24 +2560,32 @@ extern "C" aqr_status aqr_build_batched(const uint8_t* codes, const float* X, in
                 }
             }
             const auto tb = now();
-            link_chunk(g.get(), codes, dp, ids, nb, keys.data(), efc, hcnt.data(), T, dirty, mark);
+            link_chunk(g.get(), codes, dp, ids, nb, keys.data(), efc, hcnt, T, dirty, mark);
             const auto tc = now();
             const int32_t nr = (int32_t)dirty.size();
             if ((int64_t)nr > max_dirty) {
                 release();
                 return fail(AQR_ERR_STATE, "aqr_build_batched: more changed rows than staged");
             }
-            hrow.assign(dirty.begin(), dirty.end());
-            hdat.resize((size_t)nr * W);
             for (int32_t r = 0; r < nr; ++r) {
-                if ((int64_t)hrow[r] >= n) {
+                if ((int64_t)dirty[r] >= n) {
                     release();
                     return fail(AQR_ERR_STATE, "aqr_build_batched: row id out of range");
                 }
-                std::memcpy(&hdat[(size_t)r * W], &g->adj0[(size_t)hrow[r] * W], sizeof(uint32_t) * W);
+                hrow[r] = dirty[r];
             }
-            if ((e = hipMemcpy(rowd, hrow.data(), (size_t)nr * 4, hipMemcpyHostToDevice)) != hipSuccess ||
-                (e = hipMemcpy(datd, hdat.data(), (size_t)nr * W * 4, hipMemcpyHostToDevice)) != hipSuccess) {
+            // gather the changed rows into the staging buffer, in parallel
+            const int TG = (int)std::max<int64_t>(1, std::min<int64_t>(T, nr / 4096));
+            const uint32_t* adj = g->adj0.data();
+            parallel_for_threads(TG, [&](int t) {
+                const int32_t r0 = (int32_t)((int64_t)nr * t / TG);
+                const int32_t r1 = (int32_t)((int64_t)nr * (t + 1) / TG);
+                for (int32_t r = r0; r < r1; ++r)
+                    std::memcpy(&hdat[(size_t)r * W], &adj[(size_t)hrow[r] * W],
+                                sizeof(uint32_t) * W);
+            });
+            if ((e = hipMemcpy(rowd, hrow, (size_t)nr * 4, hipMemcpyHostToDevice)) != hipSuccess ||
+                (e = hipMemcpy(datd, hdat, (size_t)nr * W * 4, hipMemcpyHostToDevice)) != hipSuccess) {
                 release();
                 return hip_fail(e, "aqr_build_batched: copy");
             }
