@@ -129,15 +129,21 @@ def recall_at(ids, X, Q, gt_ids, gt_d, k=10):
 
 
 # Re-rank settings swept after ef, cheapest first: Table 3's "0.97+" row, the
-# upper ends of the ranges of the sensitivity analysis (Section 4.4), and early
-# termination switched off with growing exact re-rank depth.
+# upper ends of the ranges of the sensitivity analysis (Section 4.4), early
+# termination switched off with growing exact re-rank depth, and then a longer
+# candidate list A (N_c = ef/2 instead of ef/3).  Fields: name, N_rerank,
+# tau_gap, tau_ratio, m_ef (N_c = clamp(floor(ef_eff / m_ef), k, ef_eff)).
 RERANK_CONFIGS = [
-    ("table3", 28, 0.010, 1.008),
-    ("sec4.4", 28, 0.03, 1.02),
-    ("no-et", 28, float("inf"), float("inf")),
-    ("no-et-50", 50, float("inf"), float("inf")),
-    ("no-et-100", 100, float("inf"), float("inf")),
+    ("table3", 28, 0.010, 1.008, 3),
+    ("sec4.4", 28, 0.03, 1.02, 3),
+    ("no-et", 28, float("inf"), float("inf"), 3),
+    ("no-et-50", 50, float("inf"), float("inf"), 3),
+    ("no-et-100", 100, float("inf"), float("inf"), 3),
+    ("no-et-50-nc2", 50, float("inf"), float("inf"), 2),
+    ("no-et-100-nc2", 100, float("inf"), float("inf"), 2),
 ]
+# the serving calibration keeps N_c = ef/3: its server and batch plans use m_ef 3
+RERANK_CONFIGS_M3 = [c for c in RERANK_CONFIGS if c[4] == 3]
 
 
 ASSEMBLY = 0  # re-rank assembly: 0 fill (default reading), 1 union (--assembly union)
@@ -150,8 +156,8 @@ class AqrRunner:
         self.torch = torch
         self.aqr = aqr
         self.rerank = rerank
-        _, nrr, tg, tr = rerank
-        self.plan = aqr.QueryPlan(ix, nq, k, max(ef, k), visited_log2=visited_log2,
+        _, nrr, tg, tr, m_ef = rerank
+        self.plan = aqr.QueryPlan(ix, nq, k, max(ef, k), m_ef=m_ef, visited_log2=visited_log2,
                                   waves_per_block=waves_per_block, n_rerank=nrr, tau_gap=tg,
                                   tau_ratio=tr, assembly=ASSEMBLY)
         self.k = torch.full((nq,), k, dtype=torch.int32, device=device)
@@ -304,7 +310,7 @@ def bench_batched(args, torch, aqr, W, wl, dev, threads):
     kd = torch.from_numpy(kq).to(dev)
     efd = torch.from_numpy(efq).to(dev)
     cfg = rerank_by_name(args.rerank or "table3")
-    _, nrr, tg, tr = cfg
+    _, nrr, tg, tr, _ = cfg
 
     S = min(nq, args.tune_sample)
     log(f"autotune on {S} queries")
@@ -488,7 +494,7 @@ def bench_serving(args, torch, aqr, W, wl, dev, threads):
                                                                    512]
     pick, sweep = None, []
     for ef in efs:
-        for cfg in RERANK_CONFIGS:
+        for cfg in RERANK_CONFIGS_M3:
             r = AqrRunner(aqr, ix, C, 10, ef, dev, rerank=cfg)
             ids, _ = r.step(Qd[:C])
             torch.cuda.synchronize()
@@ -505,7 +511,7 @@ def bench_serving(args, torch, aqr, W, wl, dev, threads):
         pick = (best[0], rerank_by_name(best[1]))
     ef98, cfg = pick
     rec98 = next(r for e, c, r in sweep if e == ef98 and c == cfg[0])
-    _, nrr, tg, tr = cfg
+    _, nrr, tg, tr, _ = cfg
     streams = {
         "fixed": (np.full(nq, 10, np.int32), np.full(nq, ef98, np.int32)),
         "mixed": (kq, efq),
@@ -973,7 +979,7 @@ def main():
     d_pad = info["d_pad"]
     s0 = (2 * ginfo["M"] + 15) // 16 * 16
     s1 = (ginfo["M"] + 15) // 16 * 16
-    nc = min(max(max(ef_a, k) // 3, k), max(ef_a, k))
+    nc = min(max(max(ef_a, k) // aqr_pick[2][4], k), max(ef_a, k))
     # algorithmic bytes of one search launch (distinct evaluations)
     code_bytes = int((cnt_big[:, 1].sum() + cnt_big[:, 2].sum() + nq) * d_pad)
     adj_bytes = int(cnt_big[:, 0].sum() * s0 * 4 + cnt_big[:, 4].sum() * s1 * 4)
@@ -1080,8 +1086,9 @@ def main():
         index = dict(X=X, codes=codes, d=d, min=info["min"], scale=info["scale"], graph=gx)
         log(f"CPU oracle on {S} queries with {orc.get_threads()} threads")
         t = time.perf_counter()
-        _, nrr_, tg_, tr_ = aqr_pick[2]
-        ref = orc.query(index, Q[:S], k, ef_a, n_rerank=nrr_, tau_gap=tg_, tau_ratio=tr_,
+        _, nrr_, tg_, tr_, mef_ = aqr_pick[2]
+        ref = orc.query(index, Q[:S], k, ef_a, m_ef=mef_, n_rerank=nrr_, tau_gap=tg_,
+                        tau_ratio=tr_,
                         assembly=ASSEMBLY)
         dt = time.perf_counter() - t
         cpu = {"value": round(S / dt, 1), "unit": "queries/s", "cores": orc.get_threads(),
@@ -1092,7 +1099,7 @@ def main():
         S1 = max(1, S // 10)
         orc.set_threads(1)
         t = time.perf_counter()
-        orc.query(index, Q[:S1], k, ef_a, n_rerank=nrr_, tau_gap=tg_, tau_ratio=tr_,
+        orc.query(index, Q[:S1], k, ef_a, m_ef=mef_, n_rerank=nrr_, tau_gap=tg_, tau_ratio=tr_,
                   assembly=ASSEMBLY)
         cpu["one_thread_value"] = round(S1 / (time.perf_counter() - t), 1)
         orc.set_threads(threads)
@@ -1131,7 +1138,7 @@ def main():
             "M_i": ginfo["M"],
             "graph_build": ("batched, device searches; quantiser density on the device"
                             if args.gpu_build else "host"),
-            "delta": round(info["delta"], 6), "m_ef": 3,
+            "delta": round(info["delta"], 6), "m_ef": aqr_pick[2][4],
             "rerank": aqr_pick[2][0], "n_rerank": aqr_pick[2][1],
             "assembly": "union" if ASSEMBLY else "fill",
             "tau_gap": finite_or_none(aqr_pick[2][2]),

@@ -53,7 +53,7 @@ def small(orc):
 
 
 def run_stage1(index, Q, k, ef, nc=None, ef_max=None, out_stride=None, tap_cap=0, vb=0,
-               order=None, waves_per_block=0, blocks=0):
+               order=None, waves_per_block=0, blocks=0, m_ef=3):
     torch = _torch()
     from paper_2602_21600_amd import aqr
     nq = Q.shape[0]
@@ -64,7 +64,7 @@ def run_stage1(index, Q, k, ef, nc=None, ef_max=None, out_stride=None, tap_cap=0
         ef_max = int(efe.max())
     if out_stride is None:
         out_stride = int(nc.max()) if nc is not None else int(
-            np.minimum(np.maximum(efe // 3, k), efe).max())
+            np.minimum(np.maximum(efe // m_ef, k), efe).max())
     dev = "cuda"
     Qd = torch.from_numpy(np.ascontiguousarray(Q, np.float32)).to(dev)
     kd = torch.from_numpy(k).to(dev)
@@ -82,8 +82,8 @@ def run_stage1(index, Q, k, ef, nc=None, ef_max=None, out_stride=None, tap_cap=0
                     counts=torch.zeros((nq, 8), dtype=torch.int32, device=dev))
     od = None if order is None else torch.from_numpy(np.ascontiguousarray(order, np.int32)).to(dev)
     aqr.aqr_search(index["ix"], Qd, kd, efd, cid, cD, cnt, ws, ef_max, out_stride, nc=ncd,
-                   visited_log2=vb, taps=taps, order=od, waves_per_block=waves_per_block,
-                   blocks=blocks)
+                   m_ef=m_ef, visited_log2=vb, taps=taps, order=od,
+                   waves_per_block=waves_per_block, blocks=blocks)
     torch.cuda.synchronize()
     res = dict(cand_id=cid.cpu().numpy().view(np.uint32), cand_D=cD.cpu().numpy().view(np.uint32),
                cand_cnt=cnt.cpu().numpy(), Qd=Qd, kd=kd, cid_d=cid, cnt_d=cnt)
@@ -92,14 +92,14 @@ def run_stage1(index, Q, k, ef, nc=None, ef_max=None, out_stride=None, tap_cap=0
     return res
 
 
-def oracle_stage1(orc, index, Q, k, ef, nc=None, tap_cap=0):
+def oracle_stage1(orc, index, Q, k, ef, nc=None, tap_cap=0, m_ef=3):
     nq = Q.shape[0]
     k = np.broadcast_to(np.asarray(k, np.int32), (nq,))
     ef = np.broadcast_to(np.asarray(ef, np.int32), (nq,))
     efe = np.zeros(nq, np.int32)
     ncc = np.zeros(nq, np.int32)
     for i in range(nq):
-        efe[i], ncc[i] = orc.param_map(int(k[i]), int(ef[i]), 3)
+        efe[i], ncc[i] = orc.param_map(int(k[i]), int(ef[i]), m_ef)
     if nc is not None:
         ncc = np.asarray(nc, np.int32)
     qc = orc.encode(Q, index["min"], index["scale"], stride=index["codes"].shape[1])
@@ -149,6 +149,25 @@ def test_stage1_bit_exact_small(orc, small, ef):
         assert ge < cap
         gset = set(g["evaluated"][q, :ge].tolist()) | {int(o["expanded"][q, 0])}
         assert gset == set(o["visited"][q, :nv].tolist())
+
+
+@pytest.mark.parametrize("m_ef", [1, 2, 5])
+def test_stage1_candidate_count_mapping(orc, small, m_ef):
+    # N_c = clamp(floor(ef_eff / m_ef), k, ef_eff) derived on the device for
+    # other ratios than 3, with mixed k and ef; then Stages 2-3 on the longer
+    # (or shorter) candidate lists
+    Q = small["Q"][:300]
+    nq = Q.shape[0]
+    rng = np.random.default_rng(m_ef)
+    k = rng.choice([1, 10, 50], nq).astype(np.int32)
+    ef = rng.choice([16, 100, 288], nq).astype(np.int32)
+    g = run_stage1(small, Q, k, ef, ef_max=288, m_ef=m_ef)
+    o, _ = oracle_stage1(orc, small, Q, k, ef, m_ef=m_ef)
+    compare_stage1(g, o, nq)
+    k10 = np.full(nq, 10, np.int32)
+    g = run_stage1(small, Q, k10, 288, m_ef=m_ef)
+    gr = _rerank_gpu(small, g, 10, force_et=0, n_rerank=50)
+    check_rerank(orc, small, Q, g, 10, gr, force_et=0, n_rerank=50)
 
 
 def test_stage1_forgetful_cache_is_exact(orc, small):
