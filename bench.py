@@ -881,7 +881,7 @@ def main():
     # the workload's ef list, then finer steps above it, so the cheapest ef that
     # reaches the recall target is found for both searches alike
     efs = ([int(e) for e in args.efs.split(",")] if args.efs else
-           sorted(set(wl.ef) | {288, 320, 352, 384, 448, 512}))
+           sorted(set(wl.ef) | {288, 304, 320, 352, 384, 448, 512}))
 
     def recall_of(ids):
         return recall_at(ids.cpu().numpy(), X, Q, gt_ids, gt_d, k)
