@@ -27,6 +27,8 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
+from paper_2602_21600_amd import presets as PRESETS  # noqa: E402  (Table 3 rows, no torch)
+
 HBM_PEAK_GBS = 8000.0
 TARGET_RECALL = 0.98
 # further points of the recall-QPS curve, each timed like the headline point
@@ -128,12 +130,15 @@ def recall_at(ids, X, Q, gt_ids, gt_d, k=10):
     return float(recall_per_query(ids, X, Q, gt_ids, gt_d, k).mean())
 
 
-# Re-rank settings swept after ef, cheapest first: Table 3's "0.97+" row, the
-# upper ends of the ranges of the sensitivity analysis (Section 4.4), early
-# termination switched off with growing exact re-rank depth, and then a longer
-# candidate list A (N_c = ef/2 instead of ef/3).  Fields: name, N_rerank,
-# tau_gap, tau_ratio, m_ef (N_c = clamp(floor(ef_eff / m_ef), k, ef_eff)).
+# Re-rank settings swept after ef, cheapest first: the rows of Table 3 below
+# "0.97+", its "0.97+" row, the upper ends of the ranges of the sensitivity
+# analysis (Section 4.4), early termination switched off with growing exact
+# re-rank depth, and then a longer candidate list A (N_c = ef/2 instead of
+# ef/3).  Fields: name, N_rerank, tau_gap, tau_ratio, m_ef
+# (N_c = clamp(floor(ef_eff / m_ef), k, ef_eff)).
 RERANK_CONFIGS = [
+    *((f"table3-{lo:.2f}", nrr, gap, ratio, mef)
+      for lo, _, nrr, gap, ratio, mef in PRESETS.TABLE3[:-1]),
     ("table3", 28, 0.010, 1.008, 3),
     ("sec4.4", 28, 0.03, 1.02, 3),
     ("no-et", 28, float("inf"), float("inf"), 3),

@@ -252,3 +252,19 @@ def test_rerank_from_supplied_order(orc):
                     a_order=np.array([[2, 0, 1]], np.uint32))
     assert rr["id"][0].tolist() == [2]
     assert rr["dist"][0].tolist() == [900.0]
+
+
+def test_library_presets_match_table3(orc):
+    from paper_2602_21600_amd import presets
+    spec = json.load(open(os.path.join(GOLDEN, "table3_presets.json")))
+    assert len(presets.TABLE3) == len(spec["rows"])
+    for row, (lo, nc, rr, gap, ratio, mult) in zip(spec["rows"], presets.TABLE3):
+        assert float(row[0].split("-")[0].rstrip("+")) == lo
+        assert (row[1], row[2], row[3], row[4], row[5]) == (nc, rr, gap, ratio, mult)
+    for t, first in ((0.80, 0.85), (0.87, 0.85), (0.90, 0.90), (0.93, 0.90), (0.96, 0.95),
+                     (0.98, 0.97), (0.999, 0.97)):
+        p = presets.table3(t)
+        row = next(r for r in presets.TABLE3 if r[0] == first)
+        assert (p["nc"], p["n_rerank"], p["m_ef"]) == (row[1], row[2], row[5])
+        # the search width of the row maps back to its N_c (Section 3.2)
+        assert orc.param_map(10, p["ef"], p["m_ef"]) == (p["ef"], p["nc"])
