@@ -19,9 +19,12 @@
  *     the calling thread.  No C++ exception crosses this interface and the
  *     library never aborts.
  *   - Host pointers are read during the call only.  Device pointers are
- *     allocated and owned by the caller; the library allocates no device
- *     memory.  Handles (aqr_quantizer, aqr_graph, aqr_index) are created and
- *     freed by the library.
+ *     allocated and owned by the caller; the query path allocates no device
+ *     memory (only the build-time calls aqr_build_batched,
+ *     aqr_quantize_device and aqr_density with device != 0 allocate device
+ *     memory of their own, and free it before they return).  Handles
+ *     (aqr_quantizer, aqr_graph, aqr_index) are created and freed by the
+ *     library.
  *   - Device calls are asynchronous on the given stream (a hipStream_t passed
  *     as void*, NULL = default stream).  Arguments are validated on the host
  *     before any launch; a device fault surfaces at the caller's next
@@ -72,6 +75,11 @@ typedef struct aqr_qparams {
     double p_max;             /* maximum percentile width P_max, fraction (0.01) */
     int32_t M0;               /* base connectivity M_0 */
     int32_t efc0;             /* base construction depth ef_0 */
+    int32_t weights;          /* density weights w_j of Alg. 1 (Eq. 1, eta): 0 = the
+                                 printed formula, every w_j the mean density, so
+                                 eta = 0; 1 = per-dimension weights, w_j the mean
+                                 one-dimensional k_rho-NN density along dimension j
+                                 over the measured points (eta > 0) */
 } aqr_qparams;
 
 typedef struct aqr_qinfo {

@@ -252,6 +252,64 @@ double orc_percentile_sorted(const double* v, int64_t n, double p) {
 }
 
 /*
+ * Per-dimension density weights: the reading of Algorithm 1's w_j in which
+ * each dimension has a density of its own.  For dimension j, point i has the
+ * one-dimensional density rho_i^(j) = 1 / (mean of the k smallest squared
+ * differences (x_ij - x_lj)^2 over the other points l + eps), k as in
+ * orc_density; w_j is the mean of rho_i^(j) over the measured points (all n,
+ * or the sample of orc_density when n > threshold), summed in point order.
+ * Each point's k smallest values are summed in ascending order.
+ * Brute force over all pairs.  Returns 0, or -1 on bad arguments.
+ */
+int32_t orc_dim_weights(const float* X, int64_t n, int32_t d, int32_t k_rho, double eps,
+                        int64_t n_s, int64_t threshold, double* w) {
+    if (!X || !w || n < 1 || d < 1 || k_rho < 1 || k_rho > 64 || n_s < 1) return -1;
+    int64_t ns = n_s < n ? n_s : n;
+    int sampled = n > threshold;
+    int64_t m = sampled ? ns : n;
+    int32_t k = (int64_t)k_rho < n - 1 ? k_rho : (int32_t)(n - 1);
+#pragma omp parallel for schedule(dynamic, 1)
+    for (int32_t j = 0; j < d; j++) {
+        double sum = 0.0;
+        for (int64_t s = 0; s < m; s++) {
+            int64_t i = sampled ? (int64_t)((s * n) / ns) : s;
+            double best[64];
+            int32_t cnt = 0;
+            double xi = (double)X[i * d + j];
+            for (int64_t l = 0; l < n; l++) {
+                if (l == i) continue;
+                double t = xi - (double)X[l * d + j];
+                double v = t * t;
+                if (cnt < k) {
+                    int32_t p = cnt++;
+                    while (p > 0 && best[p - 1] > v) {
+                        best[p] = best[p - 1];
+                        p--;
+                    }
+                    best[p] = v;
+                } else if (k > 0 && v < best[k - 1]) {
+                    int32_t p = k - 1;
+                    while (p > 0 && best[p - 1] > v) {
+                        best[p] = best[p - 1];
+                        p--;
+                    }
+                    best[p] = v;
+                }
+            }
+            double mean = 0.0;
+            if (k > 0) {
+                double acc = 0.0;
+                for (int32_t t = 0; t < k; t++) acc += best[t];
+                mean = acc / (double)k;
+            }
+            sum += 1.0 / (mean + eps);
+        }
+        w[j] = sum / (double)m;
+    }
+    return 0;
+}
+
+/*
  * Quantiser training (Alg. 1, Stage 2).
  *   p_lo = delta*p_max, p_hi = 1 - delta*p_max (fractions)
  *   min_j, max_j = FP32 rounding of the p_lo / p_hi percentiles of column j
@@ -260,10 +318,12 @@ double orc_percentile_sorted(const double* v, int64_t n, double p) {
  *   s_dist = sqrt( sum_j (max_j-min_j)^2 w_j / sum_j 255^2 w_j )   (Eq. 1)
  *   eta = sigma_w / mean_w (mean taken as w_0 + mean of (w_j - w_0))
  * scalars_out: [delta, p_lo, p_hi, s_dist, eta, w_mean]
+ * w_in (d doubles) gives the weights of the per-dimension reading
+ * (orc_dim_weights); NULL takes the literal reading above.
  */
 int32_t orc_train_ranges(const float* X, int64_t n, int32_t d, const double* rho, double eps,
                          double p_max, float* mn, float* mx, float* scale,
-                         double* scalars_out) {
+                         double* scalars_out, const double* w_in) {
     if (!X || !rho || !mn || !mx || !scale || !scalars_out || n < 1 || d < 1) return -1;
     double delta = orc_delta(rho, n, eps);
     double p_lo = delta * p_max;
@@ -291,7 +351,7 @@ int32_t orc_train_ranges(const float* X, int64_t n, int32_t d, const double* rho
     for (int64_t i = 0; i < n; i++) rsum += rho[i];
     double* w = (double*)malloc((size_t)d * sizeof(double));
     if (!w) return -1;
-    for (int32_t j = 0; j < d; j++) w[j] = rsum / (double)n;
+    for (int32_t j = 0; j < d; j++) w[j] = w_in ? w_in[j] : rsum / (double)n;
     double shift = 0.0;
     for (int32_t j = 0; j < d; j++) shift += w[j] - w[0];
     double wbar = w[0] + shift / (double)d;

@@ -47,8 +47,10 @@ def _load():
     lib.orc_percentile_sorted.argtypes = [_f64p, _i64, _f64]
     lib.orc_percentile_sorted.restype = _f64
     lib.orc_train_ranges.argtypes = [_f32p, _i64, _i32, _f64p, _f64, _f64, _f32p, _f32p, _f32p,
-                                     _f64p]
+                                     _f64p, C.c_void_p]
     lib.orc_train_ranges.restype = _i32
+    lib.orc_dim_weights.argtypes = [_f32p, _i64, _i32, _i32, _f64, _i64, _i64, _f64p]
+    lib.orc_dim_weights.restype = _i32
     lib.orc_build_params.argtypes = [_i32, _i32, _f64, _f64, _i32p]
     lib.orc_encode.argtypes = [_f32p, _i64, _i32, _f32p, _f32p, _u8p, _i32]
     lib.orc_encode.restype = _i32
@@ -128,22 +130,36 @@ def build_params(M0, efc0, delta_, eta):
     return int(out[0]), int(out[1])
 
 
+def dim_weights(X, k_rho=10, eps=1e-6, n_s=5000, threshold=10000):
+    """Per-dimension density weights w_j (the per-dimension reading of
+    Algorithm 1's w_j): mean one-dimensional k_rho-NN density along j."""
+    X = np.ascontiguousarray(X, np.float32)
+    n, d = X.shape
+    w = np.zeros(d, np.float64)
+    _check(_load().orc_dim_weights(X, n, d, k_rho, eps, n_s, threshold, w), "dim_weights")
+    return w
+
+
 def train(X, p_max=0.01, M0=16, efc0=200, k_rho=10, eps=1e-6, n_s=5000, threshold=10000,
-          rho=None):
-    """Alg. 1 stages 1-2 plus the build parameters.  Returns a dict."""
+          rho=None, weights=0):
+    """Alg. 1 stages 1-2 plus the build parameters.  Returns a dict.
+    weights 0: every w_j is the mean density (the literal reading);
+    1: per-dimension weights (dim_weights)."""
     X = np.ascontiguousarray(X, np.float32)
     n, d = X.shape
     if rho is None:
         rho = density(X, k_rho, eps, n_s, threshold)
+    w = dim_weights(X, k_rho, eps, n_s, threshold) if weights == 1 else None
     mn = np.zeros(d, np.float32)
     mx = np.zeros(d, np.float32)
     sc = np.zeros(d, np.float32)
     s = np.zeros(6, np.float64)
-    _check(_load().orc_train_ranges(X, n, d, rho, eps, p_max, mn, mx, sc, s), "train_ranges")
+    _check(_load().orc_train_ranges(X, n, d, rho, eps, p_max, mn, mx, sc, s,
+                                    None if w is None else w.ctypes.data), "train_ranges")
     M_i, efc = build_params(M0, efc0, s[0], s[4])
     return dict(rho=rho, delta=float(s[0]), p_lo=float(s[1]), p_hi=float(s[2]),
                 s_dist=float(s[3]), eta=float(s[4]), w_mean=float(s[5]), min=mn, max=mx,
-                scale=sc, M=M_i, efc=efc, d=d, p_max=p_max)
+                scale=sc, M=M_i, efc=efc, d=d, p_max=p_max, w=w)
 
 
 def encode(X, mn, scale, stride=None):

@@ -27,7 +27,7 @@ class AqrError(RuntimeError):
 class QParams(C.Structure):
     _fields_ = [("k_rho", C.c_int32), ("threads", C.c_int32), ("n_sample", C.c_int64),
                 ("sample_threshold", C.c_int64), ("eps", C.c_double), ("p_max", C.c_double),
-                ("M0", C.c_int32), ("efc0", C.c_int32)]
+                ("M0", C.c_int32), ("efc0", C.c_int32), ("weights", C.c_int32)]
 
 
 class QInfo(C.Structure):
@@ -238,9 +238,9 @@ def aqr_version():
     return int(lib().aqr_version())
 
 
-def default_qparams(M0=16, efc0=200, p_max=0.01, threads=0):
+def default_qparams(M0=16, efc0=200, p_max=0.01, threads=0, weights=0):
     return dict(k_rho=10, threads=threads, n_sample=5000, sample_threshold=10000, eps=1e-6,
-                p_max=p_max, M0=M0, efc0=efc0)
+                p_max=p_max, M0=M0, efc0=efc0, weights=weights)
 
 
 def aqr_quantize(X, params=None, qz=None, codes=True, device=False):

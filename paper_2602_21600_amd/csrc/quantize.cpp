@@ -11,13 +11,16 @@
 // linear-interpolation percentiles of column j (order statistics at
 // h = p*(n-1), interpolated in FP64, rounded to FP32); scale_j =
 // 255 / ((max_j - min_j) + eps) in FP32.  The density weights w_j are the
-// mean density for every j, Eq. 1 gives s_dist, eta = sigma_w / mean_w.
+// mean density for every j (the printed formula), or with weights = 1 the
+// mean one-dimensional density along j; Eq. 1 gives s_dist,
+// eta = sigma_w / mean_w.
 // Build parameters M_i = floor(M_0 (1 + delta (1 + eta))) and
 // ef^c = floor(ef_0 / (1 + delta eta)).
 #include <algorithm>
 #include <atomic>
 #include <cmath>
 #include <cstring>
+#include <limits>
 #include <new>
 
 #include "internal.hpp"
@@ -121,6 +124,58 @@ aqr_status densities(const float* X, int64_t n, int32_t d, const aqr_qparams& p,
     return AQR_OK;
 }
 
+// Per-dimension weights (aqr_qparams.weights = 1): w_j = mean over the
+// measured points of 1 / (mean of the k smallest squared differences to the
+// other values of column j + eps).  Each column is sorted once; a point's k
+// nearest values are then the nearer of the two sides, taken outward from
+// one copy of its own value, so they arrive in ascending order and are
+// summed in that order.
+aqr_status dim_weights(const float* X, int64_t n, int32_t d, const aqr_qparams& p, int T,
+                       std::vector<double>& w) {
+    const int64_t ns = std::min<int64_t>(p.n_sample, n);
+    const bool sampled = n > p.sample_threshold;
+    const int64_t m = sampled ? ns : n;
+    const int k = (int)std::min<int64_t>(p.k_rho, n - 1);
+    if (p.k_rho > 64) return fail(AQR_ERR_INVALID_ARG, "aqr_quantize: k_rho must be <= 64");
+    w.assign(d, 0.0);
+    const double inf = std::numeric_limits<double>::infinity();
+    std::atomic<int32_t> next{0};
+    parallel_for_threads(std::max(1, std::min<int>(T, d)), [&](int) {
+        std::vector<double> col(n);
+        for (;;) {
+            const int32_t j = next.fetch_add(1);
+            if (j >= d) break;
+            for (int64_t i = 0; i < n; ++i) col[i] = (double)X[i * d + j];
+            std::sort(col.begin(), col.end());
+            double sum = 0.0;
+            for (int64_t s = 0; s < m; ++s) {
+                const int64_t i = sampled ? (s * n) / ns : s;
+                const double v = (double)X[i * d + j];
+                const int64_t at = std::lower_bound(col.begin(), col.end(), v) - col.begin();
+                int64_t lo = at - 1, hi = at + 1;
+                double acc = 0.0;
+                for (int u = 0; u < k; ++u) {
+                    const double tl = lo >= 0 ? v - col[lo] : 0.0;
+                    const double th = hi < n ? col[hi] - v : 0.0;
+                    const double dl = lo >= 0 ? tl * tl : inf;
+                    const double dh = hi < n ? th * th : inf;
+                    if (dl <= dh) {
+                        acc += dl;
+                        --lo;
+                    } else {
+                        acc += dh;
+                        ++hi;
+                    }
+                }
+                const double mean = k > 0 ? acc / (double)k : 0.0;
+                sum += 1.0 / (mean + p.eps);
+            }
+            w[j] = sum / (double)m;
+        }
+    });
+    return AQR_OK;
+}
+
 // Linear-interpolation percentile from the two order statistics around h.
 double percentile_of(std::vector<double>& col, double p) {
     const int64_t n = (int64_t)col.size();
@@ -196,10 +251,16 @@ aqr_status train(const float* X, int64_t n, int32_t d, const aqr_qparams& p, int
             q.scale[j] = 255.0f / denom;
         }
     });
-    // density weights: the mean density for every dimension
-    double rsum = 0.0;
-    for (int64_t i = 0; i < n; ++i) rsum += rho[i];
-    std::vector<double> w(d, rsum / (double)n);
+    // density weights: the mean density for every dimension, or per dimension
+    std::vector<double> w;
+    if (p.weights == 1) {
+        st = dim_weights(X, n, d, p, T, w);
+        if (st != AQR_OK) return st;
+    } else {
+        double rsum = 0.0;
+        for (int64_t i = 0; i < n; ++i) rsum += rho[i];
+        w.assign(d, rsum / (double)n);
+    }
     double shift = 0.0;
     for (int32_t j = 0; j < d; ++j) shift += w[j] - w[0];
     const double wbar = w[0] + shift / (double)d;
@@ -248,7 +309,8 @@ aqr_status quantize(const float* X, int64_t n, int32_t d, const aqr_qparams* p,
         if (!q) {
             if (!p) return fail(AQR_ERR_INVALID_ARG, w + ": params required to train");
             if (p->k_rho < 1 || p->n_sample < 1 || !(p->eps > 0) || p->p_max < 0 ||
-                p->p_max > 0.5 || p->M0 < 2 || p->efc0 < 1)
+                p->p_max > 0.5 || p->M0 < 2 || p->efc0 < 1 || p->weights < 0 ||
+                p->weights > 1)
                 return fail(AQR_ERR_INVALID_ARG, w + ": parameter out of range");
             q = new aqr_quantizer();
             created = true;

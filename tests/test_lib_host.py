@@ -105,6 +105,30 @@ def test_density_rejects_bad_parameters():
             aqr.aqr_density(X, p)
 
 
+@pytest.mark.parametrize("n,d,threshold", [(2000, 12, 10000), (3000, 20, 1000), (900, 37, 10000)])
+def test_quantize_per_dimension_weights_match_oracle(orc, n, d, threshold):
+    # the per-dimension reading of w_j: eta > 0, and with it M_i, ef^c and
+    # s_dist, identical to the oracle's; the codes do not depend on w_j
+    X, _ = W.tiny(n, d, seed=n, clusters=5)
+    X[100:140] = X[5]
+    p = aqr.default_qparams(weights=1)
+    p.update(sample_threshold=threshold, n_sample=500)
+    qz, codes = aqr.aqr_quantize(X, p)
+    a = aqr.aqr_quantizer_info(qz)
+    r = orc.train(X, weights=1, n_s=500, threshold=threshold)
+    assert a["eta"] == r["eta"] and a["eta"] > 0.0
+    assert (a["s_dist"], a["w_mean"], a["M"], a["efc"]) == (r["s_dist"], r["w_mean"], r["M"],
+                                                            r["efc"])
+    assert a["M"] > orc.train(X, n_s=500, threshold=threshold)["M"]
+    np.testing.assert_array_equal(codes, orc.encode(X, r["min"], r["scale"], stride=a["d_pad"]))
+
+
+def test_quantize_rejects_unknown_weights():
+    X = np.random.default_rng(0).standard_normal((50, 4)).astype(np.float32)
+    with pytest.raises(aqr.AqrError):
+        aqr.aqr_quantize(X, aqr.default_qparams(weights=2))
+
+
 def test_quantize_encode_only(orc):
     X, Y = W.tiny(800, 16, seed=2, nq=50)
     qz, codes = aqr.aqr_quantize(X, aqr.default_qparams())

@@ -176,3 +176,76 @@ def test_encode_pads_stride_with_zeros(orc):
     codes = orc.encode(X, np.zeros(5, np.float32), np.full(5, 10.0, np.float32), stride=16)
     assert codes.shape == (3, 16)
     assert np.all(codes[:, :5] == 10) and np.all(codes[:, 5:] == 0)
+
+
+# ---- per-dimension density weights (the per-dimension reading of w_j) ----
+
+def _spaced_columns(n, steps, seed):
+    """Column j holds 0, a_j, 2 a_j, ... (exact in FP32), rows shuffled."""
+    rng = np.random.default_rng(seed)
+    X = np.stack([np.arange(n, dtype=np.float64) * a for a in steps], 1).astype(np.float32)
+    return X[rng.permutation(n)]
+
+
+@pytest.mark.parametrize("k", [2, 4])
+def test_dim_weights_evenly_spaced_closed_form(orc, k):
+    # on an evenly spaced column with step a, an inner point's k nearest
+    # squared differences are a^2 {1,1,4,4,...}; the two points at each end
+    # have one-sided neighbourhoods
+    n, eps = 400, 1e-6
+    steps = [0.5, 1.0, 2.0, 4.0]
+    X = _spaced_columns(n, steps, seed=k)
+    w = orc.dim_weights(X, k_rho=k, eps=eps)
+    for j, a in enumerate(steps):
+        a2 = a * a
+        if k == 2:
+            inner = 1.0 / (a2 + eps)
+            ends = 2 * [1.0 / (2.5 * a2 + eps)]
+            n_inner = n - 2
+        else:
+            inner = 1.0 / (2.5 * a2 + eps)
+            ends = 2 * [1.0 / (3.75 * a2 + eps), 1.0 / (7.5 * a2 + eps)]
+            n_inner = n - 4
+        want = (n_inner * inner + sum(ends)) / n
+        np.testing.assert_allclose(w[j], want, rtol=1e-12)
+    # the weights differ across dimensions, so eta > 0 and follows from them
+    tr = orc.train(X, M0=16, efc0=200, k_rho=k, weights=1)
+    np.testing.assert_array_equal(tr["w"], w)
+    np.testing.assert_allclose(tr["eta"], np.std(w) / np.mean(w), rtol=1e-12)
+    rng_ = tr["max"].astype(np.float64) - tr["min"].astype(np.float64)
+    np.testing.assert_allclose(tr["s_dist"], np.sqrt(np.sum(rng_ ** 2 * w) / np.sum(255.0 ** 2 * w)),
+                               rtol=1e-12)
+    assert tr["M"] == int(np.floor(16 * (1.0 + tr["delta"] * (1.0 + tr["eta"]))))
+    assert tr["efc"] == int(np.floor(200 / (1.0 + tr["delta"] * tr["eta"])))
+
+
+def test_dim_weights_match_bruteforce_with_sampling_and_ties(orc):
+    rng = np.random.default_rng(5)
+    n, d, k, eps = 90, 3, 5, 1e-6
+    X = rng.standard_normal((n, d)).astype(np.float32)
+    X[10:20, 1] = X[3, 1]  # ties at difference 0 in one column
+    for n_s, threshold in ((90, 1000), (25, 40)):
+        m = min(n_s, n)
+        S = [(s * n) // m for s in range(m)] if n > threshold else list(range(n))
+        want = []
+        for j in range(d):
+            col = X[:, j].astype(np.float64)
+            dens = []
+            for i in S:
+                diff = np.delete((col[i] - col) ** 2, i)
+                dens.append(1.0 / (np.sort(diff)[:k].mean() + eps))
+            want.append(np.mean(dens))
+        got = orc.dim_weights(X, k_rho=k, eps=eps, n_s=n_s, threshold=threshold)
+        np.testing.assert_allclose(got, want, rtol=1e-12)
+
+
+def test_dim_weights_equal_columns_give_zero_eta(orc):
+    # identical columns have identical weights: eta = 0 exactly, and the
+    # per-dimension reading then leaves M_i and ef^c as the literal one does
+    rng = np.random.default_rng(2)
+    c = rng.standard_normal(500).astype(np.float32)
+    X = np.stack([c, c, c, c], 1)
+    tr1 = orc.train(X, M0=16, efc0=200, weights=1)
+    tr0 = orc.train(X, M0=16, efc0=200)
+    assert tr1["eta"] == 0.0
+    assert (tr1["M"], tr1["efc"]) == (tr0["M"], tr0["efc"])
