@@ -152,6 +152,7 @@ RERANK_CONFIGS_M3 = [c for c in RERANK_CONFIGS if c[4] == 3]
 
 
 ASSEMBLY = 0  # re-rank assembly: 0 fill (default reading), 1 union (--assembly union)
+WEIGHTS = {"equal": 0, "per-dim": 1}  # aqr_qparams.weights (--weights)
 
 
 class AqrRunner:
@@ -662,7 +663,8 @@ def build_index(args, wl, X, threads):
             f"density on the {'GPU' if args.gpu_build else 'host'}")
         t = time.perf_counter()
         qz, codes = aqr.aqr_quantize(X, aqr.default_qparams(M0=wl.M0, efc0=wl.efc0,
-                                                            p_max=p_max, threads=threads),
+                                                            p_max=p_max, threads=threads,
+                                                            weights=WEIGHTS[args.weights]),
                                      device=args.gpu_build)
         t_quant = time.perf_counter() - t
         t = time.perf_counter()
@@ -825,6 +827,10 @@ def main():
                          "aqr_build) instead of with the density search and the batched "
                          "build's chunk searches on the GPU (aqr_quantize_device, "
                          "aqr_build_batched)")
+    ap.add_argument("--weights", choices=tuple(WEIGHTS), default="equal",
+                    help="density weights w_j of Eq. 1 and eta: 'equal' (the printed formula, "
+                         "eta = 0) or 'per-dim' (one-dimensional densities per dimension, "
+                         "eta > 0, which raises M_i and lowers ef^c)")
     ap.add_argument("--sq8", action="store_true",
                     help="plain 8-bit scalar quantisation (P_max = 0) and a plain HNSW graph at "
                          "M_0 and ef_0^c: the paper's scalar-quantisation baseline")
@@ -1138,9 +1144,12 @@ def main():
             "workload": f"{args.workload}: {n:,} x {d} FP32 L2, {wl.n_clusters}-cluster "
                         f"Gaussian mixture; {nq:,} queries; k={k}"
                         + ("; plain SQ8 baseline (P_max 0, graph at M_0)" if args.sq8 else "")
-                        + ("" if args.gpu_build else "; graph from the host build"),
+                        + ("" if args.gpu_build else "; graph from the host build")
+                        + ("; per-dimension density weights" if args.weights == "per-dim"
+                           else ""),
             "n": n, "d": d, "nq": nq, "k": k, "ef": ef_a, "M0": wl.M0, "efc0": wl.efc0,
-            "M_i": ginfo["M"],
+            "M_i": ginfo["M"], "efc": ginfo["efc"], "weights": args.weights,
+            "eta": round(info["eta"], 6),
             "graph_build": ("batched, device searches; quantiser density on the device"
                             if args.gpu_build else "host"),
             "delta": round(info["delta"], 6), "m_ef": aqr_pick[2][4],
