@@ -147,8 +147,6 @@ RERANK_CONFIGS = [
     ("no-et-50-nc2", 50, float("inf"), float("inf"), 2),
     ("no-et-100-nc2", 100, float("inf"), float("inf"), 2),
 ]
-# the serving calibration keeps N_c = ef/3: its server and batch plans use m_ef 3
-RERANK_CONFIGS_M3 = [c for c in RERANK_CONFIGS if c[4] == 3]
 
 
 ASSEMBLY = 0  # re-rank assembly: 0 fill (default reading), 1 union (--assembly union)
@@ -500,7 +498,7 @@ def bench_serving(args, torch, aqr, W, wl, dev, threads):
                                                                    512]
     pick, sweep = None, []
     for ef in efs:
-        for cfg in RERANK_CONFIGS_M3:
+        for cfg in RERANK_CONFIGS:
             r = AqrRunner(aqr, ix, C, 10, ef, dev, rerank=cfg)
             ids, _ = r.step(Qd[:C])
             torch.cuda.synchronize()
@@ -517,7 +515,7 @@ def bench_serving(args, torch, aqr, W, wl, dev, threads):
         pick = (best[0], rerank_by_name(best[1]))
     ef98, cfg = pick
     rec98 = next(r for e, c, r in sweep if e == ef98 and c == cfg[0])
-    _, nrr, tg, tr, _ = cfg
+    _, nrr, tg, tr, mef = cfg
     streams = {
         "fixed": (np.full(nq, 10, np.int32), np.full(nq, ef98, np.int32)),
         "mixed": (kq, efq),
@@ -525,8 +523,8 @@ def bench_serving(args, torch, aqr, W, wl, dev, threads):
     # batch capacity of each stream (same queries, one launch)
     batch_qps = {}
     for name, (ks, es) in streams.items():
-        plan = aqr.BatchPlan(ix, nq, k_max, ef_max, n_rerank=nrr, tau_gap=tg, tau_ratio=tr,
-                             use_graph=True)
+        plan = aqr.BatchPlan(ix, nq, k_max, ef_max, m_ef=mef, n_rerank=nrr, tau_gap=tg,
+                             tau_ratio=tr, use_graph=True)
         plan.load(Qd, torch.from_numpy(ks).to(dev), torch.from_numpy(es).to(dev))
         ms, _ = timed(torch, lambda m: plan.launch(nq), 3, 1)
         batch_qps[name] = nq / (ms / 1e3)
@@ -568,8 +566,8 @@ def bench_serving(args, torch, aqr, W, wl, dev, threads):
         "adjacency_bytes": adj_b, "io_bytes": io_b,
     }
 
-    sv = aqr.Server(ix, k_max, ef_max, ring=args.ring, n_rerank=nrr, tau_gap=tg, tau_ratio=tr,
-                    idle_ms=200, visited_log2=args.serve_vb)
+    sv = aqr.Server(ix, k_max, ef_max, ring=args.ring, m_ef=mef, n_rerank=nrr, tau_gap=tg,
+                    tau_ratio=tr, idle_ms=200, visited_log2=args.serve_vb)
     results = {}
     try:
         # warm up the server (kernel launch, caches)
@@ -618,7 +616,7 @@ def bench_serving(args, torch, aqr, W, wl, dev, threads):
             "graph_build": ("batched, device searches; quantiser density on the device"
                             if args.gpu_build else "host"),
             "delta": round(info["delta"], 6), "ef": ef98, "recall@10": rec98,
-            "rerank": cfg[0], "n_rerank": nrr,
+            "rerank": cfg[0], "n_rerank": nrr, "m_ef": mef,
             "tau_gap": finite_or_none(tg), "tau_ratio": finite_or_none(tr), "ring": args.ring, "k_max": k_max,
             "ef_max": ef_max, "parallelism": "single GPU, resident persistent server kernel",
         },

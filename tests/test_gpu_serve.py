@@ -137,3 +137,23 @@ def test_serve_replay_trace(small):
         check_row(ids[q], dist[q], ref, q)
     assert np.all(lat > 0) and wall >= arrivals[-1]
     assert np.all(svc > 0) and np.all(svc <= lat + 1e-3)
+
+
+def test_serve_longer_candidate_list_equals_batch(small):
+    # m_ef = 2 (N_c = ef/2): the server sizes its candidate lists by m_ef and
+    # must still return the batch path's rows for the same settings
+    from paper_2602_21600_amd import aqr
+    from test_gpu_batch import run_plan
+    Q, k, ef = small["Q"][:200], small["k"][:200], small["ef"][:200]
+    ref = run_plan(small, Q, k, ef, m_ef=2, n_rerank=50, tau_gap=float("inf"),
+                   tau_ratio=float("inf"))[0]
+    sv = aqr.Server(small["ix"], K_MAX, EF_MAX, ring=256, m_ef=2, n_rerank=50,
+                    tau_gap=float("inf"), tau_ratio=float("inf"))
+    try:
+        tickets = [sv.submit(Q[q], k[q], ef[q]) for q in range(Q.shape[0])]
+        assert all(t is not None for t in tickets)
+        for q, t in enumerate(tickets):
+            r = wait(sv, t)
+            check_row(r[0], r[1], ref, q)
+    finally:
+        sv.stop()
