@@ -176,17 +176,21 @@ aqr_status dim_weights(const float* X, int64_t n, int32_t d, const aqr_qparams& 
     return AQR_OK;
 }
 
-// Linear-interpolation percentile from the two order statistics around h.
-double percentile_of(std::vector<double>& col, double p) {
+// Linear-interpolation percentile from the two order statistics around h,
+// interpolated in FP64.  The column may hold the FP32 values themselves:
+// widening to FP64 is exact and keeps the order, so the order statistics
+// are the same.
+template <class T>
+double percentile_of(std::vector<T>& col, double p) {
     const int64_t n = (int64_t)col.size();
-    if (n == 1) return col[0];
+    if (n == 1) return (double)col[0];
     const double h = p * (double)(n - 1);
-    if (h <= 0.0) return *std::min_element(col.begin(), col.end());
-    if (h >= (double)(n - 1)) return *std::max_element(col.begin(), col.end());
+    if (h <= 0.0) return (double)*std::min_element(col.begin(), col.end());
+    if (h >= (double)(n - 1)) return (double)*std::max_element(col.begin(), col.end());
     const int64_t lo = (int64_t)std::floor(h);
     std::nth_element(col.begin(), col.begin() + lo, col.end());
-    const double a = col[lo];
-    const double b = *std::min_element(col.begin() + lo + 1, col.end());
+    const double a = (double)col[lo];
+    const double b = (double)*std::min_element(col.begin() + lo + 1, col.end());
     return a + (h - (double)lo) * (b - a);
 }
 
@@ -236,19 +240,32 @@ aqr_status train(const float* X, int64_t n, int32_t d, const aqr_qparams& p, int
     q.mn.assign(d, 0.f);
     q.mx.assign(d, 0.f);
     q.scale.assign(d, 0.f);
+    // columns are gathered a group at a time, so that one pass over the rows
+    // reads each cache line of X once for the whole group
+    constexpr int32_t G = 8;
+    const int32_t ngroups = (d + G - 1) / G;
     std::atomic<int32_t> next{0};
-    parallel_for_threads(std::min<int>(T, d), [&](int) {
-        std::vector<double> col(n);
+    parallel_for_threads(std::max(1, std::min<int>(T, ngroups)), [&](int) {
+        std::vector<float> cols((size_t)G * n), work(n);
         for (;;) {
-            int32_t j = next.fetch_add(1);
-            if (j >= d) break;
-            for (int64_t i = 0; i < n; ++i) col[i] = (double)X[i * d + j];
-            q.mn[j] = (float)percentile_of(col, p_lo);
-            for (int64_t i = 0; i < n; ++i) col[i] = (double)X[i * d + j];
-            q.mx[j] = (float)percentile_of(col, p_hi);
-            float range = q.mx[j] - q.mn[j];
-            float denom = range + (float)p.eps;
-            q.scale[j] = 255.0f / denom;
+            const int32_t gi = next.fetch_add(1);
+            if (gi >= ngroups) break;
+            const int32_t j0 = gi * G, gw = std::min(G, d - j0);
+            for (int64_t i = 0; i < n; ++i) {
+                const float* r = X + i * d + j0;
+                for (int32_t c = 0; c < gw; ++c) cols[(size_t)c * n + i] = r[c];
+            }
+            for (int32_t c = 0; c < gw; ++c) {
+                const float* col = &cols[(size_t)c * n];
+                const int32_t j = j0 + c;
+                work.assign(col, col + n);
+                q.mn[j] = (float)percentile_of(work, p_lo);
+                work.assign(col, col + n);
+                q.mx[j] = (float)percentile_of(work, p_hi);
+                float range = q.mx[j] - q.mn[j];
+                float denom = range + (float)p.eps;
+                q.scale[j] = 255.0f / denom;
+            }
         }
     });
     // density weights: the mean density for every dimension, or per dimension
