@@ -215,7 +215,8 @@ void aqr_graph_free(aqr_graph* g);
  * does not depend on threads.  codes: host, n x d_pad; X: host FP32 n x d,
  * the vectors the codes encode (the device search encodes them again).  The
  * call allocates and frees device memory for the index and the chunks
- * (hipMalloc) and waits for its work; seed_n >= n is aqr_build.  Levels and
+ * (hipMalloc) and pinned host staging for the chunk copies (hipHostMalloc),
+ * and waits for its work; seed_n >= n is aqr_build.  Levels and
  * p as in aqr_build; efc <= 1024.
  */
 aqr_status aqr_build_batched(const uint8_t* codes, const float* X, int64_t n, int32_t d,
