@@ -177,6 +177,74 @@ def _dev_ptr(t):
     return C.c_void_p(t.data_ptr())
 
 
+def _need(name, t, dtypes, ndim, rows=None, cols=None, optional=False):
+    """Host-side argument checks of a device tensor before a launch: dtype,
+    rank, at least `rows` rows and, for 2-D tensors, at least `cols` columns
+    (exactly `cols` when cols is a tuple (n,)).  A kernel reads and writes
+    through raw pointers, so a narrower dtype or a short buffer would be read
+    or written past its end on the device."""
+    if t is None:
+        if optional:
+            return
+        raise ValueError(f"{name}: missing")
+    import torch
+    if not isinstance(t, torch.Tensor):
+        raise ValueError(f"{name}: expected a torch tensor")
+    if t.dtype not in dtypes:
+        raise ValueError(f"{name}: dtype {t.dtype}, expected one of {dtypes}")
+    if t.dim() != ndim:
+        raise ValueError(f"{name}: {t.dim()}-D, expected {ndim}-D")
+    if rows is not None and t.shape[0] < rows:
+        raise ValueError(f"{name}: {t.shape[0]} rows, at least {rows} needed")
+    if cols is not None and ndim == 2:
+        if isinstance(cols, tuple):
+            if t.shape[1] != cols[0]:
+                raise ValueError(f"{name}: {t.shape[1]} columns, expected {cols[0]}")
+        elif t.shape[1] < cols:
+            raise ValueError(f"{name}: {t.shape[1]} columns, at least {cols} needed")
+    if not t.is_contiguous():
+        raise ValueError(f"{name}: expected a contiguous tensor")
+
+
+def _i32_types():
+    import torch
+    return (torch.int32,)
+
+
+def _f32_types():
+    import torch
+    return (torch.float32,)
+
+
+def _u8_types():
+    import torch
+    return (torch.uint8,)
+
+
+def _check_queries(ix, Q):
+    _need("Q", Q, _f32_types(), 2, cols=(ix.d,))
+    return Q.shape[0]
+
+
+def _check_search_args(ix, Q, k, ef, ws, order, nc=None):
+    nq = _check_queries(ix, Q)
+    _need("k", k, _i32_types(), 1, rows=nq)
+    _need("ef", ef, _i32_types(), 1, rows=nq)
+    _need("nc", nc, _i32_types(), 1, rows=nq, optional=True)
+    _need("order", order, _i32_types(), 1, rows=nq, optional=True)
+    _need("ws", ws, _u8_types(), 1)
+    return nq
+
+
+def _check_taps(taps, nq):
+    if not taps:
+        return
+    cap = int(taps.get("cap", 0))
+    _need("taps.counts", taps.get("counts"), _i32_types(), 2, rows=nq, cols=(8,), optional=True)
+    for name in ("expanded", "evaluated"):
+        _need(f"taps.{name}", taps.get(name), _i32_types(), 2, rows=nq, cols=cap, optional=True)
+
+
 def _stream_ptr(stream):
     if stream is None:
         import torch
@@ -386,6 +454,13 @@ def _taps(taps):
 
 def aqr_search(ix, Q, k, ef, cand_id, cand_D, cand_cnt, ws, ef_max, out_stride, nc=None, m_ef=3,
                waves_per_block=0, blocks=0, visited_log2=0, order=None, taps=None, stream=None):
+    nq = _check_search_args(ix, Q, k, ef, ws, order, nc)
+    _need("cand_id", cand_id, _i32_types(), 2, rows=nq, cols=out_stride)
+    _need("cand_D", cand_D, _i32_types(), 2, rows=nq, cols=out_stride)
+    _need("cand_cnt", cand_cnt, _i32_types(), 1, rows=nq)
+    if cand_id.shape[1] != out_stride or cand_D.shape[1] != out_stride:
+        raise ValueError("cand_id/cand_D: the row stride must equal out_stride")
+    _check_taps(taps, nq)
     sp = SParams(ef_max=ef_max, out_stride=out_stride, m_ef=m_ef,
                  waves_per_block=waves_per_block, blocks=blocks, visited_log2=visited_log2,
                  order=_dev_ptr(order))
@@ -398,6 +473,10 @@ def aqr_search(ix, Q, k, ef, cand_id, cand_D, cand_cnt, ws, ef_max, out_stride, 
 
 def aqr_search_fp32(ix, Q, k, ef, out_id, out_dist, ws, ef_max, out_stride, waves_per_block=0,
                     blocks=0, visited_log2=0, order=None, taps=None, stream=None):
+    nq = _check_search_args(ix, Q, k, ef, ws, order)
+    _need("out_id", out_id, _i32_types(), 2, rows=nq, cols=(out_stride,))
+    _need("out_dist", out_dist, _f32_types(), 2, rows=nq, cols=(out_stride,))
+    _check_taps(taps, nq)
     sp = SParams(ef_max=ef_max, out_stride=out_stride, m_ef=1,
                  waves_per_block=waves_per_block, blocks=blocks, visited_log2=visited_log2,
                  order=_dev_ptr(order))
@@ -409,6 +488,8 @@ def aqr_search_fp32(ix, Q, k, ef, out_id, out_dist, ws, ef_max, out_stride, wave
 
 
 def aqr_encode_queries(ix, Q, qcodes, stream=None):
+    nq = _check_queries(ix, Q)
+    _need("qcodes", qcodes, _u8_types(), 2, rows=nq, cols=(ix.d_pad,))
     _check(lib().aqr_encode_queries(ix.ptr, _dev_ptr(Q), Q.shape[0], _dev_ptr(qcodes),
                                     _stream_ptr(stream)))
 
@@ -416,7 +497,23 @@ def aqr_encode_queries(ix, Q, qcodes, stream=None):
 def aqr_rerank(ix, Q, cand_id, cand_cnt, k, out_id, out_dist, out_kind=None, n_rerank=28,
                tau_gap=0.010, tau_ratio=1.008, eps=1e-6, force_et=-1, out_stride=None,
                waves_per_block=0, taps=None, stream=None, assembly=0):
+    nq = _check_queries(ix, Q)
+    _need("cand_id", cand_id, _i32_types(), 2, rows=nq)
+    _need("cand_cnt", cand_cnt, _i32_types(), 1, rows=nq)
+    _need("k", k, _i32_types(), 1, rows=nq)
+    _need("out_id", out_id, _i32_types(), 2, rows=nq)
     out_stride = out_id.shape[1] if out_stride is None else out_stride
+    if out_id.shape[1] != out_stride:
+        raise ValueError("out_id: the row stride must equal out_stride")
+    _need("out_dist", out_dist, _f32_types(), 2, rows=nq, cols=(out_stride,))
+    _need("out_kind", out_kind, _u8_types(), 2, rows=nq, cols=(out_stride,), optional=True)
+    if taps is not None:
+        nc = cand_id.shape[1]
+        _need("taps.a_id", taps.get("a_id"), _i32_types(), 2, rows=nq, cols=(nc,), optional=True)
+        _need("taps.a_dist", taps.get("a_dist"), _f32_types(), 2, rows=nq, cols=(nc,),
+              optional=True)
+        _need("taps.et", taps.get("et"), _u8_types(), 1, rows=nq, optional=True)
+        _need("taps.nrr", taps.get("nrr"), _i32_types(), 1, rows=nq, optional=True)
     rp = RParams(n_rerank=n_rerank, out_stride=out_stride, tau_gap=tau_gap, tau_ratio=tau_ratio,
                  eps=eps, force_et=force_et, waves_per_block=waves_per_block, assembly=assembly)
     rt = None
@@ -463,8 +560,9 @@ class QueryPlan:
         self.ws = torch.zeros(aqr_search_workspace_size(), dtype=torch.uint8, device=dev)
 
     def run(self, Q, k, ef, nc=None, order=None):
-        n = Q.shape[0]
-        assert n <= self.nq
+        n = _check_queries(self.ix, Q)
+        if n > self.nq:
+            raise ValueError(f"Q: {n} queries, the plan holds {self.nq}")
         cid, cD, cc = self.cand_id[:n], self.cand_D[:n], self.cand_cnt[:n]
         aqr_search(self.ix, Q, k, ef, cid, cD, cc, self.ws, self.ef_max, self.nc_max, nc=nc,
                    m_ef=self.m_ef, order=order, **self.sp)
@@ -538,7 +636,11 @@ class BatchPlan:
         self.plan = aqr_plan_create(ix, sp, rp, self.bufs, use_graph)
 
     def load(self, Q, k, ef):
-        n = Q.shape[0]
+        n = _check_queries(self.ix, Q)
+        if n > self.nq_max:
+            raise ValueError(f"Q: {n} queries, the plan holds {self.nq_max}")
+        _need("k", k, _i32_types(), 1, rows=n)
+        _need("ef", ef, _i32_types(), 1, rows=n)
         self.bufs["Q"][:n].copy_(Q)
         self.bufs["k"][:n].copy_(k)
         self.bufs["ef"][:n].copy_(ef)
@@ -581,7 +683,9 @@ class Server(_Handle):
         super().__init__(h.value)
 
     def submit(self, q, k, ef):
-        q = np.ascontiguousarray(q, np.float32)
+        q = np.ascontiguousarray(q, np.float32).reshape(-1)
+        if q.shape[0] != self.ix.d:
+            raise ValueError(f"q: {q.shape[0]} values, the index has d = {self.ix.d}")
         t = C.c_uint64()
         st = lib().aqr_server_submit(self.ptr, _np_ptr(q), int(k), int(ef), C.byref(t))
         if st == AQR_ERR_BUSY:
@@ -608,6 +712,10 @@ class Server(_Handle):
         Q = np.ascontiguousarray(Q, np.float32)
         k = np.ascontiguousarray(k, np.int32)
         ef = np.ascontiguousarray(ef, np.int32)
+        if Q.ndim != 2 or Q.shape[0] != n or Q.shape[1] != self.ix.d:
+            raise ValueError(f"Q: shape {Q.shape}, expected ({n}, {self.ix.d})")
+        if k.shape != (n,) or ef.shape != (n,):
+            raise ValueError("k, ef: one entry per request expected")
         ids = np.empty((n, self.k_max), np.int32)
         dist = np.empty((n, self.k_max), np.float32)
         lat = np.empty(n, np.float64)

@@ -250,3 +250,66 @@ def test_server_entry_points_reject_bad_arguments(L):
     assert L.aqr_server_replay(None, 0, None, None, None, None, None, None, None, None,
                                None) == aqr.INVALID_ARG
     L.aqr_server_destroy(None)
+
+
+def test_binding_rejects_malformed_buffers():
+    # The binding checks dtype, rank and size of every buffer before any
+    # launch: a narrower dtype or a short buffer would be read or written
+    # past its end by the kernels.  Checked on the host with CPU tensors
+    # (the device check comes last, so a well-formed CPU tensor fails only
+    # for being on the host).
+    import types
+    import torch
+    from paper_2602_21600_amd import aqr
+    ix = types.SimpleNamespace(d=8, d_pad=16, ptr=None)
+    nq, ns = 5, 12
+    Q = torch.zeros((nq, 8), dtype=torch.float32)
+    k = torch.ones(nq, dtype=torch.int32)
+    ef = torch.ones(nq, dtype=torch.int32)
+    cid = torch.zeros((nq, ns), dtype=torch.int32)
+    cD = torch.zeros((nq, ns), dtype=torch.int32)
+    cnt = torch.zeros(nq, dtype=torch.int32)
+    ws = torch.zeros(256, dtype=torch.uint8)
+
+    def search(**kw):
+        a = dict(Q=Q, k=k, ef=ef, cand_id=cid, cand_D=cD, cand_cnt=cnt, ws=ws)
+        a.update(kw)
+        aqr.aqr_search(ix, a["Q"], a["k"], a["ef"], a["cand_id"], a["cand_D"], a["cand_cnt"],
+                       a["ws"], 64, ns)
+
+    bad = [
+        (dict(Q=Q.double()), "Q: dtype"),
+        (dict(Q=torch.zeros((nq, 9), dtype=torch.float32)), "Q: 9 columns"),
+        (dict(Q=torch.zeros(8, dtype=torch.float32)), "Q: 1-D"),
+        (dict(k=k.long()), "k: dtype"),
+        (dict(k=k[:3]), "k: 3 rows"),
+        (dict(ef=ef[:4]), "ef: 4 rows"),
+        (dict(cand_id=cid[:, :6].contiguous()), "cand_id: 6 columns"),
+        (dict(cand_D=torch.zeros((2, ns), dtype=torch.int32)), "cand_D: 2 rows"),
+        (dict(cand_cnt=cnt.float()), "cand_cnt: dtype"),
+        (dict(ws=ws.int()), "ws: dtype"),
+    ]
+    for kw, msg in bad:
+        with pytest.raises(ValueError, match=msg):
+            search(**kw)
+    # well-formed host tensors pass the shape checks and stop at the device check
+    with pytest.raises(ValueError, match="device tensor"):
+        search()
+
+    out_id = torch.zeros((nq, 10), dtype=torch.int32)
+    out_d = torch.zeros((nq, 10), dtype=torch.float32)
+    with pytest.raises(ValueError, match="out_dist: dtype"):
+        aqr.aqr_rerank(ix, Q, cid, cnt, k, out_id, out_d.double())
+    with pytest.raises(ValueError, match="out_dist: 7 columns"):
+        aqr.aqr_rerank(ix, Q, cid, cnt, k, out_id, torch.zeros((nq, 7)))
+    with pytest.raises(ValueError, match="k: 2 rows"):
+        aqr.aqr_rerank(ix, Q, cid, cnt, k[:2], out_id, out_d)
+    with pytest.raises(ValueError, match="out_id: 4 rows"):
+        aqr.aqr_search_fp32(ix, Q, k, ef, out_id[:4], out_d, ws, 64, 10)
+    with pytest.raises(ValueError, match="out_id: 10 columns, expected 12"):
+        aqr.aqr_search_fp32(ix, Q, k, ef, out_id, out_d, ws, 64, 12)
+    with pytest.raises(ValueError, match="qcodes: 8 columns, expected 16"):
+        aqr.aqr_encode_queries(ix, Q, torch.zeros((nq, 8), dtype=torch.uint8))
+    with pytest.raises(ValueError, match="taps.counts"):
+        aqr.aqr_search(ix, Q, k, ef, cid, cD, cnt, ws, 64, ns,
+                       taps=dict(cap=0, counts=torch.zeros((nq, 4), dtype=torch.int32)))
