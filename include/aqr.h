@@ -360,6 +360,34 @@ aqr_status aqr_search_fp32(const aqr_index* ix, const float* Q, int64_t nq, cons
                            void* stream);
 
 /* ------------------------------------------------------------------------ */
+/* exact k nearest neighbours by brute force (device)                        */
+/* ------------------------------------------------------------------------ */
+
+/*
+ * The exact truth of the recall measure (Section 4.1: recall@k against the
+ * true k nearest neighbours under L2): for each of the nq queries Q (device,
+ * nq x d FP32, row stride d) the k rows of X (device, n x d FP32, row stride
+ * d) with the smallest squared L2 distance, ordered by (distance, id).
+ * Rows are screened with FP32 matrix products on the matrix cores
+ * (|x|^2 - 2 q.x); the k + 32 best screened rows (rounded up to 16) are
+ * re-scored exactly in FP64, summing (q_j - x_j)^2 over j in order, so the
+ * distances are those of the FP64 definition bit for bit.
+ * Outputs (device): out_id [nq][k] (int32, -1 past n), out_dist [nq][k]
+ * (FP64, +inf past n); certified [nq] (nullable): 1 when an error bound of
+ * the FP32 screening proves that no row outside the re-scored candidates
+ * can enter the top k, else 0.
+ * ws: device workspace of at least aqr_knn_workspace_size(n, nq, k) bytes,
+ * 16-byte aligned, owned by the caller; it is overwritten.  1 <= k <= 128,
+ * 1 <= d <= 4096, 1 <= n < 2^31.  Inputs must be finite (non-finite values
+ * give unspecified ids, never an out-of-bounds access).  Asynchronous on
+ * stream; nq = 0 launches nothing.
+ */
+size_t aqr_knn_workspace_size(int64_t n, int64_t nq, int32_t k);
+aqr_status aqr_knn_bruteforce(const float* X, int64_t n, int32_t d, const float* Q, int64_t nq,
+                              int32_t k, int32_t* out_id, double* out_dist, uint8_t* certified,
+                              void* ws, size_t ws_bytes, void* stream);
+
+/* ------------------------------------------------------------------------ */
 /* batch plans: one captured launch sequence for uneven batches (device)     */
 /* ------------------------------------------------------------------------ */
 

@@ -119,6 +119,9 @@ _SIGS = [
                           _vp, C.POINTER(RTaps), _vp]),
     ("aqr_search_fp32", _i32, [_vp, _vp, _i64, _vp, _vp, C.POINTER(SParams), _vp, _vp, _vp,
                                _sz, C.POINTER(Taps), _vp]),
+    ("aqr_knn_workspace_size", _sz, [_i64, _i64, _i32]),
+    ("aqr_knn_bruteforce", _i32, [_vp, _i64, _i32, _vp, _i64, _i32, _vp, _vp, _vp, _vp, _sz,
+                                  _vp]),
     ("aqr_plan_create", _i32, [_vp, C.POINTER(SParams), C.POINTER(RParams),
                                C.POINTER(BatchBuffers), _i32, C.POINTER(_vp)]),
     ("aqr_plan_launch", _i32, [_vp, _i64, _vp]),
@@ -524,6 +527,40 @@ def aqr_rerank(ix, Q, cand_id, cand_cnt, k, out_id, out_dist, out_kind=None, n_r
                             _dev_ptr(cand_cnt), cand_id.shape[1], _dev_ptr(k), C.byref(rp),
                             _dev_ptr(out_id), _dev_ptr(out_dist), _dev_ptr(out_kind),
                             C.byref(rt) if rt is not None else None, _stream_ptr(stream)))
+
+
+def aqr_knn_workspace_size(n, nq, k):
+    return int(lib().aqr_knn_workspace_size(int(n), int(nq), int(k)))
+
+
+def aqr_knn_bruteforce(X, Q, k, out_id=None, out_dist=None, certified=None, ws=None,
+                       stream=None):
+    """Exact k nearest neighbours of the rows of Q among the rows of X (device
+    FP32 tensors) by brute force; returns (ids int32 [nq][k], dists FP64
+    [nq][k], certified uint8 [nq]) as device tensors."""
+    import torch
+    _need("X", X, _f32_types(), 2)
+    n, d = X.shape
+    _need("Q", Q, _f32_types(), 2, cols=(d,))
+    nq = Q.shape[0]
+    dev = X.device
+    if out_id is None:
+        out_id = torch.empty((nq, k), dtype=torch.int32, device=dev)
+    if out_dist is None:
+        out_dist = torch.empty((nq, k), dtype=torch.float64, device=dev)
+    if certified is None:
+        certified = torch.empty(nq, dtype=torch.uint8, device=dev)
+    _need("out_id", out_id, _i32_types(), 2, rows=nq, cols=(k,))
+    _need("out_dist", out_dist, (torch.float64,), 2, rows=nq, cols=(k,))
+    _need("certified", certified, _u8_types(), 1, rows=nq)
+    need = aqr_knn_workspace_size(n, nq, k)
+    if ws is None:
+        ws = torch.empty(max(need, 16), dtype=torch.uint8, device=dev)
+    _need("ws", ws, _u8_types(), 1, rows=need)
+    _check(lib().aqr_knn_bruteforce(_dev_ptr(X), n, d, _dev_ptr(Q), nq, int(k), _dev_ptr(out_id),
+                                    _dev_ptr(out_dist), _dev_ptr(certified), _dev_ptr(ws),
+                                    ws.numel(), _stream_ptr(stream)))
+    return out_id, out_dist, certified
 
 
 # --------------------------------------------------------------------------
