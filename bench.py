@@ -659,17 +659,12 @@ def build_index(args, wl, X, threads):
     n, d = X.shape
     t_quant = t_build = None
     cache = args.cache
-    if cache and os.path.exists(os.path.join(cache, "meta.json")):
+    if cache and os.path.exists(cache):
+        # one checksummed index file (aqr_index_save / aqr_index_load)
         log(f"loading index from {cache}")
-        meta = json.load(open(os.path.join(cache, "meta.json")))
-        arr = {k_: np.load(os.path.join(cache, k_ + ".npy"))
-               for k_ in ("codes", "min", "max", "scale", "level", "adj0", "upper_off",
-                          "upper_adj")}
-        codes = arr["codes"]
-        qz = aqr.aqr_quantizer_create(meta["info"], arr["min"], arr["max"], arr["scale"])
-        gx = dict(n=n, M=meta["M"], level=arr["level"], adj0=arr["adj0"],
-                  upper_off=arr["upper_off"], upper_adj=arr["upper_adj"], ep=meta["ep"])
-        g = aqr.aqr_graph_import(gx)
+        qz, g, codes, Xf = aqr.aqr_index_load(cache)
+        if Xf.shape != X.shape or not np.array_equal(Xf[:1000], X[:1000]):
+            raise SystemExit(f"{cache} holds an index of other data")
     else:
         # --sq8: the paper's plain scalar-quantisation baseline, min/max bounds
         # (P_max = 0) and a graph at the configured M_0 and ef_0^c, with no
@@ -695,17 +690,9 @@ def build_index(args, wl, X, threads):
                               level_u=W.level_draws(args.workload, n), progress=20)
         t_build = time.perf_counter() - t
         if cache:
-            os.makedirs(cache, exist_ok=True)
-            qi = aqr.aqr_quantizer_info(qz)
-            gx = aqr.aqr_graph_export(g)
-            for k_, v in (("codes", codes), ("min", qi["min"]), ("max", qi["max"]),
-                          ("scale", qi["scale"]), ("level", gx["level"]), ("adj0", gx["adj0"]),
-                          ("upper_off", gx["upper_off"]), ("upper_adj", gx["upper_adj"])):
-                np.save(os.path.join(cache, k_ + ".npy"), v)
-            info_s = {f: qi[f] for f in ("d", "d_pad", "M", "efc", "delta", "p_lo", "p_hi",
-                                         "s_dist", "eta", "w_mean")}
-            json.dump({"info": info_s, "M": gx["M"], "ep": gx["ep"]},
-                      open(os.path.join(cache, "meta.json"), "w"))
+            t = time.perf_counter()
+            aqr.aqr_index_save(cache, qz, g, codes, X)
+            log(f"index saved to {cache} in {time.perf_counter() - t:.1f} s")
     info = aqr.aqr_quantizer_info(qz)
     ginfo = aqr.aqr_graph_info(g)
     log(f"index ready: quantize {t_quant}s, build {t_build}s, delta={info['delta']:.4f} "
@@ -836,7 +823,8 @@ def main():
     ap.add_argument("--loads", default="0.1,0.5,0.8,0.9",
                     help="serving: offered loads as fractions of the saturation rate")
     ap.add_argument("--serve-seconds", type=float, default=1.0)
-    ap.add_argument("--cache", default=None, help="directory to save/load the built index")
+    ap.add_argument("--cache", default=None,
+                    help="index file: loaded when it exists, else written after the build")
     ap.add_argument("--assembly", choices=("fill", "union"), default="fill",
                     help="re-rank assembly: fill from A while fewer than k (default), or the "
                          "union of the exact results with the rest of A")

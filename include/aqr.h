@@ -224,6 +224,43 @@ aqr_status aqr_build_batched(const uint8_t* codes, const float* X, int64_t n, in
                              int64_t seed_n, int32_t batch, aqr_graph** out);
 
 /* ------------------------------------------------------------------------ */
+/* index file: quantiser, codes, FP32 rows and graph in one checksummed file */
+/* ------------------------------------------------------------------------ */
+
+typedef struct aqr_index_header {
+    int64_t n;
+    int32_t d;
+    int32_t d_pad;
+    int32_t M;
+    int32_t reserved;
+    int64_t upper_rows;
+    uint64_t file_bytes;
+} aqr_index_header;
+
+/*
+ * Write a built index (host): the quantiser of Section 3.1 (min_j, max_j,
+ * scale_j and the scalars of Alg. 1), the codes (n x d_pad bytes), the FP32
+ * rows X (n x d) that Stage 3 re-ranks with, and the HNSW graph, with a
+ * CRC-32C (Castagnoli, RFC 3720) per 64 MiB block.  n is the graph's; the
+ * file is replaced if it exists.  I/O failures give AQR_ERR_STATE.
+ */
+aqr_status aqr_index_save(const char* path, const aqr_quantizer* qz, const aqr_graph* g,
+                          const uint8_t* codes, const float* X);
+/* Read and check the header of an index file (shapes, section table, file
+ * length): AQR_ERR_CORRUPT on a mismatch or a truncated file. */
+aqr_status aqr_index_file_info(const char* path, aqr_index_header* info);
+/*
+ * Load an index file: *qz and *g receive new handles (free with
+ * aqr_quantizer_free / aqr_graph_free); codes_out (host, n x d_pad bytes)
+ * and X_out (host, n x d floats) are caller buffers sized from
+ * aqr_index_file_info.  Every block checksum, the zero padding of the code
+ * rows and the graph's structure are verified; any mismatch, a truncated
+ * file or trailing bytes give AQR_ERR_CORRUPT, and no handle is returned.
+ */
+aqr_status aqr_index_load(const char* path, aqr_quantizer** qz, aqr_graph** g,
+                          uint8_t* codes_out, float* X_out);
+
+/* ------------------------------------------------------------------------ */
 /* device index                                                              */
 /* ------------------------------------------------------------------------ */
 

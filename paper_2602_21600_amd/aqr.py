@@ -92,6 +92,11 @@ class ServerParams(C.Structure):
                 ("idle_ms", _i32), ("reserved", _i32)]
 
 
+class IndexFileInfo(C.Structure):
+    _fields_ = [("n", _i64), ("d", _i32), ("d_pad", _i32), ("M", _i32), ("reserved", _i32),
+                ("upper_rows", _i64), ("file_bytes", C.c_uint64)]
+
+
 _SIGS = [
     ("aqr_last_error", C.c_char_p, []),
     ("aqr_version", _i32, []),
@@ -108,6 +113,9 @@ _SIGS = [
     ("aqr_graph_export", _i32, [_vp, _vp, _vp, _vp, _vp]),
     ("aqr_graph_import", _i32, [_i64, _i32, _vp, _vp, _vp, _vp, _u32, C.POINTER(_vp)]),
     ("aqr_graph_free", None, [_vp]),
+    ("aqr_index_save", _i32, [C.c_char_p, _vp, _vp, _vp, _vp]),
+    ("aqr_index_file_info", _i32, [C.c_char_p, C.POINTER(IndexFileInfo)]),
+    ("aqr_index_load", _i32, [C.c_char_p, C.POINTER(_vp), C.POINTER(_vp), _vp, _vp]),
     ("aqr_index_bytes", _i32, [_vp, _vp, C.POINTER(_sz)]),
     ("aqr_index_bind", _i32, [_vp, _vp, _vp, _vp, _vp, _sz, _vp, C.POINTER(_vp)]),
     ("aqr_index_free", None, [_vp]),
@@ -419,6 +427,34 @@ def aqr_graph_import(gd):
     _check(lib().aqr_graph_import(int(gd["n"]), int(gd["M"]), _np_ptr(level), _np_ptr(adj0),
                                   _np_ptr(off), _np_ptr(upper), int(gd["ep"]), C.byref(h)))
     return Graph(h.value)
+
+
+def aqr_index_save(path, qz, g, codes, X):
+    """Write quantiser, codes, FP32 rows and graph to one checksummed file."""
+    codes = np.ascontiguousarray(codes, np.uint8)
+    X = np.ascontiguousarray(X, np.float32)
+    info = aqr_quantizer_info(qz)
+    gi = aqr_graph_info(g)
+    if codes.shape != (gi["n"], info["d_pad"]) or X.shape != (gi["n"], info["d"]):
+        raise ValueError("codes / X do not match the quantiser and the graph")
+    _check(lib().aqr_index_save(os.fsencode(path), qz.ptr, g.ptr, _np_ptr(codes), _np_ptr(X)))
+
+
+def aqr_index_file_info(path):
+    fi = IndexFileInfo()
+    _check(lib().aqr_index_file_info(os.fsencode(path), C.byref(fi)))
+    return {f: getattr(fi, f) for f, _ in IndexFileInfo._fields_ if f != "reserved"}
+
+
+def aqr_index_load(path):
+    """Returns (quantizer, graph, codes, X) from an index file."""
+    fi = aqr_index_file_info(path)
+    codes = np.empty((fi["n"], fi["d_pad"]), np.uint8)
+    X = np.empty((fi["n"], fi["d"]), np.float32)
+    q, g = _vp(), _vp()
+    _check(lib().aqr_index_load(os.fsencode(path), C.byref(q), C.byref(g), _np_ptr(codes),
+                                _np_ptr(X)))
+    return Quantizer(q.value), Graph(g.value), codes, X
 
 
 def aqr_index_bytes(qz, g):

@@ -15,7 +15,7 @@ BUILD = os.path.join(HERE, "_build")
 OUT = os.path.join(HERE, "libaqr.so")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
-HOST_SRC = ["errors.cpp", "quantize.cpp", "build.cpp"]
+HOST_SRC = ["errors.cpp", "quantize.cpp", "build.cpp", "indexio.cpp"]
 HIP_SRC = ["device.hip", "density.hip", "knn.hip"]
 
 HOST_FLAGS = ["-O3", "-std=c++17", "-fPIC", "-march=x86-64-v3", "-ffp-contract=off",
