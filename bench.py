@@ -34,47 +34,39 @@ TARGET_RECALL = 0.98
 # further points of the recall-QPS curve, each timed like the headline point
 CURVE_TARGETS = (0.90, 0.95, 0.99)
 CURVE_EXTRA_EF = (576, 640, 768, 896, 1024)
+# ef sweep per workload (the cheapest ef reaching the target is timed); the
+# default list is the workload's own ef values plus finer steps above them
+SWEEP_EF = {
+    "serving": [128, 192, 256, 320, 384, 448, 512, 576, 640, 768, 896, 1024],
+}
+# the default run: the metric on the largest configuration (10M x 96), then
+# the other full-size configurations as extra keys, each with its roofline
+DEFAULT_LEGS = ("sift1m", "gist1m")
+# oracle time budget of the CPU baseline (seconds of host work)
+CPU_SECONDS = 15.0
 
 
 def log(msg):
     print(f"[bench {time.strftime('%H:%M:%S')}] {msg}", file=sys.stderr, flush=True)
 
 
-def ground_truth(X, Q, k, device, chunk=131072, extra=32, qchunk=8192):
-    """Exact k nearest neighbours: FP32 screening, FP64 re-score of k+extra."""
+def ground_truth(X, Q, k, device, qchunk=131072):
+    """Exact k nearest neighbours (ids, FP64 squared distances, certified
+    flags) from the library's brute-force kernel: FP32 screening on the
+    matrix cores, FP64 re-score of the best k + 32."""
     import torch
-    torch.backends.cuda.matmul.allow_tf32 = False
-    Xd = torch.from_numpy(X).to(device)
-    xn = (Xd * Xd).sum(1)
-    ids_all, d_all = [], []
+    from paper_2602_21600_amd import aqr
+    Xd = torch.from_numpy(np.ascontiguousarray(X)).to(device)
+    ids_all, d_all, c_all = [], [], []
     for q0 in range(0, Q.shape[0], qchunk):
-        i, dd = _gt_chunk(Xd, xn, Q[q0:q0 + qchunk], k, device, chunk, extra)
-        ids_all.append(i)
-        d_all.append(dd)
-    del Xd, xn
+        Qd = torch.from_numpy(np.ascontiguousarray(Q[q0:q0 + qchunk])).to(device)
+        i, dd, c = aqr.aqr_knn_bruteforce(Xd, Qd, k)
+        ids_all.append(i.cpu().numpy())
+        d_all.append(dd.cpu().numpy())
+        c_all.append(c.cpu().numpy())
+    del Xd
     torch.cuda.empty_cache()
-    return np.concatenate(ids_all), np.concatenate(d_all)
-
-
-def _gt_chunk(Xd, xn, Q, k, device, chunk, extra):
-    import torch
-    Qd = torch.from_numpy(Q).to(device)
-    nq = Q.shape[0]
-    cand = k + extra
-    best_d = torch.full((nq, cand), float("inf"), device=device)
-    best_i = torch.zeros((nq, cand), dtype=torch.int64, device=device)
-    for s in range(0, Xd.shape[0], chunk):
-        e = min(Xd.shape[0], s + chunk)
-        sc = xn[s:e][None, :] - 2.0 * (Qd @ Xd[s:e].T)
-        d, i = sc.topk(min(cand, e - s), dim=1, largest=False)
-        best_d, idx = torch.cat([best_d, d], 1).topk(cand, dim=1, largest=False)
-        best_i = torch.gather(torch.cat([best_i, i + s], 1), 1, idx)
-    ids, _ = best_i.sort(dim=1)
-    diff = Xd[ids].double() - Qd[:, None, :].double()
-    dist = (diff * diff).sum(-1)
-    dist, order = dist.sort(dim=1, stable=True)
-    ids = torch.gather(ids, 1, order)
-    return ids[:, :k].cpu().numpy(), dist[:, :k].cpu().numpy()
+    return np.concatenate(ids_all), np.concatenate(d_all), np.concatenate(c_all)
 
 
 PARITY_RTOL = 1e-5  # FP32 device distances against the oracle's FP64 ones
@@ -327,7 +319,7 @@ def bench_batched(args, torch, aqr, W, wl, dev, threads):
     ix = aqr.aqr_index_bind(qz, g, codes, X, device=dev)
     k_max, ef_max = int(kq.max()), int(efq.max())
     log("ground truth")
-    gt_ids, gt_d = ground_truth(X, Q, 10, dev)
+    gt_ids, gt_d, _ = ground_truth(X, Q, 10, dev)
     Qd = torch.from_numpy(Q).to(dev)
     kd = torch.from_numpy(kq).to(dev)
     efd = torch.from_numpy(efq).to(dev)
@@ -506,7 +498,7 @@ def bench_serving(args, torch, aqr, W, wl, dev, threads):
     qz, g, codes, info, ginfo, t_quant, t_build = build_index(args, wl, X, threads)
     ix = aqr.aqr_index_bind(qz, g, codes, X, device=dev)
     log("ground truth")
-    gt_ids, gt_d = ground_truth(X, Q, 10, dev)
+    gt_ids, gt_d, _ = ground_truth(X, Q, 10, dev)
     Qd = torch.from_numpy(Q).to(dev)
     k_max, ef_max = 100, 512
 
@@ -652,13 +644,14 @@ def bench_serving(args, torch, aqr, W, wl, dev, threads):
     print(json.dumps(out, allow_nan=False), flush=True)
 
 
-def build_index(args, wl, X, threads):
-    """Quantiser and graph of the workload (built, or loaded from --cache)."""
+def build_index(args, wl, X, threads, name=None, cache="args"):
+    """Quantiser and graph of the workload (built, or loaded from an index file)."""
     from paper_2602_21600_amd import aqr
     from paper_2602_21600_amd import workloads as W
     n, d = X.shape
     t_quant = t_build = None
-    cache = args.cache
+    name = name or args.workload
+    cache = args.cache if cache == "args" else cache
     if cache and os.path.exists(cache):
         # one checksummed index file (aqr_index_save / aqr_index_load)
         log(f"loading index from {cache}")
@@ -683,11 +676,11 @@ def build_index(args, wl, X, threads):
             g = aqr.aqr_build_batched(codes, X, d, qz, threads=threads,
                                       M=wl.M0 if args.sq8 else 0,
                                       efc=wl.efc0 if args.sq8 else 0,
-                                      level_u=W.level_draws(args.workload, n), progress=20)
+                                      level_u=W.level_draws(name, n), progress=20)
         else:
             g = aqr.aqr_build(codes, d, qz, threads=threads,
                               M=wl.M0 if args.sq8 else 0, efc=wl.efc0 if args.sq8 else 0,
-                              level_u=W.level_draws(args.workload, n), progress=20)
+                              level_u=W.level_draws(name, n), progress=20)
         t_build = time.perf_counter() - t
         if cache:
             t = time.perf_counter()
@@ -790,18 +783,458 @@ def bench_build(args, wl, threads):
         "wall_s": round(time.perf_counter() - t_all, 1)}), flush=True)
 
 
+def run_search(args, torch, aqr, W, name, dev, threads, nq=None, curve_leg=True, cpu_leg=True,
+               cache=None):
+    """QPS at recall@10 >= 0.98 of one workload: build (or load) the index,
+    exact ground truth on the device, sweep ef and the re-rank settings, time
+    the cheapest AQR point and the cheapest FP32 HNSW point on the same graph,
+    the Stage-1 roofline, optionally the recall-QPS curve and the CPU oracle
+    leg.  Returns (the result dict, the context for further legs)."""
+    wl = W.WORKLOADS[name]
+    k = 10 if 10 in wl.k else wl.k[0]
+    t_all = time.perf_counter()
+
+    log(f"generating {name}")
+    X = W.base(name, args.n)
+    Q = W.queries(name, nq)
+    n, d = X.shape
+    nq = Q.shape[0]
+
+    qz, g, codes, info, ginfo, t_quant, t_build = build_index(args, wl, X, threads, name=name, cache=cache)
+    ix = aqr.aqr_index_bind(qz, g, codes, X, device=dev)
+    gt_ids = gt_d = None
+    gt_info = None
+    if not args.profile:
+        log("ground truth")
+        t = time.perf_counter()
+        gt_ids, gt_d, gt_cert = ground_truth(X, Q, k, dev)
+        gt_info = {"kernel": "aqr_knn_bruteforce", "s": round(time.perf_counter() - t, 2),
+                   "certified": int(gt_cert.sum()), "queries": nq}
+        log(f"ground truth: {gt_info}")
+    Qd = torch.from_numpy(Q).to(dev)
+
+    # the workload's ef list, then finer steps above it, so the cheapest ef that
+    # reaches the recall target is found for both searches alike
+    efs = ([int(e) for e in args.efs.split(",")] if args.efs else SWEEP_EF.get(
+        name, sorted(set(wl.ef) | {288, 304, 320, 352, 384, 448, 512})))
+
+    def recall_of(ids):
+        return recall_at(ids.cpu().numpy(), X, Q, gt_ids, gt_d, k)
+
+    aqr_table, fp_table = [], []
+    aqr_pick = fp_pick = None
+    if args.profile:
+        cfg = rerank_by_name(args.rerank or "no-et")
+        aqr_pick = (args.ef or 256, float("nan"), cfg)
+    else:
+        def trial(ef, cfg):
+            r = AqrRunner(aqr, ix, nq, k, ef, dev, rerank=cfg)
+            ids, _ = r.step(Qd)
+            torch.cuda.synchronize()
+            rec = recall_of(ids)
+            aqr_table.append((ef, cfg[0], round(rec, 5)))
+            log(f"aqr ef={ef} rerank={cfg[0]} recall@10={rec:.4f}")
+            return rec
+
+        for ef in efs:
+            # the most exhaustive re-rank setting first: when it misses the
+            # target at this ef, the cheaper settings (fewer candidates, fewer
+            # exact distances) are not tried
+            top = RERANK_CONFIGS[-1]
+            if trial(ef, top) < TARGET_RECALL:
+                continue
+            for cfg in RERANK_CONFIGS[:-1]:
+                rec = trial(ef, cfg)
+                if rec >= TARGET_RECALL:
+                    aqr_pick = (ef, rec, cfg)
+                    break
+            if aqr_pick is None:
+                aqr_pick = (ef, next(r for e, c, r in aqr_table if e == ef and c == top[0]), top)
+            break
+        if aqr_pick is None:
+            best = max(aqr_table, key=lambda t: t[2])
+            aqr_pick = (best[0], best[2], next(c for c in RERANK_CONFIGS if c[0] == best[1]))
+        for ef in efs:
+            r = Fp32Runner(aqr, ix, nq, k, ef, dev)
+            ids, _ = r.step(Qd)
+            torch.cuda.synchronize()
+            rec = recall_of(ids)
+            fp_table.append((ef, round(rec, 5)))
+            log(f"fp32 ef={ef} recall@10={rec:.4f}")
+            if rec >= TARGET_RECALL:
+                fp_pick = (ef, rec)
+                break
+        if fp_pick is None:
+            # the target is out of reach on this sweep: the best recall reached
+            best_f = max(fp_table, key=lambda t: t[1])
+            fp_pick = (best_f[0], best_f[1])
+
+    # ---- tuning (results do not depend on it) and the timed AQR path ----
+    ef_a = aqr_pick[0]
+    # launch shape of the timed search without --tune: the one the tuning
+    # loop below picks on the default workload (results do not depend on it)
+    tuning = {"visited_log2": 8, "waves_per_block": 4}
+    if args.vb or args.wpb:
+        tuning = {"visited_log2": args.vb, "waves_per_block": args.wpb}
+    elif args.tune and not args.profile:
+        best_ms = None
+        r0 = AqrRunner(aqr, ix, nq, k, ef_a, dev, rerank=aqr_pick[2], **tuning)
+        spin_up(torch, lambda m: r0.search_only(Qd))
+        for vb in (6, 7, 8, 9, 10, 11, 12):
+            for wpb in (1, 2, 4):
+                try:
+                    r = AqrRunner(aqr, ix, nq, k, ef_a, dev, visited_log2=vb,
+                                  waves_per_block=wpb, rerank=aqr_pick[2])
+                    ms_t, _ = timed(torch, lambda m: r.search_only(Qd), 5, 1)
+                except aqr.AqrError as e:  # LDS limit of the device
+                    log(f"tune visited_log2={vb} waves_per_block={wpb}: skipped ({e})")
+                    continue
+                log(f"tune visited_log2={vb} waves_per_block={wpb}: {ms_t:.3f} ms")
+                if best_ms is None or ms_t < best_ms:
+                    best_ms, tuning = ms_t, {"visited_log2": vb, "waves_per_block": wpb}
+        log(f"tuning picked {tuning}")
+    runner = AqrRunner(aqr, ix, nq, k, ef_a, dev, rerank=aqr_pick[2], **tuning)
+
+    def aqr_step(marks):
+        if marks:
+            marks[0].record()
+            runner.search_only(Qd)
+            marks[1].record()
+            runner.rerank_only(Qd)
+            marks[2].record()
+        else:
+            runner.step(Qd)
+
+    log(f"timing AQR at ef={ef_a}: warmup {args.warmup}, steps {args.steps}")
+    ms_aqr, per = timed(torch, aqr_step, args.steps, args.warmup, kernel_events=3)
+    qps_aqr = nq / (ms_aqr / 1e3)
+    search_ms, rerank_ms = per
+    log(f"AQR {qps_aqr:,.0f} QPS ({ms_aqr:.3f} ms/step; search {search_ms:.3f} ms, "
+        f"rerank {rerank_ms:.3f} ms)")
+
+    # per-query counters (separate, untimed run with a large visited cache so
+    # that evaluations count distinct nodes)
+    counts = torch.zeros((nq, 8), dtype=torch.int32, device=dev)
+    big = AqrRunner(aqr, ix, nq, k, ef_a, dev, visited_log2=14, waves_per_block=1,
+                    rerank=aqr_pick[2])
+    big.search_only(Qd, taps=dict(cap=0, counts=counts))
+    torch.cuda.synchronize()
+    cnt_big = counts.cpu().numpy().astype(np.int64)
+    counts.zero_()
+    runner.search_only(Qd, taps=dict(cap=0, counts=counts))
+    torch.cuda.synchronize()
+    cnt = counts.cpu().numpy().astype(np.int64)
+    d_pad = info["d_pad"]
+    s0 = (2 * ginfo["M"] + 15) // 16 * 16
+    s1 = (ginfo["M"] + 15) // 16 * 16
+    nc = min(max(max(ef_a, k) // aqr_pick[2][4], k), max(ef_a, k))
+    # algorithmic bytes of one search launch (distinct evaluations)
+    code_bytes = int((cnt_big[:, 1].sum() + cnt_big[:, 2].sum() + nq) * d_pad)
+    adj_bytes = int(cnt_big[:, 0].sum() * s0 * 4 + cnt_big[:, 4].sum() * s1 * 4)
+    io_bytes = int(nq * (4 * d + 8 * nc + 4))
+    alg_bytes = code_bytes + adj_bytes + io_bytes
+    achieved = alg_bytes / (search_ms / 1e3) / 1e9
+    reeval = float(cnt[:, 1].sum() / max(1, cnt_big[:, 1].sum()) - 1.0)
+    lat_us = cnt[:, 5] / 100.0  # 100 MHz real-time clock
+    sha = source_sha()
+    prof_name = (f"search_{'sq8' if args.sq8 else 'u8'}_{name}_ef{ef_a}"
+                 f"_vb{tuning['visited_log2']}"
+                 f"_wpb{tuning['waves_per_block']}")
+    traffic = traffic_from_profile(prof_name, sha)
+
+    copy_info = None
+    if args.profile:
+        # a plain copy of known size: its FETCH_SIZE/WRITE_SIZE readings scale
+        # the counters of the search kernel to bytes
+        src = torch.empty(args.copy_mib << 20, dtype=torch.uint8, device=dev).fill_(1)
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        copy_info = {"bytes": args.copy_mib << 20}
+
+    # ---- timed FP32 baseline ----
+    fp = None
+    if fp_pick is not None:
+        ef_f = fp_pick[0]
+        # the baseline gets the same launch-shape treatment as the AQR search:
+        # without --tune, the shape the tuning loop picks for it on the default
+        # workload (FP32 rows are 4x the bytes, so a larger visited cache pays)
+        fp_tuning = ({"visited_log2": args.vb, "waves_per_block": args.wpb}
+                     if (args.vb or args.wpb) else {"visited_log2": 10, "waves_per_block": 4})
+        if args.tune and not args.profile and not (args.vb or args.wpb):
+            best_ms = None
+            r0 = Fp32Runner(aqr, ix, nq, k, ef_f, dev, **fp_tuning)
+            spin_up(torch, lambda m: r0.step(Qd))
+            for vb in (6, 7, 8, 9, 10, 11, 12):
+                for wpb in (1, 2, 4):
+                    try:
+                        r = Fp32Runner(aqr, ix, nq, k, ef_f, dev, visited_log2=vb,
+                                       waves_per_block=wpb)
+                        ms_t, _ = timed(torch, lambda m: r.step(Qd), 5, 1)
+                    except aqr.AqrError as e:
+                        log(f"tune fp32 visited_log2={vb} waves_per_block={wpb}: skipped ({e})")
+                        continue
+                    log(f"tune fp32 visited_log2={vb} waves_per_block={wpb}: {ms_t:.3f} ms")
+                    if best_ms is None or ms_t < best_ms:
+                        best_ms, fp_tuning = ms_t, {"visited_log2": vb, "waves_per_block": wpb}
+            log(f"fp32 tuning picked {fp_tuning}")
+        frun = Fp32Runner(aqr, ix, nq, k, ef_f, dev, **fp_tuning)
+
+        def fp_step(marks):
+            if marks:
+                marks[0].record()
+                frun.step(Qd)
+                marks[1].record()
+            else:
+                frun.step(Qd)
+
+        log(f"timing FP32 HNSW at ef={ef_f}")
+        ms_fp, per_fp = timed(torch, fp_step, args.steps, args.warmup, kernel_events=2)
+        counts.zero_()
+        frun.step(Qd, taps=dict(cap=0, counts=counts))
+        torch.cuda.synchronize()
+        cf = counts.cpu().numpy().astype(np.int64)
+        xs = (d + 3) // 4 * 4
+        fp_bytes = int((cf[:, 1].sum() + cf[:, 2].sum() + nq) * xs * 4 +
+                       cf[:, 0].sum() * s0 * 4 + cf[:, 4].sum() * s1 * 4 + nq * (4 * d + 8 * k))
+        fp = {"value": round(nq / (ms_fp / 1e3), 1), "unit": "queries/s", "ef": ef_f,
+              "tuning": fp_tuning,
+              "recall@10": round(fp_pick[1], 5),
+              "reached_target": bool(fp_pick[1] >= TARGET_RECALL),
+              "ms_per_step": round(ms_fp, 4),
+              "kernel_ms": round(per_fp[0], 4),
+              "achieved_GBps": round(fp_bytes / (per_fp[0] / 1e3) / 1e9, 1),
+              "p50_query_us": round(float(np.percentile(cf[:, 5] / 100.0, 50)), 2),
+              "p99_query_us": round(float(np.percentile(cf[:, 5] / 100.0, 99)), 2),
+              "sweep": fp_table}
+        log(f"FP32 {fp['value']:,.0f} QPS at ef={ef_f}")
+
+    # ---- recall-QPS curve: the cheapest setting of each search at further
+    # recall targets, timed the same way (the sweeps above stop at 0.98, so
+    # they are continued for higher targets) ----
+    curve = None
+    if curve_leg and not args.profile and not args.no_curve:
+        curve = recall_qps_curve(args, torch, aqr, ix, Qd, nq, k, dev, efs, aqr_table, fp_table,
+                                 tuning, fp_tuning if fp is not None else None, recall_of)
+        curve.append({"target": TARGET_RECALL,
+                      "aqr": {"ef": ef_a, "rerank": aqr_pick[2][0],
+                              "recall@10": round(aqr_pick[1], 5), "qps": round(qps_aqr, 1)},
+                      "fp32": ({"ef": fp["ef"], "recall@10": fp["recall@10"],
+                                "qps": fp["value"]} if fp else None),
+                      "speedup": round(qps_aqr / fp["value"], 3) if fp else None})
+        curve.sort(key=lambda c: c["target"])
+
+    # ---- CPU oracle baseline on a bounded sample of the same queries ----
+    cpu = None
+    parity = None
+    if cpu_leg and not args.no_cpu and not args.profile:
+        cpu, parity = cpu_oracle_leg(args, aqr, g, X, Q, codes, info, d, k, ef_a, aqr_pick[2],
+                                     runner.plan, threads, nq)
+
+    out = {
+        "metric": "QPS at recall@10>=0.98 on 1 MI355X, AQR-int8 vs FP32 HNSW; p50/p99 latency",
+        "value": round(qps_aqr, 1),
+        "unit": "queries/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_aqr, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "u8",
+        "data": "synthetic",
+        "config": {
+            "workload": f"{name}: {n:,} x {d} FP32 L2, {wl.n_clusters}-cluster "
+                        f"Gaussian mixture; {nq:,} queries; k={k}"
+                        + ("; plain SQ8 baseline (P_max 0, graph at M_0)" if args.sq8 else "")
+                        + ("" if args.gpu_build else "; graph from the host build")
+                        + ("; per-dimension density weights" if args.weights == "per-dim"
+                           else ""),
+            "n": n, "d": d, "nq": nq, "k": k, "ef": ef_a, "M0": wl.M0, "efc0": wl.efc0,
+            "M_i": ginfo["M"], "efc": ginfo["efc"], "weights": args.weights,
+            "eta": round(info["eta"], 6),
+            "graph_build": ("batched, device searches; quantiser density on the device"
+                            if args.gpu_build else "host"),
+            "delta": round(info["delta"], 6), "m_ef": aqr_pick[2][4],
+            "rerank": aqr_pick[2][0], "n_rerank": aqr_pick[2][1],
+            "assembly": "union" if ASSEMBLY else "fill",
+            "tau_gap": finite_or_none(aqr_pick[2][2]),
+            "tau_ratio": finite_or_none(aqr_pick[2][3]),
+            "recall@10": finite_or_none(round(aqr_pick[1], 5)), "tuning": tuning,
+            "global_batch": nq, "parallelism": "single GPU, one wavefront per query",
+        },
+        "roofline": {
+            "bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+            "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+            "traffic": traffic, "traffic_profile": prof_name,
+            "kernel": "k_search (Stage 1, 8-bit codes)",
+            "kernel_ms": round(search_ms, 4),
+            "alg_bytes_per_launch": alg_bytes,
+            "code_bytes": code_bytes, "adjacency_bytes": adj_bytes, "io_bytes": io_bytes,
+            "code_gather_GBps": round(code_bytes / (search_ms / 1e3) / 1e9, 1),
+            "code_gather_frac": round(code_bytes / (search_ms / 1e3) / 1e9 / HBM_PEAK_GBS, 4),
+            "reevaluation_overhead": round(reeval, 4),
+            "expansions_per_query": round(float(cnt[:, 0].mean()), 2),
+            "evaluations_per_query": round(float(cnt[:, 1].mean()), 1),
+        },
+        "rerank_ms": round(rerank_ms, 4),
+        "stage1_device_us": {"p50": round(float(np.percentile(lat_us, 50)), 2),
+                             "p99": round(float(np.percentile(lat_us, 99)), 2),
+                             "what": "per-query Stage-1 device time inside the batch"},
+        "ground_truth": gt_info,
+        "fp32_hnsw": fp,
+        "speedup_vs_fp32": (round(qps_aqr / fp["value"], 3) if fp else None),
+        "aqr_sweep": aqr_table,
+        "recall_qps_curve": curve,
+        "cpu_baseline": cpu,
+        "parity_sample": parity,
+        "build_s": {"quantize": t_quant and round(t_quant, 1),
+                    "graph": t_build and round(t_build, 1)},
+        "device_hip_sha": sha,
+        "copy_kernel": copy_info,
+        "wall_s": round(time.perf_counter() - t_all, 1),
+    }
+    ctx = dict(ix=ix, X=X, Q=Q, Qd=Qd, gt_ids=gt_ids, gt_d=gt_d, ef=ef_a, cfg=aqr_pick[2], k=k,
+               info=info, ginfo=ginfo, g=g, codes=codes, tuning=tuning, n=n, d=d, nq=nq,
+               t_all=t_all)
+    return out, ctx
+
+
+def host_info():
+    """Host CPU description for the CPU baseline."""
+    model = None
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    try:
+        affinity = len(os.sched_getaffinity(0))
+    except AttributeError:
+        affinity = None
+    return {"nproc": os.cpu_count(), "affinity": affinity, "model": model}
+
+
+def cpu_oracle_leg(args, aqr, g, X, Q, codes, info, d, k, ef, cfg, plan, threads, nq):
+    """The oracle (plain C, FP64) on the host cores the job may use, on a
+    sample of the same queries sized to about CPU_SECONDS of work, and the
+    parity of the device results with it on that sample."""
+    import oracle as orc
+    gx = aqr.aqr_graph_export(g)
+    index = dict(X=X, codes=codes, d=d, min=info["min"], scale=info["scale"], graph=gx)
+    _, nrr, tg, tr, mef = cfg
+
+    def run(S, th):
+        orc.set_threads(th)
+        t = time.perf_counter()
+        r = orc.query(index, Q[:S], k, ef, m_ef=mef, n_rerank=nrr, tau_gap=tg, tau_ratio=tr,
+                      assembly=ASSEMBLY)
+        return r, time.perf_counter() - t
+
+    # size the sample from a short pilot on all threads
+    S0 = min(nq, 256)
+    _, dt0 = run(S0, threads)
+    S = int(min(args.cpu_sample or nq, nq, max(S0, S0 * CPU_SECONDS / max(dt0, 1e-3))))
+    log(f"CPU oracle on {S} queries with {threads} threads (pilot {S0} in {dt0:.2f} s)")
+    ref, dt = run(S, threads)
+    S1 = max(16, min(S, int(S0 * 2.0 / max(dt0 * threads, 1e-3))))
+    _, dt1 = run(S1, 1)
+    orc.set_threads(threads)
+    cpu = {"value": round(S / dt, 1), "unit": "queries/s", "cores": threads, "kind": "oracle",
+           "sample": f"first {S} of the {nq} queries, same index and settings (ef={ef}, k={k}, "
+                     f"re-rank {cfg[0]}); encode + Stage 1 + Stages 2-3, FP64 re-rank; "
+                     f"{dt:.1f} s of host time",
+           "one_thread_value": round(S1 / dt1, 1), "one_thread_sample": S1,
+           "host": host_info()}
+    s1 = ref["stage1"]
+    gid = plan.cand_id[:S].cpu().numpy().view(np.uint32)
+    gcnt = plan.cand_cnt[:S].cpu().numpy()
+    exact = sum(int(gcnt[q] == s1["cand_cnt"][q] and
+                    np.array_equal(gid[q, :gcnt[q]], s1["cand_id"][q, :gcnt[q]]))
+                for q in range(S))
+    same, tied = topk_agreement(plan.out_id[:S].cpu().numpy(), plan.out_dist[:S].cpu().numpy(),
+                                ref, X, Q, np.full(S, k))
+    parity = {"queries": S, "stage1_bit_exact": exact, "topk_identical": same,
+              "topk_differ_only_by_ties": tied}
+    log(f"oracle {cpu['value']:,.1f} QPS; parity {parity}")
+    return cpu, parity
+
+
+def serving_leg(args, torch, aqr, W, name, ctx, dev, loads=(0.5, 0.9), seconds=1.0):
+    """Request latency on the same index: the resident server at the headline
+    setting (k = 10, the timed ef and re-rank), Poisson arrivals at fractions
+    of its saturation rate, and the workload's mixed stream (k in {1,10,100},
+    per-query ef) at the highest load.  Latency runs from each request's
+    arrival to the poll that finds it complete."""
+    ix, Q, X = ctx["ix"], ctx["Q"], ctx["X"]
+    gt_ids, gt_d = ctx["gt_ids"], ctx["gt_d"]
+    _, nrr, tg, tr, mef = ctx["cfg"]
+    ef = ctx["ef"]
+    nq = Q.shape[0]
+    ks_mix, efs_mix = W.query_params(name, nq)
+    efs_mix = np.minimum(efs_mix, 1024)
+    k_max, ef_max = 100, max(ef, int(efs_mix.max()))
+    sv = aqr.Server(ix, k_max, ef_max, ring=args.ring, m_ef=mef, n_rerank=nrr, tau_gap=tg,
+                    tau_ratio=tr, idle_ms=200, visited_log2=args.serve_vb)
+    streams = {"fixed": (np.full(nq, 10, np.int32), np.full(nq, ef, np.int32)),
+               "mixed": (ks_mix.astype(np.int32), efs_mix.astype(np.int32))}
+    res = {}
+    try:
+        w = min(nq, 2000)
+        sv.replay(np.zeros(w), Q[:w], streams["fixed"][0][:w], streams["fixed"][1][:w])
+        for si, (sname, (ks, es)) in enumerate(streams.items()):
+            m = min(nq, 20_000)
+            _, _, _, wall, svc = sv.replay(np.zeros(m), Q[:m], ks[:m], es[:m], service=True)
+            sat = m / wall
+            rows = []
+            for li, load in enumerate(loads if sname == "fixed" else loads[-1:]):
+                rate = load * sat
+                cnt = int(min(nq, max(5000, rate * seconds)))
+                arr = W.poisson_arrivals(rate, cnt, seed=7000 + 100 * si + li)
+                ids, _, lat, wall, svc = sv.replay(arr, Q[:cnt], ks[:cnt], es[:cnt], service=True)
+                rq = recall_per_query(ids, X, Q[:cnt], gt_ids[:cnt], gt_d[:cnt],
+                                      np.minimum(ks[:cnt], 10))
+                row = {"load": load, "offered_qps": round(rate, 1),
+                       "achieved_qps": round(cnt / wall, 1), "requests": cnt,
+                       "p50_ms": round(float(np.percentile(lat, 50)) * 1e3, 4),
+                       "p99_ms": round(float(np.percentile(lat, 99)) * 1e3, 4),
+                       "service_p50_ms": round(float(np.percentile(svc, 50)) * 1e3, 4),
+                       "service_p99_ms": round(float(np.percentile(svc, 99)) * 1e3, 4),
+                       "recall@min(k,10)": round(float(rq.mean()), 5)}
+                rows.append(row)
+                log(f"serving {sname} load {load}: {row}")
+            res[sname] = {"saturation_qps": round(sat, 1), "loads": rows}
+    finally:
+        sv.stop()
+    return res
+
+
 def main():
+    T0 = time.perf_counter()
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=200,
                     help="untimed steps before each timed region: an idle GPU sits at a low "
                          "clock and needs a fraction of a second of steady load to leave it")
-    ap.add_argument("--workload", default="sift1m")
+    ap.add_argument("--workload", default="serving",
+                    help="workload of the headline line (default: the 10M x 96 configuration, "
+                         "followed by the --legs workloads as extra keys)")
+    ap.add_argument("--legs", default=",".join(DEFAULT_LEGS),
+                    help="further workloads measured after the default headline")
+    ap.add_argument("--no-legs", action="store_true")
+    ap.add_argument("--no-serve-leg", action="store_true",
+                    help="skip the request-latency leg through the server kernel")
     ap.add_argument("--n", type=int, default=None, help="base subset (testing only)")
     ap.add_argument("--nq", type=int, default=None)
     ap.add_argument("--efs", default=None, help="comma-separated ef sweep")
-    ap.add_argument("--cpu-sample", type=int, default=10000)
+    ap.add_argument("--cpu-sample", type=int, default=0,
+                    help="cap of the CPU oracle's sample (0: sized to about 15 s of host work)")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--profile", action="store_true",
                     help="skip sweeps and the CPU leg; time the AQR path at --ef")
@@ -873,327 +1306,41 @@ def main():
     if args.build_only:
         return bench_build(args, wl, threads)
     if args.workload == "batched":
-        if args.cpu_sample == 10000:
+        if args.cpu_sample == 0:
             args.cpu_sample = 300
         return bench_batched(args, torch, aqr, W, wl, dev, threads)
     if args.serve:
         return bench_serving(args, torch, aqr, W, wl, dev, threads)
-    k = 10 if 10 in wl.k else wl.k[0]
-    t_all = time.perf_counter()
-
-    log(f"generating {args.workload}")
-    X = W.base(args.workload, args.n)
-    Q = W.queries(args.workload, args.nq)
-    n, d = X.shape
-    nq = Q.shape[0]
-
-    qz, g, codes, info, ginfo, t_quant, t_build = build_index(args, wl, X, threads)
-    ix = aqr.aqr_index_bind(qz, g, codes, X, device=dev)
-    gt_ids = gt_d = None
-    if not args.profile:
-        log("ground truth")
-        gt_ids, gt_d = ground_truth(X, Q, k, dev)
-    Qd = torch.from_numpy(Q).to(dev)
-
-    # the workload's ef list, then finer steps above it, so the cheapest ef that
-    # reaches the recall target is found for both searches alike
-    efs = ([int(e) for e in args.efs.split(",")] if args.efs else
-           sorted(set(wl.ef) | {288, 304, 320, 352, 384, 448, 512}))
-
-    def recall_of(ids):
-        return recall_at(ids.cpu().numpy(), X, Q, gt_ids, gt_d, k)
-
-    aqr_table, fp_table = [], []
-    aqr_pick = fp_pick = None
-    if args.profile:
-        cfg = rerank_by_name(args.rerank or "no-et")
-        aqr_pick = (args.ef or 256, float("nan"), cfg)
-    else:
-        for ef in efs:
-            for cfg in RERANK_CONFIGS:
-                r = AqrRunner(aqr, ix, nq, k, ef, dev, rerank=cfg)
-                ids, _ = r.step(Qd)
-                torch.cuda.synchronize()
-                rec = recall_of(ids)
-                aqr_table.append((ef, cfg[0], round(rec, 5)))
-                log(f"aqr ef={ef} rerank={cfg[0]} recall@10={rec:.4f}")
-                if rec >= TARGET_RECALL:
-                    aqr_pick = (ef, rec, cfg)
-                    break
-            if aqr_pick:
-                break
-        if aqr_pick is None:
-            best = max(aqr_table, key=lambda t: t[2])
-            aqr_pick = (best[0], best[2], next(c for c in RERANK_CONFIGS if c[0] == best[1]))
-        for ef in efs:
-            r = Fp32Runner(aqr, ix, nq, k, ef, dev)
-            ids, _ = r.step(Qd)
-            torch.cuda.synchronize()
-            rec = recall_of(ids)
-            fp_table.append((ef, round(rec, 5)))
-            log(f"fp32 ef={ef} recall@10={rec:.4f}")
-            if rec >= TARGET_RECALL:
-                fp_pick = (ef, rec)
-                break
-        if fp_pick is None:
-            fp_pick = (efs[-1], fp_table[-1][1])
-
-    # ---- tuning (results do not depend on it) and the timed AQR path ----
-    ef_a = aqr_pick[0]
-    # launch shape of the timed search without --tune: the one the tuning
-    # loop below picks on the default workload (results do not depend on it)
-    tuning = {"visited_log2": 8, "waves_per_block": 4}
-    if args.vb or args.wpb:
-        tuning = {"visited_log2": args.vb, "waves_per_block": args.wpb}
-    elif args.tune and not args.profile:
-        best_ms = None
-        r0 = AqrRunner(aqr, ix, nq, k, ef_a, dev, rerank=aqr_pick[2], **tuning)
-        spin_up(torch, lambda m: r0.search_only(Qd))
-        for vb in (6, 7, 8, 9, 10, 11, 12):
-            for wpb in (1, 2, 4):
-                try:
-                    r = AqrRunner(aqr, ix, nq, k, ef_a, dev, visited_log2=vb,
-                                  waves_per_block=wpb, rerank=aqr_pick[2])
-                    ms_t, _ = timed(torch, lambda m: r.search_only(Qd), 5, 1)
-                except aqr.AqrError as e:  # LDS limit of the device
-                    log(f"tune visited_log2={vb} waves_per_block={wpb}: skipped ({e})")
-                    continue
-                log(f"tune visited_log2={vb} waves_per_block={wpb}: {ms_t:.3f} ms")
-                if best_ms is None or ms_t < best_ms:
-                    best_ms, tuning = ms_t, {"visited_log2": vb, "waves_per_block": wpb}
-        log(f"tuning picked {tuning}")
-    runner = AqrRunner(aqr, ix, nq, k, ef_a, dev, rerank=aqr_pick[2], **tuning)
-
-    def aqr_step(marks):
-        if marks:
-            marks[0].record()
-            runner.search_only(Qd)
-            marks[1].record()
-            runner.rerank_only(Qd)
-            marks[2].record()
-        else:
-            runner.step(Qd)
-
-    log(f"timing AQR at ef={ef_a}: warmup {args.warmup}, steps {args.steps}")
-    ms_aqr, per = timed(torch, aqr_step, args.steps, args.warmup, kernel_events=3)
-    qps_aqr = nq / (ms_aqr / 1e3)
-    search_ms, rerank_ms = per
-    log(f"AQR {qps_aqr:,.0f} QPS ({ms_aqr:.3f} ms/step; search {search_ms:.3f} ms, "
-        f"rerank {rerank_ms:.3f} ms)")
-
-    # per-query counters (separate, untimed run with a large visited cache so
-    # that evaluations count distinct nodes)
-    counts = torch.zeros((nq, 8), dtype=torch.int32, device=dev)
-    big = AqrRunner(aqr, ix, nq, k, ef_a, dev, visited_log2=14, waves_per_block=1,
-                    rerank=aqr_pick[2])
-    big.search_only(Qd, taps=dict(cap=0, counts=counts))
-    torch.cuda.synchronize()
-    cnt_big = counts.cpu().numpy().astype(np.int64)
-    counts.zero_()
-    runner.search_only(Qd, taps=dict(cap=0, counts=counts))
-    torch.cuda.synchronize()
-    cnt = counts.cpu().numpy().astype(np.int64)
-    d_pad = info["d_pad"]
-    s0 = (2 * ginfo["M"] + 15) // 16 * 16
-    s1 = (ginfo["M"] + 15) // 16 * 16
-    nc = min(max(max(ef_a, k) // aqr_pick[2][4], k), max(ef_a, k))
-    # algorithmic bytes of one search launch (distinct evaluations)
-    code_bytes = int((cnt_big[:, 1].sum() + cnt_big[:, 2].sum() + nq) * d_pad)
-    adj_bytes = int(cnt_big[:, 0].sum() * s0 * 4 + cnt_big[:, 4].sum() * s1 * 4)
-    io_bytes = int(nq * (4 * d + 8 * nc + 4))
-    alg_bytes = code_bytes + adj_bytes + io_bytes
-    achieved = alg_bytes / (search_ms / 1e3) / 1e9
-    reeval = float(cnt[:, 1].sum() / max(1, cnt_big[:, 1].sum()) - 1.0)
-    lat_us = cnt[:, 5] / 100.0  # 100 MHz real-time clock
-    sha = source_sha()
-    prof_name = (f"search_{'sq8' if args.sq8 else 'u8'}_{args.workload}_ef{ef_a}"
-                 f"_vb{tuning['visited_log2']}"
-                 f"_wpb{tuning['waves_per_block']}")
-    traffic = traffic_from_profile(prof_name, sha)
-
-    copy_info = None
-    if args.profile:
-        # a plain copy of known size: its FETCH_SIZE/WRITE_SIZE readings scale
-        # the counters of the search kernel to bytes
-        src = torch.empty(args.copy_mib << 20, dtype=torch.uint8, device=dev).fill_(1)
-        dst = torch.empty_like(src)
-        for _ in range(3):
-            dst.copy_(src)
-        torch.cuda.synchronize()
-        copy_info = {"bytes": args.copy_mib << 20}
-
-    # ---- timed FP32 baseline ----
-    fp = None
-    if fp_pick is not None:
-        ef_f = fp_pick[0]
-        # the baseline gets the same launch-shape treatment as the AQR search:
-        # without --tune, the shape the tuning loop picks for it on the default
-        # workload (FP32 rows are 4x the bytes, so a larger visited cache pays)
-        fp_tuning = ({"visited_log2": args.vb, "waves_per_block": args.wpb}
-                     if (args.vb or args.wpb) else {"visited_log2": 10, "waves_per_block": 4})
-        if args.tune and not args.profile and not (args.vb or args.wpb):
-            best_ms = None
-            r0 = Fp32Runner(aqr, ix, nq, k, ef_f, dev, **fp_tuning)
-            spin_up(torch, lambda m: r0.step(Qd))
-            for vb in (6, 7, 8, 9, 10, 11, 12):
-                for wpb in (1, 2, 4):
-                    try:
-                        r = Fp32Runner(aqr, ix, nq, k, ef_f, dev, visited_log2=vb,
-                                       waves_per_block=wpb)
-                        ms_t, _ = timed(torch, lambda m: r.step(Qd), 5, 1)
-                    except aqr.AqrError as e:
-                        log(f"tune fp32 visited_log2={vb} waves_per_block={wpb}: skipped ({e})")
-                        continue
-                    log(f"tune fp32 visited_log2={vb} waves_per_block={wpb}: {ms_t:.3f} ms")
-                    if best_ms is None or ms_t < best_ms:
-                        best_ms, fp_tuning = ms_t, {"visited_log2": vb, "waves_per_block": wpb}
-            log(f"fp32 tuning picked {fp_tuning}")
-        frun = Fp32Runner(aqr, ix, nq, k, ef_f, dev, **fp_tuning)
-
-        def fp_step(marks):
-            if marks:
-                marks[0].record()
-                frun.step(Qd)
-                marks[1].record()
-            else:
-                frun.step(Qd)
-
-        log(f"timing FP32 HNSW at ef={ef_f}")
-        ms_fp, per_fp = timed(torch, fp_step, args.steps, args.warmup, kernel_events=2)
-        counts.zero_()
-        frun.step(Qd, taps=dict(cap=0, counts=counts))
-        torch.cuda.synchronize()
-        cf = counts.cpu().numpy().astype(np.int64)
-        xs = (d + 3) // 4 * 4
-        fp_bytes = int((cf[:, 1].sum() + cf[:, 2].sum() + nq) * xs * 4 +
-                       cf[:, 0].sum() * s0 * 4 + cf[:, 4].sum() * s1 * 4 + nq * (4 * d + 8 * k))
-        fp = {"value": round(nq / (ms_fp / 1e3), 1), "unit": "queries/s", "ef": ef_f,
-              "tuning": fp_tuning,
-              "recall@10": round(fp_pick[1], 5), "ms_per_step": round(ms_fp, 4),
-              "kernel_ms": round(per_fp[0], 4),
-              "achieved_GBps": round(fp_bytes / (per_fp[0] / 1e3) / 1e9, 1),
-              "p50_query_us": round(float(np.percentile(cf[:, 5] / 100.0, 50)), 2),
-              "p99_query_us": round(float(np.percentile(cf[:, 5] / 100.0, 99)), 2),
-              "sweep": fp_table}
-        log(f"FP32 {fp['value']:,.0f} QPS at ef={ef_f}")
-
-    # ---- recall-QPS curve: the cheapest setting of each search at further
-    # recall targets, timed the same way (the sweeps above stop at 0.98, so
-    # they are continued for higher targets) ----
-    curve = None
-    if not args.profile and not args.no_curve:
-        curve = recall_qps_curve(args, torch, aqr, ix, Qd, nq, k, dev, efs, aqr_table, fp_table,
-                                 tuning, fp_tuning if fp is not None else None, recall_of)
-        curve.append({"target": TARGET_RECALL,
-                      "aqr": {"ef": ef_a, "rerank": aqr_pick[2][0],
-                              "recall@10": round(aqr_pick[1], 5), "qps": round(qps_aqr, 1)},
-                      "fp32": ({"ef": fp["ef"], "recall@10": fp["recall@10"],
-                                "qps": fp["value"]} if fp else None),
-                      "speedup": round(qps_aqr / fp["value"], 3) if fp else None})
-        curve.sort(key=lambda c: c["target"])
-
-    # ---- CPU oracle baseline on a sample of the same queries ----
-    cpu = None
-    parity = None
-    if not args.no_cpu and not args.profile:
-        import oracle as orc
-        orc.set_threads(threads)
-        S = min(args.cpu_sample, nq)
-        gx = aqr.aqr_graph_export(g)
-        index = dict(X=X, codes=codes, d=d, min=info["min"], scale=info["scale"], graph=gx)
-        log(f"CPU oracle on {S} queries with {orc.get_threads()} threads")
-        t = time.perf_counter()
-        _, nrr_, tg_, tr_, mef_ = aqr_pick[2]
-        ref = orc.query(index, Q[:S], k, ef_a, m_ef=mef_, n_rerank=nrr_, tau_gap=tg_,
-                        tau_ratio=tr_,
-                        assembly=ASSEMBLY)
-        dt = time.perf_counter() - t
-        cpu = {"value": round(S / dt, 1), "unit": "queries/s", "cores": orc.get_threads(),
-               "kind": "oracle",
-               "sample": f"first {S} of the {nq} queries, same index, ef={ef_a}, k={k}; "
-                         f"encode + Stage 1 + Stages 2-3 in FP64"}
-        # the same oracle on one thread, on a tenth of the sample
-        S1 = max(1, S // 10)
-        orc.set_threads(1)
-        t = time.perf_counter()
-        orc.query(index, Q[:S1], k, ef_a, m_ef=mef_, n_rerank=nrr_, tau_gap=tg_, tau_ratio=tr_,
-                  assembly=ASSEMBLY)
-        cpu["one_thread_value"] = round(S1 / (time.perf_counter() - t), 1)
-        orc.set_threads(threads)
-        s1 = ref["stage1"]
-        gid = runner.plan.cand_id[:S].cpu().numpy().view(np.uint32)
-        gcnt = runner.plan.cand_cnt[:S].cpu().numpy()
-        exact = sum(int(gcnt[q] == s1["cand_cnt"][q] and
-                        np.array_equal(gid[q, :gcnt[q]], s1["cand_id"][q, :gcnt[q]]))
-                    for q in range(S))
-        same, tied = topk_agreement(runner.plan.out_id[:S].cpu().numpy(),
-                                    runner.plan.out_dist[:S].cpu().numpy(), ref, X, Q,
-                                    np.full(S, k))
-        parity = {"queries": S, "stage1_bit_exact": exact, "topk_identical": same,
-                  "topk_differ_only_by_ties": tied}
-        log(f"oracle {cpu['value']:,.1f} QPS; parity {parity}")
-
-    out = {
-        "metric": "QPS at recall@10>=0.98 on 1 MI355X, AQR-int8 vs FP32 HNSW; p50/p99 latency",
-        "value": round(qps_aqr, 1),
-        "unit": "queries/s",
-        "n_gpus": 1,
-        "steps": args.steps,
-        "warmup": args.warmup,
-        "ms_per_step": round(ms_aqr, 4),
-        "higher_is_better": True,
-        "scaling": "weak",
-        "vs_baseline": None,
-        "dtype": "u8",
-        "data": "synthetic",
-        "config": {
-            "workload": f"{args.workload}: {n:,} x {d} FP32 L2, {wl.n_clusters}-cluster "
-                        f"Gaussian mixture; {nq:,} queries; k={k}"
-                        + ("; plain SQ8 baseline (P_max 0, graph at M_0)" if args.sq8 else "")
-                        + ("" if args.gpu_build else "; graph from the host build")
-                        + ("; per-dimension density weights" if args.weights == "per-dim"
-                           else ""),
-            "n": n, "d": d, "nq": nq, "k": k, "ef": ef_a, "M0": wl.M0, "efc0": wl.efc0,
-            "M_i": ginfo["M"], "efc": ginfo["efc"], "weights": args.weights,
-            "eta": round(info["eta"], 6),
-            "graph_build": ("batched, device searches; quantiser density on the device"
-                            if args.gpu_build else "host"),
-            "delta": round(info["delta"], 6), "m_ef": aqr_pick[2][4],
-            "rerank": aqr_pick[2][0], "n_rerank": aqr_pick[2][1],
-            "assembly": "union" if ASSEMBLY else "fill",
-            "tau_gap": finite_or_none(aqr_pick[2][2]),
-            "tau_ratio": finite_or_none(aqr_pick[2][3]),
-            "recall@10": finite_or_none(round(aqr_pick[1], 5)), "tuning": tuning,
-            "global_batch": nq, "parallelism": "single GPU, one wavefront per query",
-        },
-        "roofline": {
-            "bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
-            "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-            "traffic": traffic, "traffic_profile": prof_name,
-            "kernel": "k_search (Stage 1, 8-bit codes)",
-            "kernel_ms": round(search_ms, 4),
-            "alg_bytes_per_launch": alg_bytes,
-            "code_bytes": code_bytes, "adjacency_bytes": adj_bytes, "io_bytes": io_bytes,
-            "reevaluation_overhead": round(reeval, 4),
-            "expansions_per_query": round(float(cnt[:, 0].mean()), 2),
-            "evaluations_per_query": round(float(cnt[:, 1].mean()), 1),
-        },
-        "rerank_ms": round(rerank_ms, 4),
-        "latency_us": {"p50": round(float(np.percentile(lat_us, 50)), 2),
-                       "p99": round(float(np.percentile(lat_us, 99)), 2),
-                       "what": "per-query Stage-1 device time inside the batch"},
-        "fp32_hnsw": fp,
-        "speedup_vs_fp32": (round(qps_aqr / fp["value"], 3) if fp else None),
-        "aqr_sweep": aqr_table,
-        "recall_qps_curve": curve,
-        "cpu_baseline": cpu,
-        "parity_sample": parity,
-        "build_s": {"quantize": t_quant and round(t_quant, 1),
-                    "graph": t_build and round(t_build, 1)},
-        "device_hip_sha": sha,
-        "copy_kernel": copy_info,
-        "wall_s": round(time.perf_counter() - t_all, 1),
-    }
+    nq = args.nq
+    single = args.profile or args.no_legs or args.workload != "serving"
+    out, ctx = run_search(args, torch, aqr, W, args.workload, dev, threads, nq=nq,
+                          curve_leg=args.workload != "serving", cpu_leg=True, cache=args.cache)
+    if not args.profile and not args.no_serve_leg:
+        log("serving leg on the same index")
+        sres = serving_leg(args, torch, aqr, W, args.workload, ctx, dev)
+        head = sres["fixed"]["loads"][-1]
+        out["latency_ms"] = {
+            "p50": head["p50_ms"], "p99": head["p99_ms"], "load": head["load"],
+            "achieved_qps": head["achieved_qps"],
+            "what": "request latency from arrival to completion through the resident server "
+                    "(Poisson arrivals at this fraction of its saturation rate; k=10 at the "
+                    "headline ef and re-rank setting), queueing included"}
+        out["serving"] = sres
+    if not single:
+        import gc
+        out["legs"] = {}
+        for leg in [x for x in args.legs.split(",") if x]:
+            del ctx
+            gc.collect()
+            torch.cuda.empty_cache()
+            log(f"leg {leg}")
+            lo, ctx = run_search(args, torch, aqr, W, leg, dev, threads, nq=None,
+                                 curve_leg=False, cpu_leg=False, cache=None)
+            out["legs"][leg] = {f: lo[f] for f in (
+                "value", "unit", "ms_per_step", "config", "roofline", "rerank_ms",
+                "stage1_device_us", "fp32_hnsw", "speedup_vs_fp32", "ground_truth", "build_s",
+                "wall_s")}
+    out["wall_s"] = round(time.perf_counter() - T0, 1)
     print(json.dumps(out, allow_nan=False), flush=True)
 
 
