@@ -292,6 +292,10 @@ typedef struct aqr_sparams {
     int32_t waves_per_block; /* 0 = library default */
     int32_t blocks;       /* persistent grid size, 0 = fill the device */
     int32_t visited_log2; /* log2 of visited-cache buckets (4 ids each), 0 = 7 */
+    int32_t w_pool_pages; /* result lists W of a block come from a pool of this many
+                             pages of 64 keys (LDS), a query taking ceil(ef_eff / 64)
+                             pages while it runs; 0 = waves_per_block lists of ef_max;
+                             at least ceil(ef_max / 64), at most 255 */
     const int32_t* order; /* device, nullable: work order of the queries (a permutation) */
 } aqr_sparams;
 

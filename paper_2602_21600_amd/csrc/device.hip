@@ -67,6 +67,8 @@ struct Idx {
     const float* qscale;     // dp (padding 1)
     int64_t n;
     int32_t d, dp, xs, s0, s1;
+    int32_t cs;              // code row stride in bytes (>= dp, whole 128-byte lines)
+    int32_t xst;             // FP32 row stride in floats (>= xs, whole 128-byte lines)
     uint32_t ep;
     int32_t L;
     int32_t idbits;          // ceil(log2(n)), at least 1
@@ -212,7 +214,7 @@ template <>
 struct Rows<false> {
     using Acc = uint32_t;
     __device__ static __forceinline__ uint4 load(const Idx& ix, uint32_t id, int ch) {
-        return reinterpret_cast<const uint4*>(ix.codes + (int64_t)id * ix.dp)[ch];
+        return reinterpret_cast<const uint4*>(ix.codes + (int64_t)id * ix.cs)[ch];
     }
     __device__ static __forceinline__ uint32_t part(uint4 x, uint4 q) {
         uint32_t xx = dot4(x.x, x.x, 0u);
@@ -240,7 +242,7 @@ template <>
 struct Rows<true> {
     using Acc = float;
     __device__ static __forceinline__ uint4 load(const Idx& ix, uint32_t id, int ch) {
-        return reinterpret_cast<const uint4*>(ix.X + (int64_t)id * ix.xs)[ch];
+        return reinterpret_cast<const uint4*>(ix.X + (int64_t)id * ix.xst)[ch];
     }
     __device__ static __forceinline__ float part(uint4 x, uint4 q) {
         float acc = 0.0f;
@@ -396,6 +398,7 @@ struct VisCache {
 // ---------------------------------------------------------------------------
 struct SearchLds {
     int ef_cap, st_cap, vb, xs, dp;
+    bool own_w = true;  // false: W lives in the block's pool, not in this layout
     // Layout of one wave: [FP32 query | query codes | W | neighbour ids |
     // their keys | visited buckets].  W holds keys whose low bit is the
     // expanded flag.  Each array has one spare entry past its end (W: index
@@ -407,7 +410,9 @@ struct SearchLds {
     __host__ __device__ size_t off_qf() const { return 0; }
     __host__ __device__ size_t off_qc() const { return (size_t)xs * 4; }
     __host__ __device__ size_t off_mk() const { return r16(off_qc() + (size_t)dp); }
-    __host__ __device__ size_t off_st() const { return r16(off_mk() + (size_t)(ef_cap + 1) * 8); }
+    __host__ __device__ size_t off_st() const {
+        return r16(off_mk() + (own_w ? (size_t)(ef_cap + 1) * 8 : (size_t)8));  // pooled: the spare entry only
+    }
     __host__ __device__ size_t off_sk() const { return off_st() + (size_t)st_cap * 4; }
     __host__ __device__ size_t off_vis() const { return off_sk() + (size_t)st_cap * 8; }
     __host__ __device__ size_t bytes() const { return r16(off_vis() + ((size_t)8 << vb) + 16); }
@@ -432,6 +437,8 @@ struct SearchArgs {
     int32_t mode;       // 0: Stage-1 candidates; 1: FP32 baseline top-k
     int32_t lg, nch;    // row geometry
     size_t wave_lds;
+    int32_t pool_pages; // W pool of a block: pages of 64 keys (k_search)
+    size_t pool_bytes;  // pool header + pages
     uint32_t* out_id;
     uint32_t* out_D;    // mode 0: integer D; mode 1: FP32 distance bits
     int32_t* out_cnt;
@@ -462,12 +469,11 @@ __device__ __forceinline__ uint64_t readlane64(uint64_t v, int l) {
 template <bool F32, int CPL, int U, int LG, bool TAPS>
 __device__ __forceinline__ void search_query(const SearchArgs& a, const int64_t q, const int efe,
                                              const int nc, const int lane,
-                                             const VisCache& vis, uint64_t* mk,
+                                             const VisCache& vis, uint64_t* mk, uint64_t* spare,
                                              uint32_t* st_id, uint64_t* st_key, uint64_t* visb,
                                              float* qf, uint8_t* qc) {
     const Idx& ix = a.ix;
     const int st_cap = st_cap_of(ix.s0, ix.s1);  // index of the spare neighbour-id entry
-    const int ef_cap = a.ef_cap;                 // index of the spare W entry
     uint32_t qq = 0;
     if (!F32) {
         uint32_t part = 0;
@@ -614,7 +620,8 @@ __device__ __forceinline__ void search_query(const SearchArgs& a, const int64_t 
                 n -= half;
             }
             // The last step reads W[lo] and W[lo + 1] together (lo + 1 <=
-            // wsize <= ef_cap: inside the array, the spare entry at worst).
+            // wsize: inside W, or the LDS word just past W's capacity, whose
+            // value is not used since lo + 1 == wsize leaves lo == wsize).
             // The entry at the key's place shows whether the key is already
             // in W (a node the visited cache forgot); such a key is dropped.
             const uint64_t w0 = mk[lo], w1 = mk[lo + 1];
@@ -653,11 +660,11 @@ __device__ __forceinline__ void search_query(const SearchArgs& a, const int64_t 
                         sh += __builtin_amdgcn_readlane(lo, (int)__builtin_ctzll(it)) <= i ? 1 : 0;
                 }
                 const int p = i + sh;
-                const int dst = v && p < efe ? p : ef_cap;  // others write the spare entry
-                mk[dst] = w;
+                uint64_t* dst = v && p < efe ? mk + p : spare;  // others write the spare entry
+                *dst = w;
             }
-            const int dst = mine && pos < efe ? pos : ef_cap;
-            mk[dst] = key;
+            uint64_t* dst = mine && pos < efe ? mk + pos : spare;
+            *dst = key;
             // the smallest admitted key has rank 0: its position is lo_min
             first = min(first, lo_min);
             wsize = min(efe, wsize + m_adm);
@@ -707,6 +714,65 @@ __device__ __forceinline__ void search_query(const SearchArgs& a, const int64_t 
 template <bool F32, int CPL, int LG>
 constexpr int search_waves_per_eu() { return !F32 && (CPL << LG) <= 16 ? 7 : 1; }
 
+// ---------------------------------------------------------------------------
+// W pool of a block: pages of 64 keys shared by the block's waves.  A wave
+// takes ceil(ef_eff / 64) contiguous pages for one query and returns them
+// after it, so a block holds as many result lists at once as their sizes
+// fit, not waves_per_block lists of ef_max each.  Allocation is first fit
+// under a block lock, by lane 0.  A wave that finds no room records itself
+// as the waiting wave; while one wave waits no other wave allocates, so the
+// waiting wave is served as soon as enough pages are returned (every other
+// wave either holds pages and will return them after its query, or holds
+// none), and the pool holds at least one list of ef_max.
+// ---------------------------------------------------------------------------
+struct PoolHdr {
+    int lock;
+    int want;                 // 1 + the waiting wave, or 0
+    unsigned char owner[8];   // [pool_pages]: 1 + the owning wave, or 0 (extends past the struct)
+};
+
+__host__ __device__ constexpr size_t pool_hdr_bytes(int pages) {
+    return ((size_t)8 + (size_t)pages + 15) & ~(size_t)15;
+}
+
+// lane 0 only: the first page of a run of `need` free pages, or -1
+__device__ __forceinline__ int pool_try(PoolHdr* h, int pages, int need, int me) {
+    while (atomicCAS(&h->lock, 0, 1) != 0) __builtin_amdgcn_s_sleep(1);
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+    volatile unsigned char* own = h->owner;
+    volatile int* want = &h->want;
+    int r = -1;
+    const int w = *want;
+    if (w == 0 || w == me) {
+        int run = 0;
+        for (int i = 0; i < pages; ++i) {
+            run = own[i] ? 0 : run + 1;
+            if (run == need) {
+                r = i + 1 - need;
+                break;
+            }
+        }
+        if (r >= 0) {
+            for (int j = 0; j < need; ++j) own[r + j] = (unsigned char)me;
+            if (w == me) *want = 0;
+        } else if (w == 0) {
+            *want = me;
+        }
+    }
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+    atomicExch(&h->lock, 0);
+    return r;
+}
+
+__device__ __forceinline__ void pool_release(PoolHdr* h, int start, int need) {
+    while (atomicCAS(&h->lock, 0, 1) != 0) __builtin_amdgcn_s_sleep(1);
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+    volatile unsigned char* own = h->owner;
+    for (int j = 0; j < need; ++j) own[start + j] = 0;
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+    atomicExch(&h->lock, 0);
+}
+
 template <bool F32, int CPL, int U, int LG, bool TAPS>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(search_waves_per_eu<F32, CPL, LG>())))
 void k_search(SearchArgs a) {
@@ -714,11 +780,15 @@ void k_search(SearchArgs a) {
     const int lane = lane_id();
     const int wave = threadIdx.x / kWave;
     const Idx& ix = a.ix;
-    // The 8-bit search encodes the query straight from global memory, so its
-    // layout has no FP32 query (xs 0); the FP32 search keeps it in LDS.
-    const SearchLds L{a.ef_cap, st_cap_of(ix.s0, ix.s1), a.vb, F32 ? ix.xs : 0, ix.dp};
-    unsigned char* base = smem + (size_t)wave * a.wave_lds;
-    uint64_t* mk = reinterpret_cast<uint64_t*>(base + L.off_mk());
+    // Block layout: [pool header | W pool pages | wave 0 | wave 1 | ...].  The
+    // 8-bit search encodes the query straight from global memory, so its
+    // wave layout has no FP32 query (xs 0); the FP32 search keeps it in LDS.
+    // A wave's own layout holds no W, only W's spare entry.
+    PoolHdr* ph = reinterpret_cast<PoolHdr*>(smem);
+    uint64_t* pool = reinterpret_cast<uint64_t*>(smem + pool_hdr_bytes(a.pool_pages));
+    const SearchLds L{a.ef_cap, st_cap_of(ix.s0, ix.s1), a.vb, F32 ? ix.xs : 0, ix.dp, false};
+    unsigned char* base = smem + a.pool_bytes + (size_t)wave * a.wave_lds;
+    uint64_t* spare = reinterpret_cast<uint64_t*>(base + L.off_mk());
     uint32_t* st_id = reinterpret_cast<uint32_t*>(base + L.off_st());
     uint64_t* st_key = reinterpret_cast<uint64_t*>(base + L.off_sk());
     uint64_t* visb = reinterpret_cast<uint64_t*>(base + L.off_vis());
@@ -726,6 +796,10 @@ void k_search(SearchArgs a) {
     uint8_t* qc = base + L.off_qc();
 
     VisCache vis{visb, a.vb, max(ix.idbits, a.vb + 1)};
+
+    for (int i = threadIdx.x; i < (int)pool_hdr_bytes(a.pool_pages) / 4; i += blockDim.x)
+        reinterpret_cast<int*>(smem)[i] = 0;
+    __syncthreads();
 
     for (;;) {
         // Every lane takes part in the work-counter atomic (only lane 0 adds
@@ -773,8 +847,22 @@ void k_search(SearchArgs a) {
                     }
                 }
             } else {
-                search_query<F32, CPL, U, LG, TAPS>(a, q, efe, nc, lane, vis, mk, st_id, st_key,
-                                             visb, qf, qc);
+                // the query's W: ceil(ef_eff / 64) pages of the block's pool
+                const int need = (efe + kWave - 1) / kWave;
+                int start = -1;
+                for (;;) {
+                    int r = -1;
+                    if (lane == 0) r = pool_try(ph, a.pool_pages, need, wave + 1);
+                    wsync();
+                    start = uni(r);
+                    if (start >= 0) break;
+                    __builtin_amdgcn_s_sleep(4);
+                }
+                search_query<F32, CPL, U, LG, TAPS>(a, q, efe, nc, lane, vis,
+                                                    pool + (size_t)start * kWave, spare, st_id,
+                                                    st_key, visb, qf, qc);
+                wsync();
+                if (lane == 0) pool_release(ph, start, need);
             }
         }
         wsync();
@@ -937,7 +1025,7 @@ __device__ __forceinline__ void rerank_query(const RerankArgs& a, const int lane
                 const int ch = g.sub + c * g.G;
                 if (id != kNone && ch < g.nch) {
                     const uint4 x =
-                        reinterpret_cast<const uint4*>(ix.codes + (int64_t)id * ix.dp)[ch];
+                        reinterpret_cast<const uint4*>(ix.codes + (int64_t)id * ix.cs)[ch];
                     s += asym_chunk(x, qr[c], mr[c], sr[c]);
                 }
             }
@@ -1304,8 +1392,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k
         } else {
             // Stage 1 writes its N_c candidates into the search part; the
             // re-rank reads them from there
-            search_query<false, CPL, U, LG, false>(sa, 0, efe, nc, lane, vis, mk, st_id, st_key,
-                                           visb, qf, qc);
+            search_query<false, CPL, U, LG, false>(sa, 0, efe, nc, lane, vis, mk, mk + ef_cap,
+                                                   st_id, st_key, visb, qf, qc);
             const int cnt = uni(*reinterpret_cast<const int*>(st_id));
             for (int j = lane; j < cnt; j += kWave) rids[j] = (uint32_t)mk[j] >> 1;
             wsync();
@@ -1354,9 +1442,22 @@ namespace {
 
 struct Layout {
     size_t codes, X, adj0, ubase, uadj, qmin, qscale, total;
-    int32_t dp, xs, s0, s1;
+    int32_t dp, xs, s0, s1, cs, xst;
     int64_t rows;
 };
+
+// Row stride of a gathered row of b bytes: the next power of two up to 128,
+// whole 128-byte lines beyond.  A row then never straddles more cache lines
+// than its length needs (a 96-byte row at a 96-byte stride touches 1.5
+// lines on average, at a 128-byte stride one).
+int64_t line_stride(int64_t b) {
+    if (b <= 128) {
+        int64_t p = 16;
+        while (p < b) p <<= 1;
+        return p;
+    }
+    return (b + 127) / 128 * 128;
+}
 
 size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
@@ -1365,14 +1466,16 @@ Layout layout_of(const aqr_quantizer* qz, const aqr_graph* g) {
     const int64_t n = g->n;
     L.dp = qz->info.d_pad;
     L.xs = round_up(qz->info.d, 4);
+    L.cs = (int32_t)line_stride(L.dp);
+    L.xst = (int32_t)(line_stride((int64_t)L.xs * 4) / 4);
     L.s0 = round_up(2 * g->M, 16);
     L.s1 = round_up(g->M, 16);
     L.rows = std::max<int64_t>(g->upper_off[n], 1);
     size_t o = 0;
     L.codes = o;
-    o = align256(o + (size_t)n * L.dp);
+    o = align256(o + (size_t)n * L.cs);
     L.X = o;
-    o = align256(o + (size_t)n * L.xs * 4);
+    o = align256(o + (size_t)n * L.xst * 4);
     L.adj0 = o;
     o = align256(o + (size_t)n * L.s0 * 4);
     L.ubase = o;
@@ -1437,11 +1540,19 @@ extern "C" aqr_status aqr_index_bind(const aqr_quantizer* qz, const aqr_graph* g
         // host staging in the device layout
         std::vector<float> xs;
         const float* Xsrc = X;
-        if (L.xs != d) {
-            xs.assign((size_t)n * L.xs, 0.0f);
+        if (L.xst != d) {
+            xs.assign((size_t)n * L.xst, 0.0f);
             for (int64_t i = 0; i < n; ++i)
-                std::memcpy(&xs[(size_t)i * L.xs], X + i * d, sizeof(float) * d);
+                std::memcpy(&xs[(size_t)i * L.xst], X + i * d, sizeof(float) * d);
             Xsrc = xs.data();
+        }
+        std::vector<uint8_t> cst;
+        const uint8_t* Csrc = codes;
+        if (L.cs != L.dp) {
+            cst.assign((size_t)n * L.cs, 0);
+            for (int64_t i = 0; i < n; ++i)
+                std::memcpy(&cst[(size_t)i * L.cs], codes + i * L.dp, (size_t)L.dp);
+            Csrc = cst.data();
         }
         std::vector<uint32_t> a0((size_t)n * L.s0, AQR_NONE);
         for (int64_t i = 0; i < n; ++i)
@@ -1462,8 +1573,8 @@ extern "C" aqr_status aqr_index_bind(const aqr_quantizer* qz, const aqr_graph* g
             const void* src;
             size_t bytes;
         } cps[] = {
-            {L.codes, codes, (size_t)n * L.dp},
-            {L.X, Xsrc, (size_t)n * L.xs * 4},
+            {L.codes, Csrc, (size_t)n * L.cs},
+            {L.X, Xsrc, (size_t)n * L.xst * 4},
             {L.adj0, a0.data(), a0.size() * 4},
             {L.ubase, ub.data(), ub.size() * 4},
             {L.uadj, ua.data(), ua.size() * 4},
@@ -1489,6 +1600,8 @@ extern "C" aqr_status aqr_index_bind(const aqr_quantizer* qz, const aqr_graph* g
         v.d = d;
         v.dp = L.dp;
         v.xs = L.xs;
+        v.cs = L.cs;
+        v.xst = L.xst;
         v.s0 = L.s0;
         v.s1 = L.s1;
         v.ep = g->ep;
@@ -1666,13 +1779,22 @@ aqr_status run_search(const aqr_index* ix, const float* Q, int64_t nq, const int
     if (v.s0 > 256)
         return fail(AQR_ERR_INVALID_ARG, std::string(who) + ": layer-0 rows above 256 entries are not supported");
     const int ef_cap = (sp->ef_max + 63) / 64 * 64;  // W capacity: whole 64-entry slots
+    // W comes from a pool of 64-key pages per block; by default it holds one
+    // list of ef_max for every wave
+    const int max_pages = ef_cap / 64;
+    const int pool_pages = sp->w_pool_pages > 0 ? sp->w_pool_pages : wpb * max_pages;
+    if (pool_pages < max_pages)
+        return fail(AQR_ERR_INVALID_ARG, std::string(who) + ": w_pool_pages below one result list of ef_max");
+    if (pool_pages > 255)
+        return fail(AQR_ERR_INVALID_ARG, std::string(who) + ": w_pool_pages above 255");
     dev::SearchLds sl{ef_cap,
                       std::max(v.s0, v.s1) <= 64 ? 64 : (std::max(v.s0, v.s1) + 63) / 64 * 64, vb,
-                      f32 ? v.xs : 0, v.dp};  // the 8-bit search keeps no FP32 query in LDS
+                      f32 ? v.xs : 0, v.dp, false};  // the 8-bit search keeps no FP32 query in LDS
     const size_t wl = sl.bytes();
-    const size_t lds = wl * wpb;
+    const size_t pool_bytes = dev::SearchLds::r16(dev::pool_hdr_bytes(pool_pages) + (size_t)pool_pages * 64 * 8);
+    const size_t lds = pool_bytes + wl * wpb;
     if (lds > ix->max_lds)
-        return fail(AQR_ERR_INVALID_ARG, std::string(who) + ": LDS per block exceeds the device limit (lower ef_max, visited_log2 or waves_per_block)");
+        return fail(AQR_ERR_INVALID_ARG, std::string(who) + ": LDS per block exceeds the device limit (lower ef_max, visited_log2, waves_per_block or w_pool_pages)");
     dev::SearchArgs a{};
     a.ix = v;
     a.Q = Q;
@@ -1690,6 +1812,8 @@ aqr_status run_search(const aqr_index* ix, const float* Q, int64_t nq, const int
     a.nch = nch;
     a.lg = std::max(2, pow2_lg_for(nch));
     a.wave_lds = wl;
+    a.pool_pages = pool_pages;
+    a.pool_bytes = pool_bytes;
     a.out_id = out_id;
     a.out_D = out_D;
     a.out_cnt = out_cnt;

@@ -62,25 +62,54 @@ def same(a, b, nq):
     np.testing.assert_array_equal(a["kind"], b["kind"])
 
 
-def test_batch_matches_oracle(orc, small):
-    from test_gpu_parity import oracle_stage1
+@pytest.mark.parametrize("et", ["table3", "off"])
+def test_batch_matches_oracle(orc, small, et):
+    # Stage 1 of the whole uneven batch bit-exact against the oracle; Stages
+    # 2-3 by the parity protocol (distances within 1e-5, ids equal up to ties
+    # inside that tolerance, early-termination decisions equal except within
+    # 1e-5 of a threshold), with Table 3's thresholds and with early
+    # termination off
+    import torch
+    from paper_2602_21600_amd import aqr
+    from test_gpu_parity import check_rerank, oracle_stage1
     Q, k, ef = small["Q"], small["k"], small["ef"]
     inf = float("inf")
-    out = run_plan(small, Q, k, ef, tau_gap=inf, tau_ratio=inf)[0]
+    tau = dict(tau_gap=0.010, tau_ratio=1.008) if et == "table3" else dict(tau_gap=inf,
+                                                                           tau_ratio=inf)
+    out = run_plan(small, Q, k, ef, **tau)[0]
     o, _ = oracle_stage1(orc, small, Q, k, ef)
     np.testing.assert_array_equal(out["cand_cnt"], o["cand_cnt"])
     for q in range(Q.shape[0]):
         c = o["cand_cnt"][q]
         np.testing.assert_array_equal(out["cand_id"][q, :c], o["cand_id"][q, :c])
-    # final lists: the oracle re-ranks the same candidates; distances within
-    # 1e-5 and ids equal up to ties inside that tolerance
-    ref = orc.rerank(small["X"], small["codes"], small["min"], small["scale"], Q,
-                     np.ascontiguousarray(out["cand_id"]), out["cand_cnt"], k, tau_gap=inf,
-                     tau_ratio=inf, k_stride=100)
-    for q in range(Q.shape[0]):
-        kq = int(k[q])
-        np.testing.assert_allclose(out["dist"][q, :kq], ref["dist"][q, :kq], rtol=1e-5)
-        assert np.all(out["id"][q, kq:] == -1)
+    # the plan's Stages 2-3 once more on its own candidates, with the taps the
+    # protocol needs: the same kernel on the same inputs gives the same rows
+    nq, ncs = out["cand_id"].shape
+    dev = "cuda"
+    Qd = torch.from_numpy(Q).to(dev)
+    cid = torch.from_numpy(np.ascontiguousarray(out["cand_id"]).view(np.int32)).to(dev)
+    cnt = torch.from_numpy(out["cand_cnt"]).to(dev)
+    kd = torch.from_numpy(k).to(dev)
+    oid = torch.zeros((nq, 100), dtype=torch.int32, device=dev)
+    od = torch.zeros((nq, 100), dtype=torch.float32, device=dev)
+    ok = torch.zeros((nq, 100), dtype=torch.uint8, device=dev)
+    taps = dict(a_id=torch.zeros((nq, ncs), dtype=torch.int32, device=dev),
+                a_dist=torch.zeros((nq, ncs), dtype=torch.float32, device=dev),
+                et=torch.zeros(nq, dtype=torch.uint8, device=dev),
+                nrr=torch.zeros(nq, dtype=torch.int32, device=dev))
+    aqr.aqr_rerank(small["ix"], Qd, cid, cnt, kd, oid, od, ok, n_rerank=28, taps=taps, **tau)
+    torch.cuda.synchronize()
+    gr = dict(id=oid.cpu().numpy(), dist=od.cpu().numpy(), kind=ok.cpu().numpy())
+    gr.update({kk: v.cpu().numpy() for kk, v in taps.items()})
+    gr["a_id"] = gr["a_id"].view(np.uint32)
+    np.testing.assert_array_equal(gr["id"], out["id"])
+    np.testing.assert_array_equal(gr["dist"].view(np.uint32), out["dist"].view(np.uint32))
+    s1 = dict(cand_id=np.ascontiguousarray(out["cand_id"]), cand_cnt=out["cand_cnt"])
+    check_rerank(orc, small, Q, s1, k, gr, n_rerank=28, **tau)
+    if et == "table3":
+        assert gr["et"].sum() > 0  # the termination test acted on part of the batch
+    for q in range(nq):
+        assert np.all(out["id"][q, k[q]:] == -1)
 
 
 def test_alone_equals_batch_and_orders(orc, small):
@@ -120,6 +149,10 @@ def test_graph_replays_equal_eager(orc, small):
     dict(waves_per_block=1, visited_log2=8, rerank_waves_per_block=2),
     dict(waves_per_block=2, visited_log2=10, rerank_waves_per_block=4),
     dict(waves_per_block=4, visited_log2=6, rerank_waves_per_block=1, blocks=5),
+    # W pools smaller than one list of ef_max per wave: queries wait for pages
+    dict(waves_per_block=4, visited_log2=7, w_pool_pages=8),
+    dict(waves_per_block=4, visited_log2=8, w_pool_pages=13, blocks=7),
+    dict(waves_per_block=2, visited_log2=9, w_pool_pages=9),
 ])
 def test_tuning_does_not_change_results(orc, small, tuning):
     Q, k, ef = small["Q"], small["k"], small["ef"]
