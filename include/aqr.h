@@ -475,19 +475,39 @@ void aqr_plan_free(aqr_plan* plan);
 /* ------------------------------------------------------------------------ */
 
 typedef struct aqr_server_params {
-    int32_t ring;         /* request slots (the admission limit) */
+    int32_t ring;         /* request slots: requests admitted and not yet collected */
     int32_t k_max;        /* largest k accepted (row length of a result) */
-    int32_t ef_max;       /* largest ef accepted (<= 1024; sizes the LDS of every wave) */
+    int32_t ef_max;       /* largest ef accepted (<= 1024) */
     int32_t m_ef;         /* ef multiplier of N_c */
     int32_t n_rerank;     /* N_rerank */
     float tau_gap, tau_ratio, eps;  /* early termination (Table 3 row "0.97+": 0.010, 1.008) */
     int32_t waves_per_block;        /* 0 = 4 */
-    int32_t visited_log2;           /* 0 = 9: the serving kernel runs four waves per SIMD,
-                                       so its LDS has room for the larger cache; values
-                                       below idbits - 15 are raised to it */
+    int32_t visited_log2;           /* largest visited cache of a request (log2 buckets of
+                                       four ids), 0 = 9; a request gets
+                                       2^clamp(ceil(log2 ef_eff) + 1, lo, this), lo = the
+                                       smallest that keeps the stored id remainder within
+                                       15 bits (idbits - 15, at least 4) */
     int32_t idle_ms;      /* the kernel exits after this long without unclaimed requests */
-    int32_t reserved;
+    int32_t w_pool_pages; /* per-request LDS of a block: a pool of this many 512-byte pages
+                             shared by its waves; 0 = waves_per_block times the largest
+                             request; at most 255 */
+    int64_t state_budget; /* bytes of request state (query, result ids and distances) in
+                             pinned host memory; 0 = ring requests at k_max */
+    int64_t lds_budget_pages; /* admission limit on the LDS pages of requests admitted and
+                                 not yet collected; 0 = what the resident blocks' pools hold
+                                 at once */
 } aqr_server_params;
+
+typedef struct aqr_server_usage_t {
+    int32_t ring;
+    int32_t slots_used;
+    int64_t lds_budget_pages;
+    int64_t lds_used_pages;
+    int64_t state_budget;
+    int64_t state_used;
+    int32_t blocks;       /* resident blocks of the server kernel */
+    int32_t pool_pages;   /* LDS pool pages of a block */
+} aqr_server_usage_t;
 
 typedef struct aqr_server aqr_server;
 
@@ -504,31 +524,47 @@ size_t aqr_server_workspace_size(void);
  * needed.  While the kernel runs, its blocks hold most of the device; other
  * work on the device runs in what they leave free, and aqr_server_stop (or
  * idle_ms of quiet) releases it.  ws: caller-owned device workspace
- * (aqr_server_workspace_size() bytes) for the claim counters.  Each request runs Stage 1 and Stages 2-3
- * with the same code as aqr_search/aqr_rerank, so its result equals the
- * batch result for the same query, k and ef.
+ * (aqr_server_workspace_size() bytes) for the claim counters.
+ *
+ * Memory per request, sized by its own k and ef (not k_max and ef_max):
+ * LDS pages from its block's pool for the result list W (ef_eff keys), the
+ * neighbour staging and a visited cache that grows with ef_eff, overlaid
+ * after Stage 1 by the Stage 2-3 arrays for its N_c candidates; and request
+ * state in pinned host memory (the query and k ids and distances).
+ * Admission charges both against the server's budgets
+ * (aqr_server_request_cost) and returns them when the result is collected.
+ * Each request runs Stage 1 and Stages 2-3 with the same code as
+ * aqr_search/aqr_rerank, so its result equals the batch result for the same
+ * query, k and ef, whatever else is in flight.
  */
 aqr_status aqr_server_create(const aqr_index* ix, const aqr_server_params* p, void* ws,
                              size_t ws_bytes, aqr_server** server);
 /* Admit one request (host query of d floats); *ticket is an opaque handle
- * for aqr_server_poll.  A slot stays taken until its result is collected:
- * AQR_ERR_BUSY when all `ring` slots are taken; AQR_ERR_INVALID_ARG when k or
- * ef exceed the server limits. */
+ * for aqr_server_poll.  AQR_ERR_BUSY when the request does not fit: no free
+ * slot, its queue entry not yet read by a worker, or its LDS pages or state
+ * bytes beyond what the budgets have left; it fits again once earlier
+ * results are collected.  AQR_ERR_INVALID_ARG when k or ef exceed the
+ * server limits. */
 aqr_status aqr_server_submit(aqr_server* s, const float* q, int32_t k, int32_t ef,
                              uint64_t* ticket);
 /* *done = 1 and the result row (k_max entries, padded with (-1, +inf)) is
  * copied when the request is complete; the slot is then free again. */
 aqr_status aqr_server_poll(aqr_server* s, uint64_t ticket, int32_t* out_id, float* out_dist,
                            int32_t* done);
+/* The LDS pages and state bytes a request of this k and ef is charged. */
+aqr_status aqr_server_request_cost(const aqr_server* s, int32_t k, int32_t ef,
+                                   int32_t* lds_pages, int64_t* state_bytes);
+/* Budgets and what is in use. */
+aqr_status aqr_server_usage(aqr_server* s, aqr_server_usage_t* usage);
 aqr_status aqr_server_stop(aqr_server* s);
 void aqr_server_destroy(aqr_server* s);
 /*
  * Replay an arrival trace from the host: request i (query Q[i], k[i], ef[i])
  * arrives at arrival_s[i] seconds after the start and is submitted then, or
- * as soon as a slot frees up; latency_s[i] runs from its arrival to the poll
- * that finds it complete; service_s[i] (nullable) is the device time from
- * the wave's claim of the request to its completion.  out_id/out_dist
- * (nullable): [n][k_max].
+ * as soon as the server admits it; latency_s[i] runs from its arrival to the
+ * poll that finds it complete; service_s[i] (nullable) is the device time
+ * from the wave's claim of the request to its completion.  out_id/out_dist
+ * (nullable): [n][k_max].  AQR_ERR_STATE when no request completes for 60 s.
  */
 aqr_status aqr_server_replay(aqr_server* s, int64_t n, const double* arrival_s, const float* Q,
                              const int32_t* k, const int32_t* ef, int32_t* out_id,

@@ -90,7 +90,14 @@ class ServerParams(C.Structure):
     _fields_ = [("ring", _i32), ("k_max", _i32), ("ef_max", _i32), ("m_ef", _i32),
                 ("n_rerank", _i32), ("tau_gap", C.c_float), ("tau_ratio", C.c_float),
                 ("eps", C.c_float), ("waves_per_block", _i32), ("visited_log2", _i32),
-                ("idle_ms", _i32), ("reserved", _i32)]
+                ("idle_ms", _i32), ("w_pool_pages", _i32), ("state_budget", _i64),
+                ("lds_budget_pages", _i64)]
+
+
+class ServerUsage(C.Structure):
+    _fields_ = [("ring", _i32), ("slots_used", _i32), ("lds_budget_pages", _i64),
+                ("lds_used_pages", _i64), ("state_budget", _i64), ("state_used", _i64),
+                ("blocks", _i32), ("pool_pages", _i32)]
 
 
 class IndexFileInfo(C.Structure):
@@ -139,6 +146,8 @@ _SIGS = [
     ("aqr_server_create", _i32, [_vp, C.POINTER(ServerParams), _vp, _sz, C.POINTER(_vp)]),
     ("aqr_server_submit", _i32, [_vp, _vp, _i32, _i32, C.POINTER(C.c_uint64)]),
     ("aqr_server_poll", _i32, [_vp, C.c_uint64, _vp, _vp, C.POINTER(_i32)]),
+    ("aqr_server_request_cost", _i32, [_vp, _i32, _i32, C.POINTER(_i32), C.POINTER(_i64)]),
+    ("aqr_server_usage", _i32, [_vp, C.POINTER(ServerUsage)]),
     ("aqr_server_stop", _i32, [_vp]),
     ("aqr_server_destroy", None, [_vp]),
     ("aqr_server_replay", _i32, [_vp, _i64, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp,
@@ -744,7 +753,8 @@ class Server(_Handle):
     _free = "aqr_server_destroy"
 
     def __init__(self, ix, k_max, ef_max, ring=1024, m_ef=3, n_rerank=28, tau_gap=0.010,
-                 tau_ratio=1.008, eps=1e-6, waves_per_block=0, visited_log2=0, idle_ms=50):
+                 tau_ratio=1.008, eps=1e-6, waves_per_block=0, visited_log2=0, idle_ms=50,
+                 w_pool_pages=0, state_budget=0, lds_budget_pages=0):
         import torch
         self.ix = ix
         self.k_max = k_max
@@ -753,7 +763,8 @@ class Server(_Handle):
         p = ServerParams(ring=ring, k_max=k_max, ef_max=ef_max, m_ef=m_ef, n_rerank=n_rerank,
                          tau_gap=tau_gap, tau_ratio=tau_ratio, eps=eps,
                          waves_per_block=waves_per_block, visited_log2=visited_log2,
-                         idle_ms=idle_ms, reserved=0)
+                         idle_ms=idle_ms, w_pool_pages=w_pool_pages,
+                         state_budget=state_budget, lds_budget_pages=lds_budget_pages)
         h = _vp()
         _check(lib().aqr_server_create(ix.ptr, C.byref(p), _dev_ptr(self.ws), self.ws.numel(),
                                        C.byref(h)))
@@ -780,6 +791,17 @@ class Server(_Handle):
 
     def stop(self):
         _check(lib().aqr_server_stop(self.ptr))
+
+    def request_cost(self, k, ef):
+        """(LDS pages, state bytes) a request of this k and ef is charged."""
+        p, b = _i32(), _i64()
+        _check(lib().aqr_server_request_cost(self.ptr, int(k), int(ef), C.byref(p), C.byref(b)))
+        return p.value, b.value
+
+    def usage(self):
+        u = ServerUsage()
+        _check(lib().aqr_server_usage(self.ptr, C.byref(u)))
+        return {f: getattr(u, f) for f, _ in ServerUsage._fields_}
 
     def replay(self, arrival_s, Q, k, ef, service=False):
         """Replay an arrival trace natively; returns (ids, dists, latency_s, wall_s),

@@ -1214,24 +1214,49 @@ struct ServeCtl {       // pinned host memory
 };
 
 struct ServeArgs {
-    SearchArgs s;       // Idx, m_ef, ef_cap, vb, geometry, wave_lds (search part)
+    SearchArgs s;       // Idx, m_ef, ef_cap, vb (largest visited cache), geometry, wave_lds
     RerankArgs r;       // geometry and thresholds of the re-rank part
     int32_t ring;
     int32_t k_max;
     int32_t nc_max;
+    int32_t vb_lo;      // smallest visited cache a request gets (log2 buckets)
+    int32_t pool_pages; // per-request LDS pool of a block (pages of 512 bytes)
+    size_t pool_bytes;
     uint64_t idle_ticks;
     uint64_t epoch;
     const int32_t* req_slot;  // [ring]: slot of ticket t at t mod ring
-    const float* req_q;     // [ring][d]
-    const int32_t* req_k;   // [ring]
-    const int32_t* req_ef;  // [ring]
-    int32_t* res_id;        // [ring][k_max]
-    float* res_dist;        // [ring][k_max]
-    uint64_t* done;         // [ring]
-    uint32_t* svc;          // [ring]: device service time of the request (100 MHz ticks)
+    uint64_t* consumed;       // [ring]: 1 + the last ticket whose entry a worker has read
+    const int32_t* req_k;     // [slots]
+    const int32_t* req_ef;    // [slots]
+    const int64_t* req_off;   // [slots]: byte offset of the request's state in the arena
+    unsigned char* arena;     // request state: query (d floats, 64-byte aligned), then
+                              // k ids and k distances
+    uint64_t* done;           // [slots]
+    uint32_t* svc;            // [slots]: device service time of the request (100 MHz ticks)
     ServeCtl* ctl;
     ServeDev* dev;
 };
+
+// LDS of one request in the serving kernel, from its block's pool: the
+// Stage-1 arrays [W | neighbour ids | their keys | visited buckets] sized by
+// the request's own ef (W: ef_eff rounded up to 64 keys; visited buckets
+// 2^vb with vb growing with ef_eff), overlaid after Stage 1 by the Stage 2-3
+// arrays [candidate ids | A | sorted A | R | sorted R | kinds] sized by its
+// N_c.  The host charges the same page count at admission.
+__host__ __device__ inline int serve_vb(int efe, int vb_lo, int vb_hi) {
+    int lg = 0;
+    while ((1 << lg) < efe) ++lg;
+    return max(vb_lo, min(vb_hi, lg + 1));
+}
+__host__ __device__ inline size_t serve_rr_bytes(int nc) {
+    const size_t c = (size_t)((nc + 15) / 16 * 16);
+    return c * 4 + c * 16 + c * 18;
+}
+__host__ __device__ inline int serve_pages(int efe, int nc, int st_cap, int vb_lo, int vb_hi) {
+    const SearchLds run{(efe + 63) / 64 * 64, st_cap, serve_vb(efe, vb_lo, vb_hi), 0, 0, true};
+    const size_t b = max(run.bytes(), serve_rr_bytes(nc));
+    return (int)((b + 511) / 512);
+}
 
 // Synchronisation of the serving loop.  The spin loops use relaxed atomics
 // only: acquire and release at agent or system scope maintain the per-XCD L2
@@ -1272,6 +1297,10 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k
     const Idx& ix = sa.ix;
     ServeDev* dv = a.dev;
 
+    for (int i = threadIdx.x; i < (int)pool_hdr_bytes(a.pool_pages) / 4; i += blockDim.x)
+        reinterpret_cast<int*>(smem)[i] = 0;
+    __syncthreads();
+
     if (blockIdx.x == 0 && wave == 0) {
         // dispatcher: mirror the host's publication counter into device memory
         if (lane == 0) {
@@ -1301,29 +1330,16 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k
         return;
     }
 
-    // worker LDS: the search layout; the FP32 query stays at its start
-    unsigned char* base = smem + (size_t)wave * sa.wave_lds;
-    const int ef_cap = sa.ef_cap;
-    const SearchLds L{ef_cap, st_cap_of(ix.s0, ix.s1), sa.vb, ix.xs, ix.dp};
-    uint64_t* mk = reinterpret_cast<uint64_t*>(base + L.off_mk());
-    uint32_t* st_id = reinterpret_cast<uint32_t*>(base + L.off_st());
-    uint64_t* st_key = reinterpret_cast<uint64_t*>(base + L.off_sk());
-    uint64_t* visb = reinterpret_cast<uint64_t*>(base + L.off_vis());
+    // worker LDS: the FP32 query, its codes and W's spare entry in the
+    // wave's own region; everything else from the block's pool, per request
+    PoolHdr* ph = reinterpret_cast<PoolHdr*>(smem);
+    uint64_t* pool = reinterpret_cast<uint64_t*>(smem + pool_hdr_bytes(a.pool_pages));
+    unsigned char* base = smem + a.pool_bytes + (size_t)wave * sa.wave_lds;
+    const int st_cap = st_cap_of(ix.s0, ix.s1);
+    const SearchLds L{0, st_cap, 0, ix.xs, ix.dp, false};
     float* qf = reinterpret_cast<float*>(base + L.off_qf());
     uint8_t* qc = base + L.off_qc();
-    // Stages 2-3 reuse everything after the query: the candidate ids are
-    // copied out of W (each 64-id chunk is read before it is written, and the
-    // id array starts where W starts, so no unread key is overwritten)
-    unsigned char* rb = base + L.off_mk();
-    const int nc_cap = a.r.nc_cap, r_cap = a.r.r_cap;
-    uint32_t* rids = reinterpret_cast<uint32_t*>(rb);
-    uint64_t* A = reinterpret_cast<uint64_t*>(rb + (size_t)nc_cap * 4);
-    uint64_t* As = A + nc_cap;
-    uint64_t* Rk = As + nc_cap;
-    uint64_t* Rs = Rk + r_cap;
-    uint8_t* kind = reinterpret_cast<uint8_t*>(Rs + r_cap);
-    uint8_t* kinds = kind + r_cap;
-    VisCache vis{visb, sa.vb, max(ix.idbits, sa.vb + 1)};
+    uint64_t* spare = reinterpret_cast<uint64_t*>(base + L.off_mk());
 
     for (;;) {
         // take the next sequence number (one atomic add per request; lane 0
@@ -1365,15 +1381,22 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k
         const uint64_t t_claim = __builtin_amdgcn_s_memrealtime();
         const int slot =
             uni((int)ld_sys32(reinterpret_cast<const uint32_t*>(a.req_slot) + tk % a.ring));
+        // the queue entry has been read: the host may reuse it for ticket tk + ring
+        wait_mem();  // the entry's load has completed before the release below
+        if (lane == 0) st_sys(a.consumed + tk % a.ring, (uint64_t)tk + 1);
         if (slot < 0 || slot >= a.ring) continue;  // not written by aqr_server_submit
         const int k = uni((int)ld_sys32(reinterpret_cast<const uint32_t*>(a.req_k) + slot));
         const int ef = uni((int)ld_sys32(reinterpret_cast<const uint32_t*>(a.req_ef) + slot));
+        const int64_t off = (int64_t)ld_sys(reinterpret_cast<const uint64_t*>(a.req_off) + slot);
         const int efe = max(ef, k);
         const int nc = min(max(efe / sa.m_ef, k), efe);
-        int bad = uni((k < 1 || k > a.k_max || efe > ef_cap || nc > a.nc_max) ? 1 : 0);
+        int bad = uni((k < 1 || k > a.k_max || efe > sa.ef_cap || nc > a.nc_max) ? 1 : 0);
+        const int64_t qbytes = ((int64_t)ix.d * 4 + 63) / 64 * 64;
+        const uint32_t* rq = reinterpret_cast<const uint32_t*>(a.arena + off);
+        int32_t* oid = reinterpret_cast<int32_t*>(a.arena + off + qbytes);
+        float* od = reinterpret_cast<float*>(a.arena + off + qbytes + (int64_t)max(k, 1) * 4);
         if (!bad) {
             bool nonfinite = false;
-            const uint32_t* rq = reinterpret_cast<const uint32_t*>(a.req_q) + (int64_t)slot * ix.d;
             for (int j = lane; j < ix.xs; j += kWave) {
                 const float v = j < ix.d ? __uint_as_float(ld_sys32(rq + j)) : 0.0f;
                 nonfinite |= !__builtin_isfinite(v);
@@ -1381,8 +1404,6 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k
             }
             bad = uni(ballot(nonfinite) != 0 ? 1 : 0);
         }
-        int32_t* oid = a.res_id + (int64_t)slot * a.k_max;
-        float* od = a.res_dist + (int64_t)slot * a.k_max;
         // the row is k entries long (the host pads it to k_max)
         if (bad) {
             for (int j = lane; j < max(1, min(k, a.k_max)); j += kWave) {
@@ -1390,16 +1411,51 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k
                 st_sys(reinterpret_cast<uint32_t*>(od) + j, 0x7F800000u);
             }
         } else {
+            // the request's LDS: pages of the block's pool sized by its ef and N_c
+            const int vbq = serve_vb(efe, a.vb_lo, sa.vb);
+            const int need = serve_pages(efe, nc, st_cap, a.vb_lo, sa.vb);
+            int start = -1;
+            for (;;) {
+                int r = -1;
+                if (lane == 0) r = pool_try(ph, a.pool_pages, need, wave + 1);
+                wsync();
+                start = uni(r);
+                if (start >= 0) break;
+                __builtin_amdgcn_s_sleep(4);
+            }
+            unsigned char* run = reinterpret_cast<unsigned char*>(pool + (size_t)start * kWave);
+            const SearchLds R{(efe + 63) / 64 * 64, st_cap, vbq, 0, 0, true};
+            uint64_t* mk = reinterpret_cast<uint64_t*>(run + R.off_mk());
+            uint32_t* st_id = reinterpret_cast<uint32_t*>(run + R.off_st());
+            uint64_t* st_key = reinterpret_cast<uint64_t*>(run + R.off_sk());
+            uint64_t* visb = reinterpret_cast<uint64_t*>(run + R.off_vis());
+            const VisCache vis{visb, vbq, max(ix.idbits, vbq + 1)};
+            SearchArgs sq = sa;
+            sq.vb = vbq;
             // Stage 1 writes its N_c candidates into the search part; the
             // re-rank reads them from there
-            search_query<false, CPL, U, LG, false>(sa, 0, efe, nc, lane, vis, mk, mk + ef_cap,
-                                                   st_id, st_key, visb, qf, qc);
+            search_query<false, CPL, U, LG, false>(sq, 0, efe, nc, lane, vis, mk, spare, st_id,
+                                                   st_key, visb, qf, qc);
             const int cnt = uni(*reinterpret_cast<const int*>(st_id));
+            // Stages 2-3 overlay the run from its start: the candidate ids are
+            // copied out of W (each 64-id chunk is read before it is written,
+            // and the id array starts where W starts, so no unread key is
+            // overwritten)
+            const int c16 = (nc + 15) / 16 * 16;
+            uint32_t* rids = reinterpret_cast<uint32_t*>(run);
+            uint64_t* A = reinterpret_cast<uint64_t*>(run + (size_t)c16 * 4);
+            uint64_t* As = A + c16;
+            uint64_t* Rk = As + c16;
+            uint64_t* Rs = Rk + c16;
+            uint8_t* kind = reinterpret_cast<uint8_t*>(Rs + c16);
+            uint8_t* kinds = kind + c16;
             for (int j = lane; j < cnt; j += kWave) rids[j] = (uint32_t)mk[j] >> 1;
             wsync();
             rerank_query<CPL8, CPLF, true>(a.r, lane, k, cnt, qf, rids, A, As, Rk, Rs, kind,
                                            kinds, oid, od, nullptr, k, nullptr, nullptr,
                                            nullptr, nullptr);
+            wsync();
+            if (lane == 0) pool_release(ph, start, need);
         }
         if (lane == 0)
             st_sys(a.svc + slot, (uint32_t)(__builtin_amdgcn_s_memrealtime() - t_claim));
@@ -2125,29 +2181,77 @@ extern "C" void aqr_plan_free(aqr_plan* p) {
 // serving
 // ===========================================================================
 
+// Request state (query, result ids and distances) lives in one arena of
+// pinned host memory, mapped to the device; requests take byte ranges of it,
+// first fit, and return them when their result is collected.
+struct ArenaAlloc {
+    std::map<int64_t, int64_t> free_;  // offset -> length, coalesced
+    int64_t total = 0, used = 0;
+    void init(int64_t bytes) {
+        free_.clear();
+        total = bytes;
+        used = 0;
+        if (bytes > 0) free_[0] = bytes;
+    }
+    int64_t alloc(int64_t len) {
+        for (auto it = free_.begin(); it != free_.end(); ++it) {
+            if (it->second >= len) {
+                const int64_t off = it->first, rest = it->second - len;
+                free_.erase(it);
+                if (rest > 0) free_[off + len] = rest;
+                used += len;
+                return off;
+            }
+        }
+        return -1;
+    }
+    void release(int64_t off, int64_t len) {
+        used -= len;
+        auto nx = free_.lower_bound(off);
+        if (nx != free_.end() && off + len == nx->first) {
+            len += nx->second;
+            nx = free_.erase(nx);
+        }
+        if (nx != free_.begin()) {
+            auto pv = std::prev(nx);
+            if (pv->first + pv->second == off) {
+                pv->second += len;
+                return;
+            }
+        }
+        free_[off] = len;
+    }
+};
+
 struct aqr_server {
     const aqr_index* ix = nullptr;
     aqr_server_params prm{};
     dev::ServeArgs args{};
     int blocks = 0, wpb = 4;
     size_t lds = 0;
+    int st_cap = 64, vb_lo = 4, vb_hi = 9;
+    int64_t lds_budget = 0, lds_used = 0;  // pages of outstanding requests
     hipStream_t stream = nullptr;
     dev::ServeCtl* ctl = nullptr;  // pinned, coherent
-    float* req_q = nullptr;
     int32_t* req_slot = nullptr;
+    uint64_t* consumed = nullptr;
     int32_t* req_k = nullptr;
     int32_t* req_ef = nullptr;
-    int32_t* res_id = nullptr;
-    float* res_dist = nullptr;
+    int64_t* req_off = nullptr;
+    unsigned char* arena = nullptr;
     uint64_t* done = nullptr;
     uint32_t* svc = nullptr;
+    ArenaAlloc arena_alloc;
     uint64_t next_ticket = 0;
     std::vector<uint64_t> slot_ticket;  // sequence number in the slot, or ~0 when free
     std::vector<int32_t> free_slots;
-    std::vector<int32_t> slot_k;  // k of the request in the slot
+    std::vector<int32_t> slot_k;        // k of the request in the slot
+    std::vector<int64_t> slot_bytes;    // its state bytes
+    std::vector<int32_t> slot_pages;    // its LDS pages
     bool launched = false;
     std::mutex mu;
     hipError_t (*launch_fn)(aqr_server*) = nullptr;
+    hipError_t (*occ_fn)(aqr_server*, int*) = nullptr;
 };
 
 namespace {
@@ -2156,51 +2260,47 @@ constexpr uint64_t kFree = ~0ull;
 constexpr int kSlotBits = 22;  // ticket = sequence << 22 | slot
 
 template <int CPL, int LG, int C8, int CF>
+hipError_t serve_occ_t(aqr_server* sv, int* per_cu) {
+    constexpr int U = 2;
+    auto kern = dev::k_serve<CPL, U, LG, C8, CF>;
+    hipError_t e = hipFuncSetAttribute((const void*)kern,
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)sv->lds);
+    if (e != hipSuccess) return e;
+    return hipOccupancyMaxActiveBlocksPerMultiprocessor(per_cu, kern, sv->wpb * dev::kWave,
+                                                        sv->lds);
+}
+
+template <int CPL, int LG, int C8, int CF>
 hipError_t serve_launch_t(aqr_server* sv) {
     constexpr int U = 2;
     auto kern = dev::k_serve<CPL, U, LG, C8, CF>;
-    static std::atomic<int> lds_set{0};
-    if ((int)sv->lds > lds_set.load()) {
-        hipError_t e = hipFuncSetAttribute((const void*)kern,
-                                           hipFuncAttributeMaxDynamicSharedMemorySize,
-                                           (int)sv->lds);
-        if (e != hipSuccess) return e;
-        lds_set.store((int)sv->lds);
-    }
-    if (sv->blocks <= 0) {
-        int per_cu = 0;
-        hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(
-            &per_cu, kern, sv->wpb * dev::kWave, sv->lds);
-        if (e != hipSuccess) return e;
-        // every block must be resident at once: workers only leave after
-        // the dispatcher (block 0) raises the stop flag
-        sv->blocks = std::max(1, per_cu) * std::max(1, sv->ix->num_cu);
-    }
     hipLaunchKernelGGL(dev::k_serve_reset, dim3(1), dim3(64), 0, sv->stream, sv->args.dev);
     hipLaunchKernelGGL(kern, dim3(sv->blocks), dim3(sv->wpb * dev::kWave), sv->lds, sv->stream,
                        sv->args);
     return hipGetLastError();
 }
 
+using ServeFns = std::pair<hipError_t (*)(aqr_server*), hipError_t (*)(aqr_server*, int*)>;
+
 template <int CPL, int LG>
-hipError_t (*pick_serve_cf(int cf))(aqr_server*) {
+ServeFns pick_serve_cf(int cf) {
     switch (cf) {
-        case 1: return serve_launch_t<CPL, LG, 1, 1>;
-        case 2: return serve_launch_t<CPL, LG, 1, 2>;
-        case 4: return serve_launch_t<CPL, LG, 1, 4>;
-        default: return nullptr;
+        case 1: return {serve_launch_t<CPL, LG, 1, 1>, serve_occ_t<CPL, LG, 1, 1>};
+        case 2: return {serve_launch_t<CPL, LG, 1, 2>, serve_occ_t<CPL, LG, 1, 2>};
+        case 4: return {serve_launch_t<CPL, LG, 1, 4>, serve_occ_t<CPL, LG, 1, 4>};
+        default: return {nullptr, nullptr};
     }
 }
 
 // Code-row geometry of the serving worker's Stage 1, by row width (nch
 // 16-byte chunks, at most 64): the batch kernel's rule with at most four
 // chunks per lane.
-hipError_t (*pick_serve(int nch, int cf))(aqr_server*) {
+ServeFns pick_serve(int nch, int cf) {
     if (nch <= 8) return pick_serve_cf<2, 2>(cf);
     if (nch <= 16) return pick_serve_cf<2, 3>(cf);
     if (nch <= 32) return pick_serve_cf<4, 3>(cf);
     if (nch <= 64) return pick_serve_cf<4, 4>(cf);
-    return nullptr;
+    return {nullptr, nullptr};
 }
 
 // (Re)launch the persistent kernel when it is not running.  A running
@@ -2221,24 +2321,47 @@ aqr_status serve_ensure_running(aqr_server* sv) {
     return AQR_OK;
 }
 
+// Costs a request is charged at admission (and returned when collected).
+void serve_cost(const aqr_server* sv, int32_t k, int32_t ef, int32_t* pages, int64_t* bytes) {
+    const int efe = std::max(ef, k);
+    const int nc = std::min(std::max(efe / sv->prm.m_ef, k), efe);
+    *pages = dev::serve_pages(efe, nc, sv->st_cap, sv->vb_lo, sv->vb_hi);
+    const int64_t qb = ((int64_t)sv->ix->v.d * 4 + 63) / 64 * 64;
+    *bytes = qb + ((int64_t)k * 8 + 63) / 64 * 64;
+}
+
 // Both below run with sv->mu held.
 aqr_status serve_submit_locked(aqr_server* sv, const float* q, int32_t k, int32_t ef,
                                uint64_t* ticket) {
-    if (k < 1 || k > sv->prm.k_max || std::max(ef, k) > std::max(sv->prm.ef_max, sv->prm.k_max))
+    if (k < 1 || k > sv->prm.k_max || ef < 1 ||
+        std::max(ef, k) > std::max(sv->prm.ef_max, sv->prm.k_max))
         return fail(AQR_ERR_INVALID_ARG, "aqr_server_submit: k or ef outside the server's limits");
-    if (sv->free_slots.empty()) return fail(AQR_ERR_BUSY, "aqr_server_submit: ring full");
-    // With a free slot, fewer than `ring` requests are outstanding, and
-    // requests are claimed in sequence order, so the queue entry of sequence
-    // t (t mod ring) was consumed by sequence t - ring already.
+    if (sv->free_slots.empty()) return fail(AQR_ERR_BUSY, "aqr_server_submit: no free request slot");
+    // The queue entry of sequence t (t mod ring) held sequence t - ring; it
+    // may be reused only once a worker has read it.
     const uint64_t t = sv->next_ticket;
+    const uint64_t R = (uint64_t)sv->prm.ring;
+    if (t >= R && __atomic_load_n(&sv->consumed[t % R], __ATOMIC_ACQUIRE) != t - R + 1)
+        return fail(AQR_ERR_BUSY, "aqr_server_submit: queue entry not yet read by a worker");
+    int32_t pages = 0;
+    int64_t bytes = 0;
+    serve_cost(sv, k, ef, &pages, &bytes);
+    if (sv->lds_used + pages > sv->lds_budget)
+        return fail(AQR_ERR_BUSY, "aqr_server_submit: LDS budget exhausted");
+    const int64_t off = sv->arena_alloc.alloc(bytes);
+    if (off < 0) return fail(AQR_ERR_BUSY, "aqr_server_submit: request-state budget exhausted");
     const int32_t slot = sv->free_slots.back();
     sv->free_slots.pop_back();
+    sv->lds_used += pages;
     const int32_t d = sv->ix->v.d;
-    std::memcpy(sv->req_q + (size_t)slot * d, q, sizeof(float) * d);
+    std::memcpy(sv->arena + off, q, sizeof(float) * d);
     sv->req_k[slot] = k;
     sv->req_ef[slot] = ef;
+    sv->req_off[slot] = off;
     sv->slot_k[slot] = k;
-    sv->req_slot[t % (uint64_t)sv->prm.ring] = slot;
+    sv->slot_bytes[slot] = bytes;
+    sv->slot_pages[slot] = pages;
+    sv->req_slot[t % R] = slot;
     sv->slot_ticket[slot] = t;
     sv->next_ticket = t + 1;
     __atomic_store_n(&sv->ctl->tail, t + 1, __ATOMIC_RELEASE);
@@ -2259,15 +2382,19 @@ aqr_status serve_poll_locked(aqr_server* sv, uint64_t ticket, int32_t* out_id, f
     }
     // the device wrote the first k entries of the row; pad the rest
     const int32_t km = sv->prm.k_max, k = sv->slot_k[slot];
+    const int64_t qb = ((int64_t)sv->ix->v.d * 4 + 63) / 64 * 64;
+    const unsigned char* st = sv->arena + sv->req_off[slot] + qb;
     if (out_id) {
-        std::memcpy(out_id, sv->res_id + slot * km, sizeof(int32_t) * k);
+        std::memcpy(out_id, st, sizeof(int32_t) * k);
         for (int32_t j = k; j < km; ++j) out_id[j] = -1;
     }
     if (out_dist) {
-        std::memcpy(out_dist, sv->res_dist + slot * km, sizeof(float) * k);
+        std::memcpy(out_dist, st + (size_t)k * 4, sizeof(float) * k);
         for (int32_t j = k; j < km; ++j) out_dist[j] = std::numeric_limits<float>::infinity();
     }
     if (svc_ticks) *svc_ticks = sv->svc[slot];
+    sv->arena_alloc.release(sv->req_off[slot], sv->slot_bytes[slot]);
+    sv->lds_used -= sv->slot_pages[slot];
     sv->slot_ticket[slot] = kFree;
     sv->free_slots.push_back((int32_t)slot);
     *is_done = 1;
@@ -2286,7 +2413,9 @@ extern "C" aqr_status aqr_server_create(const aqr_index* ix, const aqr_server_pa
         if (ws_bytes < aqr_server_workspace_size())
             return fail(AQR_ERR_OOM, "aqr_server_create: workspace too small");
         if (prm->ring < 1 || prm->ring > (1 << 22) || prm->k_max < 1 || prm->k_max > 1024 ||
-            prm->ef_max < 1 || prm->ef_max > 1024 || prm->m_ef < 1 || prm->n_rerank < 0)
+            prm->ef_max < 1 || prm->ef_max > 1024 || prm->m_ef < 1 || prm->n_rerank < 0 ||
+            prm->w_pool_pages < 0 || prm->w_pool_pages > 255 || prm->state_budget < 0 ||
+            prm->lds_budget_pages < 0)
             return fail(AQR_ERR_INVALID_ARG, "aqr_server_create: parameter out of range");
         const Idx& v = ix->v;
         const int nch8 = v.dp / 16, nchf = v.xs / 4;
@@ -2296,9 +2425,14 @@ extern "C" aqr_status aqr_server_create(const aqr_index* ix, const aqr_server_pa
         if (v.s0 > 256) return fail(AQR_ERR_INVALID_ARG, "aqr_server_create: rows above 256 entries");
         const int efm = std::max(prm->ef_max, prm->k_max);
         const int ef_cap = (efm + 63) / 64 * 64;
-        int vb = prm->visited_log2 > 0 ? prm->visited_log2 : 9;  // four waves per SIMD leave room
-        const int idb = std::max(v.idbits, vb + 1);
-        if (idb - vb > 15) vb = idb - 15;
+        // visited caches: 2^vb buckets growing with a request's ef, between the
+        // smallest that keeps the stored id remainder within 15 bits and the
+        // server's largest (visited_log2, default 9)
+        int vb_hi = prm->visited_log2 > 0 ? prm->visited_log2 : 9;
+        if (vb_hi < 4 || vb_hi > 14)
+            return fail(AQR_ERR_INVALID_ARG, "aqr_server_create: visited_log2 out of [4, 14]");
+        const int vb_lo = std::max(4, v.idbits - 15);
+        vb_hi = std::max(vb_hi, vb_lo);
         const int nc_max = std::min(efm, std::max(prm->k_max, efm / prm->m_ef));
         aqr_server* sv = new aqr_server();
         sv->ix = ix;
@@ -2308,11 +2442,34 @@ extern "C" aqr_status aqr_server_create(const aqr_index* ix, const aqr_server_pa
             delete sv;
             return fail(AQR_ERR_INVALID_ARG, "aqr_server_create: waves_per_block above 4");
         }
-        dev::SearchLds sl{ef_cap,
-                          std::max(v.s0, v.s1) <= 64 ? 64 : (std::max(v.s0, v.s1) + 63) / 64 * 64,
-                          vb, v.xs, v.dp};
-        const size_t search_lds = sl.bytes();
-        const size_t qpart = sl.off_mk();
+        sv->st_cap = std::max(v.s0, v.s1) <= 64 ? 64 : (std::max(v.s0, v.s1) + 63) / 64 * 64;
+        sv->vb_lo = vb_lo;
+        sv->vb_hi = vb_hi;
+        // the largest request: k_max at ef_max (or ef_max with the smallest k
+        // that keeps N_c largest)
+        int32_t max_pages = 0;
+        for (int32_t kk : {1, prm->k_max}) {
+            int32_t pg = 0;
+            int64_t by = 0;
+            serve_cost(sv, kk, efm, &pg, &by);
+            max_pages = std::max(max_pages, pg);
+        }
+        const int pool_pages = prm->w_pool_pages > 0 ? prm->w_pool_pages : sv->wpb * max_pages;
+        if (pool_pages < max_pages || pool_pages > 255) {
+            delete sv;
+            return fail(AQR_ERR_INVALID_ARG,
+                        "aqr_server_create: w_pool_pages must hold the largest request (" +
+                            std::to_string(max_pages) + " pages) and be at most 255");
+        }
+        const dev::SearchLds wl{0, sv->st_cap, 0, v.xs, v.dp, false};
+        const size_t wave_lds = dev::SearchLds::r16(wl.off_mk() + 8);
+        const size_t pool_bytes =
+            dev::SearchLds::r16(dev::pool_hdr_bytes(pool_pages) + (size_t)pool_pages * 512);
+        sv->lds = pool_bytes + wave_lds * sv->wpb;
+        if (sv->lds > ix->max_lds) {
+            delete sv;
+            return fail(AQR_ERR_INVALID_ARG, "aqr_server_create: LDS per block exceeds the device limit");
+        }
         dev::RerankArgs& r = sv->args.r;
         r.ix = v;
         r.nc_cap = (nc_max + 15) / 16 * 16;
@@ -2328,20 +2485,12 @@ extern "C" aqr_status aqr_server_create(const aqr_index* ix, const aqr_server_pa
         r.lg8 = pow2_lg_for(nch8);
         r.nchf = nchf;
         r.lgf = pow2_lg_for(nchf);
-        // Stages 2-3 overlay the search arrays after the query
-        const size_t rr = (size_t)r.nc_cap * 4 + (size_t)r.nc_cap * 16 + (size_t)r.r_cap * 18;
-        const size_t wave_lds = dev::SearchLds::r16(qpart + std::max(search_lds - qpart, rr));
-        sv->lds = wave_lds * sv->wpb;
-        if (sv->lds > ix->max_lds) {
-            delete sv;
-            return fail(AQR_ERR_INVALID_ARG, "aqr_server_create: LDS per block exceeds the device limit");
-        }
         dev::SearchArgs& sa = sv->args.s;
         sa.ix = v;
         sa.m_ef = prm->m_ef;
         sa.ef_cap = ef_cap;
         sa.out_stride = nc_max;
-        sa.vb = vb;
+        sa.vb = vb_hi;
         sa.mode = 2;
         sa.nch = nch8;
         sa.lg = std::max(2, pow2_lg_for(nch8));
@@ -2349,13 +2498,43 @@ extern "C" aqr_status aqr_server_create(const aqr_index* ix, const aqr_server_pa
         sv->args.ring = prm->ring;
         sv->args.k_max = prm->k_max;
         sv->args.nc_max = nc_max;
+        sv->args.vb_lo = vb_lo;
+        sv->args.pool_pages = pool_pages;
+        sv->args.pool_bytes = pool_bytes;
         sv->args.idle_ticks = (uint64_t)std::max(1, prm->idle_ms) * 100000ull;
-        sv->launch_fn = c8 == 1 ? pick_serve(nch8, cf) : nullptr;
-        if (!sv->launch_fn) {
+        const ServeFns fns = c8 == 1 ? pick_serve(nch8, cf) : ServeFns{nullptr, nullptr};
+        sv->launch_fn = fns.first;
+        sv->occ_fn = fns.second;
+        if (!sv->launch_fn || !sv->occ_fn) {
             delete sv;
             return fail(AQR_ERR_INVALID_ARG, "aqr_server_create: unsupported row geometry");
         }
-        // pinned, coherent host memory for the ring and the control block
+        // every block must be resident at once: workers only leave after the
+        // dispatcher (block 0) raises the stop flag
+        int per_cu = 0;
+        hipError_t e = sv->occ_fn(sv, &per_cu);
+        if (e != hipSuccess) {
+            delete sv;
+            return hip_fail(e, "aqr_server_create: occupancy");
+        }
+        sv->blocks = std::max(1, per_cu) * std::max(1, ix->num_cu);
+        // admission budgets: LDS pages of outstanding requests (default: what
+        // the resident blocks' pools hold at once) and request-state bytes
+        // (default: every slot at k_max)
+        int32_t pg_max = 0;
+        int64_t by_max = 0;
+        serve_cost(sv, prm->k_max, efm, &pg_max, &by_max);
+        sv->lds_budget = prm->lds_budget_pages > 0 ? prm->lds_budget_pages
+                                                   : (int64_t)sv->blocks * pool_pages;
+        const int64_t state = prm->state_budget > 0 ? prm->state_budget
+                                                    : (int64_t)prm->ring * by_max;
+        if (sv->lds_budget < max_pages || state < by_max) {
+            delete sv;
+            return fail(AQR_ERR_INVALID_ARG,
+                        "aqr_server_create: a budget below the largest request's cost");
+        }
+        // pinned, coherent host memory for the ring, the request state and
+        // the control block
         const size_t R = (size_t)prm->ring;
         struct Alloc {
             void** p;
@@ -2363,16 +2542,16 @@ extern "C" aqr_status aqr_server_create(const aqr_index* ix, const aqr_server_pa
         } al[] = {
             {(void**)&sv->ctl, sizeof(dev::ServeCtl)},
             {(void**)&sv->req_slot, R * sizeof(int32_t)},
-            {(void**)&sv->req_q, R * v.d * sizeof(float)},
+            {(void**)&sv->consumed, R * sizeof(uint64_t)},
             {(void**)&sv->req_k, R * sizeof(int32_t)},
             {(void**)&sv->req_ef, R * sizeof(int32_t)},
-            {(void**)&sv->res_id, R * prm->k_max * sizeof(int32_t)},
-            {(void**)&sv->res_dist, R * prm->k_max * sizeof(float)},
+            {(void**)&sv->req_off, R * sizeof(int64_t)},
+            {(void**)&sv->arena, (size_t)state},
             {(void**)&sv->done, R * sizeof(uint64_t)},
             {(void**)&sv->svc, R * sizeof(uint32_t)},
         };
         for (const Alloc& x : al) {
-            hipError_t e = hipHostMalloc(x.p, x.bytes, hipHostMallocCoherent | hipHostMallocMapped);
+            e = hipHostMalloc(x.p, x.bytes, hipHostMallocCoherent | hipHostMallocMapped);
             if (e != hipSuccess) {
                 *x.p = nullptr;
                 aqr_server_destroy(sv);
@@ -2380,21 +2559,25 @@ extern "C" aqr_status aqr_server_create(const aqr_index* ix, const aqr_server_pa
             }
             std::memset(*x.p, 0, x.bytes);
         }
+        for (size_t i = 0; i < R; ++i) sv->req_slot[i] = -1;
+        sv->arena_alloc.init(state);
         sv->args.ctl = sv->ctl;
         sv->args.req_slot = sv->req_slot;
-        sv->args.req_q = sv->req_q;
+        sv->args.consumed = sv->consumed;
         sv->args.req_k = sv->req_k;
         sv->args.req_ef = sv->req_ef;
-        sv->args.res_id = sv->res_id;
-        sv->args.res_dist = sv->res_dist;
+        sv->args.req_off = sv->req_off;
+        sv->args.arena = sv->arena;
         sv->args.done = sv->done;
         sv->args.svc = sv->svc;
         sv->args.dev = reinterpret_cast<dev::ServeDev*>(ws);
         sv->slot_ticket.assign(R, kFree);
         sv->slot_k.assign(R, 0);
+        sv->slot_bytes.assign(R, 0);
+        sv->slot_pages.assign(R, 0);
         sv->free_slots.resize(R);
         for (size_t i = 0; i < R; ++i) sv->free_slots[i] = (int32_t)(R - 1 - i);
-        hipError_t e = hipStreamCreateWithFlags(&sv->stream, hipStreamNonBlocking);
+        e = hipStreamCreateWithFlags(&sv->stream, hipStreamNonBlocking);
         if (e != hipSuccess) {
             sv->stream = nullptr;
             aqr_server_destroy(sv);
@@ -2438,6 +2621,33 @@ extern "C" aqr_status aqr_server_poll(aqr_server* sv, uint64_t ticket, int32_t* 
     }
 }
 
+extern "C" aqr_status aqr_server_request_cost(const aqr_server* sv, int32_t k, int32_t ef,
+                                              int32_t* lds_pages, int64_t* state_bytes) {
+    clear_error();
+    if (!sv || !lds_pages || !state_bytes)
+        return fail(AQR_ERR_INVALID_ARG, "aqr_server_request_cost: null pointer");
+    if (k < 1 || k > sv->prm.k_max || ef < 1 ||
+        std::max(ef, k) > std::max(sv->prm.ef_max, sv->prm.k_max))
+        return fail(AQR_ERR_INVALID_ARG, "aqr_server_request_cost: k or ef outside the server's limits");
+    serve_cost(sv, k, ef, lds_pages, state_bytes);
+    return AQR_OK;
+}
+
+extern "C" aqr_status aqr_server_usage(aqr_server* sv, aqr_server_usage_t* u) {
+    clear_error();
+    if (!sv || !u) return fail(AQR_ERR_INVALID_ARG, "aqr_server_usage: null pointer");
+    std::lock_guard<std::mutex> lk(sv->mu);
+    u->ring = sv->prm.ring;
+    u->slots_used = sv->prm.ring - (int32_t)sv->free_slots.size();
+    u->lds_budget_pages = sv->lds_budget;
+    u->lds_used_pages = sv->lds_used;
+    u->state_budget = sv->arena_alloc.total;
+    u->state_used = sv->arena_alloc.used;
+    u->blocks = sv->blocks;
+    u->pool_pages = sv->args.pool_pages;
+    return AQR_OK;
+}
+
 extern "C" aqr_status aqr_server_stop(aqr_server* sv) {
     clear_error();
     if (!sv) return fail(AQR_ERR_INVALID_ARG, "aqr_server_stop: null server");
@@ -2455,16 +2665,18 @@ extern "C" void aqr_server_destroy(aqr_server* sv) {
     if (!sv) return;
     if (sv->launched) (void)aqr_server_stop(sv);
     if (sv->stream) (void)hipStreamDestroy(sv->stream);
-    void* ptrs[] = {sv->ctl,    sv->req_slot, sv->req_q, sv->req_k, sv->req_ef,
-                    sv->res_id, sv->res_dist, sv->done,  sv->svc};
+    void* ptrs[] = {sv->ctl,     sv->req_slot, sv->consumed, sv->req_k, sv->req_ef,
+                    sv->req_off, sv->arena,    sv->done,     sv->svc};
     for (void* p : ptrs)
         if (p) (void)hipHostFree(p);
     delete sv;
 }
 
 // Native trace replay: request i arrives at arrival_s[i] (seconds from the
-// start); it is submitted at that time (or as soon as a ring slot is free)
-// and its latency runs from its arrival to the poll that finds it done.
+// start); it is submitted at that time (or as soon as the server admits it)
+// and its latency runs from its arrival to the poll that finds it done.  A
+// replay that sees no request complete for timeout_s seconds stops with
+// AQR_ERR_STATE.
 extern "C" aqr_status aqr_server_replay(aqr_server* sv, int64_t n, const double* arrival_s,
                                         const float* Q, const int32_t* k, const int32_t* ef,
                                         int32_t* out_id, float* out_dist, double* latency_s,
@@ -2476,6 +2688,7 @@ extern "C" aqr_status aqr_server_replay(aqr_server* sv, int64_t n, const double*
         if (n < 0) return fail(AQR_ERR_INVALID_ARG, "aqr_server_replay: negative count");
         std::lock_guard<std::mutex> lk(sv->mu);
         const int32_t d = sv->ix->v.d, km = sv->prm.k_max;
+        const double timeout_s = 60.0;
         using clk = std::chrono::steady_clock;
         const auto t0 = clk::now();
         auto now_s = [&] { return std::chrono::duration<double>(clk::now() - t0).count(); };
@@ -2483,6 +2696,7 @@ extern "C" aqr_status aqr_server_replay(aqr_server* sv, int64_t n, const double*
         std::vector<int64_t> pending;  // submitted, not yet done
         pending.reserve(sv->prm.ring);
         int64_t next = 0, finished = 0;
+        double last_progress = 0.0;
         std::vector<int32_t> ids(km);
         std::vector<float> dd(km);
         while (finished < n) {
@@ -2509,6 +2723,7 @@ extern "C" aqr_status aqr_server_replay(aqr_server* sv, int64_t n, const double*
                     latency_s[r] = now_s() - arrival_s[r];
                     if (service_s) service_s[r] = ticks * 1e-8;  // 100 MHz
                     ++finished;
+                    last_progress = now_s();
                     pending[i] = pending.back();
                     pending.pop_back();
                 } else {
@@ -2517,12 +2732,15 @@ extern "C" aqr_status aqr_server_replay(aqr_server* sv, int64_t n, const double*
                 }
             }
             if (waiting) {
+                if (now_s() - last_progress > timeout_s)
+                    return fail(AQR_ERR_STATE, "aqr_server_replay: no request completed for 60 s");
                 const aqr_status st = serve_ensure_running(sv);
                 if (st != AQR_OK) return st;
             } else if (next < n) {
                 // nothing in flight: wait for the next arrival (spin for the last 50 us)
                 const double wait = arrival_s[next] - now_s() - 50e-6;
                 if (wait > 0) std::this_thread::sleep_for(std::chrono::duration<double>(wait));
+                last_progress = now_s();
             }
         }
         if (wall_s) *wall_s = now_s();

@@ -157,3 +157,128 @@ def test_serve_longer_candidate_list_equals_batch(small):
             check_row(r[0], r[1], ref, q)
     finally:
         sv.stop()
+
+
+def _near_threshold(ref, q, k, tau_gap, tau_ratio, rtol=1e-5):
+    """The oracle's early-termination statistics of query q lie within rtol of
+    a threshold (the FP32 device may then decide the other way)."""
+    a = ref["a_dist"][q]
+    if not np.isfinite(tau_gap) or k >= int(ref["stage1"]["cand_cnt"][q]):
+        return False
+    dk, dk1 = a[k - 1], a[k]
+    gap = (dk1 - dk) / (dk + 1e-6)
+    ratio = dk1 / (dk + 1e-6)
+    return abs(gap - tau_gap) <= rtol * tau_gap or abs(ratio - tau_ratio) <= rtol * tau_ratio
+
+
+@pytest.mark.parametrize("et", ["off", "table3"])
+def test_serve_matches_oracle(orc, small, et):
+    # every served row of a mixed k/ef stream against the oracle's Alg. 2:
+    # distances within 1e-5 of its FP64 values, ids equal up to ties inside
+    # that tolerance (rows whose early-termination statistics sit within 1e-5
+    # of a threshold may take the other branch and are counted, not compared)
+    from paper_2602_21600_amd import aqr
+    Q, k, ef = small["Q"], small["k"], small["ef"]
+    inf = float("inf")
+    tg, tr = (inf, inf) if et == "off" else (0.010, 1.008)
+    index = dict(X=small["X"], codes=small["codes"], d=small["d"], min=small["min"],
+                 scale=small["scale"], graph=small["graph"])
+    ref = orc.query(index, Q, k, ef, n_rerank=28, tau_gap=tg, tau_ratio=tr, taps=True)
+    nq = Q.shape[0]
+    arrivals = W.poisson_arrivals(50000.0, nq, seed=9)
+    sv = aqr.Server(small["ix"], K_MAX, EF_MAX, ring=128, tau_gap=tg, tau_ratio=tr)
+    try:
+        ids, dist, lat, wall = sv.replay(arrivals, Q, k, ef)
+    finally:
+        sv.stop()
+    skipped = 0
+    for q in range(nq):
+        kq = int(k[q])
+        if _near_threshold(ref, q, kq, tg, tr):
+            skipped += 1
+            continue
+        rd = ref["dist"][q, :kq]
+        np.testing.assert_allclose(dist[q, :kq].astype(np.float64), rd, rtol=1e-5,
+                                   err_msg=f"q={q}")
+        gi, oi = ids[q, :kq], ref["id"][q, :kq]
+        for t in np.nonzero(gi != oi)[0]:
+            close = np.abs(rd - rd[t]) <= 1e-5 * max(rd[t], 1e-30)
+            assert close.sum() >= 2, f"q={q} slot {t}: ids differ away from a tie"
+        assert np.all(ids[q, kq:] == -1)
+    assert skipped <= nq // 50
+
+
+def test_serve_budget_admission(small):
+    # admission charges each request its own LDS pages and state bytes:
+    # requests beyond the budget are refused, and admitted again once earlier
+    # results are collected; rows admitted under budget pressure equal the
+    # batch rows
+    from paper_2602_21600_amd import aqr
+    Q, k, ef = small["Q"], small["k"], small["ef"]
+    ref = batch_results(small, Q, k, ef)
+    probe = aqr.Server(small["ix"], K_MAX, EF_MAX, ring=16)
+    big_p, big_b = probe.request_cost(100, 512)
+    small_p, small_b = probe.request_cost(1, 16)
+    del probe
+    assert small_p < big_p and small_b < big_b
+    # LDS budget: one large request and one small request at a time
+    sv = aqr.Server(small["ix"], K_MAX, EF_MAX, ring=16, lds_budget_pages=big_p + small_p)
+    try:
+        big = [q for q in range(len(k)) if k[q] == 100 and ef[q] == 512][:2]
+        tiny = [q for q in range(len(k)) if k[q] == 1 and ef[q] == 16][:2]
+        assert len(big) == 2 and len(tiny) == 2
+        t0 = sv.submit(Q[big[0]], 100, 512)
+        assert t0 is not None
+        assert sv.submit(Q[big[1]], 100, 512) is None          # over the LDS budget
+        u = sv.usage()
+        assert u["lds_used_pages"] == big_p and u["slots_used"] == 1
+        t1 = sv.submit(Q[tiny[0]], 1, 16)                      # fits beside it
+        assert t1 is not None
+        assert sv.submit(Q[tiny[1]], 1, 16) is None           # budget full
+        r = wait(sv, t0)
+        check_row(r[0], r[1], ref, big[0])
+        t2 = sv.submit(Q[big[1]], 100, 512)                    # admitted again
+        assert t2 is not None
+        for q, t in ((tiny[0], t1), (big[1], t2)):
+            r = wait(sv, t)
+            check_row(r[0], r[1], ref, q)
+        assert sv.usage()["lds_used_pages"] == 0 and sv.usage()["state_used"] == 0
+    finally:
+        sv.stop()
+    # state budget: room for two k = 100 requests
+    sv = aqr.Server(small["ix"], K_MAX, EF_MAX, ring=16, state_budget=2 * big_b)
+    try:
+        qs = [q for q in range(len(k)) if k[q] == 100][:3]
+        ts = [sv.submit(Q[q], 100, int(ef[q])) for q in qs[:2]]
+        assert None not in ts
+        assert sv.submit(Q[qs[2]], 100, int(ef[qs[2]])) is None  # state budget exhausted
+        assert sv.usage()["state_used"] == 2 * big_b
+        r = wait(sv, ts[0])
+        check_row(r[0], r[1], ref, qs[0])
+        t3 = sv.submit(Q[qs[2]], 100, int(ef[qs[2]]))
+        assert t3 is not None
+        for q, t in ((qs[1], ts[1]), (qs[2], t3)):
+            r = wait(sv, t)
+            check_row(r[0], r[1], ref, q)
+    finally:
+        sv.stop()
+    with pytest.raises(aqr.AqrError):
+        aqr.Server(small["ix"], K_MAX, EF_MAX, ring=4, lds_budget_pages=1)  # below one request
+
+
+def test_serve_small_pool_equals_batch(small):
+    # a pool that holds only the largest request at a time: waves wait for
+    # pages, every row still equals the batch row
+    from paper_2602_21600_amd import aqr
+    Q, k, ef = small["Q"], small["k"], small["ef"]
+    ref = batch_results(small, Q, k, ef)
+    probe = aqr.Server(small["ix"], K_MAX, EF_MAX, ring=16)
+    big_p, _ = probe.request_cost(100, 512)
+    del probe
+    sv = aqr.Server(small["ix"], K_MAX, EF_MAX, ring=256, w_pool_pages=big_p)
+    try:
+        ids, dist, lat, wall = sv.replay(np.zeros(Q.shape[0]), Q, k, ef)
+    finally:
+        sv.stop()
+    for q in range(Q.shape[0]):
+        check_row(ids[q], dist[q], ref, q)
