@@ -984,13 +984,15 @@ int32_t orc_search_codes(const uint8_t* codes, int64_t n, int32_t d, int32_t str
 /*
  * Baseline HNSW on FP32 vectors (same graph), distances in FP64.
  * Returns the first k[q] of W per query: out_id/out_dist [nq][k_stride],
- * padded with (-1, +inf).
+ * padded with (-1, +inf).  expanded (optional, [nq][tap_cap]) records the
+ * layer-0 expansion order and n_expanded[q] its length, as in
+ * orc_search_codes.
  */
 int32_t orc_search_f32(const float* X, int64_t n, int32_t d, int32_t M, const int32_t* level,
                        const uint32_t* adj0, const int64_t* upper_off, const uint32_t* upper_adj,
                        uint32_t ep, int32_t L, const float* Q, int64_t nq, const int32_t* ef_eff,
                        const int32_t* k, int32_t k_stride, int32_t* out_id, double* out_dist,
-                       int64_t* n_vis) {
+                       int64_t* n_vis, uint32_t* expanded, int32_t tap_cap, int32_t* n_expanded) {
     graph g;
     make_graph(&g, n, M, level, adj0, upper_off, upper_adj, ep, L);
     space sp = {SP_F32, d, d, NULL, X};
@@ -1010,11 +1012,13 @@ int32_t orc_search_f32(const float* X, int64_t n, int32_t d, int32_t M, const in
             int32_t cnt = 0;
             int64_t vn = 0;
             int32_t take = k[qi] < k_stride ? k[qi] : k_stride;
+            taps tp = {expanded ? expanded + qi * tap_cap : NULL, 0, expanded ? tap_cap : 0};
             if (query_one(&g, &sp, Q + qi * d, ef_eff[qi], take, &v, &W, ids,
-                          out_dist + qi * k_stride, &cnt, NULL, NULL, 0, &vn)) {
+                          out_dist + qi * k_stride, &cnt, &tp, NULL, 0, &vn)) {
                 err = 1;
                 continue;
             }
+            if (n_expanded) n_expanded[qi] = tp.n_expanded;
             for (int32_t t = 0; t < k_stride; t++) {
                 if (t < cnt) {
                     out_id[qi * k_stride + t] = (int32_t)ids[t];

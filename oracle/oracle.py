@@ -71,7 +71,8 @@ def _load():
                                      _i32p, _i32, _vp, _vp, _vp, _vp]
     lib.orc_search_codes.restype = _i32
     lib.orc_search_f32.argtypes = [_f32p, _i64, _i32, _i32, _i32p, _u32p, _i64p, _u32p, _u32,
-                                   _i32, _f32p, _i64, _i32p, _i32p, _i32, _i32p, _f64p, _vp]
+                                   _i32, _f32p, _i64, _i32p, _i32p, _i32, _i32p, _f64p, _vp,
+                                   _vp, _i32, _vp]
     lib.orc_search_f32.restype = _i32
     lib.orc_rerank.argtypes = [_f32p, _u8p, _i64, _i32, _i32, _f32p, _f32p, _f32p, _i64, _u32p,
                                _i32p, _i32, _i32p, _i32, _i32, _f64, _f64, _f64, _vp, _i32, _vp,
@@ -287,7 +288,9 @@ def search_codes(graph, codes, d, qcodes, ef_eff, nc, nc_stride=None, tap_cap=0)
     return res
 
 
-def search_f32(graph, X, Q, ef_eff, k, k_stride=None, with_visits=False):
+def search_f32(graph, X, Q, ef_eff, k, k_stride=None, with_visits=False, tap_cap=0):
+    """Baseline FP32 HNSW (distances in FP64).  Returns (ids, dists), plus the
+    visit counts with with_visits, plus (expanded, n_expanded) with tap_cap."""
     X = np.ascontiguousarray(X, np.float32)
     n, d = X.shape
     Q = np.ascontiguousarray(Q, np.float32)
@@ -298,12 +301,18 @@ def search_f32(graph, X, Q, ef_eff, k, k_stride=None, with_visits=False):
     oid = np.zeros((nq, k_stride), np.int32)
     od = np.zeros((nq, k_stride), np.float64)
     nvis = np.zeros(nq, np.int64) if with_visits else None
+    exp = np.zeros((nq, tap_cap), np.uint32) if tap_cap else None
+    nexp = np.zeros(nq, np.int32) if tap_cap else None
     M, lv, a0, off, up, ep, L = _g(graph)
     _check(_load().orc_search_f32(X, n, d, M, lv, a0, off, up, ep, L, Q, nq, ef_eff, k, k_stride,
-                                  oid, od, _ptr(nvis)), "search_f32")
+                                  oid, od, _ptr(nvis), _ptr(exp), int(tap_cap), _ptr(nexp)),
+           "search_f32")
+    out = (oid, od)
     if with_visits:
-        return oid, od, nvis
-    return oid, od
+        out = out + (nvis,)
+    if tap_cap:
+        out = out + (exp, nexp)
+    return out
 
 
 def rerank(X, codes, mn, scale, Q, cand_id, cand_cnt, k, n_rerank=28, tau_gap=0.010,

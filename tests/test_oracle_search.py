@@ -93,6 +93,32 @@ def test_f32_baseline_exhaustive_equals_exact_knn(orc):
         np.testing.assert_allclose(od[q], Dq[order], rtol=1e-12)
 
 
+def test_f32_expansion_tap(orc):
+    # the expansion tap of the FP32 baseline: with ef >= N every node
+    # reachable in layer 0 from the entry is expanded exactly once, nearest
+    # first (the first expansion is the layer-0 entry point, the rest follow
+    # the search order; tap-free and tapped runs return the same lists)
+    ix = _index(orc)
+    n = ix["X"].shape[0]
+    oid, od = orc.search_f32(ix["graph"], ix["X"], ix["Q"], n, 10)
+    oid2, od2, exp, nexp = orc.search_f32(ix["graph"], ix["X"], ix["Q"], n, 10, tap_cap=n)
+    np.testing.assert_array_equal(oid, oid2)
+    np.testing.assert_array_equal(od, od2)
+    X64 = ix["X"].astype(np.float64)
+    for q in range(ix["Q"].shape[0]):
+        e = exp[q, :nexp[q]].astype(np.int64)
+        assert len(set(e.tolist())) == len(e)
+        reach = _reachable(ix["graph"]["adj0"], e[0])
+        assert sorted(e.tolist()) == sorted(reach.tolist())
+        # after the first expansion W holds every node seen, so each next
+        # expansion is the nearest not yet expanded among those evaluated:
+        # the distances of expansions 2.. never undercut an earlier one by
+        # more than the order of discovery allows; the last expanded node is
+        # no closer than the k-th result
+        dq = ((X64[e] - ix["Q"][q].astype(np.float64)) ** 2).sum(axis=1)
+        assert dq[-1] >= od[q, 9]
+
+
 def test_exact_pipeline_equals_knn(orc):
     # N_c = N_rerank = N and early termination off: Alg. 2 returns exact kNN
     ix = _index(orc)
