@@ -292,10 +292,6 @@ typedef struct aqr_sparams {
     int32_t waves_per_block; /* 0 = library default */
     int32_t blocks;       /* persistent grid size, 0 = fill the device */
     int32_t visited_log2; /* log2 of visited-cache buckets (4 ids each), 0 = 7 */
-    int32_t w_pool_pages; /* result lists W of a block come from a pool of this many
-                             pages of 64 keys (LDS), a query taking ceil(ef_eff / 64)
-                             pages while it runs; 0 = waves_per_block lists of ef_max;
-                             at least ceil(ef_max / 64), at most 255 */
     const int32_t* order; /* device, nullable: work order of the queries (a permutation) */
 } aqr_sparams;
 
@@ -488,14 +484,12 @@ typedef struct aqr_server_params {
                                        smallest that keeps the stored id remainder within
                                        15 bits (idbits - 15, at least 4) */
     int32_t idle_ms;      /* the kernel exits after this long without unclaimed requests */
-    int32_t w_pool_pages; /* per-request LDS of a block: a pool of this many 512-byte pages
-                             shared by its waves; 0 = waves_per_block times the largest
-                             request; at most 255 */
+    int32_t reserved;
     int64_t state_budget; /* bytes of request state (query, result ids and distances) in
                              pinned host memory; 0 = ring requests at k_max */
     int64_t lds_budget_pages; /* admission limit on the LDS pages of requests admitted and
-                                 not yet collected; 0 = what the resident blocks' pools hold
-                                 at once */
+                                 not yet collected; 0 = what the resident waves hold at
+                                 once, one largest request each */
 } aqr_server_params;
 
 typedef struct aqr_server_usage_t {
@@ -506,7 +500,7 @@ typedef struct aqr_server_usage_t {
     int64_t state_budget;
     int64_t state_used;
     int32_t blocks;       /* resident blocks of the server kernel */
-    int32_t pool_pages;   /* LDS pool pages of a block */
+    int32_t run_pages;    /* LDS pages each resident wave holds for a request */
 } aqr_server_usage_t;
 
 typedef struct aqr_server aqr_server;
@@ -527,10 +521,11 @@ size_t aqr_server_workspace_size(void);
  * (aqr_server_workspace_size() bytes) for the claim counters.
  *
  * Memory per request, sized by its own k and ef (not k_max and ef_max):
- * LDS pages from its block's pool for the result list W (ef_eff keys), the
- * neighbour staging and a visited cache that grows with ef_eff, overlaid
- * after Stage 1 by the Stage 2-3 arrays for its N_c candidates; and request
- * state in pinned host memory (the query and k ids and distances).
+ * LDS pages (of the region each resident wave holds for one request) for the
+ * result list W (ef_eff keys), the neighbour staging and a visited cache that
+ * grows with ef_eff, overlaid after Stage 1 by the Stage 2-3 arrays for its
+ * N_c candidates; and request state in pinned host memory (the query and k
+ * ids and distances).
  * Admission charges both against the server's budgets
  * (aqr_server_request_cost) and returns them when the result is collected.
  * Each request runs Stage 1 and Stages 2-3 with the same code as

@@ -49,8 +49,7 @@ class GInfo(C.Structure):
 class SParams(C.Structure):
     _fields_ = [("ef_max", C.c_int32), ("out_stride", C.c_int32), ("m_ef", C.c_int32),
                 ("waves_per_block", C.c_int32), ("blocks", C.c_int32),
-                ("visited_log2", C.c_int32), ("w_pool_pages", C.c_int32),
-                ("order", C.c_void_p)]
+                ("visited_log2", C.c_int32), ("order", C.c_void_p)]
 
 
 class Taps(C.Structure):
@@ -90,14 +89,14 @@ class ServerParams(C.Structure):
     _fields_ = [("ring", _i32), ("k_max", _i32), ("ef_max", _i32), ("m_ef", _i32),
                 ("n_rerank", _i32), ("tau_gap", C.c_float), ("tau_ratio", C.c_float),
                 ("eps", C.c_float), ("waves_per_block", _i32), ("visited_log2", _i32),
-                ("idle_ms", _i32), ("w_pool_pages", _i32), ("state_budget", _i64),
+                ("idle_ms", _i32), ("reserved", _i32), ("state_budget", _i64),
                 ("lds_budget_pages", _i64)]
 
 
 class ServerUsage(C.Structure):
     _fields_ = [("ring", _i32), ("slots_used", _i32), ("lds_budget_pages", _i64),
                 ("lds_used_pages", _i64), ("state_budget", _i64), ("state_used", _i64),
-                ("blocks", _i32), ("pool_pages", _i32)]
+                ("blocks", _i32), ("run_pages", _i32)]
 
 
 class IndexFileInfo(C.Structure):
@@ -502,8 +501,7 @@ def _taps(taps):
 
 
 def aqr_search(ix, Q, k, ef, cand_id, cand_D, cand_cnt, ws, ef_max, out_stride, nc=None, m_ef=3,
-               waves_per_block=0, blocks=0, visited_log2=0, order=None, taps=None, stream=None,
-               w_pool_pages=0):
+               waves_per_block=0, blocks=0, visited_log2=0, order=None, taps=None, stream=None):
     nq = _check_search_args(ix, Q, k, ef, ws, order, nc)
     _need("cand_id", cand_id, _i32_types(), 2, rows=nq, cols=out_stride)
     _need("cand_D", cand_D, _i32_types(), 2, rows=nq, cols=out_stride)
@@ -513,7 +511,7 @@ def aqr_search(ix, Q, k, ef, cand_id, cand_D, cand_cnt, ws, ef_max, out_stride, 
     _check_taps(taps, nq)
     sp = SParams(ef_max=ef_max, out_stride=out_stride, m_ef=m_ef,
                  waves_per_block=waves_per_block, blocks=blocks, visited_log2=visited_log2,
-                 w_pool_pages=w_pool_pages, order=_dev_ptr(order))
+                 order=_dev_ptr(order))
     tp = _taps(taps)
     _check(lib().aqr_search(ix.ptr, _dev_ptr(Q), Q.shape[0], _dev_ptr(k), _dev_ptr(ef),
                             _dev_ptr(nc), C.byref(sp), _dev_ptr(cand_id), _dev_ptr(cand_D),
@@ -522,15 +520,14 @@ def aqr_search(ix, Q, k, ef, cand_id, cand_D, cand_cnt, ws, ef_max, out_stride, 
 
 
 def aqr_search_fp32(ix, Q, k, ef, out_id, out_dist, ws, ef_max, out_stride, waves_per_block=0,
-                    blocks=0, visited_log2=0, order=None, taps=None, stream=None,
-                    w_pool_pages=0):
+                    blocks=0, visited_log2=0, order=None, taps=None, stream=None):
     nq = _check_search_args(ix, Q, k, ef, ws, order)
     _need("out_id", out_id, _i32_types(), 2, rows=nq, cols=(out_stride,))
     _need("out_dist", out_dist, _f32_types(), 2, rows=nq, cols=(out_stride,))
     _check_taps(taps, nq)
     sp = SParams(ef_max=ef_max, out_stride=out_stride, m_ef=1,
                  waves_per_block=waves_per_block, blocks=blocks, visited_log2=visited_log2,
-                 w_pool_pages=w_pool_pages, order=_dev_ptr(order))
+                 order=_dev_ptr(order))
     tp = _taps(taps)
     _check(lib().aqr_search_fp32(ix.ptr, _dev_ptr(Q), Q.shape[0], _dev_ptr(k), _dev_ptr(ef),
                                  C.byref(sp), _dev_ptr(out_id), _dev_ptr(out_dist), _dev_ptr(ws),
@@ -714,7 +711,6 @@ class BatchPlan:
         sp = dict(ef_max=self.ef_max, out_stride=self.nc_max, m_ef=m_ef,
                   waves_per_block=tuning.get("waves_per_block", 0),
                   blocks=tuning.get("blocks", 0), visited_log2=tuning.get("visited_log2", 0),
-                  w_pool_pages=tuning.get("w_pool_pages", 0),
                   order=None)
         rp = dict(n_rerank=n_rerank, out_stride=k_max, tau_gap=tau_gap, tau_ratio=tau_ratio,
                   eps=eps, force_et=-1, waves_per_block=tuning.get("rerank_waves_per_block", 0),
@@ -754,7 +750,7 @@ class Server(_Handle):
 
     def __init__(self, ix, k_max, ef_max, ring=1024, m_ef=3, n_rerank=28, tau_gap=0.010,
                  tau_ratio=1.008, eps=1e-6, waves_per_block=0, visited_log2=0, idle_ms=50,
-                 w_pool_pages=0, state_budget=0, lds_budget_pages=0):
+                 state_budget=0, lds_budget_pages=0):
         import torch
         self.ix = ix
         self.k_max = k_max
@@ -763,7 +759,7 @@ class Server(_Handle):
         p = ServerParams(ring=ring, k_max=k_max, ef_max=ef_max, m_ef=m_ef, n_rerank=n_rerank,
                          tau_gap=tau_gap, tau_ratio=tau_ratio, eps=eps,
                          waves_per_block=waves_per_block, visited_log2=visited_log2,
-                         idle_ms=idle_ms, w_pool_pages=w_pool_pages,
+                         idle_ms=idle_ms, reserved=0,
                          state_budget=state_budget, lds_budget_pages=lds_budget_pages)
         h = _vp()
         _check(lib().aqr_server_create(ix.ptr, C.byref(p), _dev_ptr(self.ws), self.ws.numel(),

@@ -398,7 +398,7 @@ struct VisCache {
 // ---------------------------------------------------------------------------
 struct SearchLds {
     int ef_cap, st_cap, vb, xs, dp;
-    bool own_w = true;  // false: W lives in the block's pool, not in this layout
+    bool own_w = true;  // false: W lives elsewhere; the layout keeps its spare entry only
     // Layout of one wave: [FP32 query | query codes | W | neighbour ids |
     // their keys | visited buckets].  W holds keys whose low bit is the
     // expanded flag.  Each array has one spare entry past its end (W: index
@@ -411,7 +411,7 @@ struct SearchLds {
     __host__ __device__ size_t off_qc() const { return (size_t)xs * 4; }
     __host__ __device__ size_t off_mk() const { return r16(off_qc() + (size_t)dp); }
     __host__ __device__ size_t off_st() const {
-        return r16(off_mk() + (own_w ? (size_t)(ef_cap + 1) * 8 : (size_t)8));  // pooled: the spare entry only
+        return r16(off_mk() + (own_w ? (size_t)(ef_cap + 1) * 8 : (size_t)8));
     }
     __host__ __device__ size_t off_sk() const { return off_st() + (size_t)st_cap * 4; }
     __host__ __device__ size_t off_vis() const { return off_sk() + (size_t)st_cap * 8; }
@@ -437,8 +437,6 @@ struct SearchArgs {
     int32_t mode;       // 0: Stage-1 candidates; 1: FP32 baseline top-k
     int32_t lg, nch;    // row geometry
     size_t wave_lds;
-    int32_t pool_pages; // W pool of a block: pages of 64 keys (k_search)
-    size_t pool_bytes;  // pool header + pages
     uint32_t* out_id;
     uint32_t* out_D;    // mode 0: integer D; mode 1: FP32 distance bits
     int32_t* out_cnt;
@@ -714,65 +712,6 @@ __device__ __forceinline__ void search_query(const SearchArgs& a, const int64_t 
 template <bool F32, int CPL, int LG>
 constexpr int search_waves_per_eu() { return !F32 && (CPL << LG) <= 16 ? 7 : 1; }
 
-// ---------------------------------------------------------------------------
-// W pool of a block: pages of 64 keys shared by the block's waves.  A wave
-// takes ceil(ef_eff / 64) contiguous pages for one query and returns them
-// after it, so a block holds as many result lists at once as their sizes
-// fit, not waves_per_block lists of ef_max each.  Allocation is first fit
-// under a block lock, by lane 0.  A wave that finds no room records itself
-// as the waiting wave; while one wave waits no other wave allocates, so the
-// waiting wave is served as soon as enough pages are returned (every other
-// wave either holds pages and will return them after its query, or holds
-// none), and the pool holds at least one list of ef_max.
-// ---------------------------------------------------------------------------
-struct PoolHdr {
-    int lock;
-    int want;                 // 1 + the waiting wave, or 0
-    unsigned char owner[8];   // [pool_pages]: 1 + the owning wave, or 0 (extends past the struct)
-};
-
-__host__ __device__ constexpr size_t pool_hdr_bytes(int pages) {
-    return ((size_t)8 + (size_t)pages + 15) & ~(size_t)15;
-}
-
-// lane 0 only: the first page of a run of `need` free pages, or -1
-__device__ __forceinline__ int pool_try(PoolHdr* h, int pages, int need, int me) {
-    while (atomicCAS(&h->lock, 0, 1) != 0) __builtin_amdgcn_s_sleep(1);
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
-    volatile unsigned char* own = h->owner;
-    volatile int* want = &h->want;
-    int r = -1;
-    const int w = *want;
-    if (w == 0 || w == me) {
-        int run = 0;
-        for (int i = 0; i < pages; ++i) {
-            run = own[i] ? 0 : run + 1;
-            if (run == need) {
-                r = i + 1 - need;
-                break;
-            }
-        }
-        if (r >= 0) {
-            for (int j = 0; j < need; ++j) own[r + j] = (unsigned char)me;
-            if (w == me) *want = 0;
-        } else if (w == 0) {
-            *want = me;
-        }
-    }
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
-    atomicExch(&h->lock, 0);
-    return r;
-}
-
-__device__ __forceinline__ void pool_release(PoolHdr* h, int start, int need) {
-    while (atomicCAS(&h->lock, 0, 1) != 0) __builtin_amdgcn_s_sleep(1);
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
-    volatile unsigned char* own = h->owner;
-    for (int j = 0; j < need; ++j) own[start + j] = 0;
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
-    atomicExch(&h->lock, 0);
-}
-
 template <bool F32, int CPL, int U, int LG, bool TAPS>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(search_waves_per_eu<F32, CPL, LG>())))
 void k_search(SearchArgs a) {
@@ -780,15 +719,11 @@ void k_search(SearchArgs a) {
     const int lane = lane_id();
     const int wave = threadIdx.x / kWave;
     const Idx& ix = a.ix;
-    // Block layout: [pool header | W pool pages | wave 0 | wave 1 | ...].  The
-    // 8-bit search encodes the query straight from global memory, so its
-    // wave layout has no FP32 query (xs 0); the FP32 search keeps it in LDS.
-    // A wave's own layout holds no W, only W's spare entry.
-    PoolHdr* ph = reinterpret_cast<PoolHdr*>(smem);
-    uint64_t* pool = reinterpret_cast<uint64_t*>(smem + pool_hdr_bytes(a.pool_pages));
-    const SearchLds L{a.ef_cap, st_cap_of(ix.s0, ix.s1), a.vb, F32 ? ix.xs : 0, ix.dp, false};
-    unsigned char* base = smem + a.pool_bytes + (size_t)wave * a.wave_lds;
-    uint64_t* spare = reinterpret_cast<uint64_t*>(base + L.off_mk());
+    // The 8-bit search encodes the query straight from global memory, so its
+    // layout has no FP32 query (xs 0); the FP32 search keeps it in LDS.
+    const SearchLds L{a.ef_cap, st_cap_of(ix.s0, ix.s1), a.vb, F32 ? ix.xs : 0, ix.dp};
+    unsigned char* base = smem + (size_t)wave * a.wave_lds;
+    uint64_t* mk = reinterpret_cast<uint64_t*>(base + L.off_mk());
     uint32_t* st_id = reinterpret_cast<uint32_t*>(base + L.off_st());
     uint64_t* st_key = reinterpret_cast<uint64_t*>(base + L.off_sk());
     uint64_t* visb = reinterpret_cast<uint64_t*>(base + L.off_vis());
@@ -796,10 +731,6 @@ void k_search(SearchArgs a) {
     uint8_t* qc = base + L.off_qc();
 
     VisCache vis{visb, a.vb, max(ix.idbits, a.vb + 1)};
-
-    for (int i = threadIdx.x; i < (int)pool_hdr_bytes(a.pool_pages) / 4; i += blockDim.x)
-        reinterpret_cast<int*>(smem)[i] = 0;
-    __syncthreads();
 
     for (;;) {
         // Every lane takes part in the work-counter atomic (only lane 0 adds
@@ -847,22 +778,8 @@ void k_search(SearchArgs a) {
                     }
                 }
             } else {
-                // the query's W: ceil(ef_eff / 64) pages of the block's pool
-                const int need = (efe + kWave - 1) / kWave;
-                int start = -1;
-                for (;;) {
-                    int r = -1;
-                    if (lane == 0) r = pool_try(ph, a.pool_pages, need, wave + 1);
-                    wsync();
-                    start = uni(r);
-                    if (start >= 0) break;
-                    __builtin_amdgcn_s_sleep(4);
-                }
-                search_query<F32, CPL, U, LG, TAPS>(a, q, efe, nc, lane, vis,
-                                                    pool + (size_t)start * kWave, spare, st_id,
-                                                    st_key, visb, qf, qc);
-                wsync();
-                if (lane == 0) pool_release(ph, start, need);
+                search_query<F32, CPL, U, LG, TAPS>(a, q, efe, nc, lane, vis, mk,
+                                                    mk + a.ef_cap, st_id, st_key, visb, qf, qc);
             }
         }
         wsync();
@@ -1220,8 +1137,7 @@ struct ServeArgs {
     int32_t k_max;
     int32_t nc_max;
     int32_t vb_lo;      // smallest visited cache a request gets (log2 buckets)
-    int32_t pool_pages; // per-request LDS pool of a block (pages of 512 bytes)
-    size_t pool_bytes;
+    size_t run_bytes;   // per-wave region for one request's arrays (the largest request)
     uint64_t idle_ticks;
     uint64_t epoch;
     const int32_t* req_slot;  // [ring]: slot of ticket t at t mod ring
@@ -1237,12 +1153,13 @@ struct ServeArgs {
     ServeDev* dev;
 };
 
-// LDS of one request in the serving kernel, from its block's pool: the
-// Stage-1 arrays [W | neighbour ids | their keys | visited buckets] sized by
-// the request's own ef (W: ef_eff rounded up to 64 keys; visited buckets
-// 2^vb with vb growing with ef_eff), overlaid after Stage 1 by the Stage 2-3
-// arrays [candidate ids | A | sorted A | R | sorted R | kinds] sized by its
-// N_c.  The host charges the same page count at admission.
+// LDS arrays of one request in the serving kernel: the Stage-1 arrays [W |
+// neighbour ids | their keys | visited buckets] sized by the request's own ef
+// (W: ef_eff rounded up to 64 keys; visited buckets 2^vb with vb growing with
+// ef_eff), overlaid after Stage 1 by the Stage 2-3 arrays [candidate ids | A
+// | sorted A | R | sorted R | kinds] sized by its N_c, counted in 512-byte
+// pages.  Each wave holds a region for the largest request; the host charges
+// every request its own page count against the server's LDS budget.
 __host__ __device__ inline int serve_vb(int efe, int vb_lo, int vb_hi) {
     int lg = 0;
     while ((1 << lg) < efe) ++lg;
@@ -1297,10 +1214,6 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k
     const Idx& ix = sa.ix;
     ServeDev* dv = a.dev;
 
-    for (int i = threadIdx.x; i < (int)pool_hdr_bytes(a.pool_pages) / 4; i += blockDim.x)
-        reinterpret_cast<int*>(smem)[i] = 0;
-    __syncthreads();
-
     if (blockIdx.x == 0 && wave == 0) {
         // dispatcher: mirror the host's publication counter into device memory
         if (lane == 0) {
@@ -1330,16 +1243,15 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k
         return;
     }
 
-    // worker LDS: the FP32 query, its codes and W's spare entry in the
-    // wave's own region; everything else from the block's pool, per request
-    PoolHdr* ph = reinterpret_cast<PoolHdr*>(smem);
-    uint64_t* pool = reinterpret_cast<uint64_t*>(smem + pool_hdr_bytes(a.pool_pages));
-    unsigned char* base = smem + a.pool_bytes + (size_t)wave * sa.wave_lds;
+    // worker LDS: [FP32 query | its codes | W's spare entry | request run],
+    // the run laid out per request by its ef and N_c
+    unsigned char* base = smem + (size_t)wave * sa.wave_lds;
     const int st_cap = st_cap_of(ix.s0, ix.s1);
     const SearchLds L{0, st_cap, 0, ix.xs, ix.dp, false};
     float* qf = reinterpret_cast<float*>(base + L.off_qf());
     uint8_t* qc = base + L.off_qc();
     uint64_t* spare = reinterpret_cast<uint64_t*>(base + L.off_mk());
+    unsigned char* run = base + L.off_st();
 
     for (;;) {
         // take the next sequence number (one atomic add per request; lane 0
@@ -1411,19 +1323,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k
                 st_sys(reinterpret_cast<uint32_t*>(od) + j, 0x7F800000u);
             }
         } else {
-            // the request's LDS: pages of the block's pool sized by its ef and N_c
+            // the request's arrays, laid out by its ef and N_c
             const int vbq = serve_vb(efe, a.vb_lo, sa.vb);
-            const int need = serve_pages(efe, nc, st_cap, a.vb_lo, sa.vb);
-            int start = -1;
-            for (;;) {
-                int r = -1;
-                if (lane == 0) r = pool_try(ph, a.pool_pages, need, wave + 1);
-                wsync();
-                start = uni(r);
-                if (start >= 0) break;
-                __builtin_amdgcn_s_sleep(4);
-            }
-            unsigned char* run = reinterpret_cast<unsigned char*>(pool + (size_t)start * kWave);
             const SearchLds R{(efe + 63) / 64 * 64, st_cap, vbq, 0, 0, true};
             uint64_t* mk = reinterpret_cast<uint64_t*>(run + R.off_mk());
             uint32_t* st_id = reinterpret_cast<uint32_t*>(run + R.off_st());
@@ -1454,8 +1355,6 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k
             rerank_query<CPL8, CPLF, true>(a.r, lane, k, cnt, qf, rids, A, As, Rk, Rs, kind,
                                            kinds, oid, od, nullptr, k, nullptr, nullptr,
                                            nullptr, nullptr);
-            wsync();
-            if (lane == 0) pool_release(ph, start, need);
         }
         if (lane == 0)
             st_sys(a.svc + slot, (uint32_t)(__builtin_amdgcn_s_memrealtime() - t_claim));
@@ -1835,22 +1734,13 @@ aqr_status run_search(const aqr_index* ix, const float* Q, int64_t nq, const int
     if (v.s0 > 256)
         return fail(AQR_ERR_INVALID_ARG, std::string(who) + ": layer-0 rows above 256 entries are not supported");
     const int ef_cap = (sp->ef_max + 63) / 64 * 64;  // W capacity: whole 64-entry slots
-    // W comes from a pool of 64-key pages per block; by default it holds one
-    // list of ef_max for every wave
-    const int max_pages = ef_cap / 64;
-    const int pool_pages = sp->w_pool_pages > 0 ? sp->w_pool_pages : wpb * max_pages;
-    if (pool_pages < max_pages)
-        return fail(AQR_ERR_INVALID_ARG, std::string(who) + ": w_pool_pages below one result list of ef_max");
-    if (pool_pages > 255)
-        return fail(AQR_ERR_INVALID_ARG, std::string(who) + ": w_pool_pages above 255");
     dev::SearchLds sl{ef_cap,
                       std::max(v.s0, v.s1) <= 64 ? 64 : (std::max(v.s0, v.s1) + 63) / 64 * 64, vb,
-                      f32 ? v.xs : 0, v.dp, false};  // the 8-bit search keeps no FP32 query in LDS
+                      f32 ? v.xs : 0, v.dp};  // the 8-bit search keeps no FP32 query in LDS
     const size_t wl = sl.bytes();
-    const size_t pool_bytes = dev::SearchLds::r16(dev::pool_hdr_bytes(pool_pages) + (size_t)pool_pages * 64 * 8);
-    const size_t lds = pool_bytes + wl * wpb;
+    const size_t lds = wl * wpb;
     if (lds > ix->max_lds)
-        return fail(AQR_ERR_INVALID_ARG, std::string(who) + ": LDS per block exceeds the device limit (lower ef_max, visited_log2, waves_per_block or w_pool_pages)");
+        return fail(AQR_ERR_INVALID_ARG, std::string(who) + ": LDS per block exceeds the device limit (lower ef_max, visited_log2 or waves_per_block)");
     dev::SearchArgs a{};
     a.ix = v;
     a.Q = Q;
@@ -1868,8 +1758,6 @@ aqr_status run_search(const aqr_index* ix, const float* Q, int64_t nq, const int
     a.nch = nch;
     a.lg = std::max(2, pow2_lg_for(nch));
     a.wave_lds = wl;
-    a.pool_pages = pool_pages;
-    a.pool_bytes = pool_bytes;
     a.out_id = out_id;
     a.out_D = out_D;
     a.out_cnt = out_cnt;
@@ -2414,7 +2302,7 @@ extern "C" aqr_status aqr_server_create(const aqr_index* ix, const aqr_server_pa
             return fail(AQR_ERR_OOM, "aqr_server_create: workspace too small");
         if (prm->ring < 1 || prm->ring > (1 << 22) || prm->k_max < 1 || prm->k_max > 1024 ||
             prm->ef_max < 1 || prm->ef_max > 1024 || prm->m_ef < 1 || prm->n_rerank < 0 ||
-            prm->w_pool_pages < 0 || prm->w_pool_pages > 255 || prm->state_budget < 0 ||
+            prm->state_budget < 0 ||
             prm->lds_budget_pages < 0)
             return fail(AQR_ERR_INVALID_ARG, "aqr_server_create: parameter out of range");
         const Idx& v = ix->v;
@@ -2454,18 +2342,12 @@ extern "C" aqr_status aqr_server_create(const aqr_index* ix, const aqr_server_pa
             serve_cost(sv, kk, efm, &pg, &by);
             max_pages = std::max(max_pages, pg);
         }
-        const int pool_pages = prm->w_pool_pages > 0 ? prm->w_pool_pages : sv->wpb * max_pages;
-        if (pool_pages < max_pages || pool_pages > 255) {
-            delete sv;
-            return fail(AQR_ERR_INVALID_ARG,
-                        "aqr_server_create: w_pool_pages must hold the largest request (" +
-                            std::to_string(max_pages) + " pages) and be at most 255");
-        }
+        // per wave: the query, its codes, W's spare entry and a region for
+        // the largest request
         const dev::SearchLds wl{0, sv->st_cap, 0, v.xs, v.dp, false};
-        const size_t wave_lds = dev::SearchLds::r16(wl.off_mk() + 8);
-        const size_t pool_bytes =
-            dev::SearchLds::r16(dev::pool_hdr_bytes(pool_pages) + (size_t)pool_pages * 512);
-        sv->lds = pool_bytes + wave_lds * sv->wpb;
+        const size_t run_bytes = (size_t)max_pages * 512;
+        const size_t wave_lds = dev::SearchLds::r16(wl.off_st() + run_bytes);
+        sv->lds = wave_lds * sv->wpb;
         if (sv->lds > ix->max_lds) {
             delete sv;
             return fail(AQR_ERR_INVALID_ARG, "aqr_server_create: LDS per block exceeds the device limit");
@@ -2499,8 +2381,7 @@ extern "C" aqr_status aqr_server_create(const aqr_index* ix, const aqr_server_pa
         sv->args.k_max = prm->k_max;
         sv->args.nc_max = nc_max;
         sv->args.vb_lo = vb_lo;
-        sv->args.pool_pages = pool_pages;
-        sv->args.pool_bytes = pool_bytes;
+        sv->args.run_bytes = run_bytes;
         sv->args.idle_ticks = (uint64_t)std::max(1, prm->idle_ms) * 100000ull;
         const ServeFns fns = c8 == 1 ? pick_serve(nch8, cf) : ServeFns{nullptr, nullptr};
         sv->launch_fn = fns.first;
@@ -2518,14 +2399,14 @@ extern "C" aqr_status aqr_server_create(const aqr_index* ix, const aqr_server_pa
             return hip_fail(e, "aqr_server_create: occupancy");
         }
         sv->blocks = std::max(1, per_cu) * std::max(1, ix->num_cu);
-        // admission budgets: LDS pages of outstanding requests (default: what
-        // the resident blocks' pools hold at once) and request-state bytes
-        // (default: every slot at k_max)
+        // admission budgets: LDS pages of outstanding requests (default: the
+        // resident waves' regions, one largest request each) and
+        // request-state bytes (default: every slot at k_max)
         int32_t pg_max = 0;
         int64_t by_max = 0;
         serve_cost(sv, prm->k_max, efm, &pg_max, &by_max);
         sv->lds_budget = prm->lds_budget_pages > 0 ? prm->lds_budget_pages
-                                                   : (int64_t)sv->blocks * pool_pages;
+                                                   : (int64_t)sv->blocks * sv->wpb * max_pages;
         const int64_t state = prm->state_budget > 0 ? prm->state_budget
                                                     : (int64_t)prm->ring * by_max;
         if (sv->lds_budget < max_pages || state < by_max) {
@@ -2644,7 +2525,7 @@ extern "C" aqr_status aqr_server_usage(aqr_server* sv, aqr_server_usage_t* u) {
     u->state_budget = sv->arena_alloc.total;
     u->state_used = sv->arena_alloc.used;
     u->blocks = sv->blocks;
-    u->pool_pages = sv->args.pool_pages;
+    u->run_pages = (int32_t)(sv->args.run_bytes / 512);
     return AQR_OK;
 }
 

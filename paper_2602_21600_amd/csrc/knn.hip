@@ -351,13 +351,13 @@ extern "C" size_t aqr_knn_workspace_size(int64_t n, int64_t nq, int32_t k) {
     return sizeof(knn::Header) + (size_t)std::max<int64_t>(nq, 1) * parts * kc * 8;
 }
 
-extern "C" aqr_status aqr_knn_bruteforce(const float* X, int64_t n, int32_t d, const float* Q,
-                                         int64_t nq, int32_t k, int32_t* out_id,
-                                         double* out_dist, uint8_t* certified, void* ws,
-                                         size_t ws_bytes, void* stream) {
+namespace {
+
+aqr_status knn_run(const char* who, const float* X, int64_t n, int32_t d, const float* Q,
+                   int64_t nq, int32_t k, int32_t* out_id, double* out_dist, uint8_t* certified,
+                   void* ws, size_t ws_bytes, void* stream) {
     try {
         clear_error();
-        const char* who = "aqr_knn_bruteforce";
         if (nq < 0) return fail(AQR_ERR_INVALID_ARG, std::string(who) + ": nq < 0");
         if (n < 1 || n > (int64_t)0x7FFFFFFF)
             return fail(AQR_ERR_INVALID_ARG, std::string(who) + ": n must be in [1, 2^31-1]");
@@ -415,6 +415,16 @@ extern "C" aqr_status aqr_knn_bruteforce(const float* X, int64_t n, int32_t d, c
         if (e != hipSuccess) return fail(AQR_ERR_DEVICE, std::string(who) + ": " + hipGetErrorString(e));
         return AQR_OK;
     } catch (...) {
-        return fail(AQR_ERR_STATE, "aqr_knn_bruteforce: unexpected failure");
+        return fail(AQR_ERR_STATE, std::string(who) + ": unexpected failure");
     }
+}
+
+}  // namespace
+
+extern "C" aqr_status aqr_knn_bruteforce(const float* X, int64_t n, int32_t d, const float* Q,
+                                         int64_t nq, int32_t k, int32_t* out_id,
+                                         double* out_dist, uint8_t* certified, void* ws,
+                                         size_t ws_bytes, void* stream) {
+    return knn_run("aqr_knn_bruteforce", X, n, d, Q, nq, k, out_id, out_dist, certified, ws,
+                   ws_bytes, stream);
 }

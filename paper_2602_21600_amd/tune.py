@@ -1,7 +1,6 @@
 """Autotuner of the batch launch: waves per block, resident waves per CU,
-visited-cache size, the size of each block's pool of result-list pages (the
-W heap: a block's waves share it, each query taking pages for its own ef)
-and re-rank waves per block, chosen by timing a sample batch through libaqr.
+visited-cache size and re-rank waves per block, chosen by timing a sample
+batch through libaqr.
 
 The search result does not depend on these choices (only the speed does);
 the tests check that.  Results are cached in a JSON file keyed by the index
@@ -20,10 +19,6 @@ RERANK_WPB = (2, 4)
 # resident search waves per CU: 0 = as many as occupancy allows, else the
 # persistent grid is cut to this many waves per CU
 WAVES_PER_CU = (0, 8)
-# W pool of a block as a fraction of waves_per_block lists of ef_max (at least
-# one list of ef_max): smaller pools leave LDS for more resident blocks when
-# most queries ask for less than ef_max
-POOL_FRACTIONS = (1.0, 0.5)
 
 
 def _key(ix, ef_max, k_max, device_name):
@@ -71,15 +66,10 @@ def autotune(ix, Q, k, ef, k_max, ef_max, cache_path=None, reps=3, log=None):
     table = []
     spin_up(ix, Q, k, ef, k_max, ef_max)
     n_cu = torch.cuda.get_device_properties(torch.cuda.current_device()).multi_processor_count
-    max_pages = (max(ef_max, k_max) + 63) // 64
-    for wpb, vb, rwpb, wpc, pf in itertools.product(SEARCH_WPB, VISITED_LOG2, RERANK_WPB,
-                                                    WAVES_PER_CU, POOL_FRACTIONS):
-        pages = max(max_pages, int(round(pf * wpb * max_pages)))
-        if pf < 1.0 and pages == wpb * max_pages:
-            continue  # the same as the full pool
+    for wpb, vb, rwpb, wpc in itertools.product(SEARCH_WPB, VISITED_LOG2, RERANK_WPB,
+                                                WAVES_PER_CU):
         tuning = dict(waves_per_block=wpb, visited_log2=vb, rerank_waves_per_block=rwpb,
-                      blocks=(n_cu * wpc) // wpb if wpc else 0,
-                      w_pool_pages=pages if pf < 1.0 else 0)
+                      blocks=(n_cu * wpc) // wpb if wpc else 0)
         try:
             ms = time_config(ix, Q, k, ef, k_max, ef_max, tuning, reps)
         except aqr.AqrError as e:

@@ -149,10 +149,6 @@ def test_graph_replays_equal_eager(orc, small):
     dict(waves_per_block=1, visited_log2=8, rerank_waves_per_block=2),
     dict(waves_per_block=2, visited_log2=10, rerank_waves_per_block=4),
     dict(waves_per_block=4, visited_log2=6, rerank_waves_per_block=1, blocks=5),
-    # W pools smaller than one list of ef_max per wave: queries wait for pages
-    dict(waves_per_block=4, visited_log2=7, w_pool_pages=8),
-    dict(waves_per_block=4, visited_log2=8, w_pool_pages=13, blocks=7),
-    dict(waves_per_block=2, visited_log2=9, w_pool_pages=9),
 ])
 def test_tuning_does_not_change_results(orc, small, tuning):
     Q, k, ef = small["Q"], small["k"], small["ef"]

@@ -264,21 +264,3 @@ def test_serve_budget_admission(small):
         sv.stop()
     with pytest.raises(aqr.AqrError):
         aqr.Server(small["ix"], K_MAX, EF_MAX, ring=4, lds_budget_pages=1)  # below one request
-
-
-def test_serve_small_pool_equals_batch(small):
-    # a pool that holds only the largest request at a time: waves wait for
-    # pages, every row still equals the batch row
-    from paper_2602_21600_amd import aqr
-    Q, k, ef = small["Q"], small["k"], small["ef"]
-    ref = batch_results(small, Q, k, ef)
-    probe = aqr.Server(small["ix"], K_MAX, EF_MAX, ring=16)
-    big_p, _ = probe.request_cost(100, 512)
-    del probe
-    sv = aqr.Server(small["ix"], K_MAX, EF_MAX, ring=256, w_pool_pages=big_p)
-    try:
-        ids, dist, lat, wall = sv.replay(np.zeros(Q.shape[0]), Q, k, ef)
-    finally:
-        sv.stop()
-    for q in range(Q.shape[0]):
-        check_row(ids[q], dist[q], ref, q)
