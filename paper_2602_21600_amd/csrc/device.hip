@@ -2333,13 +2333,13 @@ extern "C" aqr_status aqr_server_create(const aqr_index* ix, const aqr_server_pa
         sv->st_cap = std::max(v.s0, v.s1) <= 64 ? 64 : (std::max(v.s0, v.s1) + 63) / 64 * 64;
         sv->vb_lo = vb_lo;
         sv->vb_hi = vb_hi;
-        // the largest request: k_max at ef_max (or ef_max with the smallest k
-        // that keeps N_c largest)
+        // the largest request the kernel accepts: ef_eff up to ef_cap (the
+        // host admits at most max(ef_max, k_max)), with k = 1 or k_max
         int32_t max_pages = 0;
         for (int32_t kk : {1, prm->k_max}) {
             int32_t pg = 0;
             int64_t by = 0;
-            serve_cost(sv, kk, efm, &pg, &by);
+            serve_cost(sv, kk, ef_cap, &pg, &by);
             max_pages = std::max(max_pages, pg);
         }
         // per wave: the query, its codes, W's spare entry and a region for

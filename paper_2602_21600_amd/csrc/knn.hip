@@ -259,11 +259,13 @@ __global__ __launch_bounds__(256) void k_knn_finish(FinishArgs a) {
     double* dist = reinterpret_cast<double*>(ex);  // exact distances of sel, in sel's order
     for (int m = lane; m < m_all; m += kWave) all[m] = a.keys[q * m_all + m];
     wsync();
-    // the kc smallest keys of the partitions' lists (keys are distinct, padding last)
+    // the kc smallest keys of the partitions' lists.  Row keys are distinct;
+    // the padding of short lists repeats one value, so equal keys are ranked
+    // by position and every rank below kc is written exactly once.
     for (int m = lane; m < m_all; m += kWave) {
         const uint64_t v = all[m];
         int r = 0;
-        for (int u = 0; u < m_all; ++u) r += all[u] < v ? 1 : 0;
+        for (int u = 0; u < m_all; ++u) r += (all[u] < v || (all[u] == v && u < m)) ? 1 : 0;
         if (r < a.kc) sel[r] = v;
     }
     wsync();
@@ -272,7 +274,7 @@ __global__ __launch_bounds__(256) void k_knn_finish(FinishArgs a) {
     for (int m = lane; m < a.kc; m += kWave) {
         const uint64_t v = sel[m];
         double s = __builtin_huge_val();
-        if (v != kEmpty) {
+        if (v != kEmpty && (int64_t)(uint32_t)v < a.n) {
             const float* xr = a.X + (int64_t)(uint32_t)v * a.d;
             s = 0.0;
             for (int j = 0; j < a.d; ++j) {
