@@ -836,7 +836,20 @@ def run_search(args, torch, aqr, W, name, dev, threads, nq=None, curve_leg=True,
             log(f"aqr ef={ef} rerank={cfg[0]} recall@10={rec:.4f}")
             return rec
 
+        if args.full_sweep:
+            # the sensitivity grid: every re-rank setting at every ef (Section
+            # 4.4, Figure 3, Table 3); the headline point is chosen from it
+            for ef in efs:
+                for cfg in RERANK_CONFIGS:
+                    trial(ef, cfg)
         for ef in efs:
+            if args.full_sweep:
+                hit = [(c, r) for e, c, r in aqr_table if e == ef and r >= TARGET_RECALL]
+                if hit:
+                    first = min(hit, key=lambda t: [c[0] for c in RERANK_CONFIGS].index(t[0]))
+                    aqr_pick = (ef, first[1], rerank_by_name(first[0]))
+                    break
+                continue
             # the most exhaustive re-rank setting first: when it misses the
             # target at this ef, the cheaper settings (fewer candidates, fewer
             # exact distances) are not tried
@@ -1273,6 +1286,9 @@ def main():
     ap.add_argument("--sq8", action="store_true",
                     help="plain 8-bit scalar quantisation (P_max = 0) and a plain HNSW graph at "
                          "M_0 and ef_0^c: the paper's scalar-quantisation baseline")
+    ap.add_argument("--full-sweep", action="store_true",
+                    help="evaluate every re-rank setting at every ef of the sweep (the "
+                         "sensitivity grid of Section 4.4) before choosing the timed point")
     ap.add_argument("--no-curve", action="store_true",
                     help="skip the recall-QPS curve at recall targets "
                          + ", ".join(str(t) for t in CURVE_TARGETS))
