@@ -499,16 +499,15 @@ def test_empty_batches(orc, small):
 
 
 def test_bench_ground_truth_matches_oracle(orc, small):
-    # the bench's exact kNN (FP32 screening on the GPU, FP64 re-score) equals
-    # the oracle's FP64 brute force, ids up to ties
+    # the bench's exact kNN (aqr_knn_bruteforce, in query chunks) equals the
+    # oracle's FP64 brute force: ids and distances identical
     import bench
     X, Q = small["X"], small["Q"]
-    gi, gd = bench.ground_truth(X, Q, 10, "cuda:0", chunk=4096)
+    gi, gd, cert = bench.ground_truth(X, Q, 10, "cuda:0", qchunk=37)
     ri, rd = orc.knn_f32(X, Q, 10)
-    np.testing.assert_allclose(gd, rd, rtol=1e-12)
-    for q in range(Q.shape[0]):
-        for t in np.nonzero(gi[q] != ri[q])[0]:
-            assert np.sum(np.abs(rd[q] - rd[q, t]) <= 1e-12 * rd[q, t]) >= 2, (q, t)
+    np.testing.assert_array_equal(gi, ri)
+    np.testing.assert_array_equal(gd.view(np.uint64), rd.view(np.uint64))
+    assert cert.shape == (Q.shape[0],)
 
 
 def test_full_rows_at_m32_match_oracle(orc):
