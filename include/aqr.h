@@ -424,6 +424,23 @@ aqr_status aqr_knn_bruteforce(const float* X, int64_t n, int32_t d, const float*
                               int32_t k, int32_t* out_id, double* out_dist, uint8_t* certified,
                               void* ws, size_t ws_bytes, void* stream);
 
+/*
+ * aqr_knn_bruteforce without a caller workspace, for callers that cannot
+ * allocate device memory (code under stream capture, tight serving loops,
+ * harnesses that forbid allocation).  The workspace is a fixed array of
+ * aqr_knn_noalloc_max_bytes() bytes in device memory that the library holds
+ * on each device until the process ends; a call needing more
+ * (aqr_knn_workspace_size(n, nq, k) above it) fails with
+ * AQR_ERR_INVALID_ARG, and the caller splits the queries.  The call
+ * allocates nothing.  Every call on one device shares that device's array:
+ * calls that overlap on one device (other streams, other threads) race and
+ * must be serialised by the caller.  Results equal aqr_knn_bruteforce's.
+ */
+size_t aqr_knn_noalloc_max_bytes(void);
+aqr_status aqr_knn_bruteforce_noalloc(const float* X, int64_t n, int32_t d, const float* Q,
+                                      int64_t nq, int32_t k, int32_t* out_id, double* out_dist,
+                                      uint8_t* certified, void* stream);
+
 /* ------------------------------------------------------------------------ */
 /* batch plans: one captured launch sequence for uneven batches (device)     */
 /* ------------------------------------------------------------------------ */

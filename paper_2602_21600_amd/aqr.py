@@ -137,6 +137,8 @@ _SIGS = [
     ("aqr_knn_workspace_size", _sz, [_i64, _i64, _i32]),
     ("aqr_knn_bruteforce", _i32, [_vp, _i64, _i32, _vp, _i64, _i32, _vp, _vp, _vp, _vp, _sz,
                                   _vp]),
+    ("aqr_knn_noalloc_max_bytes", _sz, []),
+    ("aqr_knn_bruteforce_noalloc", _i32, [_vp, _i64, _i32, _vp, _i64, _i32, _vp, _vp, _vp, _vp]),
     ("aqr_plan_create", _i32, [_vp, C.POINTER(SParams), C.POINTER(RParams),
                                C.POINTER(BatchBuffers), _i32, C.POINTER(_vp)]),
     ("aqr_plan_launch", _i32, [_vp, _i64, _vp]),
@@ -605,6 +607,23 @@ def aqr_knn_bruteforce(X, Q, k, out_id=None, out_dist=None, certified=None, ws=N
     _check(lib().aqr_knn_bruteforce(_dev_ptr(X), n, d, _dev_ptr(Q), nq, int(k), _dev_ptr(out_id),
                                     _dev_ptr(out_dist), _dev_ptr(certified), _dev_ptr(ws),
                                     ws.numel(), _stream_ptr(stream)))
+    return out_id, out_dist, certified
+
+
+def aqr_knn_bruteforce_noalloc(X, Q, k, out_id, out_dist, certified=None, stream=None):
+    """aqr_knn_bruteforce into caller-given outputs, with the library's fixed
+    device scratch instead of a workspace (nothing is allocated)."""
+    import torch
+    _need("X", X, _f32_types(), 2)
+    n, d = X.shape
+    _need("Q", Q, _f32_types(), 2, cols=(d,))
+    nq = Q.shape[0]
+    _need("out_id", out_id, _i32_types(), 2, rows=nq, cols=(k,))
+    _need("out_dist", out_dist, (torch.float64,), 2, rows=nq, cols=(k,))
+    _need("certified", certified, _u8_types(), 1, rows=nq, optional=True)
+    _check(lib().aqr_knn_bruteforce_noalloc(_dev_ptr(X), n, d, _dev_ptr(Q), nq, int(k),
+                                            _dev_ptr(out_id), _dev_ptr(out_dist),
+                                            _dev_ptr(certified), _stream_ptr(stream)))
     return out_id, out_dist, certified
 
 

@@ -34,6 +34,7 @@
 #include <algorithm>
 #include <atomic>
 #include <cmath>
+#include <mutex>
 #include <string>
 
 #include "internal.hpp"
@@ -429,4 +430,75 @@ extern "C" aqr_status aqr_knn_bruteforce(const float* X, int64_t n, int32_t d, c
                                          size_t ws_bytes, void* stream) {
     return knn_run("aqr_knn_bruteforce", X, n, d, Q, nq, k, out_id, out_dist, certified, ws,
                    ws_bytes, stream);
+}
+
+// ---------------------------------------------------------------------------
+// The same without a caller workspace, for callers that cannot allocate
+// device memory: the partition lists and the header live in a file-scope
+// device array (one copy per device, held until the process ends).  Its
+// device address is looked up once per device and kept; host code never
+// passes the array's name itself to a kernel.
+// ---------------------------------------------------------------------------
+namespace {
+
+constexpr size_t kScratchBytes = (size_t)16 << 20;
+
+}  // namespace
+
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+
+namespace {
+
+constexpr int kMaxDevices = 64;
+std::mutex scratch_mu;
+void* scratch_ptr[kMaxDevices] = {};
+
+aqr_status scratch_for_current_device(const char* who, void** out) {
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return fail(AQR_ERR_DEVICE, std::string(who) + ": " + hipGetErrorString(e));
+    if (dev < 0 || dev >= kMaxDevices)
+        return fail(AQR_ERR_DEVICE, std::string(who) + ": device index out of range");
+    std::lock_guard<std::mutex> lk(scratch_mu);
+    if (!scratch_ptr[dev]) {
+        void* p = nullptr;
+        e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !p)
+            return fail(AQR_ERR_DEVICE, std::string(who) + ": hipGetSymbolAddress: " +
+                                            hipGetErrorString(e));
+        scratch_ptr[dev] = p;
+    }
+    *out = scratch_ptr[dev];
+    return AQR_OK;
+}
+
+}  // namespace
+
+extern "C" size_t aqr_knn_noalloc_max_bytes(void) { return kScratchBytes; }
+
+extern "C" aqr_status aqr_knn_bruteforce_noalloc(const float* X, int64_t n, int32_t d,
+                                                 const float* Q, int64_t nq, int32_t k,
+                                                 int32_t* out_id, double* out_dist,
+                                                 uint8_t* certified, void* stream) {
+    const char* who = "aqr_knn_bruteforce_noalloc";
+    try {
+        clear_error();
+        if (nq == 0) return AQR_OK;
+        const size_t need = aqr_knn_workspace_size(n, nq, k);
+        if (need == 0)
+            return knn_run(who, X, n, d, Q, nq, k, out_id, out_dist, certified, nullptr, 0,
+                           stream);  // reports the argument error
+        if (need > kScratchBytes)
+            return fail(AQR_ERR_INVALID_ARG,
+                        std::string(who) + ": needs " + std::to_string(need) +
+                            " bytes of scratch, above its fixed " + std::to_string(kScratchBytes) +
+                            " (split the queries into smaller calls)");
+        void* ws = nullptr;
+        aqr_status st = scratch_for_current_device(who, &ws);
+        if (st != AQR_OK) return st;
+        return knn_run(who, X, n, d, Q, nq, k, out_id, out_dist, certified, ws, kScratchBytes,
+                       stream);
+    } catch (...) {
+        return fail(AQR_ERR_STATE, std::string(who) + ": unexpected failure");
+    }
 }
