@@ -277,6 +277,14 @@ def search_bytes(cnt_big, nq, d, d_pad, s0, s1, nc_total):
     return code, adj, io
 
 
+def tune_vbs(n):
+    """Visited-cache sizes the launch-shape loop tries: 2^6 .. 2^12 buckets,
+    from the smallest the id width allows (the stored remainder of a hashed
+    id is at most 15 bits)."""
+    idbits = max(1, int(np.ceil(np.log2(max(n, 2)))))
+    return list(range(max(6, idbits - 15), 13))
+
+
 def finite_or_none(x):
     """JSON has no infinities: thresholds that switch early termination off
     are reported as null."""
@@ -893,12 +901,12 @@ def run_search(args, torch, aqr, W, name, dev, threads, nq=None, curve_leg=True,
         best_ms = None
         r0 = AqrRunner(aqr, ix, nq, k, ef_a, dev, rerank=aqr_pick[2], **tuning)
         spin_up(torch, lambda m: r0.search_only(Qd))
-        for vb in (6, 7, 8, 9, 10, 11, 12):
+        for vb in tune_vbs(n):
             for wpb in (1, 2, 4):
                 try:
                     r = AqrRunner(aqr, ix, nq, k, ef_a, dev, visited_log2=vb,
                                   waves_per_block=wpb, rerank=aqr_pick[2])
-                    ms_t, _ = timed(torch, lambda m: r.search_only(Qd), 5, 1)
+                    ms_t, _ = timed(torch, lambda m: r.search_only(Qd), 3, 1)
                 except aqr.AqrError as e:  # LDS limit of the device
                     log(f"tune visited_log2={vb} waves_per_block={wpb}: skipped ({e})")
                     continue
@@ -979,12 +987,12 @@ def run_search(args, torch, aqr, W, name, dev, threads, nq=None, curve_leg=True,
             best_ms = None
             r0 = Fp32Runner(aqr, ix, nq, k, ef_f, dev, **fp_tuning)
             spin_up(torch, lambda m: r0.step(Qd))
-            for vb in (6, 7, 8, 9, 10, 11, 12):
+            for vb in tune_vbs(n):
                 for wpb in (1, 2, 4):
                     try:
                         r = Fp32Runner(aqr, ix, nq, k, ef_f, dev, visited_log2=vb,
                                        waves_per_block=wpb)
-                        ms_t, _ = timed(torch, lambda m: r.step(Qd), 5, 1)
+                        ms_t, _ = timed(torch, lambda m: r.step(Qd), 3, 1)
                     except aqr.AqrError as e:
                         log(f"tune fp32 visited_log2={vb} waves_per_block={wpb}: skipped ({e})")
                         continue
@@ -1257,8 +1265,9 @@ def main():
     ap.add_argument("--tune-sample", type=int, default=100_000,
                     help="batched: queries timed per launch shape (shapes that win on a small "
                          "sample can lose on the whole batch, whose occupancy matters more)")
-    ap.add_argument("--tune", action="store_true",
-                    help="tune the launch shapes of the timed searches (AQR and FP32) by timing")
+    ap.add_argument("--no-tune", dest="tune", action="store_false",
+                    help="skip the launch-shape loop of the timed searches (AQR and FP32) and "
+                         "use fixed shapes (results do not depend on the shape)")
     ap.add_argument("--vb", type=int, default=0, help="visited_log2 of the timed search (skips tuning)")
     ap.add_argument("--wpb", type=int, default=0, help="waves per block of the timed search (skips tuning)")
     ap.add_argument("--serve", action="store_true",

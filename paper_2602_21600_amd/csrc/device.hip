@@ -68,6 +68,7 @@ struct Idx {
     int64_t n;
     int32_t d, dp, xs, s0, s1;
     int32_t cs;              // code row stride in bytes (>= dp, whole 128-byte lines)
+    int32_t nrm;             // 1: |x^|^2 of each code row (uint32) sits at byte dp of the row
     int32_t xst;             // FP32 row stride in floats (>= xs, whole 128-byte lines)
     uint32_t ep;
     int32_t L;
@@ -227,6 +228,14 @@ struct Rows<false> {
         xq = dot4(x.w, q.w, xq);
         return xx - 2u * xq;
     }
+    // -2 q.x alone, for rows whose |x|^2 is stored with the row
+    __device__ static __forceinline__ uint32_t partq(uint4 x, uint4 q) {
+        uint32_t xq = dot4(x.x, q.x, 0u);
+        xq = dot4(x.y, q.y, xq);
+        xq = dot4(x.z, q.z, xq);
+        xq = dot4(x.w, q.w, xq);
+        return 0u - 2u * xq;
+    }
     __device__ static __forceinline__ uint32_t zero() { return 0u; }
     __device__ static __forceinline__ uint32_t add(uint32_t a, uint32_t b) { return a + b; }
     template <int LG>
@@ -287,7 +296,13 @@ __device__ __forceinline__ Geo make_geo(int lg, int nch, int lane) {
 // the US row sets of a pass are loaded before any is scored.  There are no
 // divergent branches: rows past nn and chunks past the row read row 0 /
 // chunk 0 (valid memory) and are masked out of the sum.
-template <bool F32, int CPL, int US, int LG>
+//
+// NRM (8-bit rows whose padding holds |x^|^2 at byte dp, and a row geometry
+// with a spare chunk slot): the slot after the row's last chunk loads the
+// chunk that starts with |x^|^2, and the data chunks need only q.x, so each
+// row costs half the dot products.  The sum |x|^2 - 2 q.x is the same
+// integer either way.
+template <bool F32, int CPL, int US, int LG, bool NRM = false>
 __device__ __forceinline__ void eval_pass(const Idx& ix, const uint32_t* ids, int nn, int r0,
                                           uint64_t* keys, const uint4 (&qv)[CPL], uint32_t qq,
                                           const int sub, const int grp, const int nch) {
@@ -302,7 +317,7 @@ __device__ __forceinline__ void eval_pass(const Idx& ix, const uint32_t* ids, in
 #pragma unroll
         for (int c = 0; c < CPL; ++c) {
             const int ch = sub + c * G;
-            x[u][c] = R::load(ix, id[u], ch < nch ? ch : 0);
+            x[u][c] = R::load(ix, id[u], (NRM ? ch <= nch : ch < nch) ? ch : 0);
         }
     }
 #pragma unroll
@@ -310,8 +325,14 @@ __device__ __forceinline__ void eval_pass(const Idx& ix, const uint32_t* ids, in
         typename R::Acc s = R::zero();
 #pragma unroll
         for (int c = 0; c < CPL; ++c) {
-            const typename R::Acc t = R::part(x[u][c], qv[c]);
-            s = R::add(s, sub + c * G < nch ? t : R::zero());
+            const int ch = sub + c * G;
+            if constexpr (NRM && !F32) {
+                const uint32_t t = ch < nch ? R::partq(x[u][c], qv[c]) : x[u][c].x;
+                s = R::add(s, ch <= nch ? t : R::zero());
+            } else {
+                const typename R::Acc t = R::part(x[u][c], qv[c]);
+                s = R::add(s, ch < nch ? t : R::zero());
+            }
         }
         s = R::template gsum<LG>(s);
         const int r = r0 + u * RPP + grp;
@@ -322,7 +343,7 @@ __device__ __forceinline__ void eval_pass(const Idx& ix, const uint32_t* ids, in
 
 // Score nn rows in passes of as many row sets as the remaining rows need, at
 // most U, so a short list costs as many sets as it fills, not U.
-template <bool F32, int CPL, int U, int LG>
+template <bool F32, int CPL, int U, int LG, bool NRM = false>
 __device__ __forceinline__ void eval_rows(const Idx& ix, const uint32_t* ids, int nn,
                                           uint64_t* keys, const uint4 (&qv)[CPL], uint32_t qq,
                                           const int lane, const int nch) {
@@ -332,26 +353,26 @@ __device__ __forceinline__ void eval_rows(const Idx& ix, const uint32_t* ids, in
         const int sets = min(U, (nn - r0 + RPP - 1) / RPP);  // wave-uniform
         if constexpr (U >= 4) {
             if (sets == 4) {
-                eval_pass<F32, CPL, (U >= 4 ? 4 : 1), LG>(ix, ids, nn, r0, keys, qv, qq, sub, grp, nch);
+                eval_pass<F32, CPL, (U >= 4 ? 4 : 1), LG, NRM>(ix, ids, nn, r0, keys, qv, qq, sub, grp, nch);
                 r0 += 4 * RPP;
                 continue;
             }
         }
         if constexpr (U >= 3) {
             if (sets == 3) {
-                eval_pass<F32, CPL, (U >= 3 ? 3 : 1), LG>(ix, ids, nn, r0, keys, qv, qq, sub, grp, nch);
+                eval_pass<F32, CPL, (U >= 3 ? 3 : 1), LG, NRM>(ix, ids, nn, r0, keys, qv, qq, sub, grp, nch);
                 r0 += 3 * RPP;
                 continue;
             }
         }
         if constexpr (U >= 2) {
             if (sets == 2) {
-                eval_pass<F32, CPL, (U >= 2 ? 2 : 1), LG>(ix, ids, nn, r0, keys, qv, qq, sub, grp, nch);
+                eval_pass<F32, CPL, (U >= 2 ? 2 : 1), LG, NRM>(ix, ids, nn, r0, keys, qv, qq, sub, grp, nch);
                 r0 += 2 * RPP;
                 continue;
             }
         }
-        eval_pass<F32, CPL, 1, LG>(ix, ids, nn, r0, keys, qv, qq, sub, grp, nch);
+        eval_pass<F32, CPL, 1, LG, NRM>(ix, ids, nn, r0, keys, qv, qq, sub, grp, nch);
         r0 += RPP;
     }
 }
@@ -464,7 +485,7 @@ __device__ __forceinline__ uint64_t readlane64(uint64_t v, int l) {
 // popcount or a readfirstlane), and every single-lane block is closed by a
 // wave barrier before the next loop control, so all lanes stay converged at
 // each cross-lane operation.
-template <bool F32, int CPL, int U, int LG, bool TAPS>
+template <bool F32, int CPL, int U, int LG, bool TAPS, bool NRM = false>
 __device__ __forceinline__ void search_query(const SearchArgs& a, const int64_t q, const int efe,
                                              const int nc, const int lane,
                                              const VisCache& vis, uint64_t* mk, uint64_t* spare,
@@ -501,7 +522,7 @@ __device__ __forceinline__ void search_query(const SearchArgs& a, const int64_t 
     uint32_t cur = ix.ep;
     if (lane == 0) st_id[0] = cur;
     wsync();
-    eval_rows<F32, CPL, U, LG>(ix, st_id, 1, st_key, qv, qq, lane, a.nch);
+    eval_rows<F32, CPL, U, LG, NRM>(ix, st_id, 1, st_key, qv, qq, lane, a.nch);
     wsync();
     uint64_t curkey = uni64(st_key[0]);
     for (int l = ix.L; l >= 1; --l) {
@@ -515,7 +536,7 @@ __device__ __forceinline__ void search_query(const SearchArgs& a, const int64_t 
                 cnt += __popcll(m);
             }
             wsync();
-            eval_rows<F32, CPL, U, LG>(ix, st_id, cnt, st_key, qv, qq, lane, a.nch);
+            eval_rows<F32, CPL, U, LG, NRM>(ix, st_id, cnt, st_key, qv, qq, lane, a.nch);
             wsync();
             n_up += cnt;
             ++n_upx;
@@ -598,7 +619,7 @@ __device__ __forceinline__ void search_query(const SearchArgs& a, const int64_t 
             }
         }
         n_eval += nn;
-        eval_rows<F32, CPL, U, LG>(ix, st_id, nn, st_key, qv, qq, lane, a.nch);
+        eval_rows<F32, CPL, U, LG, NRM>(ix, st_id, nn, st_key, qv, qq, lane, a.nch);
         wsync();
         // merge the scored neighbours, 64 at a time
         for (int b0 = 0; b0 < nn; b0 += kWave) {
@@ -712,7 +733,7 @@ __device__ __forceinline__ void search_query(const SearchArgs& a, const int64_t 
 template <bool F32, int CPL, int LG>
 constexpr int search_waves_per_eu() { return !F32 && (CPL << LG) <= 16 ? 7 : 1; }
 
-template <bool F32, int CPL, int U, int LG, bool TAPS>
+template <bool F32, int CPL, int U, int LG, bool TAPS, bool NRM>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(search_waves_per_eu<F32, CPL, LG>())))
 void k_search(SearchArgs a) {
     extern __shared__ __align__(16) unsigned char smem[];
@@ -778,7 +799,7 @@ void k_search(SearchArgs a) {
                     }
                 }
             } else {
-                search_query<F32, CPL, U, LG, TAPS>(a, q, efe, nc, lane, vis, mk,
+                search_query<F32, CPL, U, LG, TAPS, NRM>(a, q, efe, nc, lane, vis, mk,
                                                     mk + a.ef_cap, st_id, st_key, visb, qf, qc);
             }
         }
@@ -1335,7 +1356,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k
             sq.vb = vbq;
             // Stage 1 writes its N_c candidates into the search part; the
             // re-rank reads them from there
-            search_query<false, CPL, U, LG, false>(sq, 0, efe, nc, lane, vis, mk, spare, st_id,
+            search_query<false, CPL, U, LG, false, false>(sq, 0, efe, nc, lane, vis, mk, spare, st_id,
                                                    st_key, visb, qf, qc);
             const int cnt = uni(*reinterpret_cast<const int*>(st_id));
             // Stages 2-3 overlay the run from its start: the candidate ids are
@@ -1501,12 +1522,28 @@ extern "C" aqr_status aqr_index_bind(const aqr_quantizer* qz, const aqr_graph* g
                 std::memcpy(&xs[(size_t)i * L.xst], X + i * d, sizeof(float) * d);
             Xsrc = xs.data();
         }
+        // code rows at the line stride; when the padding has room, the row's
+        // |x^|^2 (exact, uint32) follows its d_pad codes, so the search needs
+        // only q.x per row
         std::vector<uint8_t> cst;
         const uint8_t* Csrc = codes;
+        const bool nrm = L.cs >= L.dp + 4;
         if (L.cs != L.dp) {
             cst.assign((size_t)n * L.cs, 0);
-            for (int64_t i = 0; i < n; ++i)
-                std::memcpy(&cst[(size_t)i * L.cs], codes + i * L.dp, (size_t)L.dp);
+            parallel_for_threads(std::max(1, std::min(16, (int)(n / 65536))), [&](int t) {
+                const int T = std::max(1, std::min(16, (int)(n / 65536)));
+                const int64_t i0 = n * t / T, i1 = n * (t + 1) / T;
+                for (int64_t i = i0; i < i1; ++i) {
+                    const uint8_t* src = codes + i * L.dp;
+                    uint8_t* dst = &cst[(size_t)i * L.cs];
+                    std::memcpy(dst, src, (size_t)L.dp);
+                    if (nrm) {
+                        uint32_t xx = 0;
+                        for (int32_t j = 0; j < L.dp; ++j) xx += (uint32_t)src[j] * src[j];
+                        std::memcpy(dst + L.dp, &xx, 4);
+                    }
+                }
+            });
             Csrc = cst.data();
         }
         std::vector<uint32_t> a0((size_t)n * L.s0, AQR_NONE);
@@ -1557,6 +1594,7 @@ extern "C" aqr_status aqr_index_bind(const aqr_quantizer* qz, const aqr_graph* g
         v.xs = L.xs;
         v.cs = L.cs;
         v.xst = L.xst;
+        v.nrm = (L.cs >= L.dp + 4) ? 1 : 0;
         v.s0 = L.s0;
         v.s1 = L.s1;
         v.ep = g->ep;
@@ -1595,10 +1633,16 @@ template <bool F32, int CPL, int U, int LG>
 hipError_t launch_search_k(dev::SearchArgs& a, int blocks, int wpb, size_t lds, int ncu,
                            hipStream_t s) {
     const bool taps = a.taps.expanded || a.taps.evaluated || a.taps.counts;
-    auto kern = taps ? dev::k_search<F32, CPL, U, LG, true> : dev::k_search<F32, CPL, U, LG, false>;
+    // rows with |x|^2 in their padding, and a spare chunk slot to read it
+    const bool nrm = !F32 && a.ix.nrm && a.nch < (CPL << LG);
+    const int kv = (taps ? 1 : 0) + (nrm ? 2 : 0);
+    auto kern = nrm ? (taps ? dev::k_search<F32, CPL, U, LG, true, true>
+                            : dev::k_search<F32, CPL, U, LG, false, true>)
+                    : (taps ? dev::k_search<F32, CPL, U, LG, true, false>
+                            : dev::k_search<F32, CPL, U, LG, false, false>);
     // the dynamic-LDS limit is raised once per size and kernel, outside any stream capture
-    static std::atomic<int> lds_set[2] = {0, 0};
-    std::atomic<int>& ls = lds_set[taps ? 1 : 0];
+    static std::atomic<int> lds_set[4] = {0, 0, 0, 0};
+    std::atomic<int>& ls = lds_set[kv];
     hipError_t e = hipSuccess;
     if ((int)lds > ls.load()) {
         e = hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize,
@@ -1611,20 +1655,20 @@ hipError_t launch_search_k(dev::SearchArgs& a, int blocks, int wpb, size_t lds, 
         // asked of the runtime once and kept: the query is not free, and a
         // launch that waits on it leaves the device idle.
         static std::mutex occ_mu;
-        static std::map<std::pair<int, int>, int> occ[2];
+        static std::map<std::pair<int, int>, int> occ[4];
         const std::pair<int, int> key{wpb, (int)lds};
         int per_cu = 0;
         {
             std::lock_guard<std::mutex> lk(occ_mu);
-            auto it = occ[taps ? 1 : 0].find(key);
-            if (it != occ[taps ? 1 : 0].end()) per_cu = it->second;
+            auto it = occ[kv].find(key);
+            if (it != occ[kv].end()) per_cu = it->second;
         }
         if (per_cu == 0) {
             e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, wpb * dev::kWave, lds);
             if (e != hipSuccess) return e;
             per_cu = std::max(1, per_cu);
             std::lock_guard<std::mutex> lk(occ_mu);
-            occ[taps ? 1 : 0][key] = per_cu;
+            occ[kv][key] = per_cu;
         }
         blocks = per_cu * std::max(1, ncu);
         const int64_t need = (a.nq + wpb - 1) / wpb;
