@@ -564,24 +564,52 @@ __device__ __forceinline__ void search_query(const SearchArgs& a, const int64_t 
     int wsize = 1;
     int first = 0;
     const int nad = (ix.s0 + kWave - 1) / kWave;  // 64-entry chunks of an adjacency row (<= 4)
+    // Speculative adjacency (rows of at most 64 entries): each pop also loads
+    // the row of the next unexpanded entry of W after the popped one, and
+    // parks it in the neighbour-id array once the expansion no longer needs
+    // that array.  When no admitted key lands before that entry, it is the
+    // next pop and its row is read from LDS, so the expansion waits for one
+    // dependent global round trip (the code rows) instead of two.  Adjacency
+    // rows never change during a search, so the results are the same either
+    // way.
+    uint32_t spec = kNone;
     for (;;) {
-        // nearest unexpanded entry of W
-        int idx = -1;
-        uint64_t kc = 0;
+        // nearest unexpanded entry of W, and the one after it
+        int idx = -1, sidx = -1;
+        uint64_t kc = 0, ks = 0;
         for (int b0 = first & ~(kWave - 1); b0 < wsize; b0 += kWave) {
             const int i = b0 + lane;
             const uint64_t w = mk[i];  // inside W's capacity (whole 64-entry slots)
-            const uint64_t m = ballot(i >= first && i < wsize && (w & 1ull) == 0);
+            uint64_t m = ballot(i >= first && i < wsize && (w & 1ull) == 0);
             if (m) {
                 const int t = (int)__builtin_ctzll(m);
                 idx = b0 + t;
                 kc = readlane64(w, t);
+                m &= m - 1;
+                if (m) {
+                    const int t2 = (int)__builtin_ctzll(m);
+                    sidx = b0 + t2;
+                    ks = readlane64(w, t2);
+                } else if (b0 + kWave < wsize) {
+                    // b0 + kWave < wsize <= ef_cap, a multiple of 64: this
+                    // slot lies inside W's capacity too
+                    const int i2 = b0 + kWave + lane;
+                    const uint64_t w2 = mk[i2];
+                    const uint64_t m2 = ballot(i2 < wsize && (w2 & 1ull) == 0);
+                    if (m2) {
+                        const int t2 = (int)__builtin_ctzll(m2);
+                        sidx = b0 + kWave + t2;
+                        ks = readlane64(w2, t2);
+                    }
+                }
                 break;
             }
         }
         idx = uni(idx);
         if (idx < 0) break;
+        sidx = uni(sidx);
         const uint32_t c = (uint32_t)kc >> 1;
+        const uint32_t cn = sidx >= 0 ? (uint32_t)ks >> 1 : kNone;
         first = idx + 1;
         wsync();
         mk[idx] = kc | 1ull;  // expanded; every lane stores the same value
@@ -592,11 +620,28 @@ __device__ __forceinline__ void search_query(const SearchArgs& a, const int64_t 
         // unvisited neighbours of c
         const uint32_t* row = ix.adj0 + (int64_t)c * ix.s0;
         uint32_t e[4];
+        uint32_t nxt = kNone;  // the speculative row, in flight
+        if (nad == 1) {
+            const int j = lane < ix.s0 ? lane : 0;
+            // (the parked row is stored masked, so the two paths differ and
+            // are not folded into one flat load, which would wait for both)
+            if (uni(spec == c ? 1 : 0))
+                e[0] = st_id[lane];  // parked by the previous expansion
+            else
+                e[0] = lane < ix.s0 ? row[j] : kNone;
+            // issued after c's row on both paths (c's own row again when W
+            // holds no further unexpanded entry): waiting for c's row leaves
+            // this load outstanding
+            nxt = ix.adj0[(int64_t)(cn != kNone ? cn : c) * ix.s0 + j];
+            spec = cn;
+            e[1] = e[2] = e[3] = kNone;
+        } else {
 #pragma unroll
-        for (int b = 0; b < 4; ++b) {
-            const int j = b * kWave + lane;
-            const uint32_t v = b < nad ? row[j < ix.s0 ? j : 0] : kNone;
-            e[b] = j < ix.s0 ? v : kNone;
+            for (int b = 0; b < 4; ++b) {
+                const int j = b * kWave + lane;
+                const uint32_t v = b < nad ? row[j < ix.s0 ? j : 0] : kNone;
+                e[b] = j < ix.s0 ? v : kNone;
+            }
         }
         int nn = 0;
 #pragma unroll
@@ -611,7 +656,11 @@ __device__ __forceinline__ void search_query(const SearchArgs& a, const int64_t 
         }
         wsync();
         nn = uni(nn);
-        if (nn == 0) continue;
+        if (nn == 0) {
+            if (nad == 1) st_id[lane] = lane < ix.s0 ? nxt : kNone;  // st_cap >= 64
+            wsync();
+            continue;
+        }
         if (TAPS && a.taps.evaluated) {
             for (int j = lane; j < nn; j += kWave) {
                 const int p = (int)n_eval + j;
@@ -621,6 +670,9 @@ __device__ __forceinline__ void search_query(const SearchArgs& a, const int64_t 
         n_eval += nn;
         eval_rows<F32, CPL, U, LG, NRM>(ix, st_id, nn, st_key, qv, qq, lane, a.nch);
         wsync();
+        // the neighbour ids are consumed: park the speculative row there (the
+        // code rows were issued after it, so it has arrived)
+        if (nad == 1) st_id[lane] = lane < ix.s0 ? nxt : kNone;
         // merge the scored neighbours, 64 at a time
         for (int b0 = 0; b0 < nn; b0 += kWave) {
             const uint64_t bound = wsize == efe ? uni64(mk[efe - 1]) : ~0ull;
