@@ -54,6 +54,11 @@ namespace aqr {
 namespace dev {
 
 constexpr uint32_t kNone = 0xFFFFFFFFu;
+// Spare bytes after the code rows and after the FP32 rows of an index arena:
+// the search reads whole chunk slots of a row without clamping them to the
+// row, at most CPL * 2^LG = 1,024 slots of 16 bytes (FP32 rows of up to
+// kMaxD floats: 16 chunks per lane on 64 lanes) from the row start.
+constexpr size_t kRowSlack = 16384;
 constexpr int kWave = 64;
 constexpr int kMaxD = 4096;
 
@@ -215,7 +220,7 @@ template <>
 struct Rows<false> {
     using Acc = uint32_t;
     __device__ static __forceinline__ uint4 load(const Idx& ix, uint32_t id, int ch) {
-        return reinterpret_cast<const uint4*>(ix.codes + (int64_t)id * ix.cs)[ch];
+        return reinterpret_cast<const uint4*>(ix.codes + (uint64_t)id * (uint32_t)ix.cs)[ch];
     }
     __device__ static __forceinline__ uint32_t part(uint4 x, uint4 q) {
         uint32_t xx = dot4(x.x, x.x, 0u);
@@ -227,14 +232,6 @@ struct Rows<false> {
         xq = dot4(x.z, q.z, xq);
         xq = dot4(x.w, q.w, xq);
         return xx - 2u * xq;
-    }
-    // -2 q.x alone, for rows whose |x|^2 is stored with the row
-    __device__ static __forceinline__ uint32_t partq(uint4 x, uint4 q) {
-        uint32_t xq = dot4(x.x, q.x, 0u);
-        xq = dot4(x.y, q.y, xq);
-        xq = dot4(x.z, q.z, xq);
-        xq = dot4(x.w, q.w, xq);
-        return 0u - 2u * xq;
     }
     __device__ static __forceinline__ uint32_t zero() { return 0u; }
     __device__ static __forceinline__ uint32_t add(uint32_t a, uint32_t b) { return a + b; }
@@ -251,7 +248,7 @@ template <>
 struct Rows<true> {
     using Acc = float;
     __device__ static __forceinline__ uint4 load(const Idx& ix, uint32_t id, int ch) {
-        return reinterpret_cast<const uint4*>(ix.X + (int64_t)id * ix.xst)[ch];
+        return reinterpret_cast<const uint4*>(ix.X + (uint64_t)id * (uint32_t)ix.xst)[ch];
     }
     __device__ static __forceinline__ float part(uint4 x, uint4 q) {
         float acc = 0.0f;
@@ -294,14 +291,17 @@ __device__ __forceinline__ Geo make_geo(int lg, int nch, int lane) {
 // flag of W, and keys still order by (distance, id).  Rows are spread over
 // groups of 2^LG lanes, one 16-byte chunk per lane and CPL chunks per lane;
 // the US row sets of a pass are loaded before any is scored.  There are no
-// divergent branches: rows past nn and chunks past the row read row 0 /
-// chunk 0 (valid memory) and are masked out of the sum.
+// divergent branches: rows past nn read row 0, and chunk slots past the row
+// read whatever follows it (the row sections of the index arena end with
+// kRowSlack spare bytes, more than any geometry's CPL * 2^LG chunks), and
+// both are masked out of the sum.
 //
 // NRM (8-bit rows whose padding holds |x^|^2 at byte dp, and a row geometry
 // with a spare chunk slot): the slot after the row's last chunk loads the
 // chunk that starts with |x^|^2, and the data chunks need only q.x, so each
-// row costs half the dot products.  The sum |x|^2 - 2 q.x is the same
-// integer either way.
+// row costs half the dot products.  The query chunks past the row are zero,
+// so the slots past the row add nothing to q.x.  The sum |x|^2 - 2 q.x is the
+// same integer either way.
 template <bool F32, int CPL, int US, int LG, bool NRM = false>
 __device__ __forceinline__ void eval_pass(const Idx& ix, const uint32_t* ids, int nn, int r0,
                                           uint64_t* keys, const uint4 (&qv)[CPL], uint32_t qq,
@@ -315,21 +315,26 @@ __device__ __forceinline__ void eval_pass(const Idx& ix, const uint32_t* ids, in
         const int r = r0 + u * RPP + grp;
         id[u] = r < nn ? ids[r] : 0u;
 #pragma unroll
-        for (int c = 0; c < CPL; ++c) {
-            const int ch = sub + c * G;
-            x[u][c] = R::load(ix, id[u], (NRM ? ch <= nch : ch < nch) ? ch : 0);
-        }
+        for (int c = 0; c < CPL; ++c) x[u][c] = R::load(ix, id[u], sub + c * G);
     }
 #pragma unroll
     for (int u = 0; u < US; ++u) {
         typename R::Acc s = R::zero();
+        if constexpr (NRM && !F32) {
+            uint32_t xq = 0u, nr = 0u;
 #pragma unroll
-        for (int c = 0; c < CPL; ++c) {
-            const int ch = sub + c * G;
-            if constexpr (NRM && !F32) {
-                const uint32_t t = ch < nch ? R::partq(x[u][c], qv[c]) : x[u][c].x;
-                s = R::add(s, ch <= nch ? t : R::zero());
-            } else {
+            for (int c = 0; c < CPL; ++c) {
+                xq = dot4(x[u][c].x, qv[c].x, xq);
+                xq = dot4(x[u][c].y, qv[c].y, xq);
+                xq = dot4(x[u][c].z, qv[c].z, xq);
+                xq = dot4(x[u][c].w, qv[c].w, xq);
+                nr += sub + c * G == nch ? x[u][c].x : 0u;
+            }
+            s = nr - 2u * xq;
+        } else {
+#pragma unroll
+            for (int c = 0; c < CPL; ++c) {
+                const int ch = sub + c * G;
                 const typename R::Acc t = R::part(x[u][c], qv[c]);
                 s = R::add(s, ch < nch ? t : R::zero());
             }
@@ -683,7 +688,11 @@ __device__ __forceinline__ void search_query(const SearchArgs& a, const int64_t 
             // entries of W below the key, by bisection of the sorted list:
             // the key's count lies in [lo, lo + n] and n shrinks by its
             // half each step (the same on every lane), so every read is
-            // inside W and no lane branches
+            // inside W and no lane branches.  (Narrowing to a 64-entry slot
+            // first, by the slot heads, or a 4-way search with independent
+            // reads, cost more issue slots than the dependent reads they
+            // saved: the merge is bound by the instructions the waves of a
+            // SIMD share, not by the latency of one chain.)
             int lo = 0;
             for (int n = wsize; n > 1;) {
                 const int half = n >> 1;
@@ -716,18 +725,26 @@ __device__ __forceinline__ void search_query(const SearchArgs& a, const int64_t 
             const int pos = lo + rankA;
             // W entry i moves up by the number of admitted keys with lower
             // bound <= i.  Slots are moved from the last one down: an entry
-            // only moves up and past the slots already moved, and each slot
-            // is read whole before it is written.
+            // only moves up and past the slots already moved.  Each slot is
+            // read whole before it is written, and the slot below is read
+            // before this one is written (this slot's entries land at or
+            // above its own start, so the slot below is not overwritten).
             wsync();
-            for (int sl = (wsize - 1) >> 6; sl >= (lo_min >> 6); --sl) {
+            const int sl_lo = lo_min >> 6;
+            int sl = (wsize - 1) >> 6;
+            uint64_t wn = mk[sl * kWave + lane];  // inside W's capacity
+            for (; sl >= sl_lo; --sl) {
                 const int i = sl * kWave + lane;
                 const bool v = i < wsize && i >= lo_min;
-                const uint64_t w = mk[i];  // inside W's capacity
-                // a slot wholly above every insertion point moves by m_adm
+                const uint64_t w = wn;
+                if (sl > sl_lo) wn = mk[i - kWave];
+                // a slot wholly above every insertion point moves by m_adm;
+                // otherwise: the keys placed below the slot, then those of
+                // the keys placed inside it that lie at or below the entry
                 int sh = m_adm;
                 if (lo_max > sl * kWave) {
-                    sh = 0;
-                    for (uint64_t it = A; it != 0; it &= it - 1)
+                    sh = __popcll(ballot(mine && lo < sl * kWave));
+                    for (uint64_t it = ballot(mine && (lo >> 6) == sl); it != 0; it &= it - 1)
                         sh += __builtin_amdgcn_readlane(lo, (int)__builtin_ctzll(it)) <= i ? 1 : 0;
                 }
                 const int p = i + sh;
@@ -1501,9 +1518,9 @@ Layout layout_of(const aqr_quantizer* qz, const aqr_graph* g) {
     L.rows = std::max<int64_t>(g->upper_off[n], 1);
     size_t o = 0;
     L.codes = o;
-    o = align256(o + (size_t)n * L.cs);
+    o = align256(o + (size_t)n * L.cs + dev::kRowSlack);
     L.X = o;
-    o = align256(o + (size_t)n * L.xst * 4);
+    o = align256(o + (size_t)n * L.xst * 4 + dev::kRowSlack);
     L.adj0 = o;
     o = align256(o + (size_t)n * L.s0 * 4);
     L.ubase = o;
