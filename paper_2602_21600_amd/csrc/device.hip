@@ -797,13 +797,13 @@ __device__ __forceinline__ void search_query(const SearchArgs& a, const int64_t 
 }
 
 // Register budget: seven waves per SIMD for code rows of up to 16 chunks (a
-// few spilled values cost less than the lost wave); wider rows and the FP32
-// rows keep the compiler's choice.
-template <bool F32, int CPL, int LG>
-constexpr int search_waves_per_eu() { return !F32 && (CPL << LG) <= 16 ? 7 : 1; }
+// few spilled values cost less than the lost wave), five when four row sets
+// are in flight; wider rows and the FP32 rows keep the compiler's choice.
+template <bool F32, int CPL, int U, int LG>
+constexpr int search_waves_per_eu() { return !F32 && (CPL << LG) <= 16 ? (U >= 4 ? 5 : 7) : 1; }
 
 template <bool F32, int CPL, int U, int LG, bool TAPS, bool NRM>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(search_waves_per_eu<F32, CPL, LG>())))
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(search_waves_per_eu<F32, CPL, U, LG>())))
 void k_search(SearchArgs a) {
     extern __shared__ __align__(16) unsigned char smem[];
     const int lane = lane_id();
@@ -1480,7 +1480,8 @@ struct aqr_index {
     int device;
     int32_t M;
     int num_cu;
-    size_t max_lds;
+    size_t max_lds;     // per block
+    size_t cu_lds;      // per compute unit
 };
 
 namespace {
@@ -1683,6 +1684,7 @@ extern "C" aqr_status aqr_index_bind(const aqr_quantizer* qz, const aqr_graph* g
         }
         ix->num_cu = prop.multiProcessorCount;
         ix->max_lds = prop.sharedMemPerBlock;
+        ix->cu_lds = std::max(prop.maxSharedMemoryPerMultiProcessor, prop.sharedMemPerBlock);
         *out = ix;
         return AQR_OK;
     } catch (const std::bad_alloc&) {
@@ -1755,19 +1757,28 @@ hipError_t launch_search_k(dev::SearchArgs& a, int blocks, int wpb, size_t lds, 
 // a batch the number of rows in flight per wave sets the latency.  A batch
 // of at most one wave per SIMD (lat) leaves registers to spare, so wide
 // rows then keep four row sets in flight instead of two (128 VGPRs of rows).
+// Short code rows keep four sets in flight (a whole 64-entry adjacency row
+// scored in one pass instead of two dependent ones) when registers are not
+// what limits the waves per SIMD: with lat, or when the LDS of one wave
+// leaves room for at most five waves per SIMD (lds_few).
 template <bool F32>
 hipError_t launch_search(dev::SearchArgs& a, int nch, int blocks, int wpb, size_t lds, int ncu,
-                         hipStream_t s, bool lat) {
+                         hipStream_t s, bool lat, bool lds_few) {
     auto lg_for = [](int groups) {  // smallest lg with 2^lg >= groups, at least 2
         int lg = 2;
         while ((1 << lg) < groups) ++lg;
         return lg;
     };
     if constexpr (!F32) {
-        if (nch <= 16) {  // up to 256 bytes: 2 chunks per lane, 2 rows in flight
+        if (nch <= 16) {  // up to 256 bytes: 2 chunks per lane, 2 (4) rows in flight
+            const bool u4 = lat || lds_few;
             switch (lg_for((nch + 1) / 2)) {
-                case 2: return launch_search_k<F32, 2, 2, 2>(a, blocks, wpb, lds, ncu, s);
-                default: return launch_search_k<F32, 2, 2, 3>(a, blocks, wpb, lds, ncu, s);
+                case 2:
+                    return u4 ? launch_search_k<F32, 2, 4, 2>(a, blocks, wpb, lds, ncu, s)
+                              : launch_search_k<F32, 2, 2, 2>(a, blocks, wpb, lds, ncu, s);
+                default:
+                    return u4 ? launch_search_k<F32, 2, 4, 3>(a, blocks, wpb, lds, ncu, s)
+                              : launch_search_k<F32, 2, 2, 3>(a, blocks, wpb, lds, ncu, s);
             }
         }
         if (nch <= 32)  // up to 512 bytes: 4 chunks per lane, 2 rows in flight
@@ -1889,8 +1900,9 @@ aqr_status run_search(const aqr_index* ix, const float* Q, int64_t nq, const int
     if (cpl > 16) return fail(AQR_ERR_INVALID_ARG, std::string(who) + ": row too wide");
     if (!f32 && cpl > 4) return fail(AQR_ERR_INVALID_ARG, std::string(who) + ": code row too wide");
     const bool lat = nq <= (int64_t)ix->num_cu * 4;  // at most one wave per SIMD
-    e = f32 ? launch_search<true>(a, nch, sp->blocks, wpb, lds, ix->num_cu, s, lat)
-            : launch_search<false>(a, nch, sp->blocks, wpb, lds, ix->num_cu, s, lat);
+    const bool lds_few = ix->cu_lds / wl <= 20;       // LDS: at most five waves per SIMD
+    e = f32 ? launch_search<true>(a, nch, sp->blocks, wpb, lds, ix->num_cu, s, lat, lds_few)
+            : launch_search<false>(a, nch, sp->blocks, wpb, lds, ix->num_cu, s, lat, lds_few);
     if (e != hipSuccess) return hip_fail(e, who);
     return AQR_OK;
 }
