@@ -569,7 +569,7 @@ __device__ __forceinline__ void search_query(const SearchArgs& a, const int64_t 
     int wsize = 1;
     int first = 0;
     const int nad = (ix.s0 + kWave - 1) / kWave;  // 64-entry chunks of an adjacency row (<= 4)
-    // Speculative adjacency (rows of at most 64 entries): each pop also loads
+    // Speculative adjacency (rows of at most 128 entries): each pop also loads
     // the row of the next unexpanded entry of W after the popped one, and
     // parks it in the neighbour-id array once the expansion no longer needs
     // that array.  When no admitted key lands before that entry, it is the
@@ -625,7 +625,7 @@ __device__ __forceinline__ void search_query(const SearchArgs& a, const int64_t 
         // unvisited neighbours of c
         const uint32_t* row = ix.adj0 + (int64_t)c * ix.s0;
         uint32_t e[4];
-        uint32_t nxt = kNone;  // the speculative row, in flight
+        uint32_t nxt = kNone, nxt1 = kNone;  // the speculative row, in flight
         if (nad == 1) {
             const int j = lane < ix.s0 ? lane : 0;
             // (the parked row is stored masked, so the two paths differ and
@@ -640,6 +640,23 @@ __device__ __forceinline__ void search_query(const SearchArgs& a, const int64_t 
             nxt = ix.adj0[(int64_t)(cn != kNone ? cn : c) * ix.s0 + j];
             spec = cn;
             e[1] = e[2] = e[3] = kNone;
+        } else if (nad == 2) {
+            // rows of 65..128 entries: the same in two 64-entry chunks; every
+            // lane's first-chunk entry lies inside the row
+            const int j1 = kWave + lane;
+            const int j1c = j1 < ix.s0 ? j1 : 0;
+            if (uni(spec == c ? 1 : 0)) {
+                e[0] = st_id[lane];
+                e[1] = st_id[j1];
+            } else {
+                e[0] = lane < ix.s0 ? row[lane] : kNone;
+                e[1] = j1 < ix.s0 ? row[j1c] : kNone;
+            }
+            const uint32_t* nrow = ix.adj0 + (int64_t)(cn != kNone ? cn : c) * ix.s0;
+            nxt = nrow[lane];
+            nxt1 = nrow[j1c];
+            spec = cn;
+            e[2] = e[3] = kNone;
         } else {
 #pragma unroll
             for (int b = 0; b < 4; ++b) {
@@ -661,8 +678,14 @@ __device__ __forceinline__ void search_query(const SearchArgs& a, const int64_t 
         }
         wsync();
         nn = uni(nn);
+        // park the speculative row in the neighbour-id array (st_cap >= 64 *
+        // nad), masked past the row
+        auto park = [&]() {
+            if (nad <= 2) st_id[lane] = lane < ix.s0 ? nxt : kNone;
+            if (nad == 2) st_id[kWave + lane] = kWave + lane < ix.s0 ? nxt1 : kNone;
+        };
         if (nn == 0) {
-            if (nad == 1) st_id[lane] = lane < ix.s0 ? nxt : kNone;  // st_cap >= 64
+            park();
             wsync();
             continue;
         }
@@ -677,7 +700,7 @@ __device__ __forceinline__ void search_query(const SearchArgs& a, const int64_t 
         wsync();
         // the neighbour ids are consumed: park the speculative row there (the
         // code rows were issued after it, so it has arrived)
-        if (nad == 1) st_id[lane] = lane < ix.s0 ? nxt : kNone;
+        park();
         // merge the scored neighbours, 64 at a time
         for (int b0 = 0; b0 < nn; b0 += kWave) {
             const uint64_t bound = wsize == efe ? uni64(mk[efe - 1]) : ~0ull;
