@@ -1,7 +1,7 @@
 """Host-side checks of the benchmark's bookkeeping (no GPU): the one-GPU
 contract of --gpus, tie-inclusive recall, the parity classification of top-k
-rows, the algorithmic byte count of a Stage-1 launch and the sweep's
-settings."""
+rows, the algorithmic byte count of a Stage-1 launch, the sweep's settings
+and the tie rule of the launch-shape loop."""
 import importlib.util
 import json
 import os
@@ -82,3 +82,15 @@ def test_sweep_settings_follow_table3_then_cost_order(bench):
     off = [c for c in bench.RERANK_CONFIGS if not np.isfinite(c[2])]
     assert [c[1] for c in off if c[4] == 3] == sorted(c[1] for c in off if c[4] == 3)
     assert bench.rerank_by_name("no-et-50-nc2")[4] == 2
+
+
+def test_launch_shape_ties_go_to_the_larger_cache_then_block(bench):
+    # shapes within 1% of the fastest are equal; among them the larger visited
+    # cache, then the larger block, is taken; a clearly faster shape still wins
+    t = [(47.35, 9, 1), (47.30, 9, 2), (47.22, 9, 4), (60.5, 10, 1)]
+    assert bench.pick_shape(t, None) == {"visited_log2": 9, "waves_per_block": 4}
+    t = [(1.011, 12, 1), (1.014, 11, 1), (1.015, 12, 4), (1.2, 9, 1)]
+    assert bench.pick_shape(t, None) == {"visited_log2": 12, "waves_per_block": 4}
+    t = [(2.0, 8, 4), (2.5, 12, 4)]
+    assert bench.pick_shape(t, None) == {"visited_log2": 8, "waves_per_block": 4}
+    assert bench.pick_shape([], {"visited_log2": 7}) == {"visited_log2": 7}
