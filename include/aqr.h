@@ -203,25 +203,30 @@ void aqr_graph_free(aqr_graph* g);
 /*
  * Batched construction with the layer-0 searches on the current device
  * (the insertion step of Alg. 1 and HNSW, reordered so that many insertions
- * search at once).  First the seed is inserted on the host as aqr_build
- * does: every point below seed_n and every point with level >= 1, in id
- * order (threads == 1: sequential and deterministic).  The other points
- * (level 0) follow in id order in chunks of min(batch, max(1, floor(m / 8)))
- * points, m = points already in the graph.  Every point of a chunk searches
- * the graph as it stood before the chunk on the device (greedy descent, then
- * layer 0 with width efc), selects M neighbours with the heuristic and takes
- * them as its layer-0 list; the reverse links are added in id order (on the
- * host, different target nodes in parallel).  Given the seed, the result
- * does not depend on threads.  codes: host, n x d_pad; X: host FP32 n x d,
- * the vectors the codes encode (the device search encodes them again).  The
- * call allocates and frees device memory for the index and the chunks
- * (hipMalloc) and pinned host staging for the chunk copies (hipHostMalloc),
- * and waits for its work; seed_n >= n is aqr_build.  Levels and
- * p as in aqr_build; efc <= 1024.
+ * search at once).  Points are inserted in id order in chunks of
+ * min(cap, max(1, floor(m / 8))) points, m = points already in the graph:
+ * first the seed (every point below seed_n and every point with level >= 1)
+ * with cap = min(seed_batch, batch), then the other points with cap = batch.  Every point of a chunk searches the graph as it
+ * stood before the chunk and selects its neighbours with the heuristic: a
+ * seed point on every level it occupies (on the host, chunk points in
+ * parallel), any other point on layer 0 (on the device).  Then each point
+ * takes its lists, the reverse links are added in id order (on the host,
+ * different target nodes in parallel) and, for the seed, the entry point
+ * moves to each point above the top level, in id order.  The graph does not
+ * depend on threads; batch = 1 is sequential insertion, and seed_batch = 1
+ * with seed_n >= n is aqr_build with threads == 1 (with seed_n >= n no
+ * device is used).  Small seed chunks keep the upper layers close to those
+ * of sequential insertion (64 is a good default).
+ * codes: host, n x d_pad; X: host FP32 n x d, the vectors the codes encode
+ * (the device search encodes them again).  The call allocates and frees
+ * device memory for the index and the chunks (hipMalloc) and pinned host
+ * staging for the chunk copies (hipHostMalloc), and waits for its work.
+ * Levels and p as in aqr_build; efc <= 1024.
  */
 aqr_status aqr_build_batched(const uint8_t* codes, const float* X, int64_t n, int32_t d,
                              const aqr_quantizer* qz, const aqr_bparams* p, const double* level_u,
-                             int64_t seed_n, int32_t batch, aqr_graph** out);
+                             int64_t seed_n, int32_t seed_batch, int32_t batch,
+                             aqr_graph** out);
 
 /* ------------------------------------------------------------------------ */
 /* index file: quantiser, codes, FP32 rows and graph in one checksummed file */

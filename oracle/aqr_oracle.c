@@ -750,26 +750,36 @@ int32_t orc_build(const uint8_t* codes, int64_t n, int32_t d, int32_t stride, in
 
 /*
  * Batched construction over the 8-bit codes: the same insertion step as
- * orc_build, in an order that lets a GPU search many insertions at once.
- *   Seed: every point below seed_n and every point with level >= 1 is
- *         inserted as in orc_build, in increasing id order.
+ * orc_build, in an order that lets many insertions search at once.
+ *   Seed: every point below seed_n and every point with level >= 1, in
+ *         increasing id order, in consecutive chunks of
+ *         min(seed_batch, batch, max(1, floor(inserted / 8))) points, where
+ *         inserted counts the points already in the graph.  Every point of a chunk
+ *         plans its insertion against the graph as it stood before the
+ *         chunk: greedy descent to one level above its own, then on each of
+ *         its levels (top first) a search of width efc and the heuristic's
+ *         M neighbours.  Then every point takes its lists; then the reverse
+ *         links are added in id order, per point from its top level down;
+ *         then the entry point moves to each point above the top level, in
+ *         id order.
  *   Batches: the other points (level 0) follow in increasing id order, in
- *         consecutive chunks of min(batch, max(1, floor(inserted / 8)))
- *         points, where inserted counts the points already in the graph.
- *         Every point of a chunk searches the graph as it stood before the
- *         chunk (greedy descent on the upper layers, then layer 0 with
- *         width efc), selects M neighbours with the heuristic and takes them
- *         as its layer-0 list; then each adds the reverse links, in id order.
- * With seed_n = n this is orc_build; with batch = 1 it is orc_build over the
- * points in the order (seed points, then the rest).
+ *         chunks of min(batch, max(1, floor(inserted / 8))) points.  Every point of a chunk searches
+ *         the graph as it stood before the chunk (greedy descent on the
+ *         upper layers, then layer 0 with width efc), selects M neighbours
+ *         with the heuristic and takes them as its layer-0 list; then each
+ *         adds the reverse links, in id order.
+ * With batch = 1 this is orc_build over the points in the order (seed
+ * points, then the rest); with seed_batch = 1 and seed_n = n it is
+ * orc_build.
  */
 int32_t orc_build_batched(const uint8_t* codes, int64_t n, int32_t d, int32_t stride, int32_t M,
-                          int32_t efc, const int32_t* level, int64_t seed_n, int32_t batch,
-                          uint32_t* adj0, const int64_t* upper_off, uint32_t* upper_adj,
-                          int32_t* out2) {
+                          int32_t efc, const int32_t* level, int64_t seed_n, int32_t seed_batch,
+                          int32_t batch, uint32_t* adj0, const int64_t* upper_off,
+                          uint32_t* upper_adj, int32_t* out2) {
     if (!codes || !level || !adj0 || !upper_off || !out2 || n < 1 || M < 2 || efc < 1 ||
-        seed_n < 1 || batch < 1)
+        seed_n < 1 || seed_batch < 1 || batch < 1)
         return -1;
+    if (seed_batch > batch) seed_batch = batch;
     graph g;
     g.n = n;
     g.M = M;
@@ -792,37 +802,73 @@ int32_t orc_build_batched(const uint8_t* codes, int64_t n, int32_t d, int32_t st
     g.ep = 0;
     g.L = level[0];
     int64_t inserted = 1;
-    /* seed: ids below seed_n and every upper-level point, in id order */
-    for (int64_t i = 1; i < n; i++) {
-        if (i >= seed_n && level[i] == 0) continue;
-        const void* q = sp_point(&sp, (uint32_t)i);
-        int32_t li = level[i];
-        okey cur = {sp_dist_q(&sp, q, g.ep), g.ep};
-        for (int32_t lc = g.L; lc > li; lc--) {
-            if (search_layer(&g, &sp, q, &cur, 1, 1, lc, &v, &W, NULL)) return -1;
-            vis_reset(&v);
-            cur = W.a[0];
+    /* seed chunks: plans against the graph before the chunk, then lists,
+     * reverse links and entry point, each in id order */
+    int32_t Lmax = 0;
+    for (int64_t i = 0; i < n; i++)
+        if (level[i] > Lmax) Lmax = level[i];
+    const int64_t nl = (int64_t)Lmax + 1;
+    uint32_t* ssel = (uint32_t*)malloc((size_t)batch * nl * M * sizeof(uint32_t));
+    int32_t* snsel = (int32_t*)malloc((size_t)batch * nl * sizeof(int32_t));
+    int32_t* stop = (int32_t*)malloc((size_t)batch * sizeof(int32_t));
+    if (!ssel || !snsel || !stop) return -1;
+    int64_t next_seed = 1;
+    for (;;) {
+        int64_t want = inserted / 8;
+        if (want < 1) want = 1;
+        if (want > seed_batch) want = seed_batch;
+        int32_t nb = 0;
+        while (next_seed < n && nb < want) {
+            if (next_seed < seed_n || level[next_seed] > 0) chunk[nb++] = (uint32_t)next_seed;
+            next_seed++;
         }
-        int32_t n_eps = 1;
-        eps[0] = cur;
-        for (int32_t lc = li < g.L ? li : g.L; lc >= 0; lc--) {
-            if (search_layer(&g, &sp, q, eps, n_eps, efc, lc, &v, &W, NULL)) return -1;
-            vis_reset(&v);
-            int32_t r = select_heuristic(&sp, W.a, W.n, M, sel);
-            int32_t cap;
-            uint32_t* row = nbr_row(&g, (uint32_t)i, lc, &cap);
-            for (int32_t t = 0; t < r; t++) row[t] = sel[t];
-            for (int32_t t = 0; t < r; t++)
-                if (add_link(&g, &sp, sel[t], (uint32_t)i, lc)) return -1;
-            n_eps = (int32_t)W.n;
-            for (int32_t t = 0; t < n_eps; t++) eps[t] = W.a[t];
+        if (nb == 0) break;
+        const uint32_t ep0 = g.ep;
+        const int32_t L0 = g.L;
+        for (int32_t b = 0; b < nb; b++) {
+            const void* q = sp_point(&sp, chunk[b]);
+            int32_t li = level[chunk[b]];
+            okey cur = {sp_dist_q(&sp, q, ep0), ep0};
+            for (int32_t lc = L0; lc > li; lc--) {
+                if (search_layer(&g, &sp, q, &cur, 1, 1, lc, &v, &W, NULL)) return -1;
+                vis_reset(&v);
+                cur = W.a[0];
+            }
+            stop[b] = li < L0 ? li : L0;
+            int32_t n_eps = 1;
+            eps[0] = cur;
+            for (int32_t lc = stop[b]; lc >= 0; lc--) {
+                if (search_layer(&g, &sp, q, eps, n_eps, efc, lc, &v, &W, NULL)) return -1;
+                vis_reset(&v);
+                snsel[(int64_t)b * nl + lc] =
+                    select_heuristic(&sp, W.a, W.n, M, ssel + ((int64_t)b * nl + lc) * M);
+                n_eps = (int32_t)W.n;
+                for (int32_t t = 0; t < n_eps; t++) eps[t] = W.a[t];
+            }
         }
-        if (li > g.L) {
-            g.L = li;
-            g.ep = (uint32_t)i;
-        }
-        inserted++;
+        for (int32_t b = 0; b < nb; b++)
+            for (int32_t lc = stop[b]; lc >= 0; lc--) {
+                int32_t cap;
+                uint32_t* row = nbr_row(&g, chunk[b], lc, &cap);
+                const uint32_t* sb = ssel + ((int64_t)b * nl + lc) * M;
+                for (int32_t t = 0; t < snsel[(int64_t)b * nl + lc]; t++) row[t] = sb[t];
+            }
+        for (int32_t b = 0; b < nb; b++)
+            for (int32_t lc = stop[b]; lc >= 0; lc--) {
+                const uint32_t* sb = ssel + ((int64_t)b * nl + lc) * M;
+                for (int32_t t = 0; t < snsel[(int64_t)b * nl + lc]; t++)
+                    if (add_link(&g, &sp, sb[t], chunk[b], lc)) return -1;
+            }
+        for (int32_t b = 0; b < nb; b++)
+            if (level[chunk[b]] > g.L) {
+                g.L = level[chunk[b]];
+                g.ep = chunk[b];
+            }
+        inserted += nb;
     }
+    free(ssel);
+    free(snsel);
+    free(stop);
     /* batches of the remaining level-0 points */
     int64_t next = seed_n;
     for (;;) {

@@ -63,7 +63,7 @@ def _load():
                               _i32p]
     lib.orc_build.restype = _i32
     lib.orc_build_batched.argtypes = [_u8p, _i64, _i32, _i32, _i32, _i32, _i32p, _i64, _i32,
-                                      _u32p, _i64p, _u32p, _i32p]
+                                      _i32, _u32p, _i64p, _u32p, _i32p]
     lib.orc_build_batched.restype = _i32
     lib.orc_param_map.argtypes = [_i32, _i32, _i32, _i32p]
     lib.orc_search_codes.argtypes = [_u8p, _i64, _i32, _i32, _i32, _i32p, _u32p, _i64p, _u32p,
@@ -226,9 +226,10 @@ def build(codes, d, M, efc, level):
                 ep=int(out2[0]), L=int(out2[1]))
 
 
-def build_batched(codes, d, M, efc, level, seed_n, batch):
-    """Batched HNSW build (seed points in order, then chunks of level-0
-    points that each search the graph as it stood before the chunk)."""
+def build_batched(codes, d, M, efc, level, seed_n, batch, seed_batch=64):
+    """Batched HNSW build: chunks of at most seed_batch seed points that plan
+    on every level against the graph as it stood before the chunk, then
+    chunks of at most batch level-0 points that search it the same way."""
     codes = np.ascontiguousarray(codes, np.uint8)
     n, stride = codes.shape
     level = np.ascontiguousarray(level, np.int32)
@@ -237,7 +238,8 @@ def build_batched(codes, d, M, efc, level, seed_n, batch):
     upper = np.zeros((max(int(off[-1]), 1), M), np.uint32)
     out2 = np.zeros(2, np.int32)
     _check(_load().orc_build_batched(codes, n, d, stride, int(M), int(efc), level, int(seed_n),
-                                     int(batch), adj0, off, upper, out2), "build_batched")
+                                     int(seed_batch), int(batch), adj0, off, upper, out2),
+           "build_batched")
     return dict(n=n, M=int(M), level=level, adj0=adj0, upper_off=off, upper_adj=upper,
                 ep=int(out2[0]), L=int(out2[1]))
 

@@ -115,7 +115,7 @@ _SIGS = [
     ("aqr_quantizer_free", None, [_vp]),
     ("aqr_build", _i32, [_vp, _i64, _i32, _vp, C.POINTER(BParams), _vp, C.POINTER(_vp)]),
     ("aqr_build_batched", _i32, [_vp, _vp, _i64, _i32, _vp, C.POINTER(BParams), _vp, _i64, _i32,
-                                 C.POINTER(_vp)]),
+                                 _i32, C.POINTER(_vp)]),
     ("aqr_graph_info", _i32, [_vp, C.POINTER(GInfo)]),
     ("aqr_graph_export", _i32, [_vp, _vp, _vp, _vp, _vp]),
     ("aqr_graph_import", _i32, [_i64, _i32, _vp, _vp, _vp, _vp, _u32, C.POINTER(_vp)]),
@@ -393,7 +393,7 @@ def aqr_build(codes, d, qz, M=0, efc=0, threads=0, seed=0, level_u=None, progres
 
 
 def aqr_build_batched(codes, X, d, qz, M=0, efc=0, threads=0, seed=0, level_u=None, progress=0,
-                      seed_n=None, batch=16384):
+                      seed_n=None, batch=16384, seed_batch=64):
     """Batched build with the chunk searches on the device (aqr_build_batched).
     seed_n defaults to max(20000, n / 64)."""
     codes = np.ascontiguousarray(codes, np.uint8)
@@ -406,7 +406,7 @@ def aqr_build_batched(codes, X, d, qz, M=0, efc=0, threads=0, seed=0, level_u=No
     lu = None if level_u is None else np.ascontiguousarray(level_u, np.float64)
     h = C.c_void_p()
     _check(lib().aqr_build_batched(_np_ptr(codes), _np_ptr(X), n, d, qz.ptr, C.byref(bp),
-                                   _np_ptr(lu), seed_n, int(batch), C.byref(h)))
+                                   _np_ptr(lu), seed_n, int(seed_batch), int(batch), C.byref(h)))
     return Graph(h.value)
 
 

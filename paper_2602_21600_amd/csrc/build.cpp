@@ -20,6 +20,7 @@
 #include <chrono>
 #include <cmath>
 #include <cstring>
+#include <functional>
 #include <mutex>
 #include <new>
 #include <queue>
@@ -249,13 +250,95 @@ using namespace aqr;
 
 namespace aqr {
 
+// Insertion of the points S (ascending ids, none in the graph yet) in
+// chunks of min(chunk_max, max(1, floor(m / 8))) points, m = points already
+// in the graph.  Every point of a chunk plans its insertion against the
+// graph as it stood before the chunk: greedy descent to one level above its
+// own, then on each of its levels a search of width efc and the heuristic's
+// M neighbours.  Then each point takes its lists, the reverse links are
+// added in id order (per point from its top level down), and the entry
+// point moves to each point above the top level, in id order.  The plans
+// run on T threads; thread t applies the reverse links into the nodes x
+// with x % T == t, in the order above, so the graph does not depend on T.
+// With chunks of one point this is sequential insertion.
+static void insert_chunks(Graph& g, const uint8_t* codes, int32_t dp, const std::vector<uint32_t>& S,
+                          int32_t chunk_max, int T, const std::function<void(int64_t)>& report) {
+    Builder B(g, codes, dp, false);
+    const int32_t M = g.M, efc = g.efc;
+    std::vector<Visited> vis;
+    vis.reserve(T);
+    for (int t = 0; t < T; ++t) vis.emplace_back(g.n);
+    std::vector<std::vector<uint32_t>> sel;  // per chunk point: M per level, top level first
+    std::vector<std::vector<int32_t>> nsel;  // per chunk point and level: selected count
+    int64_t inserted = 1;                    // point 0
+    size_t pos = 0;
+    while (pos < S.size()) {
+        const int64_t want = std::min<int64_t>(chunk_max, std::max<int64_t>(1, inserted / 8));
+        const int32_t nb = (int32_t)std::min<int64_t>(want, (int64_t)(S.size() - pos));
+        const uint32_t* ids = S.data() + pos;
+        const uint32_t ep = g.ep;
+        const int32_t L = g.L;
+        sel.assign(nb, {});
+        nsel.assign(nb, {});
+        std::atomic<int32_t> nx{0};
+        const int TP = std::max(1, std::min(T, nb));
+        parallel_for_threads(TP, [&](int t) {
+            std::vector<uint64_t> eps, W;
+            for (;;) {
+                const int32_t b = nx.fetch_add(1);
+                if (b >= nb) break;
+                const uint32_t i = ids[b];
+                const int32_t top = std::min(g.level[i], L);
+                eps.assign(1, mk(B.dist(i, ep), ep));
+                for (int32_t lc = L; lc > g.level[i]; --lc) {
+                    B.search_layer(i, eps, 1, lc, vis[t], W);
+                    eps.assign(1, W[0]);
+                }
+                sel[b].assign((size_t)(top + 1) * M, kNone);
+                nsel[b].assign(top + 1, 0);
+                for (int32_t lc = top; lc >= 0; --lc) {
+                    B.search_layer(i, eps, efc, lc, vis[t], W);
+                    nsel[b][lc] = B.heuristic(W.data(), W.size(), M, &sel[b][(size_t)lc * M]);
+                    eps = W;
+                }
+            }
+        });
+        for (int32_t b = 0; b < nb; ++b)
+            for (int32_t lc = (int32_t)nsel[b].size() - 1; lc >= 0; --lc) {
+                int32_t cap;
+                uint32_t* row = B.nbrs(ids[b], lc, cap);
+                for (int32_t t = 0; t < nsel[b][lc]; ++t) row[t] = sel[b][(size_t)lc * M + t];
+            }
+        // small chunks link on one thread (starting threads would cost more);
+        // either way each list receives its links in the same order
+        const int TL = nb >= 256 ? T : 1;
+        parallel_for_threads(TL, [&](int t) {
+            for (int32_t b = 0; b < nb; ++b)
+                for (int32_t lc = (int32_t)nsel[b].size() - 1; lc >= 0; --lc)
+                    for (int32_t j = 0; j < nsel[b][lc]; ++j) {
+                        const uint32_t x = sel[b][(size_t)lc * M + j];
+                        if ((int)(x % (uint32_t)TL) == t) B.link_locked(x, ids[b], lc);
+                    }
+        });
+        for (int32_t b = 0; b < nb; ++b)
+            if (g.level[ids[b]] > g.L) {
+                g.L = g.level[ids[b]];
+                g.ep = ids[b];
+            }
+        pos += nb;
+        inserted += nb;
+        report((int64_t)pos);
+    }
+}
+
 // Levels for every point, then insertion of the seed: every point below
 // seed_n and every point with level >= 1, in id order (seed_n >= n: all
-// points, the plain build).  Level-0 points at or above seed_n are left
-// unlinked for link_chunk.
+// points, the plain build), one at a time (chunk_max 0) or in chunks
+// (insert_chunks).  Level-0 points at or above seed_n are left unlinked for
+// link_chunk.
 aqr_status build_seeded(const uint8_t* codes, int64_t n, int32_t d, const aqr_quantizer* qz,
                         const aqr_bparams* p, const double* level_u, int64_t seed_n,
-                        const char* who, aqr_graph** out) {
+                        int32_t chunk_max, const char* who, aqr_graph** out) {
     const std::string w(who);
     if (!codes || !qz || !p || !out) return fail(AQR_ERR_INVALID_ARG, w + ": null pointer");
     if (n < 1 || n > (int64_t)0xFFFFFFFEu) return fail(AQR_ERR_INVALID_ARG, w + ": n out of range");
@@ -294,7 +377,6 @@ aqr_status build_seeded(const uint8_t* codes, int64_t n, int32_t d, const aqr_qu
     for (int64_t i = 1; i < n; ++i)
         if (i < seed_n || g->level[i] > 0) S.push_back((uint32_t)i);
     const int T = host_threads(p->threads);
-    Builder B(*g, codes, qz->info.d_pad, T > 1);
     const int64_t ns = (int64_t)S.size();
     const int64_t step = p->progress > 0 ? std::max<int64_t>(1, ns / p->progress) : 0;
     const auto t0 = std::chrono::steady_clock::now();
@@ -307,6 +389,22 @@ aqr_status build_seeded(const uint8_t* codes, int64_t n, int32_t d, const aqr_qu
             std::fflush(stderr);
         }
     };
+    if (chunk_max > 0) {
+        int64_t next_step = step;
+        insert_chunks(*g, codes, qz->info.d_pad, S, chunk_max, T, [&](int64_t done) {
+            if (step && (done >= next_step || done == ns)) {
+                const double sec =
+                    std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+                std::fprintf(stderr, "[%s] %lld / %lld points inserted, %.1f s\n", who,
+                             (long long)(done + 1), (long long)(ns + 1), sec);
+                std::fflush(stderr);
+                next_step = (done / step + 1) * step;
+            }
+        });
+        *out = g;
+        return AQR_OK;
+    }
+    Builder B(*g, codes, qz->info.d_pad, T > 1);
     if (T <= 1 || ns < 1) {
         Visited vis(n);
         for (int64_t i = 0; i < ns; ++i) {
@@ -386,7 +484,7 @@ extern "C" aqr_status aqr_build(const uint8_t* codes, int64_t n, int32_t d,
                                 const double* level_u, aqr_graph** out) {
     try {
         clear_error();
-        return build_seeded(codes, n, d, qz, p, level_u, n, "aqr_build", out);
+        return build_seeded(codes, n, d, qz, p, level_u, n, 0, "aqr_build", out);
     } catch (const std::bad_alloc&) {
         return fail(AQR_ERR_OOM, "aqr_build: out of host memory");
     } catch (...) {

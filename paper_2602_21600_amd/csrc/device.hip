@@ -2295,9 +2295,14 @@ namespace {
 constexpr uint64_t kFree = ~0ull;
 constexpr int kSlotBits = 22;  // ticket = sequence << 22 | slot
 
+// Row sets in flight of the serving worker: four for short code rows (the
+// worker runs at four waves per SIMD, so registers allow them), else two.
+template <int CPL, int LG>
+constexpr int serve_u() { return (CPL << LG) <= 16 ? 4 : 2; }
+
 template <int CPL, int LG, int C8, int CF>
 hipError_t serve_occ_t(aqr_server* sv, int* per_cu) {
-    constexpr int U = 2;
+    constexpr int U = serve_u<CPL, LG>();
     auto kern = dev::k_serve<CPL, U, LG, C8, CF>;
     hipError_t e = hipFuncSetAttribute((const void*)kern,
                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)sv->lds);
@@ -2308,7 +2313,7 @@ hipError_t serve_occ_t(aqr_server* sv, int* per_cu) {
 
 template <int CPL, int LG, int C8, int CF>
 hipError_t serve_launch_t(aqr_server* sv) {
-    constexpr int U = 2;
+    constexpr int U = serve_u<CPL, LG>();
     auto kern = dev::k_serve<CPL, U, LG, C8, CF>;
     hipLaunchKernelGGL(dev::k_serve_reset, dim3(1), dim3(64), 0, sv->stream, sv->args.dev);
     hipLaunchKernelGGL(kern, dim3(sv->blocks), dim3(sv->wpb * dev::kWave), sv->lds, sv->stream,
@@ -2784,8 +2789,8 @@ extern "C" aqr_status aqr_server_replay(aqr_server* sv, int64_t n, const double*
 // ---------------------------------------------------------------------------
 extern "C" aqr_status aqr_build_batched(const uint8_t* codes, const float* X, int64_t n, int32_t d,
                                         const aqr_quantizer* qz, const aqr_bparams* p,
-                                        const double* level_u, int64_t seed_n, int32_t batch,
-                                        aqr_graph** out) {
+                                        const double* level_u, int64_t seed_n,
+                                        int32_t seed_batch, int32_t batch, aqr_graph** out) {
     const char* who = "aqr_build_batched";
     void* arena = nullptr;
     std::vector<void*> bufs, hbufs;  // device buffers, pinned host staging
@@ -2799,10 +2804,13 @@ extern "C" aqr_status aqr_build_batched(const uint8_t* codes, const float* X, in
     try {
         clear_error();
         if (!X || !out) return fail(AQR_ERR_INVALID_ARG, "aqr_build_batched: null pointer");
-        if (seed_n < 1 || batch < 1)
-            return fail(AQR_ERR_INVALID_ARG, "aqr_build_batched: seed_n and batch must be >= 1");
+        if (seed_n < 1 || seed_batch < 1 || batch < 1)
+            return fail(AQR_ERR_INVALID_ARG,
+                        "aqr_build_batched: seed_n, seed_batch and batch must be >= 1");
         aqr_graph* g0 = nullptr;
-        aqr_status st = build_seeded(codes, n, d, qz, p, level_u, std::min(seed_n, n), who, &g0);
+        aqr_status st =
+            build_seeded(codes, n, d, qz, p, level_u, std::min(seed_n, n),
+                         std::min(seed_batch, batch), who, &g0);
         if (st != AQR_OK) return st;
         std::unique_ptr<aqr_graph> g(g0);
         const int32_t M = g->M, efc = g->efc;

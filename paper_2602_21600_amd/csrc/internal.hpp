@@ -47,9 +47,12 @@ struct aqr_graph : aqr::Graph {};
 
 namespace aqr {
 // Graph construction pieces shared with the device build (build.cpp).
+// chunk_max 0: the seed is inserted one point at a time (concurrently when
+// p->threads > 1); chunk_max >= 1: in chunks (see build.cpp), the same graph
+// for every thread count.
 aqr_status build_seeded(const uint8_t* codes, int64_t n, int32_t d, const aqr_quantizer* qz,
                         const aqr_bparams* p, const double* level_u, int64_t seed_n,
-                        const char* who, aqr_graph** out);
+                        int32_t chunk_max, const char* who, aqr_graph** out);
 void link_chunk(aqr_graph* g, const uint8_t* codes, int32_t dp, const uint32_t* ids, int32_t nb,
                 const uint64_t* cand, int32_t stride, const int32_t* cnt, int threads,
                 std::vector<uint32_t>& dirty, std::vector<uint8_t>& mark);

@@ -49,13 +49,13 @@ def test_batched_build_matches_oracle(orc, n, d, M0, efc0, seed_n, batch):
     _same(aqr.aqr_graph_export(g), og)
 
 
-def test_batched_build_with_everything_seeded_is_the_plain_build(orc):
+def test_batched_build_with_everything_seeded_in_unit_chunks_is_the_plain_build(orc):
     _torch()
     from paper_2602_21600_amd import aqr
     X, _ = W.tiny(1500, 16, seed=11, clusters=4)
     qz, codes, _ = _quantised(X, 8, 40)
     u = 1.0 - np.random.default_rng(3).random(1500)
-    g1 = aqr.aqr_build_batched(codes, X, 16, qz, threads=1, level_u=u, seed_n=1500)
+    g1 = aqr.aqr_build_batched(codes, X, 16, qz, threads=1, level_u=u, seed_n=1500, batch=1)
     g2 = aqr.aqr_build(codes, 16, qz, threads=1, level_u=u)
     _same(aqr.aqr_graph_export(g1), aqr.aqr_graph_export(g2))
 
@@ -96,6 +96,8 @@ def test_batched_build_rejects_bad_arguments(orc):
         aqr.aqr_build_batched(codes, X, 16, qz, seed_n=0)
     with pytest.raises(aqr.AqrError):
         aqr.aqr_build_batched(codes, X, 16, qz, batch=0)
+    with pytest.raises(aqr.AqrError):
+        aqr.aqr_build_batched(codes, X, 16, qz, seed_batch=0)
 
 
 def test_batched_build_tiny_index_matches_oracle(orc):

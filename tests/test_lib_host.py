@@ -313,3 +313,32 @@ def test_binding_rejects_malformed_buffers():
     with pytest.raises(ValueError, match="taps.counts"):
         aqr.aqr_search(ix, Q, k, ef, cid, cD, cnt, ws, 64, ns,
                        taps=dict(cap=0, counts=torch.zeros((nq, 4), dtype=torch.int32)))
+
+
+def test_chunked_seed_is_thread_independent_and_matches_oracle(orc):
+    # seed_n = n: every point is seeded, so aqr_build_batched inserts them all
+    # in chunks on the host and never needs a device; the graph must be the
+    # same on one and on eight threads and equal the oracle's chunked build,
+    # and chunks of one point must give the sequential build
+    X, _ = W.tiny(2500, 20, seed=17, clusters=5)
+    qz, codes, ref = _train_both(orc, X, M0=8, efc0=40)
+    info = aqr.aqr_quantizer_info(qz)
+    n = X.shape[0]
+    u = 1.0 - np.random.default_rng(23).random(n)
+    g1 = aqr.aqr_graph_export(aqr.aqr_build_batched(codes, X, 20, qz, threads=1, level_u=u,
+                                                    seed_n=n, batch=64))
+    g8 = aqr.aqr_graph_export(aqr.aqr_build_batched(codes, X, 20, qz, threads=8, level_u=u,
+                                                    seed_n=n, batch=64))
+    og = orc.build_batched(codes, 20, info["M"], info["efc"], orc.levels(u, info["M"]), n, 64)
+    rows = og["upper_off"][-1]
+    for eg in (g1, g8):
+        np.testing.assert_array_equal(eg["adj0"], og["adj0"])
+        np.testing.assert_array_equal(eg["upper_adj"][:rows], og["upper_adj"][:rows])
+        assert (eg["ep"], eg["L"]) == (og["ep"], og["L"])
+    seq = aqr.aqr_graph_export(aqr.aqr_build(codes, 20, qz, threads=1, level_u=u))
+    unit = aqr.aqr_graph_export(aqr.aqr_build_batched(codes, X, 20, qz, threads=4, level_u=u,
+                                                      seed_n=n, batch=1))
+    np.testing.assert_array_equal(unit["adj0"], seq["adj0"])
+    np.testing.assert_array_equal(unit["upper_adj"][:rows], seq["upper_adj"][:rows])
+    assert (unit["ep"], unit["L"]) == (seq["ep"], seq["L"])
+    assert not np.array_equal(g1["adj0"], seq["adj0"])  # chunks of up to 64 points differ

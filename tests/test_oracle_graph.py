@@ -154,11 +154,33 @@ def _same_graph(a, b):
     assert (a["ep"], a["L"]) == (b["ep"], b["L"])
 
 
-def test_batched_build_with_everything_seeded_is_sequential(orc):
+def test_batched_build_with_everything_seeded_in_unit_chunks_is_sequential(orc):
     X, _, _, codes = _codes(orc, 1200, 16, 3)
     lv = orc.levels(W.level_draws("small", 1200), 10)
-    _same_graph(orc.build_batched(codes, 16, 10, 40, lv, seed_n=1200, batch=64),
+    _same_graph(orc.build_batched(codes, 16, 10, 40, lv, seed_n=1200, batch=1),
                 orc.build(codes, 16, 10, 40, lv))
+
+
+def test_chunked_seed_keeps_invariants_and_recall(orc):
+    # every point seeded, in chunks of up to 64: points of a chunk plan on
+    # every level against the graph before the chunk, so the graph differs
+    # from the sequential one but keeps the invariants and its recall
+    n, M, efc, d = 3000, 12, 60, 24
+    X, Q, tr, codes = _codes(orc, n, d, 6)
+    lv = orc.levels(W.level_draws("small", n), M)
+    gb = orc.build_batched(codes, d, M, efc, lv, seed_n=n, batch=64)
+    gs = orc.build(codes, d, M, efc, lv)
+    check_invariants(gb, M)
+    assert not np.array_equal(gb["adj0"], gs["adj0"])
+    qc = orc.encode(Q, tr["min"], tr["scale"], stride=codes.shape[1])
+    truth, _ = orc.knn_codes(codes, d, qc, 10)
+    rec = []
+    for g in (gb, gs):
+        s1 = orc.search_codes(g, codes, d, qc, 40, 40)
+        hits = [len(set(s1["cand_id"][q, :10].tolist()) & set(truth[q].tolist()))
+                for q in range(Q.shape[0])]
+        rec.append(np.mean(hits) / 10)
+    assert rec[0] >= rec[1] - 0.02, rec
 
 
 def test_batched_build_with_unit_chunks_is_sequential(orc):
