@@ -430,14 +430,17 @@ aqr_status build_seeded(const uint8_t* codes, int64_t n, int32_t d, const aqr_qu
 // One chunk of the batched build: ids (ascending) with their layer-0
 // candidates (keys (D << 32) | id, ascending, cnt[b] of them at row b of a
 // [nb][stride] array), each from a search of the graph as it stood before
-// the chunk.  Selects M neighbours per point with the heuristic, sets the
-// points' layer-0 lists, then adds the reverse links: thread t owns the
+// the chunk.  Selects M neighbours per point with the heuristic (or takes
+// the selections sel_in / nsel_in made on the device from the same
+// candidates), sets the points' layer-0 lists, then adds the reverse links:
+// thread t owns the
 // target nodes x with x % T == t and applies the links into them in the
 // order they were generated (id order, as a sequential pass would), so the
 // result does not depend on T.  dirty receives every id whose layer-0 list
 // changed; mark (n bytes, all zero) is scratch and left all zero.
 void link_chunk(aqr_graph* g, const uint8_t* codes, int32_t dp, const uint32_t* ids, int32_t nb,
-                const uint64_t* cand, int32_t stride, const int32_t* cnt, int threads,
+                const uint64_t* cand, int32_t stride, const int32_t* cnt,
+                const uint32_t* sel_in, const int32_t* nsel_in, int threads,
                 std::vector<uint32_t>& dirty, std::vector<uint8_t>& mark) {
     const int32_t M = g->M;
     Builder B(*g, codes, dp, false);
@@ -449,8 +452,13 @@ void link_chunk(aqr_graph* g, const uint8_t* codes, int32_t dp, const uint32_t* 
         for (;;) {
             const int32_t b = nx.fetch_add(1);
             if (b >= nb) break;
-            ns[b] = B.heuristic(cand + (size_t)b * stride, (size_t)std::max(0, cnt[b]), M,
-                                &sel[(size_t)b * M]);
+            if (sel_in) {
+                ns[b] = std::min(std::max(nsel_in[b], 0), M);
+                std::memcpy(&sel[(size_t)b * M], &sel_in[(size_t)b * M], sizeof(uint32_t) * M);
+            } else {
+                ns[b] = B.heuristic(cand + (size_t)b * stride, (size_t)std::max(0, cnt[b]), M,
+                                    &sel[(size_t)b * M]);
+            }
             uint32_t* row = g->adj0.data() + (int64_t)ids[b] * 2 * M;
             for (int32_t t = 0; t < 2 * M; ++t) row[t] = t < ns[b] ? sel[(size_t)b * M + t] : kNone;
         }

@@ -910,6 +910,57 @@ __global__ void k_scatter_rows(uint32_t* adj0, int32_t s0, const uint32_t* rows,
     adj0[(int64_t)rows[r] * s0 + c] = data[i];
 }
 
+// Batched build: the neighbour heuristic of the insertion step (Alg. 1's
+// HNSW construction) for every point of a chunk, one wave per point.  The
+// candidates of point b are cand_id / cand_D[b * stride + t], t < cnt[b]:
+// ascending keys (D, id), D = |x - x_b|^2 over the codes.  Candidate e is
+// kept when no point s kept before it has |x_e - x_s|^2 < D_e, until M are
+// kept.  Lane t holds the t-th kept id and computes |x_e - x_s|^2 over the
+// d_pad code bytes as |x_e|^2 + |x_s|^2 - 2 x_e.x_s, the integer the host
+// heuristic computes (below 2^32 for d_pad <= 66,000).  M <= 64.
+__global__ __launch_bounds__(256) void k_select(Idx ix, const uint32_t* cand_id,
+                                                const uint32_t* cand_D, const int32_t* cnt,
+                                                int32_t nb, int32_t stride, int32_t M,
+                                                uint32_t* sel, int32_t* nsel) {
+    const int lane = lane_id();
+    const int64_t b = (int64_t)blockIdx.x * (blockDim.x / kWave) + threadIdx.x / kWave;
+    if (b >= nb) return;  // the whole wave
+    const int nch = ix.dp / 16;
+    const int c = min(max(cnt[b], 0), stride);
+    uint32_t s = kNone;  // this lane's kept id (lanes below r)
+    uint32_t ss = 0;     // its |x_s|^2
+    int r = 0;
+    for (int i = 0; i < c && r < M; ++i) {
+        const uint32_t e = cand_id[b * stride + i];  // one address on every lane
+        const uint32_t de = cand_D[b * stride + i];
+        const uint4* xe = reinterpret_cast<const uint4*>(ix.codes + (uint64_t)e * (uint32_t)ix.cs);
+        const uint4* xs =
+            reinterpret_cast<const uint4*>(ix.codes + (uint64_t)(lane < r ? s : e) * (uint32_t)ix.cs);
+        uint32_t ee = 0u, es = 0u;
+        for (int ch = 0; ch < nch; ++ch) {
+            const uint4 a = xe[ch], q = xs[ch];
+            ee = dot4(a.x, a.x, ee);
+            ee = dot4(a.y, a.y, ee);
+            ee = dot4(a.z, a.z, ee);
+            ee = dot4(a.w, a.w, ee);
+            es = dot4(a.x, q.x, es);
+            es = dot4(a.y, q.y, es);
+            es = dot4(a.z, q.z, es);
+            es = dot4(a.w, q.w, es);
+        }
+        const bool closer = lane < r && ee + ss - 2u * es < de;
+        if (ballot(closer) == 0) {  // wave-uniform
+            if (lane == r) {
+                s = e;
+                ss = ee;
+            }
+            ++r;
+        }
+    }
+    if (lane < M) sel[b * M + lane] = lane < r ? s : kNone;
+    if (lane == 0) nsel[b] = r;
+}
+
 __global__ void k_reset(int32_t* counter) {
     if (threadIdx.x == 0 && blockIdx.x == 0) *counter = 0;
 }
@@ -2851,6 +2902,10 @@ extern "C" aqr_status aqr_build_batched(const uint8_t* codes, const float* X, in
         uint32_t* cidd = (uint32_t*)dalloc((size_t)B * efc * 4);
         uint32_t* cDd = (uint32_t*)dalloc((size_t)B * efc * 4);
         void* ws = dalloc(aqr_search_workspace_size());
+        // the heuristic's selections on the device (one wave per point, M <= 64)
+        const bool dev_select = M <= 64;
+        uint32_t* seld = (uint32_t*)dalloc((size_t)B * M * 4);
+        int32_t* nseld = (int32_t*)dalloc((size_t)B * 4);
         uint32_t* rowd = (uint32_t*)dalloc((size_t)max_dirty * 4);
         uint32_t* datd = (uint32_t*)dalloc((size_t)max_dirty * W * 4);
         for (void* b : bufs)
@@ -2870,6 +2925,8 @@ extern "C" aqr_status aqr_build_batched(const uint8_t* codes, const float* X, in
         uint32_t* hid = (uint32_t*)halloc((size_t)B * efc * 4);
         uint32_t* hD = (uint32_t*)halloc((size_t)B * efc * 4);
         int32_t* hcnt = (int32_t*)halloc((size_t)B * 4);
+        uint32_t* hsel = (uint32_t*)halloc((size_t)B * M * 4);
+        int32_t* hnsel = (int32_t*)halloc((size_t)B * 4);
         uint32_t* hrow = (uint32_t*)halloc((size_t)max_dirty * 4);
         uint32_t* hdat = (uint32_t*)halloc((size_t)max_dirty * W * 4);
         for (void* b : hbufs)
@@ -2922,9 +2979,19 @@ extern "C" aqr_status aqr_build_batched(const uint8_t* codes, const float* X, in
                 release();
                 return st;
             }
-            if ((e = hipMemcpy(hid, cidd, (size_t)nb * efc * 4, hipMemcpyDeviceToHost)) != hipSuccess ||
-                (e = hipMemcpy(hD, cDd, (size_t)nb * efc * 4, hipMemcpyDeviceToHost)) != hipSuccess ||
-                (e = hipMemcpy(hcnt, cntd, (size_t)nb * 4, hipMemcpyDeviceToHost)) != hipSuccess) {
+            if (dev_select) {
+                hipLaunchKernelGGL(dev::k_select, dim3((unsigned)((nb + 3) / 4)), dim3(256), 0,
+                                   nullptr, ix->v, cidd, cDd, cntd, nb, efc, M, seld, nseld);
+                if ((e = hipGetLastError()) != hipSuccess ||
+                    (e = hipMemcpy(hcnt, cntd, (size_t)nb * 4, hipMemcpyDeviceToHost)) != hipSuccess ||
+                    (e = hipMemcpy(hsel, seld, (size_t)nb * M * 4, hipMemcpyDeviceToHost)) != hipSuccess ||
+                    (e = hipMemcpy(hnsel, nseld, (size_t)nb * 4, hipMemcpyDeviceToHost)) != hipSuccess) {
+                    release();
+                    return hip_fail(e, "aqr_build_batched: selection");
+                }
+            } else if ((e = hipMemcpy(hid, cidd, (size_t)nb * efc * 4, hipMemcpyDeviceToHost)) != hipSuccess ||
+                       (e = hipMemcpy(hD, cDd, (size_t)nb * efc * 4, hipMemcpyDeviceToHost)) != hipSuccess ||
+                       (e = hipMemcpy(hcnt, cntd, (size_t)nb * 4, hipMemcpyDeviceToHost)) != hipSuccess) {
                 release();
                 return hip_fail(e, "aqr_build_batched: copy");
             }
@@ -2933,13 +3000,26 @@ extern "C" aqr_status aqr_build_batched(const uint8_t* codes, const float* X, in
                     release();
                     return fail(AQR_ERR_STATE, "aqr_build_batched: a chunk search returned no candidates");
                 }
+                if (dev_select) {
+                    if (hnsel[b] < 0 || hnsel[b] > M) {
+                        release();
+                        return fail(AQR_ERR_STATE, "aqr_build_batched: selection count out of range");
+                    }
+                    for (int32_t t = 0; t < hnsel[b]; ++t)
+                        if ((int64_t)hsel[(size_t)b * M + t] >= n) {
+                            release();
+                            return fail(AQR_ERR_STATE, "aqr_build_batched: selected id out of range");
+                        }
+                    continue;
+                }
                 for (int32_t t = 0; t < hcnt[b]; ++t) {
                     const size_t o = (size_t)b * efc + t;
                     keys[o] = ((uint64_t)hD[o] << 32) | hid[o];
                 }
             }
             const auto tb = now();
-            link_chunk(g.get(), codes, dp, ids, nb, keys.data(), efc, hcnt, T, dirty, mark);
+            link_chunk(g.get(), codes, dp, ids, nb, keys.data(), efc, hcnt,
+                       dev_select ? hsel : nullptr, dev_select ? hnsel : nullptr, T, dirty, mark);
             const auto tc = now();
             const int32_t nr = (int32_t)dirty.size();
             if ((int64_t)nr > max_dirty) {
@@ -2983,7 +3063,7 @@ extern "C" aqr_status aqr_build_batched(const uint8_t* codes, const float* X, in
             if (p->progress > 0 && ((int64_t)pos >= next_report || pos == R.size())) {
                 std::fprintf(stderr,
                              "[%s] %lld / %lld chunked points linked, %.1f s (device search "
-                             "%.1f s, host linking %.1f s, row upload %.1f s)\n",
+                             "and selection %.1f s, host linking %.1f s, row upload %.1f s)\n",
                              who, (long long)pos, (long long)R.size(), secs(t0, now()), t_search,
                              t_link, t_rows);
                 std::fflush(stderr);

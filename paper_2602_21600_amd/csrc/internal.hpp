@@ -53,8 +53,11 @@ namespace aqr {
 aqr_status build_seeded(const uint8_t* codes, int64_t n, int32_t d, const aqr_quantizer* qz,
                         const aqr_bparams* p, const double* level_u, int64_t seed_n,
                         int32_t chunk_max, const char* who, aqr_graph** out);
+// sel / nsel (nb x M, nb), when given, are the heuristic's selections made
+// elsewhere (the device); otherwise link_chunk selects from cand / cnt.
 void link_chunk(aqr_graph* g, const uint8_t* codes, int32_t dp, const uint32_t* ids, int32_t nb,
-                const uint64_t* cand, int32_t stride, const int32_t* cnt, int threads,
+                const uint64_t* cand, int32_t stride, const int32_t* cnt,
+                const uint32_t* sel_in, const int32_t* nsel_in, int threads,
                 std::vector<uint32_t>& dirty, std::vector<uint8_t>& mark);
 // Stage-1 densities on the current device (density.hip): for each of the m
 // sample rows S[s] of X (host, n x d), the FP64 sum in ascending order of the
