@@ -32,6 +32,7 @@
 // across the G lanes by DPP lane permutes.  FP32 rows use fused
 // multiply-add on direct differences.
 #include <hip/hip_runtime.h>
+#include <hipcub/hipcub.hpp>
 
 #include <algorithm>
 #include <atomic>
@@ -963,6 +964,136 @@ __global__ __launch_bounds__(256) void k_select(Idx ix, const uint32_t* cand_id,
 
 __global__ void k_reset(int32_t* counter) {
     if (threadIdx.x == 0 && blockIdx.x == 0) *counter = 0;
+}
+
+// ---------------------------------------------------------------------------
+// Batched build, reverse links on the device (lists of 2M <= 63 entries)
+// ---------------------------------------------------------------------------
+// Chunk point b takes its own layer-0 list (its nsel[b] selections, the rest
+// empty), and every link x <- ids[b] of its selections is listed as key x,
+// value b * M + t: in the order the links are made.  Unused entries get key
+// kNone and sort last.
+__global__ void k_link_prep(uint32_t* adj0, int32_t s0, int32_t cap, const uint32_t* ids,
+                            const uint32_t* sel, const int32_t* nsel, int32_t nb, int32_t M,
+                            uint32_t* lkey, uint32_t* lval) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < (int64_t)nb * M) {
+        const int64_t b = i / M;
+        const int t = (int)(i - b * M);
+        lkey[i] = t < nsel[b] ? sel[i] : kNone;
+        lval[i] = (uint32_t)i;
+    }
+    if (i < (int64_t)nb * cap) {
+        const int64_t b = i / cap;
+        const int j = (int)(i - b * cap);
+        adj0[(int64_t)ids[b] * s0 + j] = (j < M && j < nsel[b]) ? sel[b * M + j] : kNone;
+    }
+}
+
+// Start of each run of equal targets in the sorted link keys (any order).
+__global__ void k_link_heads(const uint32_t* key, int64_t N, int32_t* seg, int32_t* nseg) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= N) return;
+    const uint32_t x = key[i];
+    if (x != kNone && (i == 0 || key[i - 1] != x)) seg[atomicAdd(nseg, 1)] = (int32_t)i;
+}
+
+__device__ __forceinline__ uint64_t shfl_xor_u64(uint64_t v, int m) {
+    const uint32_t lo = shfl_xor_u32((uint32_t)v, m), hi = shfl_xor_u32((uint32_t)(v >> 32), m);
+    return ((uint64_t)hi << 32) | lo;
+}
+
+// Bitonic sort of one 64-bit key per lane, ascending by lane.
+__device__ __forceinline__ uint64_t wave_sort_u64(uint64_t k, int lane) {
+    for (int size = 2; size <= kWave; size <<= 1)
+        for (int stride = size >> 1; stride > 0; stride >>= 1) {
+            const uint64_t o = shfl_xor_u64(k, stride);
+            const bool up = (lane & size) == 0, low = (lane & stride) == 0;
+            k = (low == up) ? (o < k ? o : k) : (o > k ? o : k);
+        }
+    return k;
+}
+
+// |x_a|^2 and x_a.x_b over the d_pad code bytes (rows at stride cs).
+__device__ __forceinline__ void code_dots(const Idx& ix, uint32_t a, uint32_t b, uint32_t& aa,
+                                          uint32_t& ab) {
+    const uint4* xa = reinterpret_cast<const uint4*>(ix.codes + (uint64_t)a * (uint32_t)ix.cs);
+    const uint4* xb = reinterpret_cast<const uint4*>(ix.codes + (uint64_t)b * (uint32_t)ix.cs);
+    aa = 0u;
+    ab = 0u;
+    for (int ch = 0; ch < ix.dp / 16; ++ch) {
+        const uint4 p = xa[ch], q = xb[ch];
+        aa = dot4(p.x, p.x, aa);
+        aa = dot4(p.y, p.y, aa);
+        aa = dot4(p.z, p.z, aa);
+        aa = dot4(p.w, p.w, aa);
+        ab = dot4(p.x, q.x, ab);
+        ab = dot4(p.y, q.y, ab);
+        ab = dot4(p.z, q.z, ab);
+        ab = dot4(p.w, q.w, ab);
+    }
+}
+
+// One wave per target x (the runs found by k_link_heads, taken from a work
+// counter): lane j holds entry j of x's list; the links into x are applied
+// in the order they were made, as the host does one by one: a self link or
+// an id already listed is skipped, a list with room takes the id at its end,
+// and a full list of cap entries is shrunk with the heuristic over its
+// entries and the new id, keyed (|x_e - x_x|^2, e) ascending.
+__global__ __launch_bounds__(256) void k_link(Idx ix, uint32_t* adj0, int32_t s0, int32_t cap,
+                                              const uint32_t* ids, int32_t M,
+                                              const uint32_t* key, const uint32_t* val, int64_t N,
+                                              const int32_t* seg, const int32_t* nseg,
+                                              int32_t* counter) {
+    const int lane = lane_id();
+    const int ns = uni(*nseg);
+    for (;;) {
+        const int got = atomicAdd(counter, lane == 0 ? 1 : 0);
+        const int s = uni(got);
+        if (s >= ns) break;
+        const int64_t i0 = seg[s];
+        const uint32_t x = (uint32_t)uni((int)key[i0]);
+        uint32_t r = lane < cap ? adj0[(int64_t)x * s0 + lane] : kNone;
+        int cnt = __popcll(ballot(r != kNone));
+        uint32_t xx, unused;
+        code_dots(ix, x, x, xx, unused);
+        for (int64_t i = i0; i < N; ++i) {
+            if (uni(key[i] != x ? 1 : 0)) break;
+            const uint32_t y = (uint32_t)uni((int)ids[val[i] / (uint32_t)M]);
+            if (y == x) continue;
+            if (ballot(r == y) != 0) continue;
+            if (cnt < cap) {
+                if (lane == cnt) r = y;
+                ++cnt;
+                continue;
+            }
+            // full: the cap entries and y (lane cap), keyed by distance to x
+            const uint32_t e = lane < cap ? r : (lane == cap ? y : x);
+            uint32_t ee, ex;
+            code_dots(ix, e, x, ee, ex);
+            uint64_t k = lane <= cap ? ((uint64_t)(ee + xx - 2u * ex) << 32) | e : ~0ull;
+            k = wave_sort_u64(k, lane);
+            uint32_t kept = kNone, kn = 0u;
+            int rr = 0;
+            for (int c = 0; c <= cap && rr < cap; ++c) {
+                const uint64_t kc = readlane64(k, c);
+                const uint32_t ec = (uint32_t)kc, dc = (uint32_t)(kc >> 32);
+                uint32_t cc, cs;
+                code_dots(ix, ec, lane < rr ? kept : ec, cc, cs);
+                const bool closer = lane < rr && cc + kn - 2u * cs < dc;
+                if (ballot(closer) == 0) {
+                    if (lane == rr) {
+                        kept = ec;
+                        kn = cc;
+                    }
+                    ++rr;
+                }
+            }
+            r = lane < rr ? kept : kNone;
+            cnt = rr;
+        }
+        if (lane < cap) adj0[(int64_t)x * s0 + lane] = r;
+    }
 }
 
 constexpr int kOrderMaxEf = 1024;
@@ -2906,6 +3037,26 @@ extern "C" aqr_status aqr_build_batched(const uint8_t* codes, const float* X, in
         const bool dev_select = M <= 64;
         uint32_t* seld = (uint32_t*)dalloc((size_t)B * M * 4);
         int32_t* nseld = (int32_t*)dalloc((size_t)B * 4);
+        // the reverse links on the device too when a full list and its new
+        // entry fit one wave (2M + 1 <= 64): links sorted by target, one wave
+        // per target; the host graph is read back after the last chunk
+        const bool dev_link = dev_select && 2 * M + 1 <= dev::kWave;
+        const int32_t cap = 2 * M;
+        const int64_t NL = (int64_t)B * M;  // links of a full chunk
+        uint32_t* idsd = (uint32_t*)dalloc((size_t)B * 4);
+        uint32_t* lkey = (uint32_t*)dalloc((size_t)NL * 4);
+        uint32_t* lval = (uint32_t*)dalloc((size_t)NL * 4);
+        uint32_t* lkey_s = (uint32_t*)dalloc((size_t)NL * 4);
+        uint32_t* lval_s = (uint32_t*)dalloc((size_t)NL * 4);
+        int32_t* segd = (int32_t*)dalloc((size_t)NL * 4);
+        int32_t* ctrd = (int32_t*)dalloc(2 * 4);  // run count, work counter
+        size_t sort_bytes = 0;
+        if ((e = hipcub::DeviceRadixSort::SortPairs(nullptr, sort_bytes, lkey, lkey_s, lval, lval_s,
+                                                    (int)NL)) != hipSuccess) {
+            release();
+            return hip_fail(e, "aqr_build_batched: link sort size");
+        }
+        void* sort_tmp = dalloc(sort_bytes);
         uint32_t* rowd = (uint32_t*)dalloc((size_t)max_dirty * 4);
         uint32_t* datd = (uint32_t*)dalloc((size_t)max_dirty * W * 4);
         for (void* b : bufs)
@@ -3018,56 +3169,117 @@ extern "C" aqr_status aqr_build_batched(const uint8_t* codes, const float* X, in
                 }
             }
             const auto tb = now();
-            link_chunk(g.get(), codes, dp, ids, nb, keys.data(), efc, hcnt,
-                       dev_select ? hsel : nullptr, dev_select ? hnsel : nullptr, T, dirty, mark);
-            const auto tc = now();
-            const int32_t nr = (int32_t)dirty.size();
-            if ((int64_t)nr > max_dirty) {
-                release();
-                return fail(AQR_ERR_STATE, "aqr_build_batched: more changed rows than staged");
-            }
-            for (int32_t r = 0; r < nr; ++r) {
-                if ((int64_t)dirty[r] >= n) {
+            if (dev_link) {
+                const int64_t nl = (int64_t)nb * M;
+                uint32_t* adj0d = const_cast<uint32_t*>(ix->v.adj0);
+                if ((e = hipMemcpy(idsd, ids, (size_t)nb * 4, hipMemcpyHostToDevice)) != hipSuccess) {
                     release();
-                    return fail(AQR_ERR_STATE, "aqr_build_batched: row id out of range");
+                    return hip_fail(e, "aqr_build_batched: copy");
                 }
-                hrow[r] = dirty[r];
+                hipLaunchKernelGGL(dev::k_link_prep, dim3((unsigned)(((int64_t)nb * cap + 255) / 256)),
+                                   dim3(256), 0, nullptr, adj0d, s0, cap, idsd, seld, nseld, nb, M,
+                                   lkey, lval);
+                size_t sb = sort_bytes;
+                if ((e = hipGetLastError()) != hipSuccess ||
+                    (e = hipcub::DeviceRadixSort::SortPairs(sort_tmp, sb, lkey, lkey_s, lval, lval_s,
+                                                            (int)nl)) != hipSuccess) {
+                    release();
+                    return hip_fail(e, "aqr_build_batched: link sort");
+                }
+                hipLaunchKernelGGL(dev::k_reset, dim3(1), dim3(64), 0, nullptr, ctrd);
+                hipLaunchKernelGGL(dev::k_reset, dim3(1), dim3(64), 0, nullptr, ctrd + 1);
+                hipLaunchKernelGGL(dev::k_link_heads, dim3((unsigned)((nl + 255) / 256)), dim3(256),
+                                   0, nullptr, lkey_s, nl, segd, ctrd);
+                const int64_t lb = std::max<int64_t>(
+                    1, std::min<int64_t>((nl + 3) / 4, (int64_t)std::max(1, ix->num_cu) * 8));
+                hipLaunchKernelGGL(dev::k_link, dim3((unsigned)lb), dim3(256), 0, nullptr, ix->v,
+                                   adj0d, s0, cap, idsd, M, lkey_s, lval_s, nl, segd, ctrd,
+                                   ctrd + 1);
+                if ((e = hipGetLastError()) != hipSuccess || (e = hipDeviceSynchronize()) != hipSuccess) {
+                    release();
+                    return hip_fail(e, "aqr_build_batched: device links");
+                }
+                t_search += secs(ta, tb);
+                t_link += secs(tb, now());
+            } else {
+                link_chunk(g.get(), codes, dp, ids, nb, keys.data(), efc, hcnt,
+                           dev_select ? hsel : nullptr, dev_select ? hnsel : nullptr, T, dirty, mark);
+                const auto tc = now();
+                const int32_t nr = (int32_t)dirty.size();
+                if ((int64_t)nr > max_dirty) {
+                    release();
+                    return fail(AQR_ERR_STATE, "aqr_build_batched: more changed rows than staged");
+                }
+                for (int32_t r = 0; r < nr; ++r) {
+                    if ((int64_t)dirty[r] >= n) {
+                        release();
+                        return fail(AQR_ERR_STATE, "aqr_build_batched: row id out of range");
+                    }
+                    hrow[r] = dirty[r];
+                }
+                // gather the changed rows into the staging buffer, in parallel
+                const int TG = (int)std::max<int64_t>(1, std::min<int64_t>(T, nr / 4096));
+                const uint32_t* adj = g->adj0.data();
+                parallel_for_threads(TG, [&](int t) {
+                    const int32_t r0 = (int32_t)((int64_t)nr * t / TG);
+                    const int32_t r1 = (int32_t)((int64_t)nr * (t + 1) / TG);
+                    for (int32_t r = r0; r < r1; ++r)
+                        std::memcpy(&hdat[(size_t)r * W], &adj[(size_t)hrow[r] * W],
+                                    sizeof(uint32_t) * W);
+                });
+                if ((e = hipMemcpy(rowd, hrow, (size_t)nr * 4, hipMemcpyHostToDevice)) != hipSuccess ||
+                    (e = hipMemcpy(datd, hdat, (size_t)nr * W * 4, hipMemcpyHostToDevice)) != hipSuccess) {
+                    release();
+                    return hip_fail(e, "aqr_build_batched: copy");
+                }
+                const int64_t tot = (int64_t)nr * W;
+                hipLaunchKernelGGL(dev::k_scatter_rows, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0,
+                                   nullptr, const_cast<uint32_t*>(ix->v.adj0), s0, rowd, datd, nr, W);
+                if ((e = hipGetLastError()) != hipSuccess || (e = hipDeviceSynchronize()) != hipSuccess) {
+                    release();
+                    return hip_fail(e, "aqr_build_batched: row update");
+                }
+                t_search += secs(ta, tb);
+                t_link += secs(tb, tc);
+                t_rows += secs(tc, now());
             }
-            // gather the changed rows into the staging buffer, in parallel
-            const int TG = (int)std::max<int64_t>(1, std::min<int64_t>(T, nr / 4096));
-            const uint32_t* adj = g->adj0.data();
-            parallel_for_threads(TG, [&](int t) {
-                const int32_t r0 = (int32_t)((int64_t)nr * t / TG);
-                const int32_t r1 = (int32_t)((int64_t)nr * (t + 1) / TG);
-                for (int32_t r = r0; r < r1; ++r)
-                    std::memcpy(&hdat[(size_t)r * W], &adj[(size_t)hrow[r] * W],
-                                sizeof(uint32_t) * W);
-            });
-            if ((e = hipMemcpy(rowd, hrow, (size_t)nr * 4, hipMemcpyHostToDevice)) != hipSuccess ||
-                (e = hipMemcpy(datd, hdat, (size_t)nr * W * 4, hipMemcpyHostToDevice)) != hipSuccess) {
-                release();
-                return hip_fail(e, "aqr_build_batched: copy");
-            }
-            const int64_t tot = (int64_t)nr * W;
-            hipLaunchKernelGGL(dev::k_scatter_rows, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0,
-                               nullptr, const_cast<uint32_t*>(ix->v.adj0), s0, rowd, datd, nr, W);
-            if ((e = hipGetLastError()) != hipSuccess || (e = hipDeviceSynchronize()) != hipSuccess) {
-                release();
-                return hip_fail(e, "aqr_build_batched: row update");
-            }
-            t_search += secs(ta, tb);
-            t_link += secs(tb, tc);
-            t_rows += secs(tc, now());
             pos += nb;
             inserted += nb;
             if (p->progress > 0 && ((int64_t)pos >= next_report || pos == R.size())) {
                 std::fprintf(stderr,
                              "[%s] %lld / %lld chunked points linked, %.1f s (device search "
-                             "and selection %.1f s, host linking %.1f s, row upload %.1f s)\n",
+                             "and selection %.1f s, linking %.1f s, row upload %.1f s)\n",
                              who, (long long)pos, (long long)R.size(), secs(t0, now()), t_search,
                              t_link, t_rows);
                 std::fflush(stderr);
                 next_report = (int64_t)pos + std::max<int64_t>(1, (int64_t)R.size() / p->progress);
+            }
+        }
+        if (dev_link) {
+            // the device adjacency is the graph's layer 0 now (rows at stride
+            // s0): read back in blocks of rows through pinned staging, each
+            // block repacked to 2M entries per row on the host threads
+            const int64_t rb = std::max<int64_t>(1, ((int64_t)64 << 20) / ((int64_t)s0 * 4));
+            uint32_t* stage = (uint32_t*)halloc((size_t)rb * s0 * 4);
+            if (!stage) {
+                release();
+                return fail(AQR_ERR_OOM, "aqr_build_batched: pinned host memory for the read back");
+            }
+            for (int64_t r0 = 0; r0 < n; r0 += rb) {
+                const int64_t nr = std::min<int64_t>(rb, n - r0);
+                if ((e = hipMemcpy(stage, ix->v.adj0 + r0 * s0, (size_t)nr * s0 * 4,
+                                   hipMemcpyDeviceToHost)) != hipSuccess) {
+                    release();
+                    return hip_fail(e, "aqr_build_batched: read back");
+                }
+                const int TR = (int)std::max<int64_t>(1, std::min<int64_t>(T, nr / 4096));
+                uint32_t* dst = g->adj0.data();
+                parallel_for_threads(TR, [&](int t) {
+                    const int64_t a = nr * t / TR, z = nr * (t + 1) / TR;
+                    for (int64_t r = a; r < z; ++r)
+                        std::memcpy(&dst[(size_t)(r0 + r) * W], &stage[(size_t)r * s0],
+                                    sizeof(uint32_t) * W);
+                });
             }
         }
         release();
