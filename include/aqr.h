@@ -209,10 +209,12 @@ void aqr_graph_free(aqr_graph* g);
  * with cap = min(seed_batch, batch), then the other points with cap = batch.  Every point of a chunk searches the graph as it
  * stood before the chunk and selects its neighbours with the heuristic: a
  * seed point on every level it occupies (on the host, chunk points in
- * parallel), any other point on layer 0 (on the device).  Then each point
- * takes its lists, the reverse links are added in id order (on the host,
- * different target nodes in parallel) and, for the seed, the entry point
- * moves to each point above the top level, in id order.  The graph does not
+ * parallel), any other point on layer 0 (search and selection on the
+ * device; the selection on the host when M > 64).  Then each point takes
+ * its lists, the reverse links are added in id order per target (for the
+ * other points on the device when 2M + 1 <= 64, else on the host, different
+ * target nodes in parallel) and, for the seed, the entry point moves to
+ * each point above the top level, in id order.  The graph does not
  * depend on threads; batch = 1 is sequential insertion, and seed_batch = 1
  * with seed_n >= n is aqr_build with threads == 1 (with seed_n >= n no
  * device is used).  Small seed chunks keep the upper layers close to those
