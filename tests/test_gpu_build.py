@@ -1,9 +1,11 @@
 """Batched graph construction with the chunk searches on the device.
 
-Given a sequential seed (threads = 1) the batched build is deterministic,
-so it must equal the oracle's batched build bit for bit: levels, entry
-point, every layer-0 and upper-layer list.  With a parallel seed only the
-graph invariants and the recall of the result are checked.
+The batched build is deterministic on every thread count, so it must equal
+the oracle's batched build bit for bit: levels, entry point, every layer-0
+and upper-layer list.  Its chunks select neighbours and add reverse links
+on the device when the lists are short enough (M <= 31), select on the
+device and link on the host for M <= 64, and do both on the host beyond;
+each form is checked against the oracle.
 """
 import numpy as np
 import pytest
@@ -46,6 +48,23 @@ def test_batched_build_matches_oracle(orc, n, d, M0, efc0, seed_n, batch):
     g = aqr.aqr_build_batched(codes, X, d, qz, threads=1, level_u=u, seed_n=seed_n, batch=batch)
     og = orc.build_batched(codes, d, info["M"], info["efc"], orc.levels(u, info["M"]),
                            seed_n, batch)
+    _same(aqr.aqr_graph_export(g), og)
+
+
+@pytest.mark.parametrize("M", [31, 40, 70])
+def test_batched_build_list_widths_match_oracle(orc, M):
+    # M = 31: selection and reverse links on the device (2M + 1 = 63 lanes);
+    # M = 40: selection on the device, reverse links on the host; M = 70:
+    # both on the host.  Full lists are shrunk often at these widths.
+    _torch()
+    from paper_2602_21600_amd import aqr
+    n, d = 2000, 20
+    X, _ = W.tiny(n, d, seed=31 + M, clusters=5)
+    qz, codes, info = _quantised(X, 8, 40)
+    u = 1.0 - np.random.default_rng(M).random(n)
+    g = aqr.aqr_build_batched(codes, X, d, qz, M=M, efc=96, threads=8, level_u=u, seed_n=300,
+                              batch=128)
+    og = orc.build_batched(codes, d, M, 96, orc.levels(u, M), 300, 128)
     _same(aqr.aqr_graph_export(g), og)
 
 
