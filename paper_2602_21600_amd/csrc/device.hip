@@ -386,18 +386,25 @@ __device__ __forceinline__ void eval_rows(const Idx& ix, const uint32_t* ids, in
 // ---------------------------------------------------------------------------
 // forgetful visited cache: buckets of four 16-bit entries
 // ---------------------------------------------------------------------------
-// h = id * C mod 2^B is a bijection of [0, 2^B) (C odd); the top vb bits of
-// h choose the bucket and the low B - vb bits (<= 15) are stored with a
-// valid bit, so (bucket, entry) identifies the id exactly.  A bucket keeps
-// its four most recent entries.
+// h = id * C mod 2^B is a bijection of [0, 2^B) (C odd).  With nb buckets,
+// 2^vb <= nb < 2^(vb+1), the bucket is floor(h * nb / 2^B) and the low
+// B - vb bits of h (<= 15) are stored with a valid bit.  Two values of h with
+// the same low bits lie at least 2^(B-vb) >= 2^B / nb apart, one bucket's
+// width, so they fall in different buckets: (bucket, entry) identifies the
+// id exactly for any such nb (nb = 2^vb: the top vb bits choose the bucket).
+// A bucket keeps its four most recent entries.
 struct VisCache {
     uint64_t* b;
-    int vb;      // log2 buckets
+    int vb;      // floor(log2 nb)
     int B;       // hash width
+    uint32_t nb;  // buckets
+    __device__ __forceinline__ uint32_t bucket_of(uint32_t h) const {
+        return __umulhi(h << (32 - B), nb);
+    }
     __device__ __forceinline__ bool test_insert(uint32_t id) const {
         const uint32_t mask = B >= 32 ? 0xFFFFFFFFu : ((1u << B) - 1u);
         const uint32_t h = (id * 0x9E3779B1u) & mask;
-        const uint32_t bucket = h >> (B - vb);
+        const uint32_t bucket = bucket_of(h);
         const uint32_t e = (h & ((1u << (B - vb)) - 1u)) | 0x8000u;
         const uint64_t w = b[bucket];
         const bool hit = ((uint32_t)(w & 0xFFFFu) == e) | ((uint32_t)((w >> 16) & 0xFFFFu) == e) |
@@ -406,16 +413,16 @@ struct VisCache {
         return hit;
     }
     // Whole-wave form: lanes with nothing to insert (an invalid id, or a
-    // hit) write the spare bucket 2^vb instead of branching around the store.
+    // hit) write the spare bucket nb instead of branching around the store.
     __device__ __forceinline__ bool test_insert_if(uint32_t id, bool valid) const {
         const uint32_t mask = B >= 32 ? 0xFFFFFFFFu : ((1u << B) - 1u);
         const uint32_t h = ((valid ? id : 0u) * 0x9E3779B1u) & mask;
-        const uint32_t bucket = h >> (B - vb);
+        const uint32_t bucket = bucket_of(h);
         const uint32_t e = (h & ((1u << (B - vb)) - 1u)) | 0x8000u;
         const uint64_t w = b[bucket];
         const bool hit = ((uint32_t)(w & 0xFFFFu) == e) | ((uint32_t)((w >> 16) & 0xFFFFu) == e) |
                          ((uint32_t)((w >> 32) & 0xFFFFu) == e) | ((uint32_t)(w >> 48) == e);
-        b[valid && !hit ? bucket : (1u << vb)] = (w << 16) | e;
+        b[valid && !hit ? bucket : nb] = (w << 16) | e;
         return hit;
     }
 };
@@ -426,11 +433,12 @@ struct VisCache {
 struct SearchLds {
     int ef_cap, st_cap, vb, xs, dp;
     bool own_w = true;  // false: W lives elsewhere; the layout keeps its spare entry only
+    int xb = 0;         // visited buckets beyond 2^vb (fewer than 2^vb)
     // Layout of one wave: [FP32 query | query codes | W | neighbour ids |
     // their keys | visited buckets].  W holds keys whose low bit is the
     // expanded flag.  Each array has one spare entry past its end (W: index
     // ef_cap; the neighbour ids: index st_cap, which is the first key slot;
-    // the visited buckets: index 2^vb): lanes with nothing to store write
+    // the visited buckets: index 2^vb + xb): lanes with nothing to store write
     // there, so stores need no divergent branch.  The query comes first so
     // that the serving kernel can reuse everything after it for Stages 2-3.
     __host__ __device__ static size_t r16(size_t o) { return (o + 15) & ~(size_t)15; }
@@ -442,7 +450,9 @@ struct SearchLds {
     }
     __host__ __device__ size_t off_sk() const { return off_st() + (size_t)st_cap * 4; }
     __host__ __device__ size_t off_vis() const { return off_sk() + (size_t)st_cap * 8; }
-    __host__ __device__ size_t bytes() const { return r16(off_vis() + ((size_t)8 << vb) + 16); }
+    __host__ __device__ size_t bytes() const {
+        return r16(off_vis() + (size_t)8 * (((size_t)1 << vb) + xb) + 16);
+    }
 };
 
 __device__ __forceinline__ int st_cap_of(int s0, int s1) {
@@ -461,6 +471,7 @@ struct SearchArgs {
     int32_t ef_cap;
     int32_t out_stride;
     int32_t vb;
+    int32_t xb;         // visited buckets beyond 2^vb
     int32_t mode;       // 0: Stage-1 candidates; 1: FP32 baseline top-k
     int32_t lg, nch;    // row geometry
     size_t wave_lds;
@@ -560,7 +571,7 @@ __device__ __forceinline__ void search_query(const SearchArgs& a, const int64_t 
 
 
     // ---- layer-0 search with width efe ----
-    for (int i = lane; i < (1 << a.vb); i += kWave) visb[i] = 0ull;
+    for (int i = lane; i < (int)vis.nb; i += kWave) visb[i] = 0ull;
     wsync();
     if (lane == 0) {
         vis.test_insert((uint32_t)curkey >> 1);
@@ -835,7 +846,7 @@ void k_search(SearchArgs a) {
     const Idx& ix = a.ix;
     // The 8-bit search encodes the query straight from global memory, so its
     // layout has no FP32 query (xs 0); the FP32 search keeps it in LDS.
-    const SearchLds L{a.ef_cap, st_cap_of(ix.s0, ix.s1), a.vb, F32 ? ix.xs : 0, ix.dp};
+    const SearchLds L{a.ef_cap, st_cap_of(ix.s0, ix.s1), a.vb, F32 ? ix.xs : 0, ix.dp, true, a.xb};
     unsigned char* base = smem + (size_t)wave * a.wave_lds;
     uint64_t* mk = reinterpret_cast<uint64_t*>(base + L.off_mk());
     uint32_t* st_id = reinterpret_cast<uint32_t*>(base + L.off_st());
@@ -844,7 +855,7 @@ void k_search(SearchArgs a) {
     float* qlds = reinterpret_cast<float*>(base + L.off_qf());
     uint8_t* qc = base + L.off_qc();
 
-    VisCache vis{visb, a.vb, max(ix.idbits, a.vb + 1)};
+    VisCache vis{visb, a.vb, max(ix.idbits, a.vb + 1), (1u << a.vb) + (uint32_t)a.xb};
 
     for (;;) {
         // Every lane takes part in the work-counter atomic (only lane 0 adds
@@ -1625,9 +1636,10 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k
             uint32_t* st_id = reinterpret_cast<uint32_t*>(run + R.off_st());
             uint64_t* st_key = reinterpret_cast<uint64_t*>(run + R.off_sk());
             uint64_t* visb = reinterpret_cast<uint64_t*>(run + R.off_vis());
-            const VisCache vis{visb, vbq, max(ix.idbits, vbq + 1)};
+            const VisCache vis{visb, vbq, max(ix.idbits, vbq + 1), 1u << vbq};
             SearchArgs sq = sa;
             sq.vb = vbq;
+            sq.xb = 0;
             // Stage 1 writes its N_c candidates into the search part; the
             // re-rank reads them from there
             search_query<false, CPL, U, LG, false, false>(sq, 0, efe, nc, lane, vis, mk, spare, st_id,
@@ -1905,9 +1917,20 @@ extern "C" size_t aqr_search_workspace_size(void) { return 256; }
 
 namespace {
 
+// Blocks per CU that the LDS holds.  gfx950 allocates a block's LDS in
+// 1,280-byte units (160 KB / 128): five blocks of 32,000 bytes are resident
+// on a CU, five of 32,256 bytes are not.  The runtime's occupancy query
+// counts in smaller units and reports five for the latter, so its answer is
+// capped by this one.
+constexpr size_t kLdsUnit = 1280;
+inline size_t lds_alloc(size_t bytes) { return (bytes + kLdsUnit - 1) / kLdsUnit * kLdsUnit; }
+inline int lds_blocks_per_cu(size_t cu_lds, size_t block_lds) {
+    return block_lds == 0 ? INT_MAX : (int)(cu_lds / lds_alloc(block_lds));
+}
+
 template <bool F32, int CPL, int U, int LG>
 hipError_t launch_search_k(dev::SearchArgs& a, int blocks, int wpb, size_t lds, int ncu,
-                           hipStream_t s) {
+                           size_t cu_lds, hipStream_t s) {
     const bool taps = a.taps.expanded || a.taps.evaluated || a.taps.counts;
     // rows with |x|^2 in their padding, and a spare chunk slot to read it
     const bool nrm = !F32 && a.ix.nrm && a.nch < (CPL << LG);
@@ -1942,6 +1965,7 @@ hipError_t launch_search_k(dev::SearchArgs& a, int blocks, int wpb, size_t lds, 
         if (per_cu == 0) {
             e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, wpb * dev::kWave, lds);
             if (e != hipSuccess) return e;
+            if (cu_lds > 0) per_cu = std::min(per_cu, lds_blocks_per_cu(cu_lds, lds));
             per_cu = std::max(1, per_cu);
             std::lock_guard<std::mutex> lk(occ_mu);
             occ[kv][key] = per_cu;
@@ -1968,7 +1992,7 @@ hipError_t launch_search_k(dev::SearchArgs& a, int blocks, int wpb, size_t lds, 
 // leaves room for at most five waves per SIMD (lds_few).
 template <bool F32>
 hipError_t launch_search(dev::SearchArgs& a, int nch, int blocks, int wpb, size_t lds, int ncu,
-                         hipStream_t s, bool lat, bool lds_few) {
+                         size_t cu_lds, hipStream_t s, bool lat, bool lds_few) {
     auto lg_for = [](int groups) {  // smallest lg with 2^lg >= groups, at least 2
         int lg = 2;
         while ((1 << lg) < groups) ++lg;
@@ -1979,31 +2003,31 @@ hipError_t launch_search(dev::SearchArgs& a, int nch, int blocks, int wpb, size_
             const bool u4 = lat || lds_few;
             switch (lg_for((nch + 1) / 2)) {
                 case 2:
-                    return u4 ? launch_search_k<F32, 2, 4, 2>(a, blocks, wpb, lds, ncu, s)
-                              : launch_search_k<F32, 2, 2, 2>(a, blocks, wpb, lds, ncu, s);
+                    return u4 ? launch_search_k<F32, 2, 4, 2>(a, blocks, wpb, lds, ncu, cu_lds, s)
+                              : launch_search_k<F32, 2, 2, 2>(a, blocks, wpb, lds, ncu, cu_lds, s);
                 default:
-                    return u4 ? launch_search_k<F32, 2, 4, 3>(a, blocks, wpb, lds, ncu, s)
-                              : launch_search_k<F32, 2, 2, 3>(a, blocks, wpb, lds, ncu, s);
+                    return u4 ? launch_search_k<F32, 2, 4, 3>(a, blocks, wpb, lds, ncu, cu_lds, s)
+                              : launch_search_k<F32, 2, 2, 3>(a, blocks, wpb, lds, ncu, cu_lds, s);
             }
         }
         if (nch <= 32)  // up to 512 bytes: 4 chunks per lane, 2 rows in flight
-            return launch_search_k<F32, 4, 2, 3>(a, blocks, wpb, lds, ncu, s);
+            return launch_search_k<F32, 4, 2, 3>(a, blocks, wpb, lds, ncu, cu_lds, s);
         if (nch <= 64)  // up to 1 KB: 8 chunks per lane, 2 (lat: 4) rows in flight
-            return lat ? launch_search_k<F32, 8, 4, 3>(a, blocks, wpb, lds, ncu, s)
-                       : launch_search_k<F32, 8, 2, 3>(a, blocks, wpb, lds, ncu, s);
-        if (nch <= 128) return launch_search_k<F32, 8, 1, 4>(a, blocks, wpb, lds, ncu, s);
-        return launch_search_k<F32, 8, 1, 5>(a, blocks, wpb, lds, ncu, s);
+            return lat ? launch_search_k<F32, 8, 4, 3>(a, blocks, wpb, lds, ncu, cu_lds, s)
+                       : launch_search_k<F32, 8, 2, 3>(a, blocks, wpb, lds, ncu, cu_lds, s);
+        if (nch <= 128) return launch_search_k<F32, 8, 1, 4>(a, blocks, wpb, lds, ncu, cu_lds, s);
+        return launch_search_k<F32, 8, 1, 5>(a, blocks, wpb, lds, ncu, cu_lds, s);
     } else {
         if (nch <= 16) {  // up to 64 floats: 2 chunks per lane
             switch (lg_for((nch + 1) / 2)) {
-                case 2: return launch_search_k<F32, 2, 2, 2>(a, blocks, wpb, lds, ncu, s);
-                default: return launch_search_k<F32, 2, 2, 3>(a, blocks, wpb, lds, ncu, s);
+                case 2: return launch_search_k<F32, 2, 2, 2>(a, blocks, wpb, lds, ncu, cu_lds, s);
+                default: return launch_search_k<F32, 2, 2, 3>(a, blocks, wpb, lds, ncu, cu_lds, s);
             }
         }
         if (nch <= 64) {  // up to 256 floats: 2 chunks per lane on up to 32 lanes
             switch (lg_for((nch + 1) / 2)) {
-                case 4: return launch_search_k<F32, 2, 2, 4>(a, blocks, wpb, lds, ncu, s);
-                default: return launch_search_k<F32, 2, 2, 5>(a, blocks, wpb, lds, ncu, s);
+                case 4: return launch_search_k<F32, 2, 2, 4>(a, blocks, wpb, lds, ncu, cu_lds, s);
+                default: return launch_search_k<F32, 2, 2, 5>(a, blocks, wpb, lds, ncu, cu_lds, s);
             }
         }
         if (nch <= 256) {  // up to 1,024 floats: 8 chunks per lane on up to 32 lanes
@@ -2011,15 +2035,15 @@ hipError_t launch_search(dev::SearchArgs& a, int nch, int blocks, int wpb, size_
                 case 2:
                 case 3:
                 case 4:
-                    return lat ? launch_search_k<F32, 8, 4, 4>(a, blocks, wpb, lds, ncu, s)
-                               : launch_search_k<F32, 8, 2, 4>(a, blocks, wpb, lds, ncu, s);
+                    return lat ? launch_search_k<F32, 8, 4, 4>(a, blocks, wpb, lds, ncu, cu_lds, s)
+                               : launch_search_k<F32, 8, 2, 4>(a, blocks, wpb, lds, ncu, cu_lds, s);
                 default:
-                    return lat ? launch_search_k<F32, 8, 4, 5>(a, blocks, wpb, lds, ncu, s)
-                               : launch_search_k<F32, 8, 2, 5>(a, blocks, wpb, lds, ncu, s);
+                    return lat ? launch_search_k<F32, 8, 4, 5>(a, blocks, wpb, lds, ncu, cu_lds, s)
+                               : launch_search_k<F32, 8, 2, 5>(a, blocks, wpb, lds, ncu, cu_lds, s);
             }
         }
-        if (nch <= 512) return launch_search_k<F32, 8, 1, 6>(a, blocks, wpb, lds, ncu, s);
-        return launch_search_k<F32, 16, 1, 6>(a, blocks, wpb, lds, ncu, s);
+        if (nch <= 512) return launch_search_k<F32, 8, 1, 6>(a, blocks, wpb, lds, ncu, cu_lds, s);
+        return launch_search_k<F32, 16, 1, 6>(a, blocks, wpb, lds, ncu, cu_lds, s);
     }
 }
 
@@ -2066,10 +2090,22 @@ aqr_status run_search(const aqr_index* ix, const float* Q, int64_t nq, const int
     dev::SearchLds sl{ef_cap,
                       std::max(v.s0, v.s1) <= 64 ? 64 : (std::max(v.s0, v.s1) + 63) / 64 * 64, vb,
                       f32 ? v.xs : 0, v.dp};  // the 8-bit search keeps no FP32 query in LDS
+    const size_t wl0 = sl.bytes();
+    if (wl0 * wpb > ix->max_lds)
+        return fail(AQR_ERR_INVALID_ARG, std::string(who) + ": LDS per block exceeds the device limit (lower ef_max, visited_log2 or waves_per_block)");
+    // The LDS that the blocks resident per CU leave unused holds more visited
+    // buckets (fewer than 2^vb more): the same blocks stay resident, and the
+    // cache forgets fewer of the nodes a query meets.
+    const size_t per_cu = (size_t)lds_blocks_per_cu(ix->cu_lds, wl0 * wpb);
+    if (per_cu >= 1) {
+        const size_t block = std::min(ix->cu_lds / per_cu / kLdsUnit * kLdsUnit, (size_t)ix->max_lds);
+        const size_t room = block / wpb;
+        size_t xb = room > wl0 ? (room - wl0) / 8 : 0;
+        sl.xb = (int)std::min(xb, ((size_t)1 << vb) - 1);
+        while (sl.xb > 0 && sl.bytes() > room) --sl.xb;
+    }
     const size_t wl = sl.bytes();
     const size_t lds = wl * wpb;
-    if (lds > ix->max_lds)
-        return fail(AQR_ERR_INVALID_ARG, std::string(who) + ": LDS per block exceeds the device limit (lower ef_max, visited_log2 or waves_per_block)");
     dev::SearchArgs a{};
     a.ix = v;
     a.Q = Q;
@@ -2082,6 +2118,7 @@ aqr_status run_search(const aqr_index* ix, const float* Q, int64_t nq, const int
     a.ef_cap = sl.ef_cap;
     a.out_stride = sp->out_stride;
     a.vb = vb;
+    a.xb = sl.xb;
     a.mode = f32 ? 1 : 0;
     const int nch = f32 ? v.xs / 4 : v.dp / 16;
     a.nch = nch;
@@ -2105,9 +2142,9 @@ aqr_status run_search(const aqr_index* ix, const float* Q, int64_t nq, const int
     if (cpl > 16) return fail(AQR_ERR_INVALID_ARG, std::string(who) + ": row too wide");
     if (!f32 && cpl > 4) return fail(AQR_ERR_INVALID_ARG, std::string(who) + ": code row too wide");
     const bool lat = nq <= (int64_t)ix->num_cu * 4;  // at most one wave per SIMD
-    const bool lds_few = ix->cu_lds / wl <= 20;       // LDS: at most five waves per SIMD
-    e = f32 ? launch_search<true>(a, nch, sp->blocks, wpb, lds, ix->num_cu, s, lat, lds_few)
-            : launch_search<false>(a, nch, sp->blocks, wpb, lds, ix->num_cu, s, lat, lds_few);
+    const bool lds_few = ix->cu_lds / wl0 <= 20;      // LDS: at most five waves per SIMD
+    e = f32 ? launch_search<true>(a, nch, sp->blocks, wpb, lds, ix->num_cu, ix->cu_lds, s, lat, lds_few)
+            : launch_search<false>(a, nch, sp->blocks, wpb, lds, ix->num_cu, ix->cu_lds, s, lat, lds_few);
     if (e != hipSuccess) return hip_fail(e, who);
     return AQR_OK;
 }
@@ -2733,6 +2770,7 @@ extern "C" aqr_status aqr_server_create(const aqr_index* ix, const aqr_server_pa
             delete sv;
             return hip_fail(e, "aqr_server_create: occupancy");
         }
+        per_cu = std::min(per_cu, lds_blocks_per_cu(ix->cu_lds, sv->lds));
         sv->blocks = std::max(1, per_cu) * std::max(1, ix->num_cu);
         // admission budgets: LDS pages of outstanding requests (default: the
         // resident waves' regions, one largest request each) and
