@@ -300,6 +300,16 @@ typedef struct aqr_sparams {
     int32_t blocks;       /* persistent grid size, 0 = fill the device */
     int32_t visited_log2; /* log2 of visited-cache buckets (4 ids each), 0 = 7 */
     const int32_t* order; /* device, nullable: work order of the queries (a permutation) */
+    /* Two list sizes in one launch (0 = off): small_waves of the
+     * waves_per_block waves of each block (0 <= small_waves < waves_per_block)
+     * keep LDS for lists of ef_small (1 <= ef_small < ef_max) instead of
+     * ef_max, so more waves fit on a CU.  Queries with ef_eff > ef_small go
+     * to the other waves, which take the rest once those are done.  The
+     * split expects order to list the queries with ef_eff > ef_small first
+     * (as a longest-first order does); if it does not, only the ef_max waves
+     * search.  No result depends on these fields. */
+    int32_t ef_small;
+    int32_t small_waves;
 } aqr_sparams;
 
 typedef struct aqr_taps {

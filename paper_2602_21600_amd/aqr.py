@@ -49,7 +49,8 @@ class GInfo(C.Structure):
 class SParams(C.Structure):
     _fields_ = [("ef_max", C.c_int32), ("out_stride", C.c_int32), ("m_ef", C.c_int32),
                 ("waves_per_block", C.c_int32), ("blocks", C.c_int32),
-                ("visited_log2", C.c_int32), ("order", C.c_void_p)]
+                ("visited_log2", C.c_int32), ("order", C.c_void_p), ("ef_small", C.c_int32),
+                ("small_waves", C.c_int32)]
 
 
 class Taps(C.Structure):
@@ -503,7 +504,8 @@ def _taps(taps):
 
 
 def aqr_search(ix, Q, k, ef, cand_id, cand_D, cand_cnt, ws, ef_max, out_stride, nc=None, m_ef=3,
-               waves_per_block=0, blocks=0, visited_log2=0, order=None, taps=None, stream=None):
+               waves_per_block=0, blocks=0, visited_log2=0, order=None, taps=None, stream=None,
+               ef_small=0, small_waves=0):
     nq = _check_search_args(ix, Q, k, ef, ws, order, nc)
     _need("cand_id", cand_id, _i32_types(), 2, rows=nq, cols=out_stride)
     _need("cand_D", cand_D, _i32_types(), 2, rows=nq, cols=out_stride)
@@ -513,7 +515,7 @@ def aqr_search(ix, Q, k, ef, cand_id, cand_D, cand_cnt, ws, ef_max, out_stride, 
     _check_taps(taps, nq)
     sp = SParams(ef_max=ef_max, out_stride=out_stride, m_ef=m_ef,
                  waves_per_block=waves_per_block, blocks=blocks, visited_log2=visited_log2,
-                 order=_dev_ptr(order))
+                 order=_dev_ptr(order), ef_small=ef_small, small_waves=small_waves)
     tp = _taps(taps)
     _check(lib().aqr_search(ix.ptr, _dev_ptr(Q), Q.shape[0], _dev_ptr(k), _dev_ptr(ef),
                             _dev_ptr(nc), C.byref(sp), _dev_ptr(cand_id), _dev_ptr(cand_D),
@@ -522,14 +524,15 @@ def aqr_search(ix, Q, k, ef, cand_id, cand_D, cand_cnt, ws, ef_max, out_stride, 
 
 
 def aqr_search_fp32(ix, Q, k, ef, out_id, out_dist, ws, ef_max, out_stride, waves_per_block=0,
-                    blocks=0, visited_log2=0, order=None, taps=None, stream=None):
+                    blocks=0, visited_log2=0, order=None, taps=None, stream=None, ef_small=0,
+                    small_waves=0):
     nq = _check_search_args(ix, Q, k, ef, ws, order)
     _need("out_id", out_id, _i32_types(), 2, rows=nq, cols=(out_stride,))
     _need("out_dist", out_dist, _f32_types(), 2, rows=nq, cols=(out_stride,))
     _check_taps(taps, nq)
     sp = SParams(ef_max=ef_max, out_stride=out_stride, m_ef=1,
                  waves_per_block=waves_per_block, blocks=blocks, visited_log2=visited_log2,
-                 order=_dev_ptr(order))
+                 order=_dev_ptr(order), ef_small=ef_small, small_waves=small_waves)
     tp = _taps(taps)
     _check(lib().aqr_search_fp32(ix.ptr, _dev_ptr(Q), Q.shape[0], _dev_ptr(k), _dev_ptr(ef),
                                  C.byref(sp), _dev_ptr(out_id), _dev_ptr(out_dist), _dev_ptr(ws),
@@ -730,7 +733,8 @@ class BatchPlan:
         sp = dict(ef_max=self.ef_max, out_stride=self.nc_max, m_ef=m_ef,
                   waves_per_block=tuning.get("waves_per_block", 0),
                   blocks=tuning.get("blocks", 0), visited_log2=tuning.get("visited_log2", 0),
-                  order=None)
+                  order=None, ef_small=tuning.get("ef_small", 0),
+                  small_waves=tuning.get("small_waves", 0))
         rp = dict(n_rerank=n_rerank, out_stride=k_max, tau_gap=tau_gap, tau_ratio=tau_ratio,
                   eps=eps, force_et=-1, waves_per_block=tuning.get("rerank_waves_per_block", 0),
                   assembly=assembly)

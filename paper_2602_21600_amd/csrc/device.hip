@@ -432,26 +432,41 @@ struct VisCache {
 // ---------------------------------------------------------------------------
 struct SearchLds {
     int ef_cap, st_cap, vb, xs, dp;
-    bool own_w = true;  // false: W lives elsewhere; the layout keeps its spare entry only
-    int xb = 0;         // visited buckets beyond 2^vb (fewer than 2^vb)
+    bool own_w = true;   // false: W lives elsewhere; the layout keeps its spare entry only
+    int xb = 0;          // visited buckets beyond 2^vb (fewer than 2^vb)
+    bool w_last = false; // W after the visited buckets (the batch kernel)
     // Layout of one wave: [FP32 query | query codes | W | neighbour ids |
-    // their keys | visited buckets].  W holds keys whose low bit is the
-    // expanded flag.  Each array has one spare entry past its end (W: index
-    // ef_cap; the neighbour ids: index st_cap, which is the first key slot;
-    // the visited buckets: index 2^vb + xb): lanes with nothing to store write
-    // there, so stores need no divergent branch.  The query comes first so
-    // that the serving kernel can reuse everything after it for Stages 2-3.
+    // their keys | visited buckets], or with w_last [FP32 query | query
+    // codes | neighbour ids | their keys | visited buckets | W].  W holds
+    // keys whose low bit is the expanded flag.  Each array has one spare
+    // entry past its end (W: index ef_cap; the neighbour ids: index st_cap,
+    // which is the first key slot; the visited buckets: index 2^vb + xb):
+    // lanes with nothing to store write there, so stores need no divergent
+    // branch.  The query comes first so that the serving kernel can reuse
+    // everything after it for Stages 2-3, from W on.  With W last, only W's
+    // size depends on ef_cap, so waves with lists of two sizes share every
+    // other offset; between the buckets and W lie two words of the wave's
+    // work claims (off_claim) and a free word just below W.
     __host__ __device__ static size_t r16(size_t o) { return (o + 15) & ~(size_t)15; }
     __host__ __device__ size_t off_qf() const { return 0; }
     __host__ __device__ size_t off_qc() const { return (size_t)xs * 4; }
-    __host__ __device__ size_t off_mk() const { return r16(off_qc() + (size_t)dp); }
+    __host__ __device__ size_t w_bytes() const { return own_w ? (size_t)(ef_cap + 1) * 8 : (size_t)8; }
     __host__ __device__ size_t off_st() const {
-        return r16(off_mk() + (own_w ? (size_t)(ef_cap + 1) * 8 : (size_t)8));
+        return w_last ? r16(off_qc() + (size_t)dp) : r16(off_mk() + w_bytes());
     }
     __host__ __device__ size_t off_sk() const { return off_st() + (size_t)st_cap * 4; }
     __host__ __device__ size_t off_vis() const { return off_sk() + (size_t)st_cap * 8; }
-    __host__ __device__ size_t bytes() const {
+    __host__ __device__ size_t vis_end() const {
         return r16(off_vis() + (size_t)8 * (((size_t)1 << vb) + xb) + 16);
+    }
+    __host__ __device__ size_t off_claim() const {
+        return r16(off_vis() + (size_t)8 * (((size_t)1 << vb) + xb) + 8);
+    }
+    __host__ __device__ size_t off_mk() const {
+        return w_last ? off_claim() + 16 : r16(off_qc() + (size_t)dp);
+    }
+    __host__ __device__ size_t bytes() const {
+        return w_last ? r16(off_mk() + w_bytes()) : vis_end();
     }
 };
 
@@ -472,13 +487,16 @@ struct SearchArgs {
     int32_t out_stride;
     int32_t vb;
     int32_t xb;         // visited buckets beyond 2^vb
+    int32_t nsw;        // waves per block with lists of ef_cap2 (the last nsw; 0: none)
+    int32_t ef_cap2;
+    size_t wave_lds2;   // LDS of such a wave
     int32_t mode;       // 0: Stage-1 candidates; 1: FP32 baseline top-k
     int32_t lg, nch;    // row geometry
     size_t wave_lds;
     uint32_t* out_id;
     uint32_t* out_D;    // mode 0: integer D; mode 1: FP32 distance bits
     int32_t* out_cnt;
-    int32_t* counter;
+    int32_t* counter;   // [0]: claims of positions [0, c); [1]: c; [2]: claims of [c, nq)
     Taps taps;
 };
 
@@ -844,10 +862,16 @@ void k_search(SearchArgs a) {
     const int lane = lane_id();
     const int wave = threadIdx.x / kWave;
     const Idx& ix = a.ix;
+    // With two list sizes the block's last nsw waves hold lists of ef_cap2
+    // and follow the others in LDS.
+    const int nbw = (int)(blockDim.x / kWave) - a.nsw;
+    const bool small = wave >= nbw;
+    const int ef_cap = small ? a.ef_cap2 : a.ef_cap;
     // The 8-bit search encodes the query straight from global memory, so its
     // layout has no FP32 query (xs 0); the FP32 search keeps it in LDS.
-    const SearchLds L{a.ef_cap, st_cap_of(ix.s0, ix.s1), a.vb, F32 ? ix.xs : 0, ix.dp, true, a.xb};
-    unsigned char* base = smem + (size_t)wave * a.wave_lds;
+    const SearchLds L{ef_cap, st_cap_of(ix.s0, ix.s1), a.vb, F32 ? ix.xs : 0, ix.dp, true, a.xb, true};
+    unsigned char* base = smem + (small ? (size_t)nbw * a.wave_lds + (size_t)(wave - nbw) * a.wave_lds2
+                                        : (size_t)wave * a.wave_lds);
     uint64_t* mk = reinterpret_cast<uint64_t*>(base + L.off_mk());
     uint32_t* st_id = reinterpret_cast<uint32_t*>(base + L.off_st());
     uint64_t* st_key = reinterpret_cast<uint64_t*>(base + L.off_sk());
@@ -857,14 +881,47 @@ void k_search(SearchArgs a) {
 
     VisCache vis{visb, a.vb, max(ix.idbits, a.vb + 1), (1u << a.vb) + (uint32_t)a.xb};
 
+    // Work: positions [0, c) of the order (the queries with lists above
+    // ef_cap2) go to the waves with lists of ef_cap, from counter[0]; the
+    // rest, [c, nq), to every wave once it has no other work, from
+    // counter[2].  Without two sizes, or when the order is not split at c
+    // (c < 0), the ef_cap waves take everything from counter[0] and the
+    // others leave.  The claim state lives in two LDS words of the wave, so
+    // that no register carries it across the search: claim[0] = r >= 0
+    // while claiming [0, r) from counter[0], -(c + 1) once claiming [c, nq)
+    // from counter[2]; claim[1] = the wave's list capacity.  Every lane
+    // stores the same values.
+    int* claim = reinterpret_cast<int*>(base + L.off_claim());
+    {
+        int r0 = (int)a.nq;
+        if (a.nsw > 0) {
+            const int cs = uni(a.counter[1]);
+            if (cs < 0 && small) return;  // the whole wave
+            r0 = cs < 0 ? (int)a.nq : small ? -(cs + 1) : cs;
+        }
+        claim[0] = r0;
+        claim[1] = ef_cap;
+        wsync();
+    }
     for (;;) {
         // Every lane takes part in the work-counter atomic (only lane 0 adds
         // one) and lane 0's old value is read with readfirstlane: no divergent
         // branch precedes this cross-lane read, and the branches below that
         // steer the loop are on wave-uniform values.
-        const int got = atomicAdd(a.counter, lane == 0 ? 1 : 0);
-        const int w = uni(got);
-        if ((int64_t)w >= a.nq) break;
+        const int r = uni(claim[0]);
+        int w;
+        if (r >= 0) {
+            w = uni(atomicAdd(a.counter, lane == 0 ? 1 : 0));
+            if (w >= r) {
+                if (a.nsw == 0 || r == (int)a.nq) break;
+                claim[0] = -(r + 1);
+                wsync();
+                continue;
+            }
+        } else {
+            w = -r - 1 + uni(atomicAdd(a.counter + 2, lane == 0 ? 1 : 0));
+            if ((int64_t)w >= a.nq) break;
+        }
         const int64_t q = a.order ? (int64_t)a.order[w] : (int64_t)w;
         if (uni((q >= 0 && q < a.nq) ? 1 : 0)) {  // skip entries outside [0, nq)
             const int k = a.kq[q];
@@ -879,8 +936,9 @@ void k_search(SearchArgs a) {
             } else {
                 nc = k;
             }
+            const int cap = uni(claim[1]);
             int bad =
-                uni((k < 1 || efe > a.ef_cap || nc < 1 || nc > a.out_stride || nc > efe) ? 1 : 0);
+                uni((k < 1 || efe > cap || nc < 1 || nc > a.out_stride || nc > efe) ? 1 : 0);
             float* qf = F32 ? qlds : const_cast<float*>(a.Q + q * ix.d);
             if (!bad) {
                 // reject non-finite values; the FP32 search copies the query
@@ -903,8 +961,9 @@ void k_search(SearchArgs a) {
                     }
                 }
             } else {
-                search_query<F32, CPL, U, LG, TAPS, NRM>(a, q, efe, nc, lane, vis, mk,
-                                                    mk + a.ef_cap, st_id, st_key, visb, qf, qc);
+                // lanes with nothing to store in W write the free word below it
+                search_query<F32, CPL, U, LG, TAPS, NRM>(a, q, efe, nc, lane, vis, mk, mk - 1,
+                                                    st_id, st_key, visb, qf, qc);
             }
         }
         wsync();
@@ -975,6 +1034,35 @@ __global__ __launch_bounds__(256) void k_select(Idx ix, const uint32_t* cand_id,
 
 __global__ void k_reset(int32_t* counter) {
     if (threadIdx.x == 0 && blockIdx.x == 0) *counter = 0;
+}
+
+// Two list sizes: c = the number of queries with ef_eff = max(ef, k) above
+// ef_small; counter[1] = c when the order lists exactly those queries first
+// (positions [0, c)), else -1; both claim counters start at zero.  One block.
+__global__ __launch_bounds__(1024) void k_split(const int32_t* kq, const int32_t* efq,
+                                                 const int32_t* order, int64_t nq,
+                                                 int32_t ef_small, int32_t* counter) {
+    __shared__ int32_t cnt[2];
+    if (threadIdx.x < 2) cnt[threadIdx.x] = 0;
+    __syncthreads();
+    int big = 0;
+    for (int64_t q = threadIdx.x; q < nq; q += blockDim.x)
+        big += max(efq[q], kq[q]) > ef_small ? 1 : 0;
+    atomicAdd(&cnt[0], big);
+    __syncthreads();
+    const int64_t c = cnt[0];
+    int placed = 0;  // positions below c that hold such a query
+    for (int64_t w = threadIdx.x; w < c; w += blockDim.x) {
+        const int64_t q = order ? (int64_t)order[w] : w;
+        placed += (q >= 0 && q < nq && max(efq[q], kq[q]) > ef_small) ? 1 : 0;
+    }
+    atomicAdd(&cnt[1], placed);
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        counter[0] = 0;
+        counter[1] = cnt[1] == cnt[0] ? cnt[0] : -1;
+        counter[2] = 0;
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -2086,26 +2174,34 @@ aqr_status run_search(const aqr_index* ix, const float* Q, int64_t nq, const int
         return fail(AQR_ERR_INVALID_ARG, std::string(who) + ": waves_per_block must be 1, 2 or 4");
     if (v.s0 > 256)
         return fail(AQR_ERR_INVALID_ARG, std::string(who) + ": layer-0 rows above 256 entries are not supported");
+    const int nsw = sp->small_waves;
+    if (nsw < 0 || nsw >= wpb)
+        return fail(AQR_ERR_INVALID_ARG, std::string(who) + ": small_waves must be in [0, waves_per_block)");
+    if (nsw > 0 && (sp->ef_small < 1 || sp->ef_small >= sp->ef_max))
+        return fail(AQR_ERR_INVALID_ARG, std::string(who) + ": ef_small must be in [1, ef_max)");
     const int ef_cap = (sp->ef_max + 63) / 64 * 64;  // W capacity: whole 64-entry slots
-    dev::SearchLds sl{ef_cap,
-                      std::max(v.s0, v.s1) <= 64 ? 64 : (std::max(v.s0, v.s1) + 63) / 64 * 64, vb,
-                      f32 ? v.xs : 0, v.dp};  // the 8-bit search keeps no FP32 query in LDS
-    const size_t wl0 = sl.bytes();
-    if (wl0 * wpb > ix->max_lds)
+    const int st_cap = std::max(v.s0, v.s1) <= 64 ? 64 : (std::max(v.s0, v.s1) + 63) / 64 * 64;
+    // the 8-bit search keeps no FP32 query in LDS
+    dev::SearchLds sl{ef_cap, st_cap, vb, f32 ? v.xs : 0, v.dp, true, 0, true};
+    dev::SearchLds sl2{nsw > 0 ? (sp->ef_small + 63) / 64 * 64 : 0, st_cap, vb, f32 ? v.xs : 0, v.dp,
+                       true, 0, true};
+    auto block_bytes = [&]() { return sl.bytes() * (wpb - nsw) + (nsw > 0 ? sl2.bytes() * nsw : 0); };
+    const size_t blk0 = block_bytes();
+    if (blk0 > ix->max_lds)
         return fail(AQR_ERR_INVALID_ARG, std::string(who) + ": LDS per block exceeds the device limit (lower ef_max, visited_log2 or waves_per_block)");
     // The LDS that the blocks resident per CU leave unused holds more visited
     // buckets (fewer than 2^vb more): the same blocks stay resident, and the
     // cache forgets fewer of the nodes a query meets.
-    const size_t per_cu = (size_t)lds_blocks_per_cu(ix->cu_lds, wl0 * wpb);
+    const size_t per_cu = (size_t)lds_blocks_per_cu(ix->cu_lds, blk0);
     if (per_cu >= 1) {
-        const size_t block = std::min(ix->cu_lds / per_cu / kLdsUnit * kLdsUnit, (size_t)ix->max_lds);
-        const size_t room = block / wpb;
-        size_t xb = room > wl0 ? (room - wl0) / 8 : 0;
-        sl.xb = (int)std::min(xb, ((size_t)1 << vb) - 1);
-        while (sl.xb > 0 && sl.bytes() > room) --sl.xb;
+        const size_t room = std::min(ix->cu_lds / per_cu / kLdsUnit * kLdsUnit, (size_t)ix->max_lds);
+        size_t xb = room > blk0 ? (room - blk0) / (8 * (size_t)wpb) : 0;
+        sl.xb = sl2.xb = (int)std::min(xb, ((size_t)1 << vb) - 1);
+        while (sl.xb > 0 && block_bytes() > room) sl.xb = sl2.xb = sl.xb - 1;
     }
     const size_t wl = sl.bytes();
-    const size_t lds = wl * wpb;
+    const size_t lds = block_bytes();
+    const size_t wl0 = blk0 / wpb;  // mean LDS of a wave before the extra buckets
     dev::SearchArgs a{};
     a.ix = v;
     a.Q = Q;
@@ -2119,6 +2215,9 @@ aqr_status run_search(const aqr_index* ix, const float* Q, int64_t nq, const int
     a.out_stride = sp->out_stride;
     a.vb = vb;
     a.xb = sl.xb;
+    a.nsw = nsw;
+    a.ef_cap2 = sl2.ef_cap;
+    a.wave_lds2 = nsw > 0 ? sl2.bytes() : 0;
     a.mode = f32 ? 1 : 0;
     const int nch = f32 ? v.xs / 4 : v.dp / 16;
     a.nch = nch;
@@ -2135,7 +2234,11 @@ aqr_status run_search(const aqr_index* ix, const float* Q, int64_t nq, const int
         a.taps.counts = taps->counts;
     }
     hipStream_t s = (hipStream_t)stream;
-    hipLaunchKernelGGL(dev::k_reset, dim3(1), dim3(64), 0, s, a.counter);
+    if (nsw > 0)
+        hipLaunchKernelGGL(dev::k_split, dim3(1), dim3(1024), 0, s, k, ef, sp->order, nq,
+                           sp->ef_small, a.counter);
+    else
+        hipLaunchKernelGGL(dev::k_reset, dim3(1), dim3(64), 0, s, a.counter);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return hip_fail(e, who);
     const int cpl = cpl_for(nch);

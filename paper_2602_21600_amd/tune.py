@@ -1,6 +1,7 @@
 """Autotuner of the batch launch: waves per block, resident waves per CU,
 visited-cache size and re-rank waves per block, chosen by timing a sample
-batch through libaqr.
+batch through libaqr; then, on the best of those, a second list size for
+part of each block's waves (waves whose LDS holds lists of ef_small only).
 
 The search result does not depend on these choices (only the speed does);
 the tests check that.  Results are cached in a JSON file keyed by the index
@@ -19,6 +20,21 @@ RERANK_WPB = (2, 4)
 # resident search waves per CU: 0 = as many as occupancy allows, else the
 # persistent grid is cut to this many waves per CU
 WAVES_PER_CU = (0, 8)
+# second list size: ef_small as a fraction of ef_max (rounded up to whole
+# 64-entry slots), on 1 .. waves_per_block - 1 waves of each block
+SMALL_FRACTIONS = (4, 2)
+
+
+def small_choices(wpb, ef_max):
+    """(ef_small, small_waves) pairs tried for a block of wpb waves."""
+    out = []
+    for f in SMALL_FRACTIONS:
+        es = (ef_max // f + 63) // 64 * 64
+        if 1 <= es < ef_max:
+            for sw in range(1, wpb):
+                if (es, sw) not in out:
+                    out.append((es, sw))
+    return out
 
 
 def _key(ix, ef_max, k_max, device_name):
@@ -81,6 +97,22 @@ def autotune(ix, Q, k, ef, k_max, ef_max, cache_path=None, reps=3, log=None):
             log(f"tune {tuning}: {ms:.3f} ms")
     if not table:
         raise RuntimeError("autotune: no configuration could run")
+    best = min(table, key=lambda t: t[1])[0]
+    # second list size, on the best single-size choice and each block size
+    for wpb in SEARCH_WPB:
+        for es, sw in small_choices(wpb, max(ef_max, k_max)):
+            tuning = dict(best, waves_per_block=wpb, ef_small=es, small_waves=sw)
+            if best.get("blocks"):
+                tuning["blocks"] = best["blocks"] * best["waves_per_block"] // wpb
+            try:
+                ms = time_config(ix, Q, k, ef, k_max, ef_max, tuning, reps)
+            except aqr.AqrError as e:
+                if log:
+                    log(f"tune {tuning}: skipped ({e})")
+                continue
+            table.append((tuning, round(ms, 4)))
+            if log:
+                log(f"tune {tuning}: {ms:.3f} ms")
     best = min(table, key=lambda t: t[1])[0]
     if cache_path:
         data = {}

@@ -149,12 +149,74 @@ def test_graph_replays_equal_eager(orc, small):
     dict(waves_per_block=1, visited_log2=8, rerank_waves_per_block=2),
     dict(waves_per_block=2, visited_log2=10, rerank_waves_per_block=4),
     dict(waves_per_block=4, visited_log2=6, rerank_waves_per_block=1, blocks=5),
+    # two list sizes in one launch
+    dict(waves_per_block=4, visited_log2=8, ef_small=128, small_waves=2),
+    dict(waves_per_block=4, visited_log2=9, ef_small=256, small_waves=3),
+    dict(waves_per_block=2, visited_log2=7, ef_small=64, small_waves=1, blocks=3),
 ])
 def test_tuning_does_not_change_results(orc, small, tuning):
     Q, k, ef = small["Q"], small["k"], small["ef"]
     base = run_plan(small, Q, k, ef)[0]
     other = run_plan(small, Q, k, ef, tuning=tuning)[0]
     same(base, other, Q.shape[0])
+
+
+def _split_words(Q, k, ef, small, tuning, longest_first):
+    # the plan's search workspace after a launch: claims of positions [0, c),
+    # the split point c (-1: the order is not split), claims of [c, nq)
+    import torch
+    from paper_2602_21600_amd import aqr
+    plan = aqr.BatchPlan(small["ix"], Q.shape[0], 100, 512, use_graph=False,
+                         longest_first=longest_first, tuning=tuning)
+    n = plan.load(torch.from_numpy(Q).cuda(), torch.from_numpy(k).cuda(),
+                  torch.from_numpy(ef).cuda())
+    plan.launch(n)
+    torch.cuda.synchronize()
+    return plan.bufs["ws"][:12].cpu().numpy().view(np.int32)
+
+
+def test_two_list_sizes_split_and_fall_back(orc, small):
+    # longest first: the split point is the number of queries whose list is
+    # above ef_small, and both claim counters pass their ranges; in the
+    # given order (not split) the small-list waves leave and the others
+    # take every query; a batch already in longest-first order splits
+    # without the order array; results are the same in every case
+    Q, k, ef = small["Q"], small["k"], small["ef"]
+    nq = Q.shape[0]
+    tuning = dict(waves_per_block=4, visited_log2=8, ef_small=128, small_waves=2)
+    big = int((np.maximum(ef, k) > 128).sum())
+    assert 0 < big < nq
+    w = _split_words(Q, k, ef, small, tuning, True)
+    assert w[1] == big and w[0] >= big and w[2] >= nq - big
+    base = run_plan(small, Q, k, ef)[0]
+    w = _split_words(Q, k, ef, small, tuning, False)
+    assert w[1] == -1 and w[0] >= nq
+    same(base, run_plan(small, Q, k, ef, longest_first=False, tuning=tuning)[0], nq)
+    srt = np.argsort(-np.maximum(ef, k), kind="stable")
+    w = _split_words(Q[srt], k[srt], ef[srt], small, tuning, False)
+    assert w[1] == big
+    out = run_plan(small, Q[srt], k[srt], ef[srt], longest_first=False, tuning=tuning)[0]
+    for key in ("cand_cnt", "id", "kind"):
+        np.testing.assert_array_equal(out[key], base[key][srt])
+    np.testing.assert_array_equal(out["dist"].view(np.uint32), base["dist"][srt].view(np.uint32))
+
+
+@pytest.mark.parametrize("bad", [dict(small_waves=4), dict(small_waves=-1),
+                                 dict(small_waves=1, ef_small=512),
+                                 dict(small_waves=1, ef_small=0)])
+def test_two_list_sizes_reject_bad_arguments(orc, small, bad):
+    import torch
+    from paper_2602_21600_amd import aqr
+    Q, k, ef = small["Q"][:8], small["k"][:8], small["ef"][:8]
+    nc = 170
+    cid = torch.empty((8, nc), dtype=torch.int32, device="cuda")
+    cD = torch.empty_like(cid)
+    cnt = torch.empty(8, dtype=torch.int32, device="cuda")
+    ws = torch.zeros(aqr.aqr_search_workspace_size(), dtype=torch.uint8, device="cuda")
+    with pytest.raises(aqr.AqrError):
+        aqr.aqr_search(small["ix"], torch.from_numpy(Q).cuda(), torch.from_numpy(k).cuda(),
+                       torch.from_numpy(ef).cuda(), cid, cD, cnt, ws, 512, nc,
+                       waves_per_block=4, **bad)
 
 
 def test_autotune_picks_a_valid_config(orc, small, tmp_path):
