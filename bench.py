@@ -325,6 +325,53 @@ def common_out(args, metric_value, ms, dtype="u8"):
     }
 
 
+def fp32_batched(args, torch, aqr, ix, Qd, kd, efd, b, X, Q, gt_ids, gt_d, efq, k10, kk, k_max,
+                 ef_max):
+    """FP32 HNSW on the batched workload's batch and order, its launch shape
+    tuned on the same batch."""
+    nq = Q.shape[0]
+    dev = Qd.device
+    out_id = torch.empty((nq, k_max), dtype=torch.int32, device=dev)
+    out_d = torch.empty((nq, k_max), dtype=torch.float32, device=dev)
+    ws = torch.zeros(aqr.aqr_search_workspace_size(), dtype=torch.uint8, device=dev)
+
+    # the baseline's launch shape is tuned on the same batch, as the AQR plan's is
+    fp_sp, best_fp = {}, None
+    spin_up(torch, lambda m: aqr.aqr_search_fp32(ix, Qd, kd, efd, out_id, out_d, ws, ef_max,
+                                                 k_max, order=b["order"]))
+    for vb in (7, 8, 9, 10, 11):
+        for wpb in (1, 2, 4):
+            cand = dict(visited_log2=vb, waves_per_block=wpb)
+            try:
+                ms_t, _ = timed(torch, lambda m: aqr.aqr_search_fp32(
+                    ix, Qd, kd, efd, out_id, out_d, ws, ef_max, k_max, order=b["order"], **cand),
+                    2, 1)
+            except aqr.AqrError as e:  # LDS limit of the device
+                log(f"tune fp32 {cand}: skipped ({e})")
+                continue
+            if best_fp is None or ms_t < best_fp:
+                best_fp, fp_sp = ms_t, cand
+    log(f"fp32 tuning picked {fp_sp}")
+
+    def fp_step(marks):
+        if marks:
+            marks[0].record()
+        aqr.aqr_search_fp32(ix, Qd, kd, efd, out_id, out_d, ws, ef_max, k_max, order=b["order"],
+                            **fp_sp)
+        if marks:
+            marks[1].record()
+
+    log("timing FP32 HNSW on the same batch")
+    ms_fp, per_fp = timed(torch, fp_step, args.steps, args.warmup, kernel_events=2)
+    rq_fp = recall_per_query(out_id.cpu().numpy(), X, Q, gt_ids, gt_d, kk)
+    fp = {"value": round(nq / (ms_fp / 1e3), 1), "unit": "queries/s", "tuning": fp_sp,
+          "ms_per_step": round(ms_fp, 4), "recall@min(k,10)": round(float(rq_fp.mean()), 5),
+          "recall@10_by_ef": {int(v): round(float(rq_fp[k10 & (efq == v)].mean()), 5)
+                              for v in np.unique(efq)}}
+    log(f"FP32 {fp['value']:,.0f} QPS; recall {rq_fp.mean():.4f}")
+    return fp
+
+
 def bench_batched(args, torch, aqr, W, wl, dev, threads):
     """Uneven batch in one captured launch: per-query k and ef, longest first,
     tuning chosen by the autotuner; FP32 HNSW on the same batch beside it."""
@@ -347,10 +394,17 @@ def bench_batched(args, torch, aqr, W, wl, dev, threads):
     cfg = rerank_by_name(args.rerank or "table3")
     _, nrr, tg, tr, _ = cfg
 
-    S = min(nq, args.tune_sample)
-    log(f"autotune on {S} queries")
-    best, table = tune.autotune(ix, Qd[:S], kd[:S], efd[:S], k_max, ef_max, reps=2, log=log)
-    log(f"autotune picked {best}")
+    if args.profile:
+        # a fixed launch shape, so that a profiler sees only the timed one
+        best = dict(waves_per_block=args.wpb or 4, visited_log2=args.vb or 8,
+                    rerank_waves_per_block=2, blocks=0)
+        table = []
+        log(f"--profile: fixed tuning {best}")
+    else:
+        S = min(nq, args.tune_sample)
+        log(f"autotune on {S} queries")
+        best, table = tune.autotune(ix, Qd[:S], kd[:S], efd[:S], k_max, ef_max, reps=2, log=log)
+        log(f"autotune picked {best}")
     plan = aqr.BatchPlan(ix, nq, k_max, ef_max, n_rerank=nrr, tau_gap=tg, tau_ratio=tr,
                          use_graph=True, tuning=best)
     plan.load(Qd, kd, efd)
@@ -398,46 +452,27 @@ def bench_batched(args, torch, aqr, W, wl, dev, threads):
     alg = code_b + adj_b + io_b
     achieved = alg / (search_ms / 1e3) / 1e9
     lat_us = cnt_big[:, 5] / 100.0
+    prof_name = (f"search_u8_batched_vb{best.get('visited_log2', 0)}"
+                 f"_wpb{best.get('waves_per_block', 0)}"
+                 + (f"_es{best['ef_small']}_sw{best['small_waves']}"
+                    if best.get("small_waves") else ""))
+    traffic = traffic_from_profile(prof_name, source_sha())
 
-    # FP32 HNSW on the same batch and order
-    out_id = torch.empty((nq, k_max), dtype=torch.int32, device=dev)
-    out_d = torch.empty((nq, k_max), dtype=torch.float32, device=dev)
-    ws = torch.zeros(aqr.aqr_search_workspace_size(), dtype=torch.uint8, device=dev)
-
-    # the baseline's launch shape is tuned on the same batch, as the AQR plan's is
-    fp_sp, best_fp = {}, None
-    spin_up(torch, lambda m: aqr.aqr_search_fp32(ix, Qd, kd, efd, out_id, out_d, ws, ef_max,
-                                                 k_max, order=b["order"]))
-    for vb in (7, 8, 9, 10, 11):
-        for wpb in (1, 2, 4):
-            cand = dict(visited_log2=vb, waves_per_block=wpb)
-            try:
-                ms_t, _ = timed(torch, lambda m: aqr.aqr_search_fp32(
-                    ix, Qd, kd, efd, out_id, out_d, ws, ef_max, k_max, order=b["order"], **cand),
-                    2, 1)
-            except aqr.AqrError as e:  # LDS limit of the device
-                log(f"tune fp32 {cand}: skipped ({e})")
-                continue
-            if best_fp is None or ms_t < best_fp:
-                best_fp, fp_sp = ms_t, cand
-    log(f"fp32 tuning picked {fp_sp}")
-
-    def fp_step(marks):
-        if marks:
-            marks[0].record()
-        aqr.aqr_search_fp32(ix, Qd, kd, efd, out_id, out_d, ws, ef_max, k_max, order=b["order"],
-                            **fp_sp)
-        if marks:
-            marks[1].record()
-
-    log("timing FP32 HNSW on the same batch")
-    ms_fp, per_fp = timed(torch, fp_step, args.steps, args.warmup, kernel_events=2)
-    rq_fp = recall_per_query(out_id.cpu().numpy(), X, Q, gt_ids, gt_d, kk)
-    fp = {"value": round(nq / (ms_fp / 1e3), 1), "unit": "queries/s", "tuning": fp_sp,
-          "ms_per_step": round(ms_fp, 4), "recall@min(k,10)": round(float(rq_fp.mean()), 5),
-          "recall@10_by_ef": {int(v): round(float(rq_fp[k10 & (efq == v)].mean()), 5)
-                              for v in np.unique(efq)}}
-    log(f"FP32 {fp['value']:,.0f} QPS; recall {rq_fp.mean():.4f}")
+    copy_info = None
+    fp = None
+    if args.profile:
+        # a plain copy of known size: its FETCH_SIZE/WRITE_SIZE readings scale
+        # the counters of the search kernel to bytes
+        src = torch.empty(args.copy_mib << 20, dtype=torch.uint8, device=dev).fill_(1)
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        copy_info = {"bytes": args.copy_mib << 20}
+        log("--profile: no FP32 baseline")
+    else:
+        fp = fp32_batched(args, torch, aqr, ix, Qd, kd, efd, b, X, Q, gt_ids, gt_d, efq, k10, kk,
+                          k_max, ef_max)
 
     cpu = parity = None
     if not args.no_cpu:
@@ -485,17 +520,20 @@ def bench_batched(args, torch, aqr, W, wl, dev, threads):
         },
         "roofline": {
             "bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
-            "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+            "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
+            "traffic_profile": prof_name,
             "kernel": "k_search (Stage 1, 8-bit codes)", "kernel_ms": round(search_ms, 4),
             "alg_bytes_per_launch": alg, "code_bytes": code_b, "adjacency_bytes": adj_b,
-            "io_bytes": io_b,
+            "io_bytes": io_b, "expansions_per_query": round(float(cnt_big[:, 0].mean()), 2),
+            "distinct_evaluations_per_query": round(float(cnt_big[:, 1].mean()), 1),
         },
         "latency_us": {"p50": round(float(np.percentile(lat_us, 50)), 2),
                        "p99": round(float(np.percentile(lat_us, 99)), 2),
                        "what": "per-query Stage-1 device time inside the batch"},
         "fp32_hnsw": fp,
-        "speedup_vs_fp32": round(qps / fp["value"], 3),
+        "speedup_vs_fp32": round(qps / fp["value"], 3) if fp else None,
         "autotune": table,
+        "copy_kernel": copy_info,
         "cpu_baseline": cpu,
         "parity_sample": parity,
         "build_s": {"quantize": t_quant and round(t_quant, 1),
@@ -1271,7 +1309,8 @@ def main():
                     help="cap of the CPU oracle's sample (0: sized to about 15 s of host work)")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--profile", action="store_true",
-                    help="skip sweeps and the CPU leg; time the AQR path at --ef")
+                    help="skip sweeps and the CPU leg; time the AQR path at --ef (batched: "
+                         "the fixed launch shape --vb/--wpb, no autotune, no FP32 baseline)")
     ap.add_argument("--ef", type=int, default=None)
     ap.add_argument("--rerank", default=None,
                     help="re-rank setting (--profile: default no-et; batched: table3)")
