@@ -67,6 +67,20 @@ def spin_up(ix, Q, k, ef, k_max, ef_max, seconds=0.5):
         torch.cuda.synchronize()
 
 
+def pick(table, tie=0.01):
+    """The fastest tuning; two list sizes only when they beat the fastest
+    single size by more than `tie` (repeat timings differ by about 0.5%, and
+    one size is the simpler launch)."""
+    best = min(table, key=lambda t: t[1])
+    if best[0].get("small_waves"):
+        single = [t for t in table if not t[0].get("small_waves")]
+        if single:
+            s = min(single, key=lambda t: t[1])
+            if s[1] <= best[1] * (1.0 + tie):
+                return s[0]
+    return best[0]
+
+
 def autotune(ix, Q, k, ef, k_max, ef_max, cache_path=None, reps=3, log=None):
     """Returns (best tuning dict, table of (tuning, ms))."""
     import torch
@@ -113,7 +127,7 @@ def autotune(ix, Q, k, ef, k_max, ef_max, cache_path=None, reps=3, log=None):
             table.append((tuning, round(ms, 4)))
             if log:
                 log(f"tune {tuning}: {ms:.3f} ms")
-    best = min(table, key=lambda t: t[1])[0]
+    best = pick(table)
     if cache_path:
         data = {}
         if os.path.exists(cache_path):

@@ -94,3 +94,13 @@ def test_launch_shape_ties_go_to_the_larger_cache_then_block(bench):
     t = [(2.0, 8, 4), (2.5, 12, 4)]
     assert bench.pick_shape(t, None) == {"visited_log2": 8, "waves_per_block": 4}
     assert bench.pick_shape([], {"visited_log2": 7}) == {"visited_log2": 7}
+
+
+def test_autotune_keeps_one_list_size_unless_two_win_clearly():
+    from paper_2602_21600_amd import tune
+    one = dict(waves_per_block=4, visited_log2=8)
+    two = dict(waves_per_block=4, visited_log2=8, ef_small=128, small_waves=1)
+    assert tune.pick([(one, 12.80), (two, 12.78)]) == one      # within 1%
+    assert tune.pick([(one, 12.80), (two, 12.50)]) == two      # more than 1% faster
+    assert tune.pick([(one, 12.70), (two, 12.90)]) == one
+    assert tune.pick([(two, 12.90)]) == two                    # nothing else ran
