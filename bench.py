@@ -585,9 +585,16 @@ def bench_serving(args, torch, aqr, W, wl, dev, threads):
     ef98, cfg = pick
     rec98 = next(r for e, c, r in sweep if e == ef98 and c == cfg[0])
     _, nrr, tg, tr, mef = cfg
+    # the mixed stream's ef is log-uniform in [16, 512], so most of its
+    # requests sit below ef_0.98; the same draws mapped onto [ef_0.98, 512]
+    # give the stream whose k >= 10 requests reach the recall target
+    lo, hi = np.log(16.0), np.log(512.0)
+    u = np.clip((np.log(efq.astype(np.float64)) - lo) / (hi - lo), 0.0, 1.0)
+    ef_hi = np.clip(np.exp(np.log(ef98) + u * (hi - np.log(ef98))).astype(np.int32), ef98, 512)
     streams = {
         "fixed": (np.full(nq, 10, np.int32), np.full(nq, ef98, np.int32)),
         "mixed": (kq, efq),
+        "mixed_from_ef98": (kq, ef_hi.astype(np.int32)),
     }
     # batch capacity of each stream (same queries, one launch)
     batch_qps = {}
@@ -657,13 +664,15 @@ def bench_serving(args, torch, aqr, W, wl, dev, threads):
                 ids, _, lat, wall, svc = sv.replay(arr, Q[idx], ks[idx], es[idx], service=True)
                 rq = recall_per_query(ids[:nq], X, Q[idx[:nq]], gt_ids[idx[:nq]],
                                       gt_d[idx[:nq]], np.minimum(ks[idx[:nq]], 10))
+                k10 = ks[idx[:nq]] >= 10
                 row = {"load": load, "offered_qps": round(rate, 1),
                        "achieved_qps": round(cnt / wall, 1), "requests": cnt,
                        "p50_ms": round(float(np.percentile(lat, 50)) * 1e3, 4),
                        "p99_ms": round(float(np.percentile(lat, 99)) * 1e3, 4),
                        "service_p50_ms": round(float(np.percentile(svc, 50)) * 1e3, 4),
                        "service_p99_ms": round(float(np.percentile(svc, 99)) * 1e3, 4),
-                       "recall@min(k,10)": round(float(rq.mean()), 5)}
+                       "recall@min(k,10)": round(float(rq.mean()), 5),
+                       "recall@10_of_k_ge_10": round(float(rq[k10].mean()), 5)}
                 rows.append(row)
                 log(f"{name} load {load}: {row}")
             results[name] = {"saturation_qps": round(sat, 1),
@@ -671,7 +680,9 @@ def bench_serving(args, torch, aqr, W, wl, dev, threads):
     finally:
         sv.stop()
 
-    head = max((r for r in results["fixed"]["loads"]), key=lambda r: r["load"])
+    # the summary row: the highest offered load at or below saturation
+    under = [r for r in results["fixed"]["loads"] if r["load"] <= 1.0] or results["fixed"]["loads"]
+    head = max(under, key=lambda r: r["load"])
     out = common_out(args, head["achieved_qps"], 1e3 / max(head["achieved_qps"], 1e-9))
     out["steps"] = head["requests"]
     out.update({
@@ -1260,9 +1271,11 @@ def serving_leg(args, torch, aqr, W, name, ctx, dev, loads=(0.5, 0.9), seconds=1
         w = min(nq, 2000)
         sv.replay(np.zeros(w), Q[:w], streams["fixed"][0][:w], streams["fixed"][1][:w])
         for si, (sname, (ks, es)) in enumerate(streams.items()):
-            m = min(nq, 20_000)
-            _, _, _, wall, svc = sv.replay(np.zeros(m), Q[:m], ks[:m], es[:m], service=True)
-            sat = m / wall
+            # saturation from the whole query set at t = 0 (with fewer
+            # requests the ramp and the tail lower the rate: 20,000 of the
+            # 10M x 96 set read 1.64M QPS, all 100,000 read 1.93M)
+            _, _, _, wall, svc = sv.replay(np.zeros(nq), Q, ks, es, service=True)
+            sat = nq / wall
             rows = []
             for li, load in enumerate(loads if sname == "fixed" else loads[-1:]):
                 rate = load * sat
@@ -1327,7 +1340,7 @@ def main():
     ap.add_argument("--ring", type=int, default=4096, help="serving: request slots")
     ap.add_argument("--serve-vb", type=int, default=0,
                     help="serving: visited_log2 of the server kernel (0: the library default)")
-    ap.add_argument("--loads", default="0.1,0.5,0.8,0.9",
+    ap.add_argument("--loads", default="0.1,0.25,0.5,0.75,0.9,1.1",
                     help="serving: offered loads as fractions of the saturation rate")
     ap.add_argument("--serve-seconds", type=float, default=1.0)
     ap.add_argument("--cache", default=None,
