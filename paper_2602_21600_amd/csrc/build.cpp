@@ -24,6 +24,7 @@
 #include <mutex>
 #include <new>
 #include <queue>
+#include <thread>
 
 #include "internal.hpp"
 
@@ -261,6 +262,40 @@ namespace aqr {
 // run on T threads; thread t applies the reverse links into the nodes x
 // with x % T == t, in the order above, so the graph does not depend on T.
 // With chunks of one point this is sequential insertion.
+// Barrier of a fixed set of threads that meet many times in a row (a chunk
+// takes a millisecond or so, far longer than a spin); a thread that waits
+// long yields its core.
+class SpinBarrier {
+  public:
+    explicit SpinBarrier(int n) : n_(n) {}
+    void wait() {
+        const unsigned gen = gen_.load(std::memory_order_acquire);
+        if (count_.fetch_add(1, std::memory_order_acq_rel) == n_ - 1) {
+            count_.store(0, std::memory_order_relaxed);
+            gen_.fetch_add(1, std::memory_order_release);
+            return;
+        }
+        for (int spins = 0; gen_.load(std::memory_order_acquire) == gen; ++spins)
+            if (spins > 2000) std::this_thread::yield();
+    }
+
+  private:
+    const int n_;
+    std::atomic<int> count_{0};
+    std::atomic<unsigned> gen_{0};
+};
+
+// The points of S, in order, in chunks of min(chunk_max, max(1, inserted / 8))
+// (Alg. 1's insertion, with every point of a chunk searching the graph as it
+// stood before the chunk): each chunk point's searches and neighbour
+// selection, then its own lists, then the reverse links of every selection
+// in (point, level, rank) order.  T threads stay for the whole seed and meet
+// at a barrier between the steps: the searches are shared out point by
+// point, the own lists by point, and the reverse links by target list, so
+// every list receives its links in the same order whatever T is.  A chunk
+// point's searches cannot reach another point of its chunk (nothing links
+// to it yet), so the lists a chunk's reverse links change are not the
+// lists of its own points.
 static void insert_chunks(Graph& g, const uint8_t* codes, int32_t dp, const std::vector<uint32_t>& S,
                           int32_t chunk_max, int T, const std::function<void(int64_t)>& report) {
     Builder B(g, codes, dp, false);
@@ -270,20 +305,34 @@ static void insert_chunks(Graph& g, const uint8_t* codes, int32_t dp, const std:
     for (int t = 0; t < T; ++t) vis.emplace_back(g.n);
     std::vector<std::vector<uint32_t>> sel;  // per chunk point: M per level, top level first
     std::vector<std::vector<int32_t>> nsel;  // per chunk point and level: selected count
-    int64_t inserted = 1;                    // point 0
+    // the chunk, published by thread 0 before the first barrier of a round
+    const uint32_t* ids = nullptr;
+    int32_t nb = 0;
+    uint32_t ep = 0;
+    int32_t L = 0;
+    bool done = false;
+    int64_t inserted = 1;  // point 0
     size_t pos = 0;
-    while (pos < S.size()) {
-        const int64_t want = std::min<int64_t>(chunk_max, std::max<int64_t>(1, inserted / 8));
-        const int32_t nb = (int32_t)std::min<int64_t>(want, (int64_t)(S.size() - pos));
-        const uint32_t* ids = S.data() + pos;
-        const uint32_t ep = g.ep;
-        const int32_t L = g.L;
-        sel.assign(nb, {});
-        nsel.assign(nb, {});
-        std::atomic<int32_t> nx{0};
-        const int TP = std::max(1, std::min(T, nb));
-        parallel_for_threads(TP, [&](int t) {
-            std::vector<uint64_t> eps, W;
+    std::atomic<int32_t> nx{0};
+    SpinBarrier bar(T);
+    parallel_for_threads(T, [&](int t) {
+        std::vector<uint64_t> eps, W;
+        for (;;) {
+            if (t == 0) {
+                done = pos >= S.size();
+                if (!done) {
+                    const int64_t want = std::min<int64_t>(chunk_max, std::max<int64_t>(1, inserted / 8));
+                    nb = (int32_t)std::min<int64_t>(want, (int64_t)(S.size() - pos));
+                    ids = S.data() + pos;
+                    ep = g.ep;
+                    L = g.L;
+                    sel.assign(nb, {});
+                    nsel.assign(nb, {});
+                    nx.store(0, std::memory_order_relaxed);
+                }
+            }
+            bar.wait();  // the chunk is published
+            if (done) return;
             for (;;) {
                 const int32_t b = nx.fetch_add(1);
                 if (b >= nb) break;
@@ -302,33 +351,32 @@ static void insert_chunks(Graph& g, const uint8_t* codes, int32_t dp, const std:
                     eps = W;
                 }
             }
-        });
-        for (int32_t b = 0; b < nb; ++b)
-            for (int32_t lc = (int32_t)nsel[b].size() - 1; lc >= 0; --lc) {
-                int32_t cap;
-                uint32_t* row = B.nbrs(ids[b], lc, cap);
-                for (int32_t t = 0; t < nsel[b][lc]; ++t) row[t] = sel[b][(size_t)lc * M + t];
-            }
-        // small chunks link on one thread (starting threads would cost more);
-        // either way each list receives its links in the same order
-        const int TL = nb >= 256 ? T : 1;
-        parallel_for_threads(TL, [&](int t) {
+            bar.wait();  // every selection is made
+            for (int32_t b = t; b < nb; b += T)
+                for (int32_t lc = (int32_t)nsel[b].size() - 1; lc >= 0; --lc) {
+                    int32_t cap;
+                    uint32_t* row = B.nbrs(ids[b], lc, cap);
+                    for (int32_t j = 0; j < nsel[b][lc]; ++j) row[j] = sel[b][(size_t)lc * M + j];
+                }
             for (int32_t b = 0; b < nb; ++b)
                 for (int32_t lc = (int32_t)nsel[b].size() - 1; lc >= 0; --lc)
                     for (int32_t j = 0; j < nsel[b][lc]; ++j) {
                         const uint32_t x = sel[b][(size_t)lc * M + j];
-                        if ((int)(x % (uint32_t)TL) == t) B.link_locked(x, ids[b], lc);
+                        if ((int)(x % (uint32_t)T) == t) B.link_locked(x, ids[b], lc);
                     }
-        });
-        for (int32_t b = 0; b < nb; ++b)
-            if (g.level[ids[b]] > g.L) {
-                g.L = g.level[ids[b]];
-                g.ep = ids[b];
+            bar.wait();  // the chunk is linked
+            if (t == 0) {
+                for (int32_t b = 0; b < nb; ++b)
+                    if (g.level[ids[b]] > g.L) {
+                        g.L = g.level[ids[b]];
+                        g.ep = ids[b];
+                    }
+                pos += nb;
+                inserted += nb;
+                report((int64_t)pos);
             }
-        pos += nb;
-        inserted += nb;
-        report((int64_t)pos);
-    }
+        }
+    });
 }
 
 // Levels for every point, then insertion of the seed: every point below
