@@ -231,3 +231,31 @@ def test_autotune_picks_a_valid_config(orc, small, tmp_path):
     again, _ = tune.autotune(small["ix"], None, None, None, 100, 512,
                              cache_path=str(tmp_path / "tune.json"))
     assert again == best
+
+
+def test_two_list_sizes_fp32_baseline(orc, small):
+    # the FP32 search keeps its query in LDS ahead of the other arrays; with
+    # two list sizes (longest-first order, a split order and the natural
+    # order that is not split) its rows equal the single-size launch's
+    import torch
+    from paper_2602_21600_amd import aqr
+    Q, k, ef = small["Q"], small["k"], small["ef"]
+    nq = Q.shape[0]
+    Qd, kd, efd = (torch.from_numpy(a).cuda() for a in (Q, k, ef))
+    ws = torch.zeros(aqr.aqr_search_workspace_size(), dtype=torch.uint8, device="cuda")
+    order = torch.from_numpy(np.argsort(-np.maximum(ef, k), kind="stable").astype(np.int32)).cuda()
+
+    def run(**kw):
+        oid = torch.full((nq, 100), -7, dtype=torch.int32, device="cuda")
+        od = torch.zeros((nq, 100), dtype=torch.float32, device="cuda")
+        aqr.aqr_search_fp32(small["ix"], Qd, kd, efd, oid, od, ws, 512, 100, **kw)
+        torch.cuda.synchronize()
+        return oid.cpu().numpy(), od.cpu().numpy()
+
+    base_id, base_d = run(waves_per_block=4, visited_log2=8)
+    for kw in (dict(order=order, ef_small=128, small_waves=2),
+               dict(order=order, ef_small=256, small_waves=3),
+               dict(ef_small=128, small_waves=1)):
+        oid, od = run(waves_per_block=4, visited_log2=8, **kw)
+        np.testing.assert_array_equal(oid, base_id, err_msg=str(kw))
+        np.testing.assert_array_equal(od.view(np.uint32), base_d.view(np.uint32), err_msg=str(kw))
