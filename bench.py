@@ -279,10 +279,11 @@ def search_bytes(cnt_big, nq, d, d_pad, s0, s1, nc_total):
 
 def tune_vbs(n):
     """Visited-cache sizes the launch-shape loop tries: 2^6 .. 2^12 buckets,
-    from the smallest the id width allows (the stored remainder of a hashed
-    id is at most 15 bits)."""
+    from the smallest the id width allows (the stored part of a hashed id is
+    at most 16 bits, and 16 only when the launch adds buckets beyond 2^vb;
+    where it cannot, the library takes the next size)."""
     idbits = max(1, int(np.ceil(np.log2(max(n, 2)))))
-    return list(range(max(6, idbits - 15), 13))
+    return list(range(max(6, idbits - 16), 13))
 
 
 def pick_shape(timings, fallback, tie=0.01):

@@ -387,25 +387,32 @@ __device__ __forceinline__ void eval_rows(const Idx& ix, const uint32_t* ids, in
 // forgetful visited cache: buckets of four 16-bit entries
 // ---------------------------------------------------------------------------
 // h = id * C mod 2^B is a bijection of [0, 2^B) (C odd).  With nb buckets,
-// 2^vb <= nb < 2^(vb+1), the bucket is floor(h * nb / 2^B) and the low
-// B - vb bits of h (<= 15) are stored with a valid bit.  Two values of h with
-// the same low bits lie at least 2^(B-vb) >= 2^B / nb apart, one bucket's
-// width, so they fall in different buckets: (bucket, entry) identifies the
-// id exactly for any such nb (nb = 2^vb: the top vb bits choose the bucket).
-// A bucket keeps its four most recent entries.
+// 2^vb <= nb < 2^(vb+1), the bucket is floor(h * nb / 2^B), and the entry is
+// h's place in its bucket, r = h * nb mod 2^B, scaled to 1 + floor(r * 65535
+// / 2^B) in [1, 65535] (0 marks an empty place).  Two values of h in one
+// bucket have places at least nb apart, so their entries differ whenever
+// nb * 65535 >= 2^B: always when B - vb <= 15, and with B - vb = 16 when
+// nb > 2^vb.  (bucket, entry) then identifies the id exactly.  With hs =
+// h * 2^(32 - B), one 32 x 32-bit product gives both: the bucket is the high
+// word of hs * nb and r * 2^(32 - B) = lo its low word, and 1 + floor(lo *
+// 65535 / 2^32) = q + [m > q or lo = 0] with q = lo >> 16, m = lo & 0xFFFF
+// (65535 m - 65536 q >= 0 exactly then), all full-rate operations.  A
+// bucket keeps its four most recent entries.
 struct VisCache {
     uint64_t* b;
     int vb;      // floor(log2 nb)
     int B;       // hash width
     uint32_t nb;  // buckets
-    __device__ __forceinline__ uint32_t bucket_of(uint32_t h) const {
-        return __umulhi(h << (32 - B), nb);
+    // bucket and entry of hs = h * 2^(32 - B)
+    __device__ __forceinline__ void place(uint32_t hs, uint32_t& bucket, uint32_t& e) const {
+        const uint64_t p = (uint64_t)hs * nb;
+        bucket = (uint32_t)(p >> 32);
+        const uint32_t lo = (uint32_t)p, q = lo >> 16;
+        e = q + (((lo & 0xFFFFu) > q || lo == 0u) ? 1u : 0u);
     }
     __device__ __forceinline__ bool test_insert(uint32_t id) const {
-        const uint32_t mask = B >= 32 ? 0xFFFFFFFFu : ((1u << B) - 1u);
-        const uint32_t h = (id * 0x9E3779B1u) & mask;
-        const uint32_t bucket = bucket_of(h);
-        const uint32_t e = (h & ((1u << (B - vb)) - 1u)) | 0x8000u;
+        uint32_t bucket, e;
+        place((id * 0x9E3779B1u) << (32 - B), bucket, e);
         const uint64_t w = b[bucket];
         const bool hit = ((uint32_t)(w & 0xFFFFu) == e) | ((uint32_t)((w >> 16) & 0xFFFFu) == e) |
                          ((uint32_t)((w >> 32) & 0xFFFFu) == e) | ((uint32_t)(w >> 48) == e);
@@ -415,10 +422,8 @@ struct VisCache {
     // Whole-wave form: lanes with nothing to insert (an invalid id, or a
     // hit) write the spare bucket nb instead of branching around the store.
     __device__ __forceinline__ bool test_insert_if(uint32_t id, bool valid) const {
-        const uint32_t mask = B >= 32 ? 0xFFFFFFFFu : ((1u << B) - 1u);
-        const uint32_t h = ((valid ? id : 0u) * 0x9E3779B1u) & mask;
-        const uint32_t bucket = bucket_of(h);
-        const uint32_t e = (h & ((1u << (B - vb)) - 1u)) | 0x8000u;
+        uint32_t bucket, e;
+        place(((valid ? id : 0u) * 0x9E3779B1u) << (32 - B), bucket, e);
         const uint64_t w = b[bucket];
         const bool hit = ((uint32_t)(w & 0xFFFFu) == e) | ((uint32_t)((w >> 16) & 0xFFFFu) == e) |
                          ((uint32_t)((w >> 32) & 0xFFFFu) == e) | ((uint32_t)(w >> 48) == e);
@@ -2167,8 +2172,8 @@ aqr_status run_search(const aqr_index* ix, const float* Q, int64_t nq, const int
     const Idx& v = ix->v;
     int vb = sp->visited_log2 > 0 ? sp->visited_log2 : 7;
     if (vb < 4 || vb > 14) return fail(AQR_ERR_INVALID_ARG, std::string(who) + ": visited_log2 out of [4, 14]");
-    const int idb = std::max(v.idbits, vb + 1);
-    if (idb - vb > 15) vb = idb - 15;  // keep the stored remainder within 15 bits
+    // at most 16 stored bits per id (16 only with more than 2^vb buckets)
+    if (std::max(v.idbits, vb + 1) - vb > 16) vb = v.idbits - 16;
     const int wpb = sp->waves_per_block > 0 ? sp->waves_per_block : 4;
     if (wpb != 1 && wpb != 2 && wpb != 4)
         return fail(AQR_ERR_INVALID_ARG, std::string(who) + ": waves_per_block must be 1, 2 or 4");
@@ -2186,22 +2191,33 @@ aqr_status run_search(const aqr_index* ix, const float* Q, int64_t nq, const int
     dev::SearchLds sl2{nsw > 0 ? (sp->ef_small + 63) / 64 * 64 : 0, st_cap, vb, f32 ? v.xs : 0, v.dp,
                        true, 0, true};
     auto block_bytes = [&]() { return sl.bytes() * (wpb - nsw) + (nsw > 0 ? sl2.bytes() * nsw : 0); };
-    const size_t blk0 = block_bytes();
-    if (blk0 > ix->max_lds)
-        return fail(AQR_ERR_INVALID_ARG, std::string(who) + ": LDS per block exceeds the device limit (lower ef_max, visited_log2 or waves_per_block)");
     // The LDS that the blocks resident per CU leave unused holds more visited
     // buckets (fewer than 2^vb more): the same blocks stay resident, and the
     // cache forgets fewer of the nodes a query meets.
-    const size_t per_cu = (size_t)lds_blocks_per_cu(ix->cu_lds, blk0);
-    if (per_cu >= 1) {
-        const size_t room = std::min(ix->cu_lds / per_cu / kLdsUnit * kLdsUnit, (size_t)ix->max_lds);
-        size_t xb = room > blk0 ? (room - blk0) / (8 * (size_t)wpb) : 0;
-        sl.xb = sl2.xb = (int)std::min(xb, ((size_t)1 << vb) - 1);
-        while (sl.xb > 0 && block_bytes() > room) sl.xb = sl2.xb = sl.xb - 1;
+    size_t blk0 = 0, per_cu = 0;
+    auto fill = [&]() {
+        sl.vb = sl2.vb = vb;
+        sl.xb = sl2.xb = 0;
+        blk0 = block_bytes();
+        per_cu = (size_t)lds_blocks_per_cu(ix->cu_lds, blk0);
+        if (per_cu >= 1) {
+            const size_t room = std::min(ix->cu_lds / per_cu / kLdsUnit * kLdsUnit, (size_t)ix->max_lds);
+            size_t xb = room > blk0 ? (room - blk0) / (8 * (size_t)wpb) : 0;
+            sl.xb = sl2.xb = (int)std::min(xb, ((size_t)1 << vb) - 1);
+            while (sl.xb > 0 && block_bytes() > room) sl.xb = sl2.xb = sl.xb - 1;
+        }
+    };
+    fill();
+    // 16 stored bits need more than 2^vb buckets; without room for one more,
+    // the cache doubles instead (15 stored bits)
+    if (std::max(v.idbits, vb + 1) - vb == 16 && sl.xb == 0) {
+        ++vb;
+        fill();
     }
+    if (blk0 > ix->max_lds)
+        return fail(AQR_ERR_INVALID_ARG, std::string(who) + ": LDS per block exceeds the device limit (lower ef_max, visited_log2 or waves_per_block)");
     const size_t wl = sl.bytes();
     const size_t lds = block_bytes();
-    const size_t wl0 = blk0 / wpb;  // mean LDS of a wave before the extra buckets
     dev::SearchArgs a{};
     a.ix = v;
     a.Q = Q;
@@ -2245,7 +2261,8 @@ aqr_status run_search(const aqr_index* ix, const float* Q, int64_t nq, const int
     if (cpl > 16) return fail(AQR_ERR_INVALID_ARG, std::string(who) + ": row too wide");
     if (!f32 && cpl > 4) return fail(AQR_ERR_INVALID_ARG, std::string(who) + ": code row too wide");
     const bool lat = nq <= (int64_t)ix->num_cu * 4;  // at most one wave per SIMD
-    const bool lds_few = ix->cu_lds / wl0 <= 20;      // LDS: at most five waves per SIMD
+    // LDS leaves at most five waves per SIMD (counted in whole blocks)
+    const bool lds_few = per_cu * (size_t)wpb <= 20;
     e = f32 ? launch_search<true>(a, nch, sp->blocks, wpb, lds, ix->num_cu, ix->cu_lds, s, lat, lds_few)
             : launch_search<false>(a, nch, sp->blocks, wpb, lds, ix->num_cu, ix->cu_lds, s, lat, lds_few);
     if (e != hipSuccess) return hip_fail(e, who);

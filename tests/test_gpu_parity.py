@@ -588,6 +588,30 @@ def test_stage1_at_19_bit_ids(orc):
     check_rerank(orc, index, Q, g, 10, gr, force_et=0, n_rerank=50)
 
 
+def test_stage1_at_20_bit_ids_with_16_bit_entries(orc):
+    # 524,289 rows need 20-bit ids.  With 2^4 visited buckets plus the ones
+    # the launch adds from spare LDS, each entry holds 16 bits: the scaled
+    # place of the hashed id in its bucket.  With 2^9 buckets it holds 11.
+    # Stage 1 stays bit-exact against the oracle (same expansions, same
+    # distinct visited set), so no entry ever names an id the cache has not
+    # seen.
+    print("index: serving rows, n = 524,289", flush=True)
+    index = _library_index("serving", 524_289, 16, 100, 120)
+    Q = index["Q"]
+    cap = 1 << 15
+    o, _ = oracle_stage1(orc, index, Q, 10, 160, tap_cap=cap)
+    for vb in (4, 9):
+        g = run_stage1(index, Q, 10, 160, vb=vb, tap_cap=cap)
+        compare_stage1(g, o, Q.shape[0])
+        for q in range(Q.shape[0]):
+            ne = int(o["n_expanded"][q])
+            np.testing.assert_array_equal(g["expanded"][q, :ne], o["expanded"][q, :ne])
+            ge = int(g["counts"][q, 1])
+            assert ge < cap
+            gset = set(g["evaluated"][q, :ge].tolist()) | {int(o["expanded"][q, 0])}
+            assert gset == set(o["visited"][q, :int(o["n_visited"][q])].tolist())
+
+
 def test_image_shaped_rows_pipeline(orc):
     # 784-dimensional rows (the Fashion-MNIST shape): 49 chunks of 16 codes
     # per row, four chunks per lane; code rows at a 896-byte stride and FP32
