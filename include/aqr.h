@@ -298,7 +298,12 @@ typedef struct aqr_sparams {
     int32_t m_ef;         /* ef multiplier when nc is not given (Table 3: 2 or 3) */
     int32_t waves_per_block; /* 0 = library default */
     int32_t blocks;       /* persistent grid size, 0 = fill the device */
-    int32_t visited_log2; /* log2 of visited-cache buckets (4 ids each), 0 = 7 */
+    int32_t visited_log2; /* log2 of visited-cache buckets (4 ids each), 0 = 7, in [4, 14];
+                             raised to (id bits - 16) when smaller.  The launch
+                             adds the buckets (fewer than 2^visited_log2) that
+                             fit in the LDS its resident blocks leave unused;
+                             with 16 stored bits it needs at least one, else it
+                             takes the next size.  No result depends on it. */
     const int32_t* order; /* device, nullable: work order of the queries (a permutation) */
     /* Two list sizes in one launch (0 = off): small_waves of the
      * waves_per_block waves of each block (0 <= small_waves < waves_per_block)
